@@ -1,0 +1,150 @@
+"""SurfaceNets oracle (test infrastructure only).
+
+Thin ctypes wrapper around ``sn_oracle.c``, the plain serial FP64 statement of
+the method (Sections 2.1-2.5 and Eq. (1) of Schroeder et al., "A
+High-Performance SurfaceNets Discrete Isocontouring Algorithm").  Only the
+tests, the package smoke check and the benchmark's CPU-baseline leg import
+this module; the GPU library never does.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libsn_oracle.so")
+_lib = None
+
+
+def build() -> str:
+    """Compile libsn_oracle.so with gcc (serial, no fast-math)."""
+    import subprocess
+
+    src = os.path.join(_HERE, "sn_oracle.c")
+    tmp = _LIB_PATH + ".tmp"
+    subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", "-ffp-contract=off", "-o", tmp, src])
+    os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build()
+        lib = ctypes.CDLL(_LIB_PATH)
+        P = ctypes.c_void_p
+        I64 = ctypes.c_int64
+        lib.orc_extract.restype = P
+        lib.orc_extract.argtypes = [P, ctypes.c_int, I64, I64, I64, P, ctypes.c_int32,
+                                    ctypes.c_uint32]
+        lib.orc_mesh_free.argtypes = [P]
+        lib.orc_mesh_free.restype = None
+        lib.orc_mesh_sizes.argtypes = [P, P]
+        lib.orc_mesh_sizes.restype = None
+        lib.orc_mesh_copy.argtypes = [P, P, P, P, P, P]
+        lib.orc_mesh_copy.restype = None
+        lib.orc_smooth.argtypes = [P, ctypes.c_int32, ctypes.c_double, ctypes.c_double, P]
+        lib.orc_smooth.restype = ctypes.c_int
+        lib.orc_centres.argtypes = [P, P]
+        lib.orc_centres.restype = None
+        lib.orc_world.argtypes = [I64, P, P, P, P]
+        lib.orc_world.restype = None
+        lib.orc_triangulate.argtypes = [P, P, P]
+        lib.orc_triangulate.restype = None
+        _lib = lib
+    return _lib
+
+
+def _p(a):
+    return None if a is None else ctypes.c_void_p(a.ctypes.data)
+
+
+@dataclass
+class OracleMesh:
+    dims: tuple            # (M, N, O)
+    cell_of: np.ndarray    # int64 [P] linear cell index i + (M-1)(j + (N-1)k)
+    quads: np.ndarray      # int32 [Q, 4]
+    pairs: np.ndarray      # uint32 [Q, 2] (front, back)
+    st_off: np.ndarray     # int64 [P+1]
+    st_ids: np.ndarray     # int32 [S]
+    _handle: int = 0
+
+    @property
+    def n_points(self):
+        return int(self.cell_of.shape[0])
+
+    @property
+    def n_quads(self):
+        return int(self.quads.shape[0])
+
+    @property
+    def n_stencil(self):
+        return int(self.st_ids.shape[0])
+
+    def cells_ijk(self) -> np.ndarray:
+        M, N, _ = self.dims
+        c = self.cell_of
+        return np.stack([c % (M - 1), (c // (M - 1)) % (N - 1), c // ((M - 1) * (N - 1))], 1)
+
+    def centres(self) -> np.ndarray:
+        out = np.empty((self.n_points, 3), dtype=np.float64)
+        _load().orc_centres(self._handle, _p(out))
+        return out
+
+    def smooth(self, iterations: int, relaxation: float, constraint: float) -> np.ndarray:
+        """Index-space positions after `iterations` Jacobi sweeps (FP64)."""
+        out = np.empty((self.n_points, 3), dtype=np.float64)
+        rc = _load().orc_smooth(self._handle, int(iterations), float(relaxation),
+                                float(constraint), _p(out))
+        if rc != 0:
+            raise MemoryError("oracle smoothing allocation failed")
+        return out
+
+    def triangulate(self):
+        tris = np.empty((2 * self.n_quads, 3), dtype=np.int32)
+        tp = np.empty((2 * self.n_quads, 2), dtype=np.uint32)
+        _load().orc_triangulate(self._handle, _p(tris), _p(tp))
+        return tris, tp
+
+    def __del__(self):
+        if self._handle and _lib is not None:
+            _lib.orc_mesh_free(self._handle)
+            self._handle = 0
+
+
+def extract(labels: np.ndarray, selected=(), background: int = 0) -> OracleMesh:
+    """Extract the SurfaceNets mesh of a label volume of shape (O, N, M)."""
+    lib = _load()
+    labels = np.ascontiguousarray(labels)
+    if labels.dtype not in (np.uint8, np.uint16, np.uint32):
+        raise TypeError("labels must be uint8, uint16 or uint32")
+    O, N, M = labels.shape
+    sel = np.ascontiguousarray(np.asarray(selected, dtype=np.uint32).reshape(-1))
+    h = lib.orc_extract(_p(labels), labels.dtype.itemsize, M, N, O,
+                        _p(sel) if sel.size else None, int(sel.size), int(background))
+    if not h:
+        raise MemoryError("oracle extraction failed")
+    sizes = np.zeros(4, dtype=np.int64)
+    lib.orc_mesh_sizes(h, _p(sizes))
+    P, Q, S = (int(x) for x in sizes[:3])
+    cell_of = np.empty(P, dtype=np.int64)
+    quads = np.empty((Q, 4), dtype=np.int32)
+    pairs = np.empty((Q, 2), dtype=np.uint32)
+    st_off = np.empty(P + 1, dtype=np.int64)
+    st_ids = np.empty(S, dtype=np.int32)
+    lib.orc_mesh_copy(h, _p(cell_of), _p(quads), _p(pairs), _p(st_off), _p(st_ids))
+    return OracleMesh((M, N, O), cell_of, quads, pairs, st_off, st_ids, h)
+
+
+def world(idx_pos: np.ndarray, origin, spacing) -> np.ndarray:
+    lib = _load()
+    idx_pos = np.ascontiguousarray(idx_pos, dtype=np.float64)
+    o = np.ascontiguousarray(origin, dtype=np.float64)
+    h = np.ascontiguousarray(spacing, dtype=np.float64)
+    out = np.empty_like(idx_pos)
+    lib.orc_world(idx_pos.shape[0], _p(idx_pos), _p(o), _p(h), _p(out))
+    return out
