@@ -1,0 +1,230 @@
+/*
+ * sn.h -- C ABI of libsn.so: SurfaceNets surface extraction and constrained
+ * smoothing of 3D integer label maps on an AMD Instinct MI355X (gfx950).
+ *
+ * The method is that of Schroeder, Tsalikis, Halle and Frisken, "A
+ * High-Performance SurfaceNets Discrete Isocontouring Algorithm":
+ *   - extraction (Sec. 2.2, 2.3): one point at the centre of every voxel cell
+ *     with an intersected edge, one quad per intersected edge joining the four
+ *     cells around it, a region-label pair per quad and a smoothing stencil
+ *     linking face-neighbour cells;
+ *   - smoothing (Eq. (1), Sec. 2.2, 2.4): double-buffered Laplacian relaxation
+ *     of the points, each held inside a box around its cell centre;
+ *   - triangulation (Sec. 2.5): two triangles per quad.
+ *
+ * Conventions (all counts are int64; ids inside meshes are int32):
+ *   - A label volume is x-fastest: value (i,j,k) at i + M*(j + N*k), where
+ *     dims = {M, N, O} are the numbers of samples along x, y, z.
+ *   - Classification (Sec. 2.1): a value is kept if it is selected and is not
+ *     the background value; every other value becomes the background value.
+ *     n_selected == 0 selects every value except the background.  An edge is
+ *     intersected iff its two classified end values differ (Sec. 2.2).
+ *   - Cell (i,j,k), 0 <= i < M-1 etc., spans samples (i..i+1, j..j+1, k..k+1).
+ *     Point ids follow the cell linear index i + (M-1)*(j + (N-1)*k).
+ *   - The quad of the intersected edge from sample s0=(i,j,k) to s1 = s0 + e_a
+ *     exists iff all four cells around the edge exist (regions that touch the
+ *     volume faces stay open, Sec. 4.2).  Quads are ordered by the sample
+ *     linear index of s0, then by axis x, y, z.  Vertex order for the edge at
+ *     (i,j,k) (right-hand normal along -e_a, i.e. facing s0):
+ *        x: (i,j-1,k-1) (i,j-1,k) (i,j,k) (i,j,k-1)
+ *        y: (i-1,j,k-1) (i,j,k-1) (i,j,k) (i-1,j,k)
+ *        z: (i-1,j-1,k) (i-1,j,k) (i,j,k) (i,j-1,k)
+ *     label_pairs[q] = (front, back) = (class(s0), class(s1)), stored in the
+ *     input dtype.
+ *   - Stencil (Sec. 2.2, 3.3): cell c links to face neighbour n iff n exists
+ *     and the shared face holds an intersected edge; entries are in face
+ *     order -x, +x, -y, +y, -z, +z, stored as CSR (offsets [P+1], ids [S]).
+ *   - Points are world coordinates origin + spacing * (i+1/2+dx, j+1/2+dy,
+ *     k+1/2+dz) in float32, xyz interleaved; d = (dx,dy,dz) are the
+ *     cell-relative offsets ("offsets"), zero before smoothing.
+ *   - Smoothing, per sweep: d <- clamp(d + lambda * mean_n(e_n + d_n - d),
+ *     -c, c) per axis, where e_n is the unit step to neighbour n and c is the
+ *     constraint distance in voxel units; no neighbours -> no motion.
+ *   - Triangles (SN_TRIS): quad (A,B,C,D) -> (A,B,C), (A,C,D); triangle 2q
+ *     and 2q+1 come from quad q and repeat its label pair.
+ *
+ * Memory: `labels` is a DEVICE pointer owned by the caller; every sn_mesh and
+ * everything it points to is device memory owned by the library until
+ * sn_mesh_free.  Host arrays passed in (selected labels, parameters) are
+ * copied during the call.  Streams are passed as `void*` holding a
+ * hipStream_t (NULL = the legacy default stream).
+ *
+ * Errors: every call returns an sn_status; out-parameters are written only on
+ * SN_OK; nothing throws across the ABI.  sn_strerror() names a status.
+ *
+ * Threads: an sn_ctx is used by one host thread at a time; the sn_serve_*
+ * calls are thread-safe.
+ */
+#ifndef SN_H
+#define SN_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum sn_status {
+    SN_OK = 0,
+    SN_EINVAL = -1,     /* a bad argument (message via sn_last_error)            */
+    SN_ENOMEM = -2,     /* device memory (or the configured budget) exhausted    */
+    SN_EDEVICE = -3,    /* a HIP runtime error                                   */
+    SN_ETOOBIG = -4,    /* a point id, quad or stencil index exceeds int32       */
+    SN_EAGAIN = -5,     /* serve: queue full, or the ticket is not finished yet  */
+    SN_ENOTFOUND = -6,  /* serve: unknown ticket                                 */
+    SN_ESHUTDOWN = -7,  /* serve: the server is stopping                         */
+    SN_ETIMEDOUT = -8   /* serve: wait timed out                                 */
+} sn_status;
+
+typedef enum sn_dtype { SN_U8 = 1, SN_U16 = 2, SN_U32 = 4 } sn_dtype;
+typedef enum sn_prim { SN_TRIS = 3, SN_QUADS = 4 } sn_prim;
+
+typedef struct sn_ctx sn_ctx;
+typedef struct sn_mesh sn_mesh;
+typedef struct sn_server sn_server;
+
+/* One label volume and its extraction parameters (Sec. 2.1, 2.2, 2.5). */
+typedef struct sn_volume {
+    const void *labels;        /* device, dims[0]*dims[1]*dims[2] values, x fastest       */
+    int32_t dtype;             /* sn_dtype: bytes per label                               */
+    int64_t dims[3];           /* M, N, O >= 1; a dim below 2 gives an empty mesh          */
+    double spacing[3];         /* > 0 and finite                                          */
+    double origin[3];          /* world position of sample (0,0,0)                        */
+    const uint32_t *selected;  /* host; duplicates allowed                                */
+    int32_t n_selected;        /* 0: every value except the background                    */
+    uint32_t background;       /* must fit the dtype; must not be in `selected`           */
+    int32_t prim;              /* sn_prim                                                 */
+} sn_volume;
+
+/* Eq. (1) parameters: sweeps >= 0, 0 <= relaxation <= 1, constraint >= 0 (voxels). */
+typedef struct sn_smooth_params {
+    int32_t iterations;
+    float relaxation;
+    float constraint;
+} sn_smooth_params;
+
+/* Borrowed device pointers, valid until sn_mesh_free. */
+typedef struct sn_mesh_view {
+    int64_t n_points, n_quads, n_stencil, n_polys;
+    int32_t prim, dtype;
+    const float *points;        /* [n_points*3] world xyz                                 */
+    const float *offsets;       /* [n_points*3] cell-relative offsets; NULL = all zero    */
+    const int32_t *polys;       /* [n_polys*prim] point ids                               */
+    const void *label_pairs;    /* [n_polys*2] (front, back), dtype bytes each            */
+    const int32_t *stencil_off; /* [n_points+1]                                           */
+    const int32_t *stencil_ids; /* [n_stencil]                                            */
+    const int32_t *quads;       /* [n_quads*4] (same as polys for SN_QUADS)               */
+} sn_mesh_view;
+
+/* ---- context -------------------------------------------------------------- */
+
+/* Bind a context to HIP device `device`.  Reads SN_AUTOTUNE_CACHE (a JSON file
+ * of schedule choices) and SN_TEST_MEM_LIMIT (a byte cap on the library's
+ * device pool, used by tests to force SN_ENOMEM) from the environment. */
+sn_status sn_ctx_create(int device, sn_ctx **out);
+void sn_ctx_destroy(sn_ctx *ctx);
+const char *sn_strerror(sn_status s);
+/* Text of the last error raised on this host thread ("" if none). */
+const char *sn_last_error(void);
+/* Library build identification, e.g. "libsn gfx950 <date>". */
+const char *sn_version(void);
+
+/* ---- plain path ----------------------------------------------------------- */
+
+/* Extract the SurfaceNets mesh of one volume (Sec. 2.3).  The call blocks until
+ * the output sizes are known (one device-to-host read of three totals), then
+ * enqueues generation on `stream` and returns; the mesh is complete once
+ * `stream` reaches that point.  Points are cell centres; offsets are NULL. */
+sn_status sn_extract(sn_ctx *ctx, const sn_volume *vol, void *stream, sn_mesh **out);
+
+/* Smooth a mesh (Eq. (1), Sec. 2.4).  Always restarts from the unsmoothed
+ * centres kept with the mesh (the smoothing cache of Sec. 3.7), so repeated
+ * calls with different parameters are independent.  Enqueued on `stream`
+ * (the sweeps are replayed from a cached HIP graph).  iterations == 0
+ * restores the centres. */
+sn_status sn_smooth(sn_ctx *ctx, sn_mesh *mesh, const sn_smooth_params *p, void *stream);
+
+sn_status sn_mesh_view_get(const sn_mesh *mesh, sn_mesh_view *out);
+
+/* Synchronous copies of mesh arrays to host memory; a NULL destination skips
+ * that array.  Sizes: points/offsets 3*P floats, polys n_polys*prim int32,
+ * labels 2*n_polys*dtype bytes, stencil_off P+1, stencil_ids S int32. */
+sn_status sn_mesh_copy_to_host(const sn_mesh *mesh, float *points, int32_t *polys, void *labels,
+                               int32_t *stencil_off, int32_t *stencil_ids, float *offsets);
+/* Waits for the mesh's outstanding work, then releases it. */
+void sn_mesh_free(sn_mesh *mesh);
+
+/* ---- batched path ---------------------------------------------------------- */
+
+/* Extract and smooth n independent volumes of any sizes together: one
+ * counting launch, one readback of all totals, one generation launch and one
+ * HIP-graph replay of the smoothing sweeps for the whole batch, with per-volume
+ * sweep counts.  per_vol may be NULL (no smoothing).  Each out_meshes[v] equals
+ * what sn_extract + sn_smooth give for volume v alone.  On failure no mesh is
+ * returned. */
+sn_status sn_batch_submit(sn_ctx *ctx, const sn_volume *vols, const sn_smooth_params *per_vol,
+                          int32_t n, void *stream, sn_mesh **out_meshes);
+
+/* ---- served path ----------------------------------------------------------- */
+
+typedef struct sn_serve_config {
+    int64_t hbm_budget_bytes; /* device bytes the server may hold for work and meshes    */
+    int32_t max_inflight;     /* requests admitted but not yet finished (>= 1)           */
+    int32_t n_streams;        /* concurrent device batches (>= 1)                        */
+    int32_t max_batch;        /* requests fused into one batch (>= 1)                    */
+    int32_t queue_capacity;   /* pending requests before sn_serve_submit says SN_EAGAIN */
+} sn_serve_config;
+
+typedef struct sn_serve_stats {
+    int64_t n_submitted, n_done, n_rejected, n_batches;
+    int64_t voxels_done, point_iters_done;
+    double p50_us, p99_us, mean_us; /* completion - submission, finished requests     */
+    double busy_s;                  /* wall time with at least one request in flight  */
+    int64_t peak_reserved_bytes;
+} sn_serve_stats;
+
+/* Start a request loop on ctx's device.  The server admits a pending request
+ * when its device-footprint estimate fits the budget next to the work in
+ * flight, fuses the admitted requests of a round into one batch (continuous
+ * batching: requests arriving while batches run join the next free stream),
+ * and keeps result meshes device-resident until claimed. */
+sn_status sn_serve_start(sn_ctx *ctx, const sn_serve_config *cfg, sn_server **out);
+/* Queue a request.  `vol->labels` must stay valid until the ticket is done. */
+sn_status sn_serve_submit(sn_server *srv, const sn_volume *vol, const sn_smooth_params *p,
+                          uint64_t *ticket);
+/* SN_OK and the mesh (ownership passes to the caller) once done; SN_EAGAIN
+ * if not yet; the request's own error status if it failed. */
+sn_status sn_serve_poll(sn_server *srv, uint64_t ticket, sn_mesh **out);
+/* As poll, but blocks up to timeout_us (< 0: forever); SN_ETIMEDOUT on expiry. */
+sn_status sn_serve_wait(sn_server *srv, uint64_t ticket, int64_t timeout_us, sn_mesh **out);
+sn_status sn_serve_stats_get(sn_server *srv, sn_serve_stats *out);
+/* Drain in-flight work, reject queued requests, stop the loop, free the server. */
+sn_status sn_serve_stop(sn_server *srv);
+
+/* ---- schedule tuning and profiling ----------------------------------------- */
+
+/* Time the candidate schedules (rows per wave of the row kernels) for the
+ * volume's size class on this device and remember the fastest for it (also
+ * written to SN_AUTOTUNE_CACHE if set).  Returns the chosen rows-per-wave. */
+sn_status sn_autotune(sn_ctx *ctx, const sn_volume *vol, void *stream, int32_t *chosen);
+/* Force the rows-per-wave schedule of the row kernels (1..16) for every later
+ * launch on this context; 0 returns to the tuned/default choice.  Results do
+ * not depend on the schedule. */
+sn_status sn_set_rows_per_wave(sn_ctx *ctx, int32_t rows_per_wave);
+
+/* Per-kernel timing: when on, every library kernel launch is bracketed by HIP
+ * events on the stream it runs on.  sn_profile_read synchronises, folds the
+ * events into per-kernel totals and fills up to `cap` records. */
+typedef struct sn_kernel_stat {
+    char name[48];
+    int64_t launches;
+    double total_ms;
+} sn_kernel_stat;
+sn_status sn_profile_enable(sn_ctx *ctx, int on);
+sn_status sn_profile_reset(sn_ctx *ctx);
+sn_status sn_profile_read(sn_ctx *ctx, sn_kernel_stat *out, int32_t cap, int32_t *n_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SN_H */

@@ -1,0 +1,381 @@
+"""MI355X SurfaceNets: Python binding of libsn.so.
+
+Argument marshalling only: every step of extraction and smoothing runs in the
+HIP kernels of ``libsn.so`` (built from ``csrc/`` for gfx950).  PyTorch is used
+for device memory and streams.  There is no fallback: if the library is
+missing, importing the binding raises.
+
+The functions mirror the C ABI in ``include/sn.h``:
+
+    ctx = Context(0)
+    mesh = ctx.extract(labels_cuda_tensor, spacing=(1, 1, 2.5), selected=(), background=0)
+    ctx.smooth(mesh, iterations=25, relaxation=0.5, constraint=1.0)
+    host = mesh.to_host()        # numpy arrays
+    meshes = ctx.batch_submit([...], [...])
+    srv = ctx.serve_start(...); t = srv.submit(...); mesh = srv.wait(t)
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsn.so")
+
+SN_OK, SN_EINVAL, SN_ENOMEM, SN_EDEVICE, SN_ETOOBIG = 0, -1, -2, -3, -4
+SN_EAGAIN, SN_ENOTFOUND, SN_ESHUTDOWN, SN_ETIMEDOUT = -5, -6, -7, -8
+SN_TRIS, SN_QUADS = 3, 4
+_NP_DT = {1: np.uint8, 2: np.uint16, 4: np.uint32}
+
+
+class SNError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"libsn status {status}: {msg}")
+        self.status = status
+
+
+class sn_volume(ctypes.Structure):
+    _fields_ = [("labels", ctypes.c_void_p), ("dtype", ctypes.c_int32),
+                ("dims", ctypes.c_int64 * 3), ("spacing", ctypes.c_double * 3),
+                ("origin", ctypes.c_double * 3), ("selected", ctypes.POINTER(ctypes.c_uint32)),
+                ("n_selected", ctypes.c_int32), ("background", ctypes.c_uint32),
+                ("prim", ctypes.c_int32)]
+
+
+class sn_smooth_params(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("relaxation", ctypes.c_float),
+                ("constraint", ctypes.c_float)]
+
+
+class sn_mesh_view(ctypes.Structure):
+    _fields_ = [("n_points", ctypes.c_int64), ("n_quads", ctypes.c_int64),
+                ("n_stencil", ctypes.c_int64), ("n_polys", ctypes.c_int64),
+                ("prim", ctypes.c_int32), ("dtype", ctypes.c_int32),
+                ("points", ctypes.c_void_p), ("offsets", ctypes.c_void_p),
+                ("polys", ctypes.c_void_p), ("label_pairs", ctypes.c_void_p),
+                ("stencil_off", ctypes.c_void_p), ("stencil_ids", ctypes.c_void_p),
+                ("quads", ctypes.c_void_p)]
+
+
+class sn_serve_config(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_int64), ("max_inflight", ctypes.c_int32),
+                ("n_streams", ctypes.c_int32), ("max_batch", ctypes.c_int32),
+                ("queue_capacity", ctypes.c_int32)]
+
+
+class sn_serve_stats(ctypes.Structure):
+    _fields_ = [("n_submitted", ctypes.c_int64), ("n_done", ctypes.c_int64),
+                ("n_rejected", ctypes.c_int64), ("n_batches", ctypes.c_int64),
+                ("voxels_done", ctypes.c_int64), ("point_iters_done", ctypes.c_int64),
+                ("p50_us", ctypes.c_double), ("p99_us", ctypes.c_double),
+                ("mean_us", ctypes.c_double), ("busy_s", ctypes.c_double),
+                ("peak_reserved_bytes", ctypes.c_int64)]
+
+
+class sn_kernel_stat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 48), ("launches", ctypes.c_int64),
+                ("total_ms", ctypes.c_double)]
+
+
+# every entry point declared in include/sn.h: (name, restype, argtypes)
+_P = ctypes.c_void_p
+_S = ctypes.c_int
+_API = [
+    ("sn_ctx_create", _S, [ctypes.c_int, ctypes.POINTER(_P)]),
+    ("sn_ctx_destroy", None, [_P]),
+    ("sn_strerror", ctypes.c_char_p, [_S]),
+    ("sn_last_error", ctypes.c_char_p, []),
+    ("sn_version", ctypes.c_char_p, []),
+    ("sn_extract", _S, [_P, ctypes.POINTER(sn_volume), _P, ctypes.POINTER(_P)]),
+    ("sn_smooth", _S, [_P, _P, ctypes.POINTER(sn_smooth_params), _P]),
+    ("sn_mesh_view_get", _S, [_P, ctypes.POINTER(sn_mesh_view)]),
+    ("sn_mesh_copy_to_host", _S, [_P, _P, _P, _P, _P, _P, _P]),
+    ("sn_mesh_free", None, [_P]),
+    ("sn_batch_submit", _S, [_P, ctypes.POINTER(sn_volume), ctypes.POINTER(sn_smooth_params),
+                             ctypes.c_int32, _P, ctypes.POINTER(_P)]),
+    ("sn_serve_start", _S, [_P, ctypes.POINTER(sn_serve_config), ctypes.POINTER(_P)]),
+    ("sn_serve_submit", _S, [_P, ctypes.POINTER(sn_volume), ctypes.POINTER(sn_smooth_params),
+                             ctypes.POINTER(ctypes.c_uint64)]),
+    ("sn_serve_poll", _S, [_P, ctypes.c_uint64, ctypes.POINTER(_P)]),
+    ("sn_serve_wait", _S, [_P, ctypes.c_uint64, ctypes.c_int64, ctypes.POINTER(_P)]),
+    ("sn_serve_stats_get", _S, [_P, ctypes.POINTER(sn_serve_stats)]),
+    ("sn_serve_stop", _S, [_P]),
+    ("sn_autotune", _S, [_P, ctypes.POINTER(sn_volume), _P, ctypes.POINTER(ctypes.c_int32)]),
+    ("sn_set_rows_per_wave", _S, [_P, ctypes.c_int32]),
+    ("sn_profile_enable", _S, [_P, ctypes.c_int]),
+    ("sn_profile_reset", _S, [_P]),
+    ("sn_profile_read", _S, [_P, ctypes.POINTER(sn_kernel_stat), ctypes.c_int32,
+                             ctypes.POINTER(ctypes.c_int32)]),
+]
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libsn.so and bind every declared entry point.  Raises if absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with __graft_entry__.build() "
+                          "(there is no CPU fallback)")
+    lib = ctypes.CDLL(path)
+    for name, res, args in _API:
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(st: int):
+    if st != SN_OK:
+        msg = _lib.sn_last_error().decode(errors="replace")
+        raise SNError(st, msg or _lib.sn_strerror(st).decode())
+
+
+def _stream_handle(stream) -> Optional[int]:
+    import torch
+
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(int(stream.cuda_stream))
+
+
+@dataclass
+class HostMesh:
+    points: np.ndarray        # float32 [P,3] world
+    offsets: np.ndarray       # float32 [P,3] cell-relative
+    polys: np.ndarray         # int32 [n_polys, prim]
+    label_pairs: np.ndarray   # dtype [n_polys, 2]
+    stencil_off: np.ndarray   # int32 [P+1]
+    stencil_ids: np.ndarray   # int32 [S]
+
+
+class Mesh:
+    """A device-resident mesh owned by libsn (freed by .free() or GC)."""
+
+    def __init__(self, handle: int, keepalive=None):
+        self._h = ctypes.c_void_p(handle)
+        self._keep = keepalive
+
+    @property
+    def handle(self):
+        return self._h
+
+    def view(self) -> sn_mesh_view:
+        v = sn_mesh_view()
+        _check(_lib.sn_mesh_view_get(self._h, ctypes.byref(v)))
+        return v
+
+    @property
+    def n_points(self):
+        return int(self.view().n_points)
+
+    @property
+    def n_quads(self):
+        return int(self.view().n_quads)
+
+    @property
+    def n_stencil(self):
+        return int(self.view().n_stencil)
+
+    def to_host(self) -> HostMesh:
+        v = self.view()
+        P, n, prim, b = int(v.n_points), int(v.n_polys), int(v.prim), int(v.dtype)
+        pts = np.empty((P, 3), np.float32)
+        off = np.empty((P, 3), np.float32)
+        polys = np.empty((n, prim), np.int32)
+        lab = np.empty((n, 2), _NP_DT[b])
+        so = np.empty(P + 1, np.int32)
+        si = np.empty(int(v.n_stencil), np.int32)
+        p = lambda a: ctypes.c_void_p(a.ctypes.data)  # noqa: E731
+        _check(_lib.sn_mesh_copy_to_host(self._h, p(pts), p(polys), p(lab), p(so), p(si), p(off)))
+        return HostMesh(pts, off, polys, lab, so, si)
+
+    def free(self):
+        if self._h and self._h.value:
+            if _lib is not None:
+                _lib.sn_mesh_free(self._h)
+            self._h = ctypes.c_void_p(0)
+        self._keep = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def to_device(a: np.ndarray, device="cuda"):
+    """Copy a host label volume (uint8/16/32) to the GPU, bit-exact (int views)."""
+    import torch
+
+    a = np.ascontiguousarray(a)
+    view = {np.dtype(np.uint8): np.uint8, np.dtype(np.uint16): np.int16,
+            np.dtype(np.uint32): np.int32}[a.dtype]
+    return torch.from_numpy(a.view(view)).to(device)
+
+
+def make_volume(labels, spacing=(1.0, 1.0, 1.0), origin=(0.0, 0.0, 0.0), selected=(),
+                background=0, prim=SN_QUADS):
+    """Build an sn_volume for a CUDA tensor of shape (O, N, M); returns (vol, keepalive)."""
+    import torch
+
+    if not isinstance(labels, torch.Tensor) or not labels.is_cuda:
+        raise TypeError("labels must be a CUDA (HIP) torch tensor")
+    if labels.dim() != 3 or not labels.is_contiguous():
+        raise ValueError("labels must be a contiguous 3-D tensor (O, N, M)")
+    b = labels.element_size()
+    if b not in (1, 2, 4) or labels.is_floating_point():
+        raise TypeError("labels must hold 8-, 16- or 32-bit integers")
+    O, N, M = labels.shape
+    v = sn_volume()
+    v.labels = labels.data_ptr()
+    v.dtype = b
+    v.dims[:] = (M, N, O)
+    v.spacing[:] = tuple(float(x) for x in spacing)
+    v.origin[:] = tuple(float(x) for x in origin)
+    sel = np.ascontiguousarray(np.asarray(list(selected), dtype=np.uint32))
+    v.selected = sel.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)) if sel.size else None
+    v.n_selected = int(sel.size)
+    v.background = int(background)
+    v.prim = int(prim)
+    return v, (labels, sel)
+
+
+def smooth_params(iterations, relaxation, constraint) -> sn_smooth_params:
+    p = sn_smooth_params()
+    p.iterations, p.relaxation, p.constraint = int(iterations), float(relaxation), float(constraint)
+    return p
+
+
+class Context:
+    def __init__(self, device: int = 0):
+        load_library()
+        h = ctypes.c_void_p()
+        _check(_lib.sn_ctx_create(int(device), ctypes.byref(h)))
+        self._h = h
+        self.device = device
+
+    def close(self):
+        if self._h and self._h.value:
+            _lib.sn_ctx_destroy(self._h)
+            self._h = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def extract(self, labels, spacing=(1.0, 1.0, 1.0), origin=(0.0, 0.0, 0.0), selected=(),
+                background=0, prim=SN_QUADS, stream=None) -> Mesh:
+        v, keep = make_volume(labels, spacing, origin, selected, background, prim)
+        out = ctypes.c_void_p()
+        _check(_lib.sn_extract(self._h, ctypes.byref(v), _stream_handle(stream), ctypes.byref(out)))
+        return Mesh(out.value, keep)
+
+    def smooth(self, mesh: Mesh, iterations=25, relaxation=0.5, constraint=1.0, stream=None):
+        p = smooth_params(iterations, relaxation, constraint)
+        _check(_lib.sn_smooth(self._h, mesh.handle, ctypes.byref(p), _stream_handle(stream)))
+
+    def batch_submit(self, volumes: Sequence[dict], params: Optional[Sequence] = None,
+                     stream=None) -> list:
+        """volumes: dicts of make_volume keyword arguments; params: (iters, relax, constr)."""
+        n = len(volumes)
+        arr = (sn_volume * n)()
+        keep = []
+        for k, d in enumerate(volumes):
+            v, kp = make_volume(**d)
+            arr[k] = v
+            keep.append(kp)
+        parr = None
+        if params is not None:
+            parr = (sn_smooth_params * n)()
+            for k, p in enumerate(params):
+                parr[k] = smooth_params(*p)
+        outs = (ctypes.c_void_p * n)()
+        _check(_lib.sn_batch_submit(self._h, arr, parr, n, _stream_handle(stream), outs))
+        return [Mesh(outs[k], keep[k]) for k in range(n)]
+
+    def autotune(self, labels, spacing=(1.0, 1.0, 1.0), selected=(), background=0,
+                 stream=None) -> int:
+        v, keep = make_volume(labels, spacing, (0, 0, 0), selected, background)
+        ch = ctypes.c_int32()
+        _check(_lib.sn_autotune(self._h, ctypes.byref(v), _stream_handle(stream), ctypes.byref(ch)))
+        return int(ch.value)
+
+    def set_rows_per_wave(self, rpw: int):
+        _check(_lib.sn_set_rows_per_wave(self._h, int(rpw)))
+
+    def profile(self, on: bool = True):
+        _check(_lib.sn_profile_enable(self._h, 1 if on else 0))
+
+    def profile_reset(self):
+        _check(_lib.sn_profile_reset(self._h))
+
+    def profile_read(self) -> dict:
+        cap = 64
+        arr = (sn_kernel_stat * cap)()
+        n = ctypes.c_int32()
+        _check(_lib.sn_profile_read(self._h, arr, cap, ctypes.byref(n)))
+        return {arr[k].name.decode(): (int(arr[k].launches), float(arr[k].total_ms))
+                for k in range(min(n.value, cap))}
+
+    def serve_start(self, hbm_budget_bytes=8 << 30, max_inflight=64, n_streams=2, max_batch=16,
+                    queue_capacity=4096) -> "Server":
+        cfg = sn_serve_config()
+        cfg.hbm_budget_bytes, cfg.max_inflight, cfg.n_streams = hbm_budget_bytes, max_inflight, n_streams
+        cfg.max_batch, cfg.queue_capacity = max_batch, queue_capacity
+        h = ctypes.c_void_p()
+        _check(_lib.sn_serve_start(self._h, ctypes.byref(cfg), ctypes.byref(h)))
+        return Server(h, self)
+
+
+class Server:
+    def __init__(self, handle, ctx):
+        self._h = handle
+        self._ctx = ctx
+        self._keep = {}
+
+    def submit(self, labels, iterations=20, relaxation=0.5, constraint=1.0, **vol_kw) -> int:
+        v, keep = make_volume(labels, **vol_kw)
+        p = smooth_params(iterations, relaxation, constraint)
+        t = ctypes.c_uint64()
+        _check(_lib.sn_serve_submit(self._h, ctypes.byref(v), ctypes.byref(p), ctypes.byref(t)))
+        self._keep[int(t.value)] = keep
+        return int(t.value)
+
+    def poll(self, ticket: int) -> Optional[Mesh]:
+        out = ctypes.c_void_p()
+        st = _lib.sn_serve_poll(self._h, ctypes.c_uint64(ticket), ctypes.byref(out))
+        if st == SN_EAGAIN:
+            return None
+        keep = self._keep.pop(ticket, None)
+        _check(st)
+        return Mesh(out.value, keep)
+
+    def wait(self, ticket: int, timeout_us: int = -1) -> Mesh:
+        out = ctypes.c_void_p()
+        st = _lib.sn_serve_wait(self._h, ctypes.c_uint64(ticket), int(timeout_us), ctypes.byref(out))
+        if st == SN_ETIMEDOUT:
+            _check(st)
+        keep = self._keep.pop(ticket, None)
+        _check(st)
+        return Mesh(out.value, keep)
+
+    def stats(self) -> dict:
+        s = sn_serve_stats()
+        _check(_lib.sn_serve_stats_get(self._h, ctypes.byref(s)))
+        return {f: getattr(s, f) for f, _ in s._fields_}
+
+    def stop(self):
+        if self._h and self._h.value:
+            _check(_lib.sn_serve_stop(self._h))
+            self._h = ctypes.c_void_p(0)
+            self._keep.clear()

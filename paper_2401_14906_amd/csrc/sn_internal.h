@@ -1,0 +1,98 @@
+// Internal declarations shared by the HIP kernels and the host runtime of
+// libsn.so.  Not part of the public ABI (include/sn.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sn {
+
+// ---- classification (Sec. 2.1) ---------------------------------------------
+// C(v) = v if v is selected and is not the background value, else background.
+enum ClassMode : int32_t {
+    CLS_IDENT = 0,   // every value selected: C is the identity
+    CLS_BITMAP = 1,  // u8/u16: bit v of `table` set <=> v selected (background bit clear)
+    CLS_SORTED = 2   // u32: `table` holds n sorted, unique selected values (no background)
+};
+
+struct ClassSpec {
+    int32_t mode;
+    uint32_t bg;
+    const uint32_t *table;
+    int32_t n;
+};
+
+// Sample lattice M x N x O; cell grid CM x CN x CO = (M-1)(N-1)(O-1).
+// A "row" r = j + CN*k is the line of cells (0..CM-1, j, k); W = 64-cell words per row.
+struct Geom {
+    int64_t M, N, O;
+    int64_t CM, CN, CO;
+    int64_t R;
+    int32_t W;
+};
+
+// Everything the row kernels need for one volume.
+struct VolDesc {
+    const void *labels;
+    int32_t dtype;  // 1, 2, 4
+    int32_t prim;   // 3 or 4
+    Geom g;
+    ClassSpec cs;
+    // row metadata (kept with the mesh)
+    uint64_t *pmask;  // [R*W] point bit per cell
+    int64_t *baseP;   // [R+1] exclusive prefix of points per row
+    int64_t *baseQ;   // [R+1] quads
+    int64_t *baseS;   // [R+1] stencil entries
+    // outputs
+    float *points;     // [P*3]
+    uint8_t *faces;    // [P] stencil face mask, bit f = face f (-x,+x,-y,+y,-z,+z)
+    int32_t *st_off;   // [P+1]
+    int32_t *st_ids;   // [S]
+    int32_t *quads;    // [Q*4]
+    void *pairs;       // [Q*2] dtype
+    int32_t *tris;     // [2Q*3] (prim 3)
+    void *tri_pairs;   // [2Q*2] dtype (prim 3)
+    const float *delta;  // emit: final offsets or nullptr (zero)
+    double origin[3], spacing[3];
+    int64_t P, Q, S;
+};
+
+// One mesh's smoothing job.
+struct SmoothDesc {
+    int64_t P;
+    const uint8_t *faces;
+    const int32_t *off;
+    const int32_t *ids;
+    float *da;
+    float *db;
+    int32_t iters;
+    double lam;
+    double dist;
+};
+
+// Scan tile status word: [63:62] flag, [61:0] value.
+constexpr uint64_t kFlagAgg = 1ull << 62;
+constexpr uint64_t kFlagPrefix = 2ull << 62;
+constexpr uint64_t kValMask = (1ull << 62) - 1;
+constexpr int kMaxRowsPerWave = 16;
+constexpr int kWavesPerBlock = 4;
+constexpr int kBlock = 64 * kWavesPerBlock;
+
+// ---- launchers (sn_kernels.hip) ----------------------------------------------
+// tile_prefix[v] = first tile of volume v, tile_prefix[nvol] = total tiles;
+// a tile is 4*rpw consecutive rows of one volume.
+hipError_t launch_count(const VolDesc *d_descs, const int64_t *d_tile_prefix, int32_t nvol,
+                        int64_t ntiles, int32_t rpw, uint64_t *d_status, uint32_t *d_ticket,
+                        int64_t *d_totals, hipStream_t s);
+hipError_t launch_generate(const VolDesc *d_descs, const int64_t *d_tile_prefix, int32_t nvol,
+                           int64_t ntiles, int32_t rpw, hipStream_t s);
+hipError_t launch_emit(const VolDesc *d_descs, const int64_t *d_tile_prefix, int32_t nvol,
+                       int64_t ntiles, int32_t rpw, hipStream_t s);
+// block_prefix[v] = first block of volume v (256 points per block)
+hipError_t launch_jacobi(const SmoothDesc *d_sd, const int64_t *d_block_prefix, int32_t nvol,
+                         int64_t nblocks, int32_t it, hipStream_t s);
+// quad blocks (256 quads per block) of the volumes with prim 3
+hipError_t launch_triangulate(const VolDesc *d_descs, const int64_t *d_block_prefix, int32_t nvol,
+                              int64_t nblocks, hipStream_t s);
+
+}  // namespace sn

@@ -1,0 +1,128 @@
+// Host-side internals of libsn.so shared by sn_runtime.hip and sn_serve.hip.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "sn.h"
+#include "sn_internal.h"
+
+namespace sn {
+
+sn_status fail(sn_status s, const std::string &msg);
+
+#define HIP_TRY(expr)                                                                   \
+    do {                                                                                \
+        hipError_t _e = (expr);                                                         \
+        if (_e != hipSuccess)                                                           \
+            return ::sn::fail(SN_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(_e)); \
+    } while (0)
+
+class Pool {
+  public:
+    static inline const hipStream_t kNoWait = reinterpret_cast<hipStream_t>(~uintptr_t(0));
+    Pool(int device, bool pinned);
+    ~Pool();
+    void *alloc(size_t bytes);  // nullptr on failure (or over the test limit)
+    // Return a block; with a stream, it is reused only after the stream's
+    // current work has completed.
+    void release(void *p, hipStream_t after);
+    void release_all(const std::vector<void *> &ps, hipStream_t after);
+    int64_t in_use() const;
+    int64_t peak() const;
+
+  private:
+    struct Pending {
+        hipEvent_t ev;
+        std::vector<void *> blocks;
+    };
+    void reclaim_locked(bool wait);
+    void raw_free(void *p);
+    bool pinned_;
+    mutable std::mutex mu_;
+    std::multimap<size_t, void *> free_;
+    std::map<void *, size_t> sizes_;
+    std::vector<Pending> pending_;
+    int64_t in_use_ = 0, peak_ = 0, limit_ = -1;
+};
+
+}  // namespace sn
+
+struct sn_ctx {
+    explicit sn_ctx(int dev);
+    ~sn_ctx();
+    int device;
+    sn::Pool pool;    // device blocks
+    sn::Pool pinned;  // pinned host staging
+    hipStream_t capture_stream = nullptr;
+    std::mutex capture_mu;
+    // profiling
+    bool profiling = false;
+    struct ProfEv {
+        std::string name;
+        hipEvent_t a, b;
+        int64_t launches;
+    };
+    std::mutex prof_mu;
+    std::vector<ProfEv> prof_pending;
+    std::map<std::string, std::pair<int64_t, double>> prof_stats;
+    // schedule table: size class -> rows per wave
+    mutable std::mutex tune_mu;
+    std::map<std::string, int32_t> tune;
+    std::string tune_path;
+    int32_t forced_rpw = 0;
+    int32_t rows_per_wave(const std::string &cls) const;
+    void load_tune_cache();
+    void save_tune_cache() const;
+};
+
+struct sn_mesh {
+    ~sn_mesh();
+    sn_ctx *ctx = nullptr;
+    sn::VolDesc d{};            // host copy (device pointers inside)
+    int64_t P = 0, Q = 0, S = 0, voxels = 0, ntiles = 0;
+    int32_t rpw = 2;
+    std::vector<void *> blocks;  // every device block owned by the mesh
+    float *da = nullptr, *db = nullptr;
+    const float *final_delta = nullptr;
+    sn::VolDesc *dd = nullptr;     // device copy of d
+    int64_t *dtp = nullptr;        // device tile prefix {0, ntiles}
+    sn::SmoothDesc *dsd = nullptr; // device smoothing descriptor
+    int64_t *dbp = nullptr;        // device block prefix {0, point blocks}
+    std::map<int32_t, hipGraphExec_t> graphs;  // sweeps -> captured graph
+    hipEvent_t done_ev = nullptr;
+    bool last_stream_valid = false;
+};
+
+namespace sn {
+
+struct ProfScope {
+    ProfScope(sn_ctx *c, const char *name, hipStream_t s, int64_t launches = 1);
+    ~ProfScope();
+    sn_ctx *c_;
+    std::string name_;
+    hipStream_t s_;
+    int64_t launches_;
+    hipEvent_t a_ = nullptr, b_ = nullptr;
+};
+
+sn_status validate_volume(const sn_volume *v);
+sn_status validate_smooth(const sn_smooth_params *p);
+Geom make_geom(const sn_volume &v);
+std::string size_class(const sn_volume &v);
+sn_status extract_many(sn_ctx *c, const sn_volume *vols, int32_t n, hipStream_t s,
+                       int32_t rpw_override, sn_mesh **out);
+sn_status smooth_many(sn_ctx *c, sn_mesh **ms, const sn_smooth_params *pv, int32_t n,
+                      hipStream_t s);
+sn_status ensure_smooth_buffers(sn_mesh *m);
+sn_status run_sweeps(sn_ctx *c, const SmoothDesc *d_sd, const int64_t *d_bp, int32_t nvol,
+                     int64_t nblocks, int32_t iters, hipStream_t s,
+                     std::map<int32_t, hipGraphExec_t> *cache);
+sn_status mesh_mark(sn_mesh *m, hipStream_t s);
+void mesh_release(sn_mesh *m);
+
+}  // namespace sn

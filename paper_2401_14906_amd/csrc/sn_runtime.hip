@@ -1,0 +1,1030 @@
+// Host runtime of libsn.so: device memory pool, contexts, meshes, the plain
+// and batched extraction/smoothing paths, the schedule tuner and profiling.
+// The request server lives in sn_serve.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <mutex>
+#include <sstream>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "sn.h"
+#include "sn_internal.h"
+#include "sn_runtime.h"
+
+using namespace sn;
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+
+static thread_local std::string g_last_error;
+
+sn_status sn::fail(sn_status s, const std::string &msg)
+{
+    g_last_error = msg;
+    return s;
+}
+
+extern "C" const char *sn_last_error(void) { return g_last_error.c_str(); }
+
+extern "C" const char *sn_strerror(sn_status s)
+{
+    switch (s) {
+    case SN_OK: return "ok";
+    case SN_EINVAL: return "invalid argument";
+    case SN_ENOMEM: return "out of device memory";
+    case SN_EDEVICE: return "HIP runtime error";
+    case SN_ETOOBIG: return "mesh index exceeds int32";
+    case SN_EAGAIN: return "try again";
+    case SN_ENOTFOUND: return "unknown ticket";
+    case SN_ESHUTDOWN: return "server stopping";
+    case SN_ETIMEDOUT: return "timed out";
+    }
+    return "unknown status";
+}
+
+extern "C" const char *sn_version(void) { return "libsn gfx950 " __DATE__; }
+
+// ---------------------------------------------------------------------------
+// Pool: caching allocator for device and pinned host blocks.  A released block
+// may carry an event; it is reused only once that event has completed, so a
+// block freed while a stream still uses it is never handed out early.
+// ---------------------------------------------------------------------------
+
+static size_t round_size(size_t n)
+{
+    if (n == 0) n = 1;
+    if (n <= (1u << 20)) return (n + 511) & ~size_t(511);
+    const size_t g = size_t(2) << 20;
+    return (n + g - 1) / g * g;
+}
+
+Pool::Pool(int /*device*/, bool pinned) : pinned_(pinned)
+{
+    if (!pinned) {
+        const char *lim = std::getenv("SN_TEST_MEM_LIMIT");
+        if (lim && *lim) limit_ = std::strtoll(lim, nullptr, 10);
+    }
+}
+
+Pool::~Pool()
+{
+    std::lock_guard<std::mutex> g(mu_);
+    reclaim_locked(true);
+    for (auto &kv : free_) raw_free(kv.second);
+    free_.clear();
+}
+
+void Pool::raw_free(void *p)
+{
+    if (pinned_)
+        (void)hipHostFree(p);
+    else
+        (void)hipFree(p);
+}
+
+void Pool::reclaim_locked(bool wait)
+{
+    for (size_t k = 0; k < pending_.size();) {
+        Pending &pd = pending_[k];
+        hipError_t q = wait ? hipEventSynchronize(pd.ev) : hipEventQuery(pd.ev);
+        if (q == hipSuccess || (q != hipErrorNotReady)) {
+            for (void *p : pd.blocks) free_.emplace(sizes_[p], p);
+            (void)hipEventDestroy(pd.ev);
+            pending_[k] = std::move(pending_.back());
+            pending_.pop_back();
+        } else {
+            ++k;
+        }
+    }
+}
+
+void *Pool::alloc(size_t bytes)
+{
+    const size_t n = round_size(bytes);
+    std::lock_guard<std::mutex> g(mu_);
+    if (limit_ >= 0 && in_use_ + (int64_t)n > limit_) return nullptr;
+    reclaim_locked(false);
+    auto it = free_.lower_bound(n);
+    if (it != free_.end() && it->first <= 2 * n + (size_t(4) << 20)) {
+        void *p = it->second;
+        free_.erase(it);
+        in_use_ += (int64_t)sizes_[p];
+        return p;
+    }
+    void *p = nullptr;
+    hipError_t e = pinned_ ? hipHostMalloc(&p, n, hipHostMallocDefault) : hipMalloc(&p, n);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        // drop every cached block (waiting for deferred ones) and retry once
+        reclaim_locked(true);
+        for (auto &kv : free_) raw_free(kv.second), sizes_.erase(kv.second);
+        free_.clear();
+        e = pinned_ ? hipHostMalloc(&p, n, hipHostMallocDefault) : hipMalloc(&p, n);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+    }
+    sizes_[p] = n;
+    in_use_ += (int64_t)n;
+    peak_ = std::max(peak_, in_use_);
+    return p;
+}
+
+void Pool::release(void *p, hipStream_t after)
+{
+    if (!p) return;
+    std::lock_guard<std::mutex> g(mu_);
+    auto it = sizes_.find(p);
+    if (it == sizes_.end()) return;
+    in_use_ -= (int64_t)it->second;
+    if (after == kNoWait) {
+        free_.emplace(it->second, p);
+        return;
+    }
+    hipEvent_t ev;
+    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess ||
+        hipEventRecord(ev, after) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipStreamSynchronize(after);
+        free_.emplace(it->second, p);
+        return;
+    }
+    pending_.push_back(Pending{ev, {p}});
+}
+
+void Pool::release_all(const std::vector<void *> &ps, hipStream_t after)
+{
+    std::lock_guard<std::mutex> g(mu_);
+    std::vector<void *> live;
+    for (void *p : ps) {
+        if (!p) continue;
+        auto it = sizes_.find(p);
+        if (it == sizes_.end()) continue;
+        in_use_ -= (int64_t)it->second;
+        live.push_back(p);
+    }
+    if (live.empty()) return;
+    hipEvent_t ev;
+    if (after == kNoWait || hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess ||
+        hipEventRecord(ev, after) != hipSuccess) {
+        (void)hipGetLastError();
+        if (after != kNoWait) (void)hipStreamSynchronize(after);
+        for (void *p : live) free_.emplace(sizes_[p], p);
+        return;
+    }
+    pending_.push_back(Pending{ev, std::move(live)});
+}
+
+int64_t Pool::in_use() const
+{
+    std::lock_guard<std::mutex> g(mu_);
+    return in_use_;
+}
+
+int64_t Pool::peak() const
+{
+    std::lock_guard<std::mutex> g(mu_);
+    return peak_;
+}
+
+// ---------------------------------------------------------------------------
+// context
+// ---------------------------------------------------------------------------
+
+extern "C" sn_status sn_ctx_create(int device, sn_ctx **out)
+{
+    if (!out) return fail(SN_EINVAL, "sn_ctx_create: out is NULL");
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) {
+        (void)hipGetLastError();
+        return fail(SN_EDEVICE, "sn_ctx_create: no such HIP device");
+    }
+    HIP_TRY(hipSetDevice(device));
+    sn_ctx *c = new sn_ctx(device);
+    if (hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking) != hipSuccess) {
+        delete c;
+        return fail(SN_EDEVICE, "sn_ctx_create: stream creation failed");
+    }
+    const char *cache = std::getenv("SN_AUTOTUNE_CACHE");
+    if (cache && *cache) {
+        c->tune_path = cache;
+        c->load_tune_cache();
+    }
+    *out = c;
+    return SN_OK;
+}
+
+extern "C" void sn_ctx_destroy(sn_ctx *c)
+{
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    (void)hipDeviceSynchronize();
+    (void)hipStreamDestroy(c->capture_stream);
+    delete c;
+}
+
+sn_ctx::sn_ctx(int dev) : device(dev), pool(dev, false), pinned(dev, true) {}
+
+sn_ctx::~sn_ctx()
+{
+    for (auto &p : prof_pending) {
+        (void)hipEventDestroy(p.a);
+        (void)hipEventDestroy(p.b);
+    }
+}
+
+// ---- profiling -------------------------------------------------------------
+
+ProfScope::ProfScope(sn_ctx *c, const char *name, hipStream_t s, int64_t launches)
+    : c_(c), name_(name), s_(s), launches_(launches)
+{
+    if (!c_ || !c_->profiling) return;
+    if (hipEventCreate(&a_) != hipSuccess || hipEventCreate(&b_) != hipSuccess) {
+        (void)hipGetLastError();
+        a_ = b_ = nullptr;
+        return;
+    }
+    (void)hipEventRecord(a_, s_);
+}
+
+ProfScope::~ProfScope()
+{
+    if (!a_) return;
+    (void)hipEventRecord(b_, s_);
+    std::lock_guard<std::mutex> g(c_->prof_mu);
+    c_->prof_pending.push_back(sn_ctx::ProfEv{name_, a_, b_, launches_});
+}
+
+extern "C" sn_status sn_profile_enable(sn_ctx *c, int on)
+{
+    if (!c) return fail(SN_EINVAL, "sn_profile_enable: ctx is NULL");
+    c->profiling = on != 0;
+    return SN_OK;
+}
+
+extern "C" sn_status sn_profile_reset(sn_ctx *c)
+{
+    if (!c) return fail(SN_EINVAL, "sn_profile_reset: ctx is NULL");
+    std::lock_guard<std::mutex> g(c->prof_mu);
+    for (auto &p : c->prof_pending) {
+        (void)hipEventSynchronize(p.b);
+        (void)hipEventDestroy(p.a);
+        (void)hipEventDestroy(p.b);
+    }
+    c->prof_pending.clear();
+    c->prof_stats.clear();
+    return SN_OK;
+}
+
+extern "C" sn_status sn_profile_read(sn_ctx *c, sn_kernel_stat *out, int32_t cap, int32_t *n_out)
+{
+    if (!c || (cap > 0 && !out)) return fail(SN_EINVAL, "sn_profile_read: bad arguments");
+    std::lock_guard<std::mutex> g(c->prof_mu);
+    for (auto &p : c->prof_pending) {
+        HIP_TRY(hipEventSynchronize(p.b));
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, p.a, p.b));
+        auto &st = c->prof_stats[p.name];
+        st.first += p.launches;
+        st.second += ms;
+        (void)hipEventDestroy(p.a);
+        (void)hipEventDestroy(p.b);
+    }
+    c->prof_pending.clear();
+    int32_t k = 0;
+    for (auto &kv : c->prof_stats) {
+        if (k < cap) {
+            std::memset(&out[k], 0, sizeof(sn_kernel_stat));
+            std::snprintf(out[k].name, sizeof(out[k].name), "%s", kv.first.c_str());
+            out[k].launches = kv.second.first;
+            out[k].total_ms = kv.second.second;
+        }
+        ++k;
+    }
+    if (n_out) *n_out = k;
+    return SN_OK;
+}
+
+// ---- schedule table ----------------------------------------------------------
+
+std::string sn::size_class(const sn_volume &v)
+{
+    // rows-per-wave matters through the number of rows and their length
+    const int64_t M = v.dims[0], R = std::max<int64_t>(1, (v.dims[1] - 1) * (v.dims[2] - 1));
+    int lm = 0, lr = 0;
+    while ((int64_t(1) << (lm + 1)) <= M) ++lm;
+    while ((int64_t(1) << (lr + 1)) <= R) ++lr;
+    std::ostringstream os;
+    os << "b" << v.dtype << "_m" << lm << "_r" << lr;
+    return os.str();
+}
+
+int32_t sn_ctx::rows_per_wave(const std::string &cls) const
+{
+    std::lock_guard<std::mutex> g(tune_mu);
+    if (forced_rpw > 0) return forced_rpw;
+    auto it = tune.find(cls);
+    if (it != tune.end()) return it->second;
+    return 2;
+}
+
+void sn_ctx::load_tune_cache()
+{
+    std::ifstream f(tune_path);
+    if (!f) return;
+    // flat JSON object {"class": rpw, ...}
+    std::string s((std::istreambuf_iterator<char>(f)), std::istreambuf_iterator<char>());
+    size_t p = 0;
+    while ((p = s.find('"', p)) != std::string::npos) {
+        size_t q = s.find('"', p + 1);
+        if (q == std::string::npos) break;
+        std::string key = s.substr(p + 1, q - p - 1);
+        size_t colon = s.find(':', q);
+        if (colon == std::string::npos) break;
+        int v = std::atoi(s.c_str() + colon + 1);
+        if (v >= 1 && v <= kMaxRowsPerWave) tune[key] = v;
+        p = colon + 1;
+    }
+}
+
+void sn_ctx::save_tune_cache() const
+{
+    if (tune_path.empty()) return;
+    std::ofstream f(tune_path);
+    f << "{";
+    bool first = true;
+    for (auto &kv : tune) {
+        f << (first ? "" : ", ") << "\"" << kv.first << "\": " << kv.second;
+        first = false;
+    }
+    f << "}\n";
+}
+
+// ---------------------------------------------------------------------------
+// validation and classification tables
+// ---------------------------------------------------------------------------
+
+sn_status sn::validate_volume(const sn_volume *v)
+{
+    if (!v) return fail(SN_EINVAL, "volume is NULL");
+    if (v->dtype != 1 && v->dtype != 2 && v->dtype != 4)
+        return fail(SN_EINVAL, "dtype must be SN_U8, SN_U16 or SN_U32");
+    for (int a = 0; a < 3; ++a) {
+        if (v->dims[a] < 1) return fail(SN_EINVAL, "dims must be >= 1");
+        if (!(v->spacing[a] > 0) || !std::isfinite(v->spacing[a]))
+            return fail(SN_EINVAL, "spacing must be positive and finite");
+        if (!std::isfinite(v->origin[a])) return fail(SN_EINVAL, "origin must be finite");
+    }
+    if (v->dims[0] > (int64_t(1) << 31) || v->dims[1] > (int64_t(1) << 31) ||
+        v->dims[2] > (int64_t(1) << 31))
+        return fail(SN_ETOOBIG, "a dimension exceeds 2^31");
+    if (v->prim != SN_QUADS && v->prim != SN_TRIS) return fail(SN_EINVAL, "prim must be SN_QUADS or SN_TRIS");
+    const uint64_t vmax = v->dtype == 4 ? 0xFFFFFFFFull : ((1ull << (8 * v->dtype)) - 1);
+    if (v->background > vmax) return fail(SN_EINVAL, "background does not fit the dtype");
+    if (v->n_selected < 0 || (v->n_selected > 0 && !v->selected))
+        return fail(SN_EINVAL, "selected labels missing");
+    for (int32_t s = 0; s < v->n_selected; ++s) {
+        if (v->selected[s] > vmax) return fail(SN_EINVAL, "a selected label does not fit the dtype");
+        if (v->selected[s] == v->background)
+            return fail(SN_EINVAL, "the background value cannot be selected");
+    }
+    const bool empty = v->dims[0] < 2 || v->dims[1] < 2 || v->dims[2] < 2;
+    if (!v->labels && !empty) return fail(SN_EINVAL, "labels is NULL");
+    return SN_OK;
+}
+
+Geom sn::make_geom(const sn_volume &v)
+{
+    Geom g;
+    g.M = v.dims[0], g.N = v.dims[1], g.O = v.dims[2];
+    const bool empty = g.M < 2 || g.N < 2 || g.O < 2;
+    g.CM = empty ? 0 : g.M - 1;
+    g.CN = empty ? 0 : g.N - 1;
+    g.CO = empty ? 0 : g.O - 1;
+    g.R = g.CN * g.CO;
+    g.W = (int32_t)((g.CM + 63) / 64);
+    return g;
+}
+
+// host form of the classification table; empty vector for the identity
+static void class_table(const sn_volume &v, int32_t *mode, std::vector<uint32_t> *tab)
+{
+    tab->clear();
+    if (v.n_selected == 0) {
+        *mode = CLS_IDENT;
+        return;
+    }
+    if (v.dtype <= 2) {
+        *mode = CLS_BITMAP;
+        tab->assign(v.dtype == 1 ? 8 : 2048, 0u);
+        for (int32_t s = 0; s < v.n_selected; ++s) {
+            const uint32_t x = v.selected[s];
+            (*tab)[x >> 5] |= 1u << (x & 31u);
+        }
+        return;
+    }
+    *mode = CLS_SORTED;
+    tab->assign(v.selected, v.selected + v.n_selected);
+    std::sort(tab->begin(), tab->end());
+    tab->erase(std::unique(tab->begin(), tab->end()), tab->end());
+}
+
+// ---------------------------------------------------------------------------
+// meshes
+// ---------------------------------------------------------------------------
+
+sn_mesh::~sn_mesh()
+{
+    for (auto &kv : graphs) (void)hipGraphExecDestroy(kv.second);
+}
+
+void sn::mesh_release(sn_mesh *m)
+{
+    if (!m) return;
+    (void)hipSetDevice(m->ctx->device);
+    if (m->last_stream_valid) {
+        // wait only for the work this mesh has enqueued
+        if (m->done_ev) (void)hipEventSynchronize(m->done_ev);
+    }
+    if (m->done_ev) (void)hipEventDestroy(m->done_ev);
+    m->ctx->pool.release_all(m->blocks, Pool::kNoWait);
+    delete m;
+}
+
+extern "C" void sn_mesh_free(sn_mesh *m) { mesh_release(m); }
+
+sn_status sn::mesh_mark(sn_mesh *m, hipStream_t s)
+{
+    if (!m->done_ev) HIP_TRY(hipEventCreateWithFlags(&m->done_ev, hipEventDisableTiming));
+    HIP_TRY(hipEventRecord(m->done_ev, s));
+    m->last_stream_valid = true;
+    return SN_OK;
+}
+
+extern "C" sn_status sn_mesh_view_get(const sn_mesh *m, sn_mesh_view *out)
+{
+    if (!m || !out) return fail(SN_EINVAL, "sn_mesh_view_get: NULL argument");
+    sn_mesh_view v;
+    std::memset(&v, 0, sizeof v);
+    v.n_points = m->P, v.n_quads = m->Q, v.n_stencil = m->S;
+    v.prim = m->d.prim, v.dtype = m->d.dtype;
+    v.points = m->d.points;
+    v.offsets = m->final_delta;
+    v.quads = m->d.quads;
+    v.stencil_off = m->d.st_off;
+    v.stencil_ids = m->d.st_ids;
+    if (m->d.prim == SN_TRIS) {
+        v.n_polys = 2 * m->Q;
+        v.polys = m->d.tris;
+        v.label_pairs = m->d.tri_pairs;
+    } else {
+        v.n_polys = m->Q;
+        v.polys = m->d.quads;
+        v.label_pairs = m->d.pairs;
+    }
+    *out = v;
+    return SN_OK;
+}
+
+extern "C" sn_status sn_mesh_copy_to_host(const sn_mesh *m, float *points, int32_t *polys,
+                                          void *labels, int32_t *st_off, int32_t *st_ids,
+                                          float *offsets)
+{
+    if (!m) return fail(SN_EINVAL, "sn_mesh_copy_to_host: mesh is NULL");
+    HIP_TRY(hipSetDevice(m->ctx->device));
+    if (m->done_ev) HIP_TRY(hipEventSynchronize(m->done_ev));
+    sn_mesh_view v;
+    sn_mesh_view_get(m, &v);
+    auto cp = [](void *dst, const void *src, size_t n) -> hipError_t {
+        if (!dst || n == 0) return hipSuccess;
+        if (!src) return hipErrorInvalidValue;
+        return hipMemcpy(dst, src, n, hipMemcpyDeviceToHost);
+    };
+    HIP_TRY(cp(points, v.points, sizeof(float) * 3 * v.n_points));
+    HIP_TRY(cp(polys, v.polys, sizeof(int32_t) * v.prim * v.n_polys));
+    HIP_TRY(cp(labels, v.label_pairs, (size_t)v.dtype * 2 * v.n_polys));
+    HIP_TRY(cp(st_off, v.stencil_off, sizeof(int32_t) * (v.n_points + 1)));
+    HIP_TRY(cp(st_ids, v.stencil_ids, sizeof(int32_t) * v.n_stencil));
+    if (offsets) {
+        if (v.offsets)
+            HIP_TRY(cp(offsets, v.offsets, sizeof(float) * 3 * v.n_points));
+        else
+            std::memset(offsets, 0, sizeof(float) * 3 * v.n_points);
+    }
+    return SN_OK;
+}
+
+// ---------------------------------------------------------------------------
+// extraction (plain = a batch of one)
+// ---------------------------------------------------------------------------
+
+namespace {
+
+struct Scratch {
+    sn_ctx *c;
+    std::vector<void *> dev, host;
+    explicit Scratch(sn_ctx *ctx) : c(ctx) {}
+    void *d(size_t n)
+    {
+        void *p = c->pool.alloc(n);
+        if (p) dev.push_back(p);
+        return p;
+    }
+    void *h(size_t n)
+    {
+        void *p = c->pinned.alloc(n);
+        if (p) host.push_back(p);
+        return p;
+    }
+    void retire(hipStream_t s)
+    {
+        c->pool.release_all(dev, s);
+        c->pinned.release_all(host, s);
+        dev.clear();
+        host.clear();
+    }
+};
+
+template <typename T>
+T *dalloc(sn_mesh *m, int64_t count)
+{
+    void *p = m->ctx->pool.alloc(sizeof(T) * (size_t)std::max<int64_t>(count, 1));
+    if (p) m->blocks.push_back(p);
+    return static_cast<T *>(p);
+}
+
+}  // namespace
+
+sn_status sn::extract_many(sn_ctx *c, const sn_volume *vols, int32_t n, hipStream_t s,
+                           int32_t rpw_override, sn_mesh **out)
+{
+    if (!c || !vols || !out || n < 1) return fail(SN_EINVAL, "extract: bad arguments");
+    for (int32_t v = 0; v < n; ++v) {
+        sn_status st = validate_volume(&vols[v]);
+        if (st != SN_OK) return st;
+    }
+    HIP_TRY(hipSetDevice(c->device));
+    std::vector<sn_mesh *> meshes(n, nullptr);
+    auto cleanup = [&](sn_status st) {
+        for (auto *m : meshes)
+            if (m) {
+                m->ctx->pool.release_all(m->blocks, s);
+                m->blocks.clear();
+                delete m;
+            }
+        return st;
+    };
+    Scratch scr(c);
+    // one schedule for the launch: the one tuned for the largest volume
+    int64_t big = 0;
+    int32_t vb = 0;
+    for (int32_t v = 0; v < n; ++v) {
+        const int64_t vox = vols[v].dims[0] * vols[v].dims[1] * vols[v].dims[2];
+        if (vox > big) big = vox, vb = v;
+    }
+    const int32_t rpw = rpw_override > 0 ? rpw_override : c->rows_per_wave(size_class(vols[vb]));
+    const int TR = kWavesPerBlock * rpw;
+
+    std::vector<int64_t> tile_prefix(n + 1, 0);
+    for (int32_t v = 0; v < n; ++v) {
+        const sn_volume &vol = vols[v];
+        sn_mesh *m = new sn_mesh();
+        meshes[v] = m;
+        m->ctx = c;
+        m->rpw = rpw;
+        VolDesc &d = m->d;
+        std::memset(&d, 0, sizeof d);
+        d.labels = vol.labels;
+        d.dtype = vol.dtype;
+        d.prim = vol.prim;
+        d.g = make_geom(vol);
+        for (int a = 0; a < 3; ++a) d.origin[a] = vol.origin[a], d.spacing[a] = vol.spacing[a];
+        std::vector<uint32_t> tab;
+        class_table(vol, &d.cs.mode, &tab);
+        d.cs.bg = vol.background;
+        d.cs.n = (int32_t)tab.size();
+        if (!tab.empty()) {
+            uint32_t *t = dalloc<uint32_t>(m, (int64_t)tab.size());
+            uint32_t *ht = static_cast<uint32_t *>(scr.h(sizeof(uint32_t) * tab.size()));
+            if (!t || !ht) {
+                scr.retire(s);
+                return cleanup(fail(SN_ENOMEM, "extract: classification table"));
+            }
+            std::memcpy(ht, tab.data(), sizeof(uint32_t) * tab.size());
+            HIP_TRY(hipMemcpyAsync(t, ht, sizeof(uint32_t) * tab.size(), hipMemcpyHostToDevice, s));
+            d.cs.table = t;
+        }
+        const int64_t R = d.g.R;
+        d.pmask = dalloc<uint64_t>(m, R * d.g.W);
+        d.baseP = dalloc<int64_t>(m, R + 1);
+        d.baseQ = dalloc<int64_t>(m, R + 1);
+        d.baseS = dalloc<int64_t>(m, R + 1);
+        if (!d.pmask || !d.baseP || !d.baseQ || !d.baseS)
+            return cleanup(fail(SN_ENOMEM, "extract: row metadata"));
+        m->ntiles = (R + TR - 1) / TR;
+        tile_prefix[v + 1] = tile_prefix[v] + m->ntiles;
+        m->voxels = vol.dims[0] * vol.dims[1] * vol.dims[2];
+    }
+    const int64_t ntiles = tile_prefix[n];
+    // device copies of descriptors, tile map and scan state
+    VolDesc *h_desc = static_cast<VolDesc *>(scr.h(sizeof(VolDesc) * n));
+    int64_t *h_tp = static_cast<int64_t *>(scr.h(sizeof(int64_t) * (n + 1)));
+    int64_t *h_tot = static_cast<int64_t *>(scr.h(sizeof(int64_t) * 3 * n));
+    VolDesc *d_desc = static_cast<VolDesc *>(scr.d(sizeof(VolDesc) * n));
+    int64_t *d_tp = static_cast<int64_t *>(scr.d(sizeof(int64_t) * (n + 1)));
+    int64_t *d_tot = static_cast<int64_t *>(scr.d(sizeof(int64_t) * 3 * n));
+    const size_t status_bytes = sizeof(uint64_t) * 3 * (size_t)std::max<int64_t>(ntiles, 1);
+    uint8_t *d_status = static_cast<uint8_t *>(scr.d(status_bytes + 256));
+    if (!h_desc || !h_tp || !h_tot || !d_desc || !d_tp || !d_tot || !d_status) {
+        scr.retire(s);
+        return cleanup(fail(SN_ENOMEM, "extract: scratch"));
+    }
+    for (int32_t v = 0; v < n; ++v) h_desc[v] = meshes[v]->d;
+    std::memcpy(h_tp, tile_prefix.data(), sizeof(int64_t) * (n + 1));
+    std::memset(h_tot, 0, sizeof(int64_t) * 3 * n);
+    HIP_TRY(hipMemcpyAsync(d_desc, h_desc, sizeof(VolDesc) * n, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(d_tp, h_tp, sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemsetAsync(d_tot, 0, sizeof(int64_t) * 3 * n, s));
+    HIP_TRY(hipMemsetAsync(d_status, 0, status_bytes + 256, s));
+    {
+        ProfScope ps(c, "k_count", s);
+        HIP_TRY(launch_count(d_desc, d_tp, n, ntiles, rpw, reinterpret_cast<uint64_t *>(d_status),
+                             reinterpret_cast<uint32_t *>(d_status + status_bytes), d_tot, s));
+    }
+    HIP_TRY(hipMemcpyAsync(h_tot, d_tot, sizeof(int64_t) * 3 * n, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+
+    // exact allocation of every output (Sec. 2.3: no incremental allocation)
+    int64_t qblocks = 0;
+    std::vector<int64_t> qprefix(n + 1, 0);
+    for (int32_t v = 0; v < n; ++v) {
+        sn_mesh *m = meshes[v];
+        VolDesc &d = m->d;
+        m->P = h_tot[3 * v], m->Q = h_tot[3 * v + 1], m->S = h_tot[3 * v + 2];
+        if (m->P >= INT32_MAX || m->Q >= INT32_MAX / 2 || m->S >= INT32_MAX) {
+            scr.retire(s);
+            return cleanup(fail(SN_ETOOBIG, "extract: mesh indices exceed int32"));
+        }
+        d.P = m->P, d.Q = m->Q, d.S = m->S;
+        d.points = dalloc<float>(m, 3 * m->P);
+        d.faces = dalloc<uint8_t>(m, m->P);
+        d.st_off = dalloc<int32_t>(m, m->P + 1);
+        d.st_ids = dalloc<int32_t>(m, m->S);
+        d.quads = dalloc<int32_t>(m, 4 * m->Q);
+        d.pairs = dalloc<uint8_t>(m, 2 * m->Q * d.dtype);
+        if (!d.points || !d.faces || !d.st_off || !d.st_ids || !d.quads || !d.pairs) {
+            scr.retire(s);
+            return cleanup(fail(SN_ENOMEM, "extract: outputs"));
+        }
+        if (d.prim == SN_TRIS) {
+            d.tris = dalloc<int32_t>(m, 6 * m->Q);
+            d.tri_pairs = dalloc<uint8_t>(m, 4 * m->Q * d.dtype);
+            if (!d.tris || !d.tri_pairs) {
+                scr.retire(s);
+                return cleanup(fail(SN_ENOMEM, "extract: triangles"));
+            }
+            qblocks += (m->Q + 255) / 256;
+        }
+        qprefix[v + 1] = qblocks;
+        h_desc[v] = d;
+    }
+    HIP_TRY(hipMemcpyAsync(d_desc, h_desc, sizeof(VolDesc) * n, hipMemcpyHostToDevice, s));
+    for (int32_t v = 0; v < n; ++v)  // volumes without cell rows still get st_off[0] = 0
+        if (meshes[v]->ntiles == 0) HIP_TRY(hipMemsetAsync(meshes[v]->d.st_off, 0, sizeof(int32_t), s));
+    {
+        ProfScope ps(c, "k_generate", s);
+        HIP_TRY(launch_generate(d_desc, d_tp, n, ntiles, rpw, s));
+    }
+    if (qblocks > 0) {
+        int64_t *h_qp = static_cast<int64_t *>(scr.h(sizeof(int64_t) * (n + 1)));
+        int64_t *d_qp = static_cast<int64_t *>(scr.d(sizeof(int64_t) * (n + 1)));
+        if (!h_qp || !d_qp) {
+            scr.retire(s);
+            return cleanup(fail(SN_ENOMEM, "extract: triangle scratch"));
+        }
+        // volumes without triangles keep an empty block range
+        int64_t acc = 0;
+        for (int32_t v = 0; v < n; ++v) {
+            h_qp[v] = acc;
+            if (meshes[v]->d.prim == SN_TRIS) acc += (meshes[v]->Q + 255) / 256;
+        }
+        h_qp[n] = acc;
+        HIP_TRY(hipMemcpyAsync(d_qp, h_qp, sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice, s));
+        ProfScope ps(c, "k_tri", s);
+        HIP_TRY(launch_triangulate(d_desc, d_qp, n, acc, s));
+    }
+    // per-mesh device descriptors for later emit/smoothing launches
+    for (int32_t v = 0; v < n; ++v) {
+        sn_mesh *m = meshes[v];
+        m->dd = dalloc<VolDesc>(m, 1);
+        m->dtp = dalloc<int64_t>(m, 2);
+        m->dsd = dalloc<SmoothDesc>(m, 1);
+        m->dbp = dalloc<int64_t>(m, 2);
+        if (!m->dd || !m->dtp || !m->dsd || !m->dbp) {
+            scr.retire(s);
+            return cleanup(fail(SN_ENOMEM, "extract: descriptors"));
+        }
+        HIP_TRY(hipMemcpyAsync(m->dd, &h_desc[v], sizeof(VolDesc), hipMemcpyHostToDevice, s));
+        int64_t *tp = static_cast<int64_t *>(scr.h(sizeof(int64_t) * 4));
+        if (!tp) {
+            scr.retire(s);
+            return cleanup(fail(SN_ENOMEM, "extract: staging"));
+        }
+        tp[0] = 0, tp[1] = m->ntiles, tp[2] = 0, tp[3] = (m->P + 255) / 256;
+        HIP_TRY(hipMemcpyAsync(m->dtp, tp, sizeof(int64_t) * 2, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(m->dbp, tp + 2, sizeof(int64_t) * 2, hipMemcpyHostToDevice, s));
+        sn_status st = mesh_mark(m, s);
+        if (st != SN_OK) {
+            scr.retire(s);
+            return cleanup(st);
+        }
+    }
+    scr.retire(s);
+    for (int32_t v = 0; v < n; ++v) out[v] = meshes[v];
+    return SN_OK;
+}
+
+extern "C" sn_status sn_extract(sn_ctx *c, const sn_volume *vol, void *stream, sn_mesh **out)
+{
+    if (!out) return fail(SN_EINVAL, "sn_extract: out is NULL");
+    return extract_many(c, vol, 1, static_cast<hipStream_t>(stream), 0, out);
+}
+
+// ---------------------------------------------------------------------------
+// smoothing
+// ---------------------------------------------------------------------------
+
+sn_status sn::validate_smooth(const sn_smooth_params *p)
+{
+    if (!p) return fail(SN_EINVAL, "smoothing parameters are NULL");
+    if (p->iterations < 0) return fail(SN_EINVAL, "iterations must be >= 0");
+    if (!(p->relaxation >= 0.f && p->relaxation <= 1.f))
+        return fail(SN_EINVAL, "relaxation must be in [0, 1]");
+    if (!(p->constraint >= 0.f) || !std::isfinite(p->constraint))
+        return fail(SN_EINVAL, "constraint must be >= 0 and finite");
+    return SN_OK;
+}
+
+sn_status sn::ensure_smooth_buffers(sn_mesh *m)
+{
+    if (m->d.P == 0 || m->da) return SN_OK;
+    m->da = dalloc<float>(m, 3 * m->P);
+    m->db = dalloc<float>(m, 3 * m->P);
+    if (!m->da || !m->db) return fail(SN_ENOMEM, "smooth: offset buffers");
+    return SN_OK;
+}
+
+// n sweeps of k_jacobi over `nvol` meshes, replayed from a captured graph
+sn_status sn::run_sweeps(sn_ctx *c, const SmoothDesc *d_sd, const int64_t *d_bp, int32_t nvol,
+                         int64_t nblocks, int32_t iters, hipStream_t s,
+                         std::map<int32_t, hipGraphExec_t> *cache)
+{
+    if (iters <= 0 || nblocks <= 0) return SN_OK;
+    if (c->profiling) {
+        // eager launches so each sweep is bracketed by its own events
+        for (int32_t it = 0; it < iters; ++it) {
+            ProfScope ps(c, "k_jacobi", s);
+            HIP_TRY(launch_jacobi(d_sd, d_bp, nvol, nblocks, it, s));
+        }
+        return SN_OK;
+    }
+    hipGraphExec_t exec = nullptr;
+    if (cache) {
+        auto it = cache->find(iters);
+        if (it != cache->end()) exec = it->second;
+    }
+    if (!exec) {
+        std::lock_guard<std::mutex> g(c->capture_mu);
+        hipGraph_t graph;
+        HIP_TRY(hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal));
+        hipError_t e = hipSuccess;
+        for (int32_t it = 0; it < iters && e == hipSuccess; ++it)
+            e = launch_jacobi(d_sd, d_bp, nvol, nblocks, it, c->capture_stream);
+        hipError_t e2 = hipStreamEndCapture(c->capture_stream, &graph);
+        if (e != hipSuccess || e2 != hipSuccess)
+            return fail(SN_EDEVICE, std::string("smooth: graph capture failed: ") +
+                                        hipGetErrorString(e != hipSuccess ? e : e2));
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess)
+            return fail(SN_EDEVICE, std::string("smooth: graph instantiate: ") + hipGetErrorString(e));
+        if (cache) (*cache)[iters] = exec;
+    }
+    hipError_t e = hipGraphLaunch(exec, s);
+    if (!cache) (void)hipGraphExecDestroy(exec);
+    if (e != hipSuccess) return fail(SN_EDEVICE, std::string("smooth: graph launch: ") + hipGetErrorString(e));
+    return SN_OK;
+}
+
+extern "C" sn_status sn_smooth(sn_ctx *c, sn_mesh *m, const sn_smooth_params *p, void *stream)
+{
+    if (!c || !m) return fail(SN_EINVAL, "sn_smooth: NULL argument");
+    sn_status st = validate_smooth(p);
+    if (st != SN_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    HIP_TRY(hipSetDevice(c->device));
+    if (m->P == 0) {
+        m->final_delta = nullptr;
+        return mesh_mark(m, s);
+    }
+    if (p->iterations > 0) {
+        st = ensure_smooth_buffers(m);
+        if (st != SN_OK) return st;
+    }
+    SmoothDesc *h = static_cast<SmoothDesc *>(c->pinned.alloc(sizeof(SmoothDesc)));
+    VolDesc *hv = static_cast<VolDesc *>(c->pinned.alloc(sizeof(VolDesc)));
+    if (!h || !hv) {
+        c->pinned.release(h, Pool::kNoWait);
+        c->pinned.release(hv, Pool::kNoWait);
+        return fail(SN_ENOMEM, "smooth: staging");
+    }
+    h->P = m->P, h->faces = m->d.faces, h->off = m->d.st_off, h->ids = m->d.st_ids;
+    h->da = m->da, h->db = m->db, h->iters = p->iterations;
+    h->lam = (double)p->relaxation, h->dist = (double)p->constraint;
+    HIP_TRY(hipMemcpyAsync(m->dsd, h, sizeof(SmoothDesc), hipMemcpyHostToDevice, s));
+    const int64_t nblocks = (m->P + 255) / 256;
+    st = run_sweeps(c, m->dsd, m->dbp, 1, nblocks, p->iterations, s, &m->graphs);
+    if (st != SN_OK) {
+        c->pinned.release(h, s);
+        c->pinned.release(hv, s);
+        return st;
+    }
+    // the last sweep `it` wrote buffer (it odd ? da : db)
+    m->final_delta = p->iterations == 0 ? nullptr : (((p->iterations - 1) & 1) ? m->da : m->db);
+    m->d.delta = m->final_delta;
+    *hv = m->d;
+    HIP_TRY(hipMemcpyAsync(m->dd, hv, sizeof(VolDesc), hipMemcpyHostToDevice, s));
+    {
+        ProfScope ps(c, "k_emit", s);
+        HIP_TRY(launch_emit(m->dd, m->dtp, 1, m->ntiles, m->rpw, s));
+    }
+    c->pinned.release(h, s);
+    c->pinned.release(hv, s);
+    return mesh_mark(m, s);
+}
+
+// ---------------------------------------------------------------------------
+// batched path
+// ---------------------------------------------------------------------------
+
+sn_status sn::smooth_many(sn_ctx *c, sn_mesh **ms, const sn_smooth_params *pv, int32_t n,
+                          hipStream_t s)
+{
+    Scratch scr(c);
+    std::vector<int64_t> bp(n + 1, 0), tp(n + 1, 0);
+    int32_t maxit = 0;
+    for (int32_t v = 0; v < n; ++v) {
+        sn_status st = validate_smooth(&pv[v]);
+        if (st != SN_OK) return st;
+        if (pv[v].iterations > 0 && ms[v]->P > 0) {
+            st = ensure_smooth_buffers(ms[v]);
+            if (st != SN_OK) return st;
+        }
+        bp[v + 1] = bp[v] + (ms[v]->P + 255) / 256;
+        tp[v + 1] = tp[v] + ms[v]->ntiles;
+        maxit = std::max(maxit, pv[v].iterations);
+    }
+    SmoothDesc *h_sd = static_cast<SmoothDesc *>(scr.h(sizeof(SmoothDesc) * n));
+    VolDesc *h_vd = static_cast<VolDesc *>(scr.h(sizeof(VolDesc) * n));
+    int64_t *h_p = static_cast<int64_t *>(scr.h(sizeof(int64_t) * 2 * (n + 1)));
+    SmoothDesc *d_sd = static_cast<SmoothDesc *>(scr.d(sizeof(SmoothDesc) * n));
+    VolDesc *d_vd = static_cast<VolDesc *>(scr.d(sizeof(VolDesc) * n));
+    int64_t *d_p = static_cast<int64_t *>(scr.d(sizeof(int64_t) * 2 * (n + 1)));
+    if (!h_sd || !h_vd || !h_p || !d_sd || !d_vd || !d_p) {
+        scr.retire(s);
+        return fail(SN_ENOMEM, "batch smooth: scratch");
+    }
+    for (int32_t v = 0; v < n; ++v) {
+        sn_mesh *m = ms[v];
+        SmoothDesc &h = h_sd[v];
+        h.P = m->P, h.faces = m->d.faces, h.off = m->d.st_off, h.ids = m->d.st_ids;
+        h.da = m->da, h.db = m->db, h.iters = m->P > 0 ? pv[v].iterations : 0;
+        h.lam = (double)pv[v].relaxation, h.dist = (double)pv[v].constraint;
+        m->final_delta =
+            h.iters == 0 ? nullptr : (((h.iters - 1) & 1) ? m->da : m->db);
+        m->d.delta = m->final_delta;
+        h_vd[v] = m->d;
+    }
+    std::memcpy(h_p, bp.data(), sizeof(int64_t) * (n + 1));
+    std::memcpy(h_p + n + 1, tp.data(), sizeof(int64_t) * (n + 1));
+    HIP_TRY(hipMemcpyAsync(d_sd, h_sd, sizeof(SmoothDesc) * n, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(d_vd, h_vd, sizeof(VolDesc) * n, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(d_p, h_p, sizeof(int64_t) * 2 * (n + 1), hipMemcpyHostToDevice, s));
+    sn_status st = run_sweeps(c, d_sd, d_p, n, bp[n], maxit, s, nullptr);
+    if (st != SN_OK) {
+        scr.retire(s);
+        return st;
+    }
+    bool same_rpw = true;
+    for (int32_t v = 1; v < n; ++v) same_rpw &= ms[v]->rpw == ms[0]->rpw;
+    {
+        ProfScope ps(c, "k_emit", s);
+        if (same_rpw) {
+            HIP_TRY(launch_emit(d_vd, d_p + n + 1, n, tp[n], ms[0]->rpw, s));
+        } else {
+            for (int32_t v = 0; v < n; ++v) {
+                HIP_TRY(hipMemcpyAsync(ms[v]->dd, &h_vd[v], sizeof(VolDesc), hipMemcpyHostToDevice, s));
+                HIP_TRY(launch_emit(ms[v]->dd, ms[v]->dtp, 1, ms[v]->ntiles, ms[v]->rpw, s));
+            }
+        }
+    }
+    // keep each mesh's own descriptor current for later per-mesh calls
+    for (int32_t v = 0; v < n; ++v)
+        HIP_TRY(hipMemcpyAsync(ms[v]->dd, &h_vd[v], sizeof(VolDesc), hipMemcpyHostToDevice, s));
+    scr.retire(s);
+    for (int32_t v = 0; v < n; ++v) {
+        st = mesh_mark(ms[v], s);
+        if (st != SN_OK) return st;
+    }
+    return SN_OK;
+}
+
+extern "C" sn_status sn_batch_submit(sn_ctx *c, const sn_volume *vols,
+                                     const sn_smooth_params *per_vol, int32_t n, void *stream,
+                                     sn_mesh **out)
+{
+    if (!c || !vols || !out || n < 1) return fail(SN_EINVAL, "sn_batch_submit: bad arguments");
+    if (per_vol)
+        for (int32_t v = 0; v < n; ++v) {
+            sn_status st = validate_smooth(&per_vol[v]);
+            if (st != SN_OK) return st;
+        }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    std::vector<sn_mesh *> ms(n, nullptr);
+    sn_status st = extract_many(c, vols, n, s, 0, ms.data());
+    if (st != SN_OK) return st;
+    if (per_vol) {
+        st = smooth_many(c, ms.data(), per_vol, n, s);
+        if (st != SN_OK) {
+            for (auto *m : ms) mesh_release(m);
+            return st;
+        }
+    }
+    for (int32_t v = 0; v < n; ++v) out[v] = ms[v];
+    return SN_OK;
+}
+
+// ---------------------------------------------------------------------------
+// schedule tuner: time k_count + k_generate for each rows-per-wave candidate
+// ---------------------------------------------------------------------------
+
+extern "C" sn_status sn_autotune(sn_ctx *c, const sn_volume *vol, void *stream, int32_t *chosen)
+{
+    if (!c || !vol) return fail(SN_EINVAL, "sn_autotune: NULL argument");
+    sn_status st = validate_volume(vol);
+    if (st != SN_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    HIP_TRY(hipSetDevice(c->device));
+    const int32_t cands[] = {1, 2, 4, 8};
+    double best = 1e30;
+    int32_t arg = 2;
+    const bool was = c->profiling;
+    c->profiling = false;
+    for (int32_t rpw : cands) {
+        double tbest = 1e30;
+        for (int rep = 0; rep < 4; ++rep) {
+            HIP_TRY(hipStreamSynchronize(s));
+            auto t0 = std::chrono::steady_clock::now();
+            sn_mesh *m = nullptr;
+            st = extract_many(c, vol, 1, s, rpw, &m);
+            if (st != SN_OK) {
+                c->profiling = was;
+                return st;
+            }
+            HIP_TRY(hipStreamSynchronize(s));
+            auto t1 = std::chrono::steady_clock::now();
+            mesh_release(m);
+            if (rep > 0) tbest = std::min(tbest, std::chrono::duration<double>(t1 - t0).count());
+        }
+        if (tbest < best) best = tbest, arg = rpw;
+    }
+    c->profiling = was;
+    {
+        std::lock_guard<std::mutex> g(c->tune_mu);
+        c->tune[size_class(*vol)] = arg;
+        c->save_tune_cache();
+    }
+    if (chosen) *chosen = arg;
+    return SN_OK;
+}
+
+extern "C" sn_status sn_set_rows_per_wave(sn_ctx *c, int32_t rpw)
+{
+    if (!c || rpw < 0 || rpw > kMaxRowsPerWave) return fail(SN_EINVAL, "sn_set_rows_per_wave: bad arguments");
+    std::lock_guard<std::mutex> g(c->tune_mu);
+    c->forced_rpw = rpw;
+    return SN_OK;
+}

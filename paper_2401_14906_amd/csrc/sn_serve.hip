@@ -1,0 +1,329 @@
+// Request server of libsn.so: continuous batching of contour requests.
+//
+// Submitted requests wait in a FIFO queue.  Each of n_streams worker threads
+// owns one HIP stream; when a worker is free it admits queued requests in
+// order while (a) the sum of device-footprint estimates of everything in
+// flight stays within the budget and (b) fewer than max_inflight requests are
+// in flight, fuses the admitted requests into one batch (one counting launch,
+// one generation launch, one captured-graph replay of the sweeps for the whole
+// batch) and runs it on its stream.  Requests arriving meanwhile join the next
+// batch of whichever worker frees first, so device work of different batches
+// overlaps.  Finished meshes stay device-resident until claimed.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "sn.h"
+#include "sn_runtime.h"
+
+using namespace sn;
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+struct Request {
+    uint64_t ticket = 0;
+    sn_volume vol{};
+    std::vector<uint32_t> selected;
+    sn_smooth_params p{};
+    int64_t footprint = 0;
+    Clock::time_point t_submit, t_done;
+    bool done = false;
+    sn_status status = SN_OK;
+    sn_mesh *mesh = nullptr;
+};
+
+// Device bytes a request may hold while in flight: row metadata exactly,
+// outputs estimated from the mesh density seen so far (bytes per voxel).
+int64_t footprint_of(const sn_volume &v, double out_bytes_per_voxel)
+{
+    const Geom g = make_geom(v);
+    const int64_t meta = g.R * g.W * 8 + 3 * 8 * (g.R + 1) + 4096;
+    const double vox = (double)v.dims[0] * (double)v.dims[1] * (double)v.dims[2];
+    return meta + (int64_t)(out_bytes_per_voxel * vox);
+}
+
+}  // namespace
+
+struct sn_server {
+    sn_ctx *ctx = nullptr;
+    sn_serve_config cfg{};
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<Request *> queue;
+    std::unordered_map<uint64_t, Request *> reqs;
+    uint64_t next_ticket = 1;
+    int64_t reserved = 0, peak_reserved = 0;
+    int32_t inflight = 0;
+    bool stopping = false;
+    std::vector<std::thread> workers;
+    std::vector<hipStream_t> streams;
+    // statistics
+    int64_t n_submitted = 0, n_done = 0, n_rejected = 0, n_batches = 0;
+    int64_t voxels_done = 0, point_iters_done = 0;
+    std::vector<double> lat_us;
+    double out_bpv = 4.0;  // running estimate of output bytes per voxel
+    Clock::time_point busy_since;
+    double busy_s = 0.0;
+    int32_t busy_count = 0;
+
+    void worker(int w);
+};
+
+void sn_server::worker(int w)
+{
+    (void)hipSetDevice(ctx->device);
+    hipStream_t s = streams[w];
+    while (true) {
+        std::vector<Request *> batch;
+        {
+            std::unique_lock<std::mutex> lk(mu);
+            cv_work.wait(lk, [&] {
+                if (stopping && queue.empty()) return true;
+                if (queue.empty() || inflight >= cfg.max_inflight) return false;
+                // the head must fit next to what is in flight (or run alone)
+                Request *h = queue.front();
+                return reserved + h->footprint <= cfg.hbm_budget_bytes || inflight == 0;
+            });
+            if (queue.empty() && stopping) return;
+            while (!queue.empty() && (int32_t)batch.size() < cfg.max_batch &&
+                   inflight < cfg.max_inflight) {
+                Request *h = queue.front();
+                const bool fits = reserved + h->footprint <= cfg.hbm_budget_bytes;
+                if (!fits && !(batch.empty() && inflight == 0)) break;
+                queue.pop_front();
+                reserved += h->footprint;
+                ++inflight;
+                batch.push_back(h);
+            }
+            peak_reserved = std::max(peak_reserved, reserved);
+            if (busy_count++ == 0) busy_since = Clock::now();
+            ++n_batches;
+        }
+        if (batch.empty()) continue;
+        const int32_t n = (int32_t)batch.size();
+        std::vector<sn_volume> vols(n);
+        std::vector<sn_smooth_params> ps(n);
+        for (int32_t k = 0; k < n; ++k) {
+            vols[k] = batch[k]->vol;
+            vols[k].selected = batch[k]->selected.empty() ? nullptr : batch[k]->selected.data();
+            ps[k] = batch[k]->p;
+        }
+        std::vector<sn_mesh *> ms(n, nullptr);
+        sn_status st = extract_many(ctx, vols.data(), n, s, 0, ms.data());
+        if (st == SN_OK) {
+            st = smooth_many(ctx, ms.data(), ps.data(), n, s);
+            if (st == SN_OK && hipStreamSynchronize(s) != hipSuccess) st = SN_EDEVICE;
+            if (st != SN_OK) {
+                for (auto *m : ms) mesh_release(m);
+                std::fill(ms.begin(), ms.end(), nullptr);
+            }
+        }
+        const auto now = Clock::now();
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            for (int32_t k = 0; k < n; ++k) {
+                Request *r = batch[k];
+                r->done = true;
+                r->status = st;
+                r->mesh = ms[k];
+                r->t_done = now;
+                reserved -= r->footprint;
+                --inflight;
+                if (st == SN_OK) {
+                    ++n_done;
+                    const int64_t vox = r->vol.dims[0] * r->vol.dims[1] * r->vol.dims[2];
+                    voxels_done += vox;
+                    point_iters_done += ms[k]->P * (int64_t)r->p.iterations;
+                    lat_us.push_back(
+                        std::chrono::duration<double, std::micro>(now - r->t_submit).count());
+                    const double bytes = 44.0 * ms[k]->P + 24.0 * ms[k]->Q + 4.0 * ms[k]->S;
+                    out_bpv = 0.9 * out_bpv + 0.1 * std::max(0.5, bytes / std::max<int64_t>(vox, 1));
+                } else {
+                    ++n_rejected;
+                }
+            }
+            if (--busy_count == 0)
+                busy_s += std::chrono::duration<double>(now - busy_since).count();
+        }
+        cv_done.notify_all();
+        cv_work.notify_all();
+    }
+}
+
+extern "C" sn_status sn_serve_start(sn_ctx *ctx, const sn_serve_config *cfg, sn_server **out)
+{
+    if (!ctx || !cfg || !out) return fail(SN_EINVAL, "sn_serve_start: NULL argument");
+    if (cfg->hbm_budget_bytes <= 0 || cfg->max_inflight < 1 || cfg->n_streams < 1 ||
+        cfg->max_batch < 1 || cfg->queue_capacity < 1 || cfg->n_streams > 16)
+        return fail(SN_EINVAL, "sn_serve_start: bad configuration");
+    HIP_TRY(hipSetDevice(ctx->device));
+    sn_server *srv = new sn_server();
+    srv->ctx = ctx;
+    srv->cfg = *cfg;
+    for (int w = 0; w < cfg->n_streams; ++w) {
+        hipStream_t s;
+        if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
+            for (auto x : srv->streams) (void)hipStreamDestroy(x);
+            delete srv;
+            return fail(SN_EDEVICE, "sn_serve_start: stream creation failed");
+        }
+        srv->streams.push_back(s);
+    }
+    for (int w = 0; w < cfg->n_streams; ++w) srv->workers.emplace_back([srv, w] { srv->worker(w); });
+    *out = srv;
+    return SN_OK;
+}
+
+extern "C" sn_status sn_serve_submit(sn_server *srv, const sn_volume *vol, const sn_smooth_params *p,
+                                     uint64_t *ticket)
+{
+    if (!srv || !vol || !p || !ticket) return fail(SN_EINVAL, "sn_serve_submit: NULL argument");
+    sn_status st = validate_volume(vol);
+    if (st != SN_OK) return st;
+    st = validate_smooth(p);
+    if (st != SN_OK) return st;
+    Request *r = new Request();
+    r->vol = *vol;
+    if (vol->n_selected > 0) r->selected.assign(vol->selected, vol->selected + vol->n_selected);
+    r->vol.selected = nullptr;
+    r->p = *p;
+    r->t_submit = Clock::now();
+    {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        if (srv->stopping) {
+            delete r;
+            return fail(SN_ESHUTDOWN, "sn_serve_submit: server stopping");
+        }
+        if ((int32_t)srv->queue.size() >= srv->cfg.queue_capacity) {
+            delete r;
+            return fail(SN_EAGAIN, "sn_serve_submit: queue full");
+        }
+        r->footprint = footprint_of(r->vol, srv->out_bpv);
+        r->ticket = srv->next_ticket++;
+        srv->reqs[r->ticket] = r;
+        srv->queue.push_back(r);
+        ++srv->n_submitted;
+        *ticket = r->ticket;
+    }
+    srv->cv_work.notify_one();
+    return SN_OK;
+}
+
+static sn_status claim_locked(sn_server *srv, std::unordered_map<uint64_t, Request *>::iterator it,
+                              sn_mesh **out)
+{
+    Request *r = it->second;
+    sn_status st = r->status;
+    if (st == SN_OK) {
+        if (out)
+            *out = r->mesh;
+        else
+            mesh_release(r->mesh);
+    }
+    srv->reqs.erase(it);
+    delete r;
+    return st == SN_OK ? SN_OK : fail(st, "serve: request failed");
+}
+
+extern "C" sn_status sn_serve_poll(sn_server *srv, uint64_t ticket, sn_mesh **out)
+{
+    if (!srv) return fail(SN_EINVAL, "sn_serve_poll: NULL server");
+    std::lock_guard<std::mutex> lk(srv->mu);
+    auto it = srv->reqs.find(ticket);
+    if (it == srv->reqs.end()) return fail(SN_ENOTFOUND, "sn_serve_poll: unknown ticket");
+    if (!it->second->done) return SN_EAGAIN;
+    return claim_locked(srv, it, out);
+}
+
+extern "C" sn_status sn_serve_wait(sn_server *srv, uint64_t ticket, int64_t timeout_us,
+                                   sn_mesh **out)
+{
+    if (!srv) return fail(SN_EINVAL, "sn_serve_wait: NULL server");
+    std::unique_lock<std::mutex> lk(srv->mu);
+    auto ready = [&] {
+        auto it = srv->reqs.find(ticket);
+        return it == srv->reqs.end() || it->second->done;
+    };
+    if (timeout_us < 0) {
+        srv->cv_done.wait(lk, ready);
+    } else if (!srv->cv_done.wait_for(lk, std::chrono::microseconds(timeout_us), ready)) {
+        return fail(SN_ETIMEDOUT, "sn_serve_wait: timed out");
+    }
+    auto it = srv->reqs.find(ticket);
+    if (it == srv->reqs.end()) return fail(SN_ENOTFOUND, "sn_serve_wait: unknown ticket");
+    return claim_locked(srv, it, out);
+}
+
+static double percentile(std::vector<double> v, double q)
+{
+    if (v.empty()) return 0.0;
+    std::sort(v.begin(), v.end());
+    const double pos = q * (double)(v.size() - 1);
+    const size_t lo = (size_t)pos;
+    const size_t hi = std::min(lo + 1, v.size() - 1);
+    return v[lo] + (pos - (double)lo) * (v[hi] - v[lo]);
+}
+
+extern "C" sn_status sn_serve_stats_get(sn_server *srv, sn_serve_stats *out)
+{
+    if (!srv || !out) return fail(SN_EINVAL, "sn_serve_stats_get: NULL argument");
+    std::lock_guard<std::mutex> lk(srv->mu);
+    sn_serve_stats s;
+    std::memset(&s, 0, sizeof s);
+    s.n_submitted = srv->n_submitted, s.n_done = srv->n_done, s.n_rejected = srv->n_rejected;
+    s.n_batches = srv->n_batches;
+    s.voxels_done = srv->voxels_done, s.point_iters_done = srv->point_iters_done;
+    s.p50_us = percentile(srv->lat_us, 0.50);
+    s.p99_us = percentile(srv->lat_us, 0.99);
+    double sum = 0;
+    for (double x : srv->lat_us) sum += x;
+    s.mean_us = srv->lat_us.empty() ? 0.0 : sum / (double)srv->lat_us.size();
+    s.busy_s = srv->busy_s + (srv->busy_count > 0
+                                  ? std::chrono::duration<double>(Clock::now() - srv->busy_since).count()
+                                  : 0.0);
+    s.peak_reserved_bytes = srv->peak_reserved;
+    *out = s;
+    return SN_OK;
+}
+
+extern "C" sn_status sn_serve_stop(sn_server *srv)
+{
+    if (!srv) return fail(SN_EINVAL, "sn_serve_stop: NULL server");
+    std::vector<Request *> rejected;
+    {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        srv->stopping = true;
+        // queued requests that never started are rejected; in-flight ones finish
+        while (!srv->queue.empty()) {
+            Request *r = srv->queue.front();
+            srv->queue.pop_front();
+            r->done = true;
+            r->status = SN_ESHUTDOWN;
+            ++srv->n_rejected;
+        }
+    }
+    srv->cv_work.notify_all();
+    srv->cv_done.notify_all();
+    for (auto &t : srv->workers) t.join();
+    (void)hipSetDevice(srv->ctx->device);
+    for (auto s : srv->streams) {
+        (void)hipStreamSynchronize(s);
+        (void)hipStreamDestroy(s);
+    }
+    for (auto &kv : srv->reqs) {
+        if (kv.second->mesh) mesh_release(kv.second->mesh);
+        delete kv.second;
+    }
+    delete srv;
+    return SN_OK;
+}

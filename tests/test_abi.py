@@ -1,0 +1,77 @@
+"""CPU checks of the boundary: libsn.so loads and exports every symbol that
+include/sn.h declares, and the Python binding binds the same set.  No
+compute call is made here (there is no GPU)."""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sn.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sn_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_2401_14906_amd as sn
+
+    if not os.path.exists(sn.LIB_PATH):
+        from paper_2401_14906_amd import _build
+
+        _build.build()
+    return sn.load_library()
+
+
+def test_header_declares_the_api():
+    fns = declared_functions()
+    for name in ("sn_extract", "sn_smooth", "sn_batch_submit", "sn_serve_start",
+                 "sn_serve_submit", "sn_serve_poll", "sn_serve_wait", "sn_serve_stop"):
+        assert name in fns
+
+
+def test_library_exports_every_declared_symbol(lib):
+    missing = [f for f in declared_functions() if not hasattr(lib, f)]
+    assert not missing, f"libsn.so lacks {missing}"
+
+
+def test_binding_covers_every_declared_symbol(lib):
+    import paper_2401_14906_amd as sn
+
+    bound = {name for name, _, _ in sn._API}
+    assert bound == set(declared_functions())
+
+
+def test_error_strings_without_gpu(lib):
+    assert lib.sn_strerror(0) == b"ok"
+    assert lib.sn_strerror(-2) == b"out of device memory"
+    assert lib.sn_version().startswith(b"libsn gfx950")
+
+
+def test_null_arguments_are_rejected_without_gpu(lib):
+    import paper_2401_14906_amd as sn
+
+    # argument validation happens before any device call
+    assert lib.sn_extract(None, None, None, None) == sn.SN_EINVAL
+    assert lib.sn_smooth(None, None, None, None) == sn.SN_EINVAL
+    assert lib.sn_mesh_view_get(None, None) == sn.SN_EINVAL
+    assert lib.sn_serve_stop(None) == sn.SN_EINVAL
+    assert b"NULL" in lib.sn_last_error() or lib.sn_last_error() != b""
+
+
+def test_struct_layouts_match_header():
+    import paper_2401_14906_amd as sn
+
+    # sizes implied by the C declarations (x86-64 SysV alignment)
+    assert ctypes.sizeof(sn.sn_volume) == 8 + 4 + 4 + 24 + 24 + 24 + 8 + 4 + 4 + 4 + 4
+    assert ctypes.sizeof(sn.sn_smooth_params) == 12
+    assert ctypes.sizeof(sn.sn_mesh_view) == 4 * 8 + 2 * 4 + 7 * 8
+    assert ctypes.sizeof(sn.sn_serve_config) == 8 + 4 * 4
+    assert ctypes.sizeof(sn.sn_serve_stats) == 6 * 8 + 4 * 8 + 8

@@ -1,0 +1,253 @@
+"""GPU parity: the HIP path (through the C ABI) against the oracle.
+
+Bar: points, quads, label pairs and stencil bit-exact; smoothed cell-relative
+offsets within 1e-5 voxel of the FP64 oracle; world points within
+1e-5 * spacing + 1 float32 ulp.  The 1e-5 bound holds by construction: each
+sweep is a convex combination followed by a clamp (non-expansive in the max
+norm), computed in FP64 and stored in FP32, so the stored error grows by at
+most half an FP32 ulp of |offset| <= constraint per sweep: <= 40 * 2^-25 ~ 1.2e-6
+for 40 sweeps at constraint 1.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def torch():
+    t = pytest.importorskip("torch")
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+@pytest.fixture(scope="module")
+def sn(torch):
+    import paper_2401_14906_amd as sn
+
+    sn.load_library()
+    return sn
+
+
+@pytest.fixture(scope="module")
+def ctx(sn):
+    c = sn.Context(0)
+    yield c
+    c.close()
+
+
+def announce(msg):
+    print(f"[case] {msg}", flush=True)
+
+
+def check_mesh(g, o, labels_dtype, prim=4):
+    assert g.points.shape[0] == o.n_points, (g.points.shape, o.n_points)
+    assert g.stencil_ids.shape[0] == o.n_stencil
+    np.testing.assert_array_equal(g.stencil_off.astype(np.int64), o.st_off)
+    np.testing.assert_array_equal(g.stencil_ids, o.st_ids)
+    if prim == 4:
+        np.testing.assert_array_equal(g.polys, o.quads)
+        np.testing.assert_array_equal(g.label_pairs.astype(np.uint32), o.pairs)
+    else:
+        tris, tp = o.triangulate()
+        np.testing.assert_array_equal(g.polys, tris)
+        np.testing.assert_array_equal(g.label_pairs.astype(np.uint32), tp)
+    assert g.label_pairs.dtype == labels_dtype
+
+
+def check_smooth(g, o, iters, lam, d, spacing=(1, 1, 1), origin=(0, 0, 0)):
+    import oracle
+
+    pos = o.smooth(iters, lam, d)
+    ref = pos - o.centres()
+    if o.n_points:
+        err = np.max(np.abs(g.offsets.astype(np.float64) - ref))
+        assert err <= TOL, f"offset error {err}"
+        w = oracle.world(pos, origin, spacing)
+        h = np.asarray(spacing, np.float64)
+        ulp = np.spacing(np.abs(w).astype(np.float32)).astype(np.float64)
+        assert np.all(np.abs(g.points.astype(np.float64) - w) <= TOL * h + ulp)
+    return ref
+
+
+def run_case(ctx, sn, vol, selected=(), background=0, iters=0, lam=0.5, d=1.0,
+             spacing=(1.0, 1.0, 1.0), origin=(0.0, 0.0, 0.0), prim=4):
+    import oracle
+
+    t = sn.to_device(vol)
+    m = ctx.extract(t, spacing=spacing, origin=origin, selected=selected, background=background,
+                    prim=prim)
+    ctx.smooth(m, iterations=iters, relaxation=lam, constraint=d)
+    g = m.to_host()
+    o = oracle.extract(vol, selected, background)
+    check_mesh(g, o, vol.dtype, prim)
+    check_smooth(g, o, iters, lam, d, spacing, origin)
+    m.free()
+    return g, o
+
+
+def test_tiny_random_cases(ctx, sn):
+    """Many small volumes: ragged rows (M not a multiple of 64), several words
+    per row, all dtypes, selections, non-zero backgrounds, degenerate dims."""
+    rng = np.random.default_rng(1234)
+    for case in range(160):
+        dims = tuple(int(x) for x in rng.integers(1, 20, size=3))
+        if case % 10 == 0:
+            dims = (int(rng.integers(60, 200)), int(rng.integers(2, 6)), int(rng.integers(2, 6)))
+        dt = [np.uint8, np.uint16, np.uint32][case % 3]
+        nv = int(rng.integers(1, 8))
+        gen = synth.blocky_tiny if case % 2 else synth.random_tiny
+        vol = gen(rng, dims, nv, dt)
+        bg = int(rng.integers(0, 3))
+        sel = ()
+        if case % 4 == 1:
+            sel = tuple(sorted({int(x) for x in rng.integers(0, nv, size=2)} - {bg}))
+        iters = int(rng.integers(0, 12))
+        lam = float(rng.choice([0.0, 0.3, 0.5, 1.0]))
+        d = float(rng.choice([0.0, 0.25, 0.8, 1.0]))
+        sp = tuple(float(x) for x in rng.uniform(0.5, 3.0, size=3))
+        org = tuple(float(x) for x in rng.uniform(-50, 50, size=3))
+        prim = 3 if case % 7 == 3 else 4
+        announce(f"tiny {case}: dims={dims} dtype={np.dtype(dt).name} sel={sel} bg={bg} "
+                 f"iters={iters} lam={lam} d={d} prim={prim}")
+        run_case(ctx, sn, vol, sel, bg, iters, lam, d, sp, org, prim)
+
+
+@pytest.mark.parametrize("rpw", [1, 2, 4, 8, 16])
+def test_schedule_invariance(ctx, sn, rpw):
+    """Every rows-per-wave schedule gives the same bytes."""
+    rng = np.random.default_rng(77)
+    vol = synth.blocky_tiny(rng, (130, 41, 19), 6, np.uint16)
+    announce(f"schedule rpw={rpw}")
+    ctx.set_rows_per_wave(rpw)
+    try:
+        run_case(ctx, sn, vol, iters=7)
+    finally:
+        ctx.set_rows_per_wave(0)
+
+
+def test_dtype_edge_values(ctx, sn):
+    rng = np.random.default_rng(5)
+    for dt, top in ((np.uint8, 255), (np.uint16, 65535), (np.uint32, 2**32 - 1)):
+        base = synth.random_tiny(rng, (23, 17, 11), 3, dt)
+        vol = np.where(base == 2, top, base).astype(dt)
+        announce(f"edge values {np.dtype(dt).name} top={top}")
+        run_case(ctx, sn, vol, iters=3)                       # top as a label
+        run_case(ctx, sn, vol, background=top, iters=3)       # top as background
+        run_case(ctx, sn, vol, selected=(top,), iters=3)      # only top selected
+        run_case(ctx, sn, vol, selected=(1, top), background=0, iters=3)
+
+
+def test_large_selection_u32(ctx, sn):
+    """A sorted-list classification with many entries (u32)."""
+    rng = np.random.default_rng(6)
+    vol = rng.integers(0, 5000, size=(20, 30, 40)).astype(np.uint32)
+    sel = tuple(int(x) for x in rng.choice(5000, size=1500, replace=False) if x != 0)
+    announce("u32 selection of 1500 labels")
+    run_case(ctx, sn, vol, selected=sel, iters=2)
+
+
+def test_degenerate_volumes(ctx, sn):
+    for dims in [(1, 1, 1), (1, 7, 7), (7, 1, 7), (7, 7, 1), (2, 2, 2), (2, 30, 2)]:
+        M, N, O = dims
+        vol = (np.arange(M * N * O) % 3).astype(np.uint16).reshape(O, N, M)
+        announce(f"degenerate {dims}")
+        run_case(ctx, sn, vol, iters=2)
+    announce("uniform volume")
+    run_case(ctx, sn, np.full((9, 8, 7), 3, np.uint16), iters=4)
+    v = np.zeros((3, 3, 3), np.uint8)
+    v[1, 1, 1] = 9
+    announce("single voxel")
+    g, _ = run_case(ctx, sn, v, iters=16, lam=0.5, d=1.0)
+    np.testing.assert_allclose(np.abs(g.offsets), 0.5 - 0.5 * (2 / 3) ** 16, atol=TOL)
+
+
+def test_spheres_small_config(ctx, sn):
+    v = synth.spheres_small()
+    announce(v.name)
+    run_case(ctx, sn, v.labels, iters=v.iterations, lam=v.relaxation, d=v.constraint)
+
+
+def test_torso_like_config(ctx, sn):
+    v = synth.torso_like()
+    announce(v.name)
+    run_case(ctx, sn, v.labels, iters=v.iterations, lam=v.relaxation, d=v.constraint,
+             spacing=v.spacing)
+
+
+def test_resmooth_restarts_from_cache(ctx, sn, torch):
+    import oracle
+
+    rng = np.random.default_rng(8)
+    vol = synth.blocky_tiny(rng, (40, 33, 21), 5, np.uint16)
+    t = sn.to_device(vol)
+    m = ctx.extract(t)
+    o = oracle.extract(vol)
+    for iters, lam, d in [(20, 0.5, 1.0), (5, 1.0, 0.3), (20, 0.5, 1.0), (0, 0.5, 1.0),
+                          (33, 0.25, 0.6)]:
+        announce(f"resmooth {iters} {lam} {d}")
+        ctx.smooth(m, iterations=iters, relaxation=lam, constraint=d)
+        check_smooth(m.to_host(), o, iters, lam, d)
+    m.free()
+
+
+def test_graph_replays_match_eager(ctx, sn, torch):
+    """The captured sweep graph, replayed many times with other device work and
+    synchronisations in between, gives the eager (profiled, uncaptured) result
+    every time."""
+    rng = np.random.default_rng(9)
+    vol = synth.blocky_tiny(rng, (70, 50, 30), 7, np.uint16)
+    t = sn.to_device(vol)
+    m = ctx.extract(t)
+    ctx.profile(True)
+    ctx.smooth(m, iterations=17, relaxation=0.5, constraint=0.7)
+    ref = m.to_host()
+    ctx.profile(False)
+    ctx.profile_reset()
+    junk = torch.zeros(1 << 20, device="cuda")
+    for rep in range(6):
+        junk.add_(1.0)
+        torch.cuda.synchronize()
+        ctx.smooth(m, iterations=17, relaxation=0.5, constraint=0.7)
+        g = m.to_host()
+        assert np.array_equal(g.offsets, ref.offsets), f"replay {rep}"
+        assert np.array_equal(g.points, ref.points), f"replay {rep}"
+    m.free()
+
+
+def test_determinism(ctx, sn):
+    rng = np.random.default_rng(10)
+    vol = synth.random_tiny(rng, (100, 60, 40), 6, np.uint32)
+    t = sn.to_device(vol)
+    outs = []
+    for _ in range(2):
+        m = ctx.extract(t)
+        ctx.smooth(m, iterations=9)
+        outs.append(m.to_host())
+        m.free()
+    for f in ("points", "offsets", "polys", "label_pairs", "stencil_off", "stencil_ids"):
+        assert np.array_equal(getattr(outs[0], f), getattr(outs[1], f)), f
+
+
+def test_invalid_arguments(ctx, sn, torch):
+    t = sn.to_device(np.zeros((4, 4, 4), np.uint16))
+    with pytest.raises(sn.SNError) as e:
+        ctx.extract(t, spacing=(0.0, 1.0, 1.0))
+    assert e.value.status == sn.SN_EINVAL
+    with pytest.raises(sn.SNError):
+        ctx.extract(t, selected=(0,), background=0)  # background selected
+    with pytest.raises(sn.SNError):
+        ctx.extract(t, background=70000)  # does not fit u16
+    m = ctx.extract(t)
+    with pytest.raises(sn.SNError):
+        ctx.smooth(m, iterations=-1)
+    with pytest.raises(sn.SNError):
+        ctx.smooth(m, relaxation=1.5)
+    m.free()
