@@ -212,9 +212,12 @@ sn_status sn_autotune(sn_ctx *ctx, const sn_volume *vol, void *stream, int32_t *
  * not depend on the schedule. */
 sn_status sn_set_rows_per_wave(sn_ctx *ctx, int32_t rows_per_wave);
 
-/* Per-kernel timing: when on, every library kernel launch is bracketed by HIP
- * events on the stream it runs on.  sn_profile_read synchronises, folds the
- * events into per-kernel totals and fills up to `cap` records. */
+/* Per-kernel timing: with on = 1 every library kernel launch is bracketed by
+ * HIP events on the stream it runs on, and a replay of the captured sweep
+ * graph is bracketed as a whole (counted as `iterations` launches of
+ * k_jacobi); with on = 2 the sweeps are launched one by one instead, each with
+ * its own events.  on = 0 turns timing off.  sn_profile_read synchronises,
+ * folds the events into per-kernel totals and fills up to `cap` records. */
 typedef struct sn_kernel_stat {
     char name[48];
     int64_t launches;

@@ -313,8 +313,9 @@ class Context:
     def set_rows_per_wave(self, rpw: int):
         _check(_lib.sn_set_rows_per_wave(self._h, int(rpw)))
 
-    def profile(self, on: bool = True):
-        _check(_lib.sn_profile_enable(self._h, 1 if on else 0))
+    def profile(self, on=True):
+        """on: False/0 off, True/1 events per launch (graph replay as a whole), 2 eager sweeps."""
+        _check(_lib.sn_profile_enable(self._h, int(on)))
 
     def profile_reset(self):
         _check(_lib.sn_profile_reset(self._h))

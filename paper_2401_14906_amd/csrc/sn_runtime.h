@@ -62,6 +62,7 @@ struct sn_ctx {
     std::mutex capture_mu;
     // profiling
     bool profiling = false;
+    bool profile_eager = false;  // sweeps launched one by one instead of a graph
     struct ProfEv {
         std::string name;
         hipEvent_t a, b;

@@ -270,8 +270,9 @@ ProfScope::~ProfScope()
 
 extern "C" sn_status sn_profile_enable(sn_ctx *c, int on)
 {
-    if (!c) return fail(SN_EINVAL, "sn_profile_enable: ctx is NULL");
+    if (!c || on < 0 || on > 2) return fail(SN_EINVAL, "sn_profile_enable: bad arguments");
     c->profiling = on != 0;
+    c->profile_eager = on == 2;
     return SN_OK;
 }
 
@@ -793,14 +794,16 @@ sn_status sn::run_sweeps(sn_ctx *c, const SmoothDesc *d_sd, const int64_t *d_bp,
                          std::map<int32_t, hipGraphExec_t> *cache)
 {
     if (iters <= 0 || nblocks <= 0) return SN_OK;
-    if (c->profiling) {
-        // eager launches so each sweep is bracketed by its own events
+    if (c->profile_eager) {
+        // eager launches, each sweep bracketed by its own events
         for (int32_t it = 0; it < iters; ++it) {
             ProfScope ps(c, "k_jacobi", s);
             HIP_TRY(launch_jacobi(d_sd, d_bp, nvol, nblocks, it, s));
         }
         return SN_OK;
     }
+    // one event pair around the whole graph replay: `iters` launches
+    ProfScope ps(c, "k_jacobi", s, iters);
     hipGraphExec_t exec = nullptr;
     if (cache) {
         auto it = cache->find(iters);

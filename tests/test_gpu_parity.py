@@ -206,7 +206,7 @@ def test_graph_replays_match_eager(ctx, sn, torch):
     vol = synth.blocky_tiny(rng, (70, 50, 30), 7, np.uint16)
     t = sn.to_device(vol)
     m = ctx.extract(t)
-    ctx.profile(True)
+    ctx.profile(2)  # eager sweeps, no graph
     ctx.smooth(m, iterations=17, relaxation=0.5, constraint=0.7)
     ref = m.to_host()
     ctx.profile(False)
