@@ -203,14 +203,15 @@ sn_status sn_serve_stop(sn_server *srv);
 
 /* ---- schedule tuning and profiling ----------------------------------------- */
 
-/* Time the candidate schedules (rows per wave of the row kernels) for the
- * volume's size class on this device and remember the fastest for it (also
- * written to SN_AUTOTUNE_CACHE if set).  Returns the chosen rows-per-wave. */
+/* Time the candidate schedules (batches of 4 cell words per wavefront in the
+ * extraction kernels) for the volume's size class on this device and remember
+ * the fastest for it (also written to SN_AUTOTUNE_CACHE if set).  Returns the
+ * chosen batches-per-wave. */
 sn_status sn_autotune(sn_ctx *ctx, const sn_volume *vol, void *stream, int32_t *chosen);
-/* Force the rows-per-wave schedule of the row kernels (1..16) for every later
- * launch on this context; 0 returns to the tuned/default choice.  Results do
- * not depend on the schedule. */
-sn_status sn_set_rows_per_wave(sn_ctx *ctx, int32_t rows_per_wave);
+/* Force the batches-per-wave schedule of the extraction kernels (1..16) for
+ * every later launch on this context; 0 returns to the tuned/default choice.
+ * Results do not depend on the schedule. */
+sn_status sn_set_batches_per_wave(sn_ctx *ctx, int32_t batches_per_wave);
 
 /* Per-kernel timing: with on = 1 every library kernel launch is bracketed by
  * HIP events on the stream it runs on, and a replay of the captured sweep

@@ -105,7 +105,7 @@ _API = [
     ("sn_serve_stats_get", _S, [_P, ctypes.POINTER(sn_serve_stats)]),
     ("sn_serve_stop", _S, [_P]),
     ("sn_autotune", _S, [_P, ctypes.POINTER(sn_volume), _P, ctypes.POINTER(ctypes.c_int32)]),
-    ("sn_set_rows_per_wave", _S, [_P, ctypes.c_int32]),
+    ("sn_set_batches_per_wave", _S, [_P, ctypes.c_int32]),
     ("sn_profile_enable", _S, [_P, ctypes.c_int]),
     ("sn_profile_reset", _S, [_P]),
     ("sn_profile_read", _S, [_P, ctypes.POINTER(sn_kernel_stat), ctypes.c_int32,
@@ -310,8 +310,8 @@ class Context:
         _check(_lib.sn_autotune(self._h, ctypes.byref(v), _stream_handle(stream), ctypes.byref(ch)))
         return int(ch.value)
 
-    def set_rows_per_wave(self, rpw: int):
-        _check(_lib.sn_set_rows_per_wave(self._h, int(rpw)))
+    def set_batches_per_wave(self, bpw: int):
+        _check(_lib.sn_set_batches_per_wave(self._h, int(bpw)))
 
     def profile(self, on=True):
         """on: False/0 off, True/1 events per launch (graph replay as a whole), 2 eager sweeps."""

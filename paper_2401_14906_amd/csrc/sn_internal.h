@@ -22,27 +22,40 @@ struct ClassSpec {
     int32_t n;
 };
 
+// Words and batches.  The cells of a volume are enumerated in their linear
+// order i + CM*(j + CN*k); a "row" r = j + CN*k is the line of cells
+// (0..CM-1, j, k), cut into W words of 64 cells (the last one ragged).  Word
+// g = r*W + w holds cells 64w .. 64w+63 of row r.  A batch is up to kU
+// consecutive words of one row (NB batches per row) and is the work item of
+// one wavefront; a tile is 4*bpw consecutive batches, the work item of one
+// workgroup and the unit of the device-wide scan.
+constexpr int kU = 4;
+constexpr int kWavesPerBlock = 4;
+constexpr int kBlock = 64 * kWavesPerBlock;
+constexpr int kMaxBatchesPerWave = 16;
+constexpr int kMaxTileWords = kWavesPerBlock * kMaxBatchesPerWave * kU;
+
 // Sample lattice M x N x O; cell grid CM x CN x CO = (M-1)(N-1)(O-1).
-// A "row" r = j + CN*k is the line of cells (0..CM-1, j, k); W = 64-cell words per row.
 struct Geom {
     int64_t M, N, O;
     int64_t CM, CN, CO;
-    int64_t R;
-    int32_t W;
+    int64_t R;    // rows
+    int32_t W;    // words per row
+    int32_t NB;   // batches per row
 };
 
-// Everything the row kernels need for one volume.
+// Everything the word kernels need for one volume.
 struct VolDesc {
     const void *labels;
     int32_t dtype;  // 1, 2, 4
     int32_t prim;   // 3 or 4
     Geom g;
     ClassSpec cs;
-    // row metadata (kept with the mesh)
+    // word metadata (kept with the mesh)
     uint64_t *pmask;  // [R*W] point bit per cell
-    int64_t *baseP;   // [R+1] exclusive prefix of points per row
-    int64_t *baseQ;   // [R+1] quads
-    int64_t *baseS;   // [R+1] stencil entries
+    int32_t *wbP;     // [R*W] id of the first point of each word
+    int32_t *wbQ;     // [R*W] index of the first quad owned by each word
+    int32_t *wbS;     // [R*W] index of the first stencil entry of each word
     // outputs
     float *points;     // [P*3]
     uint8_t *faces;    // [P] stencil face mask, bit f = face f (-x,+x,-y,+y,-z,+z)
@@ -74,20 +87,22 @@ struct SmoothDesc {
 constexpr uint64_t kFlagAgg = 1ull << 62;
 constexpr uint64_t kFlagPrefix = 2ull << 62;
 constexpr uint64_t kValMask = (1ull << 62) - 1;
-constexpr int kMaxRowsPerWave = 16;
-constexpr int kWavesPerBlock = 4;
-constexpr int kBlock = 64 * kWavesPerBlock;
 
 // ---- launchers (sn_kernels.hip) ----------------------------------------------
-// tile_prefix[v] = first tile of volume v, tile_prefix[nvol] = total tiles;
-// a tile is 4*rpw consecutive rows of one volume.
-hipError_t launch_count(const VolDesc *d_descs, const int64_t *d_tile_prefix, int32_t nvol,
-                        int64_t ntiles, int32_t rpw, uint64_t *d_status, uint32_t *d_ticket,
+// tile_prefix[v] = first tile of volume v, tile_prefix[nvol] = end; tile
+// indices are global across the launches of one extraction, and a launch
+// covers tiles tile_base .. tile_base + ntiles - 1.  bpw = batches per wave
+// (a tile is 4*bpw batches of one volume).  Every volume of a count/generate
+// launch has the given label type (bytes) and classification mode.
+hipError_t launch_count(int32_t dtype, int32_t mode, const VolDesc *d_descs,
+                        const int64_t *d_tile_prefix, int32_t nvol, int64_t tile_base,
+                        int64_t ntiles, int32_t bpw, uint64_t *d_status, uint32_t *d_ticket,
                         int64_t *d_totals, hipStream_t s);
-hipError_t launch_generate(const VolDesc *d_descs, const int64_t *d_tile_prefix, int32_t nvol,
-                           int64_t ntiles, int32_t rpw, hipStream_t s);
+hipError_t launch_generate(int32_t dtype, int32_t mode, const VolDesc *d_descs,
+                           const int64_t *d_tile_prefix, int32_t nvol, int64_t tile_base,
+                           int64_t ntiles, int32_t bpw, hipStream_t s);
 hipError_t launch_emit(const VolDesc *d_descs, const int64_t *d_tile_prefix, int32_t nvol,
-                       int64_t ntiles, int32_t rpw, hipStream_t s);
+                       int64_t ntiles, int32_t bpw, hipStream_t s);
 // block_prefix[v] = first block of volume v (256 points per block)
 hipError_t launch_jacobi(const SmoothDesc *d_sd, const int64_t *d_block_prefix, int32_t nvol,
                          int64_t nblocks, int32_t it, hipStream_t s);

@@ -1,27 +1,52 @@
 // SurfaceNets extraction and smoothing kernels for gfx950 (MI355X).
 //
-// Row kernels: one 64-lane wavefront walks one row of cells (fixed j, k) in
-// 64-cell words; lane L of word w owns cell i = 64w + L and the sample (i,j,k).
-// The four sample rows (j..j+1, k..k+1) around the cell row are read once per
-// word; the +x corner comes from the next lane (cross-lane shuffle).  Every
-// per-cell predicate becomes a 64-bit ballot, so in-row ranks of points,
-// quads and stencil entries are mbcnt popcounts and row totals are scalar
-// popcounts.  This replaces the paper's triad byte volume, trim intervals,
-// checkerboarded PRODUCE_POINT bits and 3x3 row iterator (Sec. 3.2-3.6) with
-// a 1-bit-per-cell point plane and per-row prefix bases.
+// Word kernels.  Cells are enumerated in linear order and cut into 64-cell
+// words (see sn_internal.h); lane L of a wavefront owns cell 64w + L of word
+// w and the sample at its origin.  A wavefront takes a batch of kU words of
+// one row and issues all 4*kU sample-row loads of the batch before using any
+// (the +x corner comes from the next lane).  The twelve edge cuts of a cell
+// are twelve compares whose wave ballots are 64-bit masks; points, stencil
+// faces and quads are mask algebra on scalar registers, and every rank inside
+// a word is an mbcnt.  This replaces the paper's triad byte volume, trim
+// intervals, checkerboarded PRODUCE_POINT bits and 3x3 row iterator
+// (Sec. 3.2-3.6) with a 1-bit point plane and per-word prefix bases.
 //
-//   k_count    : classify + cut edges + point/quad/stencil counts per row,
-//                point-bit plane, fused decoupled-look-back exclusive scan of
-//                the per-row counts (Sec. 2.3 passes 1-3 and the prefix sum).
-//   k_generate : points, stencil CSR, quads and label pairs at the scanned
-//                offsets, no atomics (Sec. 2.3 pass 4).
-//   k_jacobi   : one double-buffered sweep of Eq. (1) with the box
-//                constraint (Sec. 2.2, 2.4), on cell-relative offsets.
+//   k_count    : classify, cut edges, per-word point/quad/stencil counts and the
+//                point-bit plane; a fused single-pass (decoupled look-back) scan
+//                of the word counts gives every word its first point id, quad
+//                index and stencil index (Sec. 2.3 passes 1-3 and the prefix sum).
+//   k_generate : points, stencil CSR, quads and label pairs written at those
+//                bases, without atomics (Sec. 2.3 pass 4).
+//   k_jacobi   : one double-buffered sweep of Eq. (1) with the box constraint
+//                (Sec. 2.2, 2.4), on cell-relative offsets.
 //   k_emit     : world coordinates of the points from the offsets.
 //   k_tri      : two triangles per quad (Sec. 2.5).
 #include "sn_internal.h"
 
+#define SN_GLOBAL __attribute__((address_space(1)))
+#define SN_CONST __attribute__((address_space(4)))
+
 namespace sn {
+
+// Pointers read out of descriptors are generic; these casts tell the compiler
+// which memory they address (global for vector access; constant for data that
+// is read-only during the kernel and read with wave-uniform addresses, which
+// then go through the scalar unit).
+template <typename T>
+__device__ __forceinline__ SN_GLOBAL T *glb(T *p)
+{
+    return (SN_GLOBAL T *)p;
+}
+template <typename T>
+__device__ __forceinline__ const SN_GLOBAL T *glb(const T *p)
+{
+    return (const SN_GLOBAL T *)p;
+}
+template <typename T>
+__device__ __forceinline__ const SN_CONST T *cst(const T *p)
+{
+    return (const SN_CONST T *)p;
+}
 
 __device__ __forceinline__ uint32_t rank_below(uint64_t m)
 {
@@ -29,14 +54,18 @@ __device__ __forceinline__ uint32_t rank_below(uint64_t m)
                                      __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
-__device__ __forceinline__ uint64_t wave_ballot(bool p) { return __ballot(p ? 1 : 0); }
+__device__ __forceinline__ uint32_t lane_bit(uint64_t m, int lane)
+{
+    return (uint32_t)(m >> lane) & 1u;
+}
 
 __device__ __forceinline__ int find_seg(const int64_t *prefix, int n, int64_t t)
 {
+    const SN_CONST int64_t *p = cst(prefix);
     int lo = 0, hi = n - 1;
     while (lo < hi) {
         int mid = (lo + hi + 1) >> 1;
-        if (prefix[mid] <= t)
+        if (p[mid] <= t)
             lo = mid;
         else
             hi = mid - 1;
@@ -50,72 +79,176 @@ __device__ __forceinline__ uint32_t classify(uint32_t v, const ClassSpec &cs)
     if constexpr (MODE == CLS_IDENT) {
         return v;
     } else if constexpr (MODE == CLS_BITMAP) {
-        return ((cs.table[v >> 5] >> (v & 31u)) & 1u) ? v : cs.bg;
+        return ((glb(cs.table)[v >> 5] >> (v & 31u)) & 1u) ? v : cs.bg;
     } else {
+        const SN_GLOBAL uint32_t *tab = glb(cs.table);
         int lo = 0, hi = cs.n;
         while (lo < hi) {
             int mid = (lo + hi) >> 1;
-            if (cs.table[mid] < v)
+            if (tab[mid] < v)
                 lo = mid + 1;
             else
                 hi = mid;
         }
-        return (lo < cs.n && cs.table[lo] == v) ? v : cs.bg;
+        return (lo < cs.n && tab[lo] == v) ? v : cs.bg;
     }
 }
 
-// Classified values at the 8 corners of cell (i,j,k); index di + 2*dj + 4*dk.
-template <typename T, int MODE>
-__device__ __forceinline__ void load_corners(const T *__restrict__ vol, const Geom &g,
-                                             const ClassSpec &cs, int64_t i, int64_t j, int64_t k,
-                                             int lane, uint32_t c[8])
-{
-    const int64_t ic = i < g.M - 1 ? i : g.M - 1;
-    const int64_t in = (i + 1) < g.M - 1 ? (i + 1) : g.M - 1;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int dj = q & 1, dk = q >> 1;
-        const T *row = vol + g.M * ((j + dj) + g.N * (k + dk));
-        uint32_t a = classify<MODE>((uint32_t)row[ic], cs);
-        uint32_t b = __shfl_down(a, 1u);
-        if (lane == 63) b = classify<MODE>((uint32_t)row[in], cs);
-        c[2 * dj + 4 * dk] = a;
-        c[1 + 2 * dj + 4 * dk] = b;
-    }
-}
-
-struct CellPred {
-    bool point, qx, qy, qz;
-    uint32_t fmask;
+// Where a batch sits.  Batch, row and word counts of a volume fit int32 (the
+// host checks); the first batch of a wave is found with one 32-bit division
+// and the following ones by stepping.
+struct BatchPos {
+    int32_t r, j, k;
+    int32_t w0, nw;  // first word, number of words (1..kU)
+    int64_t g0;      // linear index of the first word
 };
 
-__device__ __forceinline__ bool nonuni4(uint32_t a, uint32_t b, uint32_t d, uint32_t e)
+__device__ __forceinline__ BatchPos batch_pos(const Geom &g, int64_t b)
 {
-    return !((a == b) & (a == d) & (a == e));
+    BatchPos p;
+    const uint32_t NB = (uint32_t)g.NB, CN = (uint32_t)g.CN;
+    p.r = (int32_t)((uint32_t)b / NB);
+    p.w0 = ((int32_t)b - p.r * (int32_t)NB) * kU;
+    p.j = (int32_t)((uint32_t)p.r % CN);
+    p.k = (int32_t)((uint32_t)p.r / CN);
+    p.nw = g.W - p.w0 < kU ? g.W - p.w0 : kU;
+    p.g0 = (int64_t)p.r * g.W + p.w0;
+    return p;
 }
 
-// Sec. 2.2 / 3.3 predicates of one cell and of the edges owned by its origin sample.
-__device__ __forceinline__ CellPred predicates(const uint32_t c[8], bool valid, int64_t i, int64_t j,
-                                               int64_t k, const Geom &g)
+__device__ __forceinline__ void batch_next(const Geom &g, BatchPos &p)
 {
-    CellPred p;
+    p.w0 += kU;
+    if (p.w0 >= g.W) {
+        p.w0 = 0;
+        p.r += 1;
+        p.j += 1;
+        if (p.j == (int32_t)g.CN) p.j = 0, p.k += 1;
+    }
+    p.nw = g.W - p.w0 < kU ? g.W - p.w0 : kU;
+    p.g0 = (int64_t)p.r * g.W + p.w0;
+}
+
+// Raw label loads of one batch: word u, sample row q = dj + 2*dk, plus (lane
+// 63 only) the sample just after the batch.  Issued early, consumed later:
+// the kernels keep the loads of the next batch in flight while they work on
+// the current one.
+template <typename T>
+struct LabelLoads {
+    T a[kU][4];
+    T e[4];
+};
+
+template <typename T>
+__device__ __forceinline__ void issue_labels(const T *vol_, const Geom &g, const BatchPos &bp,
+                                             int lane, LabelLoads<T> &L)
+{
+    const SN_GLOBAL T *vol = glb(vol_);
+    const int32_t M1 = (int32_t)(g.M - 1);
+    const SN_GLOBAL T *rows[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+        rows[q] = vol + g.M * ((int64_t)(bp.j + (q & 1)) + g.N * (int64_t)(bp.k + (q >> 1)));
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+        const int32_t i = 64 * (bp.w0 + u) + lane;
+        const int32_t ic = i < M1 ? i : M1;  // lanes past the row end read the last sample
+#pragma unroll
+        for (int q = 0; q < 4; ++q) L.a[u][q] = rows[q][(uint32_t)ic];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) L.e[q] = 0;
+    if (lane == 63) {
+        const int32_t in = 64 * (bp.w0 + kU) < M1 ? 64 * (bp.w0 + kU) : M1;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) L.e[q] = rows[q][(uint32_t)in];
+    }
+}
+
+// Classified values at the 8 corners of the cells 64(w0+u) + lane of the
+// batch; index di + 2*dj + 4*dk.  The +x corner comes from the next lane,
+// from lane 0 of the next word, or (last word) from the extra load of lane 63.
+template <typename T, int MODE>
+__device__ __forceinline__ void corners(const LabelLoads<T> &L, const ClassSpec &cs, int lane,
+                                        uint32_t (&c)[kU][8])
+{
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int slot = 2 * (q & 1) + 4 * (q >> 1);
+        uint32_t x[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) x[u] = classify<MODE>((uint32_t)L.a[u][q], cs);
+        const uint32_t xe = classify<MODE>((uint32_t)L.e[q], cs);
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            uint32_t y = __shfl_down(x[u], 1u);
+            const uint32_t nxt =
+                (u + 1 < kU) ? (uint32_t)__builtin_amdgcn_readlane((int)x[(u + 1) % kU], 0) : xe;
+            if (lane == 63) y = nxt;
+            c[u][slot] = x[u];
+            c[u][slot + 1] = y;
+        }
+    }
+}
+
+// Wave-wide masks of one word (bit L = cell 64w + L): a point where any of
+// the twelve edges is cut (Sec. 2.2), a stencil face where one of its four
+// edges is cut and the neighbour cell exists (Sec. 3.3), a quad per cut edge
+// owned by the cell's origin sample whose four cells exist (Sec. 2.2, open
+// boundary of Sec. 4.2).
+struct WordMasks {
+    uint64_t pt, qx, qy, qz;
+    uint64_t f[6];  // -x, +x, -y, +y, -z, +z
+};
+
+__device__ __forceinline__ WordMasks word_masks(const uint32_t c[8], int32_t w, int64_t j, int64_t k,
+                                                const Geom &g)
+{
     const uint32_t c000 = c[0], c100 = c[1], c010 = c[2], c110 = c[3];
     const uint32_t c001 = c[4], c101 = c[5], c011 = c[6], c111 = c[7];
-    const bool all_eq = (c000 == c100) & (c000 == c010) & (c000 == c110) & (c000 == c001) &
-                        (c000 == c101) & (c000 == c011) & (c000 == c111);
-    p.point = valid && !all_eq;
-    uint32_t fm = 0;
-    fm |= (i >= 1 && nonuni4(c000, c010, c001, c011)) ? 1u : 0u;
-    fm |= (i + 1 <= g.CM - 1 && nonuni4(c100, c110, c101, c111)) ? 2u : 0u;
-    fm |= (j >= 1 && nonuni4(c000, c100, c001, c101)) ? 4u : 0u;
-    fm |= (j + 1 <= g.CN - 1 && nonuni4(c010, c110, c011, c111)) ? 8u : 0u;
-    fm |= (k >= 1 && nonuni4(c000, c100, c010, c110)) ? 16u : 0u;
-    fm |= (k + 1 <= g.CO - 1 && nonuni4(c001, c101, c011, c111)) ? 32u : 0u;
-    p.fmask = valid ? fm : 0u;
-    p.qx = valid && (c000 != c100) && j >= 1 && k >= 1;
-    p.qy = valid && (c000 != c010) && i >= 1 && k >= 1;
-    p.qz = valid && (c000 != c001) && i >= 1 && j >= 1;
-    return p;
+    const uint64_t x0 = __ballot(c000 != c100), x1 = __ballot(c010 != c110);
+    const uint64_t x2 = __ballot(c001 != c101), x3 = __ballot(c011 != c111);
+    const uint64_t y0 = __ballot(c000 != c010), y1 = __ballot(c100 != c110);
+    const uint64_t y2 = __ballot(c001 != c011), y3 = __ballot(c101 != c111);
+    const uint64_t z0 = __ballot(c000 != c001), z1 = __ballot(c100 != c101);
+    const uint64_t z2 = __ballot(c010 != c011), z3 = __ballot(c110 != c111);
+    const int64_t rem = g.CM - 64 * (int64_t)w;       // cells of the row from this word on (>= 1)
+    const uint64_t valid = rem >= 64 ? ~0ull : ((1ull << rem) - 1);
+    const uint64_t hasprev = w == 0 ? ~1ull : ~0ull;  // i >= 1
+    const int64_t rem2 = rem - 1;                     // i + 1 <= CM - 1
+    const uint64_t hasnext = rem2 >= 64 ? ~0ull : (rem2 <= 0 ? 0ull : ((1ull << rem2) - 1));
+    const uint64_t ym = j >= 1 ? ~0ull : 0ull, yp = j + 1 <= g.CN - 1 ? ~0ull : 0ull;
+    const uint64_t zm = k >= 1 ? ~0ull : 0ull, zp = k + 1 <= g.CO - 1 ? ~0ull : 0ull;
+    WordMasks m;
+    m.pt = (x0 | x1 | x2 | x3 | y0 | y1 | y2 | y3 | z0 | z1 | z2 | z3) & valid;
+    m.f[0] = (y0 | y2 | z0 | z2) & valid & hasprev;
+    m.f[1] = (y1 | y3 | z1 | z3) & hasnext;
+    m.f[2] = (x0 | x2 | z0 | z1) & valid & ym;
+    m.f[3] = (x1 | x3 | z2 | z3) & valid & yp;
+    m.f[4] = (x0 | x1 | y0 | y1) & valid & zm;
+    m.f[5] = (x2 | x3 | y2 | y3) & valid & zp;
+    m.qx = x0 & valid & ym & zm;
+    m.qy = y0 & valid & hasprev & zm;
+    m.qz = z0 & valid & hasprev & ym;
+    return m;
+}
+
+__device__ __forceinline__ int64_t wave_sum(int64_t x)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o);
+    return x;
+}
+
+__device__ __forceinline__ int64_t wave_excl_scan(int64_t x, int lane)
+{
+    int64_t inc = x;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int64_t y = __shfl_up(inc, (unsigned)o);
+        if (lane >= o) inc += y;
+    }
+    return inc - x;
 }
 
 // ---------------------------------------------------------------------------
@@ -123,117 +256,184 @@ __device__ __forceinline__ CellPred predicates(const uint32_t c[8], bool valid, 
 // ---------------------------------------------------------------------------
 
 template <typename T, int MODE>
-__device__ void count_row(const VolDesc &d, int64_t r, int lane, int64_t cnt[3])
+__device__ __forceinline__ void count_process(const VolDesc &d, const BatchPos &bp,
+                                              const LabelLoads<T> &L, int lane, int64_t gt0,
+                                              int32_t (*s_wc)[kMaxTileWords])
 {
-    const Geom &g = d.g;
-    const T *vol = static_cast<const T *>(d.labels);
-    const int64_t j = r % g.CN, k = r / g.CN;
-    int64_t nP = 0, nQ = 0, nS = 0;
-    for (int32_t w = 0; w < g.W; ++w) {
-        const int64_t i = 64 * (int64_t)w + lane;
-        const bool valid = i < g.CM;
-        uint32_t c[8];
-        load_corners<T, MODE>(vol, g, d.cs, i, j, k, lane, c);
-        const CellPred p = predicates(c, valid, i, j, k, g);
-        const uint64_t bp = wave_ballot(p.point);
-        if (lane == 0) d.pmask[r * g.W + w] = bp;
-        nP += __popcll(bp);
-        nQ += __popcll(wave_ballot(p.qx)) + __popcll(wave_ballot(p.qy)) +
-              __popcll(wave_ballot(p.qz));
+    uint32_t c[kU][8];
+    corners<T, MODE>(L, d.cs, lane, c);
+    SN_GLOBAL uint64_t *pmask = glb(d.pmask);
+    const int32_t local = (int32_t)(bp.g0 - gt0);
 #pragma unroll
-        for (int f = 0; f < 6; ++f) nS += __popcll(wave_ballot((p.fmask >> f) & 1u));
+    for (int u = 0; u < kU; ++u) {
+        if (u >= bp.nw) break;
+        __builtin_amdgcn_sched_barrier(0);
+        const WordMasks m = word_masks(c[u], bp.w0 + u, bp.j, bp.k, d.g);
+        int32_t nP = 0, nQ = 0, nS = 0;
+        if (m.pt != 0) {  // no cut edge: no quad and no stencil face either
+            nP = __popcll(m.pt);
+            nQ = __popcll(m.qx) + __popcll(m.qy) + __popcll(m.qz);
+#pragma unroll
+            for (int f = 0; f < 6; ++f) nS += __popcll(m.f[f]);
+        }
+        if (lane == 0) {
+            pmask[bp.g0 + u] = m.pt;
+            s_wc[0][local + u] = nP;
+            s_wc[1][local + u] = nQ;
+            s_wc[2][local + u] = nS;
+        }
     }
-    cnt[0] = nP, cnt[1] = nQ, cnt[2] = nS;
 }
 
-__device__ void count_row_dispatch(const VolDesc &d, int64_t r, int lane, int64_t cnt[3])
+// nb consecutive batches from b0, two in flight.
+template <typename T, int MODE>
+__device__ void count_stream(const VolDesc &d, int64_t b0, int nb, int lane, int64_t gt0,
+                             int32_t (*s_wc)[kMaxTileWords])
 {
-    const int m = d.cs.mode;
-    if (d.dtype == 1) {
-        if (m == CLS_IDENT) count_row<uint8_t, CLS_IDENT>(d, r, lane, cnt);
-        else count_row<uint8_t, CLS_BITMAP>(d, r, lane, cnt);
-    } else if (d.dtype == 2) {
-        if (m == CLS_IDENT) count_row<uint16_t, CLS_IDENT>(d, r, lane, cnt);
-        else count_row<uint16_t, CLS_BITMAP>(d, r, lane, cnt);
-    } else {
-        if (m == CLS_IDENT) count_row<uint32_t, CLS_IDENT>(d, r, lane, cnt);
-        else count_row<uint32_t, CLS_SORTED>(d, r, lane, cnt);
+    const T *vol = static_cast<const T *>(d.labels);
+    LabelLoads<T> L0, L1;
+    BatchPos P0 = batch_pos(d.g, b0), P1;
+    issue_labels<T>(vol, d.g, P0, lane, L0);
+    for (int q = 0; q < nb; q += 2) {
+        if (q + 1 < nb) {
+            P1 = P0;
+            batch_next(d.g, P1);
+            issue_labels<T>(vol, d.g, P1, lane, L1);
+        }
+        count_process<T, MODE>(d, P0, L0, lane, gt0, s_wc);
+        if (q + 1 >= nb) break;
+        if (q + 2 < nb) {
+            P0 = P1;
+            batch_next(d.g, P0);
+            issue_labels<T>(vol, d.g, P0, lane, L0);
+        }
+        count_process<T, MODE>(d, P1, L1, lane, gt0, s_wc);
     }
 }
 
+// Exclusive prefixes of tile t for the three counts, by one whole wave: lane L
+// inspects tile top-L of each count's window.  Tiles before `first` (the
+// volume's first tile) read as an inclusive prefix of zero.  A count waits
+// only while a tile at or after its nearest inclusive prefix has not yet
+// published an aggregate; the nearest such tile was handed out before t, so
+// its workgroup is running and publishes without waiting on anything.
+__device__ void look_back3(const uint64_t *status, int64_t t, int64_t first, int lane,
+                           int64_t excl[3])
+{
+    int64_t top[3] = {t - 1, t - 1, t - 1};
+    bool done[3] = {false, false, false};
+    excl[0] = excl[1] = excl[2] = 0;
+    while (!(done[0] && done[1] && done[2])) {
+        uint64_t s[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const int64_t p = top[c] - lane;
+            s[c] = kFlagPrefix;
+            if (!done[c] && p >= first)
+                s[c] = __hip_atomic_load(status + 3 * p + c, __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_AGENT);
+        }
+        bool stalled = false;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            if (done[c]) continue;
+            const uint64_t flag = s[c] & ~kValMask;
+            const uint64_t pm = __ballot(flag == kFlagPrefix);
+            const uint64_t zm = __ballot(flag == 0);
+            const int lp = pm ? __builtin_ctzll(pm) : 64;
+            const uint64_t upto = lp >= 63 ? ~0ull : ((2ull << lp) - 1);
+            if (zm & upto) {
+                stalled = true;
+                continue;
+            }
+            excl[c] += wave_sum(lane <= lp ? (int64_t)(s[c] & kValMask) : 0);
+            if (pm)
+                done[c] = true;
+            else
+                top[c] -= 64;
+        }
+        if (stalled) __builtin_amdgcn_s_sleep(1);
+    }
+}
+
+template <typename T, int MODE>
 __global__ __launch_bounds__(kBlock) void k_count(const VolDesc *__restrict__ descs,
                                                   const int64_t *__restrict__ tile_prefix,
-                                                  int32_t nvol, int32_t rpw, uint64_t *status,
-                                                  uint32_t *ticket, int64_t *totals)
+                                                  int32_t nvol, int64_t tile_base, int32_t bpw,
+                                                  uint64_t *status, uint32_t *ticket,
+                                                  int64_t *totals)
 {
     __shared__ int64_t s_tile;
-    __shared__ int64_t s_cnt[3][kWavesPerBlock * kMaxRowsPerWave];
+    __shared__ int32_t s_wc[3][kMaxTileWords];
     __shared__ int64_t s_excl[3];
-    if (threadIdx.x == 0) s_tile = (int64_t)atomicAdd(ticket, 1u);
+    if (threadIdx.x == 0) s_tile = tile_base + (int64_t)atomicAdd(ticket, 1u);
     __syncthreads();
-    const int64_t t = s_tile;  // tiles are taken in launch order: predecessors are running
+    const int64_t t = s_tile;  // tiles are handed out in order: predecessors are running
     const int v = find_seg(tile_prefix, nvol, t);
     const VolDesc &d = descs[v];
-    const int TR = kWavesPerBlock * rpw;
-    const int64_t r0 = (t - tile_prefix[v]) * TR;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    for (int q = 0; q < rpw; ++q) {
-        const int lr = wave + kWavesPerBlock * q;
-        const int64_t r = r0 + lr;
-        int64_t cnt[3] = {0, 0, 0};
-        if (r < d.g.R) count_row_dispatch(d, r, lane, cnt);
+    const int64_t first = tile_prefix[v];
+    const int64_t nbv = d.g.R * d.g.NB;  // batches of this volume
+    const int TB = kWavesPerBlock * bpw;
+    const int64_t bt0 = (t - first) * TB;
+    const int64_t bt1 = bt0 + TB < nbv ? bt0 + TB : nbv;
+    const BatchPos pfirst = batch_pos(d.g, bt0), plast = batch_pos(d.g, bt1 - 1);
+    const int64_t gt0 = pfirst.g0;
+    const int32_t ntw = (int32_t)(plast.g0 + plast.nw - gt0);  // words in this tile
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    {
+        const int64_t b0 = bt0 + (int64_t)wave * bpw;
+        const int64_t nb = bt1 - b0 < bpw ? bt1 - b0 : bpw;
+        if (nb > 0) count_stream<T, MODE>(d, b0, (int)nb, lane, gt0, s_wc);
+    }
+    __syncthreads();
+    if (wave == 0) {
+        int64_t agg[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            int64_t x = 0;
+            for (int32_t i = lane; i < ntw; i += 64) x += s_wc[c][i];
+            agg[c] = wave_sum(x);
+            if (lane == 0)
+                __hip_atomic_store(status + 3 * t + c,
+                                   (t == first ? kFlagPrefix : kFlagAgg) | (uint64_t)agg[c],
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        int64_t excl[3] = {0, 0, 0};
+        if (t != first) {
+            look_back3(status, t, first, lane, excl);
+            if (lane == 0)
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+                    __hip_atomic_store(status + 3 * t + c, kFlagPrefix | (uint64_t)(excl[c] + agg[c]),
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
         if (lane == 0) {
-            s_cnt[0][lr] = cnt[0];
-            s_cnt[1][lr] = cnt[1];
-            s_cnt[2][lr] = cnt[2];
-        }
-    }
-    __syncthreads();
-    if (threadIdx.x < 3) {
-        // single-pass scan with decoupled look-back, one lane per component
-        const int comp = threadIdx.x;
-        int64_t agg = 0;
-        for (int lr = 0; lr < TR; ++lr) agg += s_cnt[comp][lr];
-        uint64_t *mine = status + 3 * t + comp;
-        int64_t excl = 0;
-        if (t == tile_prefix[v]) {
-            __hip_atomic_store(mine, kFlagPrefix | (uint64_t)agg, __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            __hip_atomic_store(mine, kFlagAgg | (uint64_t)agg, __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
-            int64_t p = t - 1;
-            while (true) {
-                const uint64_t s = __hip_atomic_load(status + 3 * p + comp, __ATOMIC_RELAXED,
-                                                     __HIP_MEMORY_SCOPE_AGENT);
-                const uint64_t flag = s & ~kValMask;
-                if (flag == 0) {
-                    __builtin_amdgcn_s_sleep(1);
-                    continue;
-                }
-                excl += (int64_t)(s & kValMask);
-                if (flag == kFlagPrefix) break;
-                --p;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                s_excl[c] = excl[c];
+                if (t == tile_prefix[v + 1] - 1) totals[3 * v + c] = excl[c] + agg[c];
             }
-            __hip_atomic_store(mine, kFlagPrefix | (uint64_t)(excl + agg), __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
         }
-        s_excl[comp] = excl;
     }
     __syncthreads();
-    if (threadIdx.x < 3) {
-        const int comp = threadIdx.x;
-        int64_t *base = comp == 0 ? d.baseP : (comp == 1 ? d.baseQ : d.baseS);
-        int64_t run = s_excl[comp];
-        for (int lr = 0; lr < TR; ++lr) {
-            const int64_t r = r0 + lr;
-            if (r >= d.g.R) break;
-            base[r] = run;
-            run += s_cnt[comp][lr];
+    // per-word bases: tile prefix + exclusive scan of the tile's word counts
+    if (wave < 3) {
+        const int c = wave;
+        SN_GLOBAL int32_t *wb = glb(c == 0 ? d.wbP : (c == 1 ? d.wbQ : d.wbS));
+        constexpr int PER = kMaxTileWords / 64;
+        int64_t loc[PER];
+        int64_t sum = 0;
+#pragma unroll
+        for (int m = 0; m < PER; ++m) {
+            const int32_t i = lane * PER + m;
+            loc[m] = sum;
+            sum += i < ntw ? s_wc[c][i] : 0;
         }
-        if (t == tile_prefix[v + 1] - 1) {
-            base[d.g.R] = run;
-            totals[3 * v + comp] = run;
+        const int64_t base = s_excl[c] + wave_excl_scan(sum, lane);
+#pragma unroll
+        for (int m = 0; m < PER; ++m) {
+            const int32_t i = lane * PER + m;
+            if (i < ntw) wb[gt0 + i] = (int32_t)(base + loc[m]);
         }
     }
 }
@@ -242,166 +442,275 @@ __global__ __launch_bounds__(kBlock) void k_count(const VolDesc *__restrict__ de
 // k_generate
 // ---------------------------------------------------------------------------
 
-template <typename T, int MODE>
-__device__ void generate_row(const VolDesc &d, int64_t r, int lane)
+template <typename T> struct Pair;
+template <> struct Pair<uint8_t> { using type = uint16_t; static constexpr int sh = 8; };
+template <> struct Pair<uint16_t> { using type = uint32_t; static constexpr int sh = 16; };
+template <> struct Pair<uint32_t> { using type = uint64_t; static constexpr int sh = 32; };
+
+template <typename T>
+__device__ __forceinline__ void store_pair(void *pairs, int32_t q, uint32_t front, uint32_t back)
+{
+    using P = typename Pair<T>::type;
+    glb(static_cast<P *>(pairs))[q] = (P)(T)front | ((P)(T)back << Pair<T>::sh);
+}
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+
+// One point's world coordinates (three consecutive floats).
+__device__ __forceinline__ void store_point(SN_GLOBAL float *points, int32_t id, float x, float y,
+                                            float z)
+{
+    SN_GLOBAL float *p = points + 3 * (int64_t)id;
+    p[0] = x, p[1] = y, p[2] = z;
+}
+
+// Word data of the own row and its five neighbour rows for one batch, loaded
+// into lanes with one vector load each: lane l < 24 holds the first point id
+// of word (l & 3) of row n = l >> 2 (own, -y, +y, -z, +z, -y-z), lanes 4..23
+// also that word's point bits; lanes u < kU hold the own word's first quad
+// and stencil index.  Read back with readlane.
+struct GenAux {
+    int32_t wbp;
+    uint64_t pmn;
+    int32_t wbq, wbs;
+};
+
+__device__ __forceinline__ void issue_gen_aux(const VolDesc &d, const BatchPos &bp, int lane,
+                                              GenAux &A)
 {
     const Geom &g = d.g;
-    const T *vol = static_cast<const T *>(d.labels);
-    T *pairs = static_cast<T *>(d.pairs);
-    const int64_t j = r % g.CN, k = r / g.CN;
-    const int32_t W = g.W;
-    const bool ym = j >= 1, yp = j + 1 <= g.CN - 1, zm = k >= 1, zp = k + 1 <= g.CO - 1;
-    // running bases: point id of the next point in each of the six rows used
-    int64_t b0 = d.baseP[r];
-    int64_t bym = ym ? d.baseP[r - 1] : 0, byp = yp ? d.baseP[r + 1] : 0;
-    int64_t bzm = zm ? d.baseP[r - g.CN] : 0, bzp = zp ? d.baseP[r + g.CN] : 0;
-    int64_t bmm = (ym && zm) ? d.baseP[r - g.CN - 1] : 0;
-    int64_t bq = d.baseQ[r], bs = d.baseS[r];
-    const uint64_t *wym = d.pmask + (r - 1) * W, *wyp = d.pmask + (r + 1) * W;
-    const uint64_t *wzm = d.pmask + (r - g.CN) * W, *wzp = d.pmask + (r + g.CN) * W;
-    const uint64_t *wmm = d.pmask + (r - g.CN - 1) * W;
-    const double ox = d.origin[0], oy = d.origin[1], oz = d.origin[2];
-    const double hx = d.spacing[0], hy = d.spacing[1], hz = d.spacing[2];
-    const float py = (float)(oy + hy * ((double)j + 0.5));
-    const float pz = (float)(oz + hz * ((double)k + 0.5));
-    for (int32_t w = 0; w < W; ++w) {
-        const int64_t i = 64 * (int64_t)w + lane;
-        const bool valid = i < g.CM;
-        uint32_t c[8];
-        load_corners<T, MODE>(vol, g, d.cs, i, j, k, lane, c);
-        const CellPred p = predicates(c, valid, i, j, k, g);
-        const uint64_t bp = wave_ballot(p.point);
-        const uint64_t mym = ym ? wym[w] : 0ull, myp = yp ? wyp[w] : 0ull;
-        const uint64_t mzm = zm ? wzm[w] : 0ull, mzp = zp ? wzp[w] : 0ull;
-        const uint64_t mmm = (ym && zm) ? wmm[w] : 0ull;
-        const int64_t R0 = b0 + rank_below(bp);
-        const int64_t Rym = bym + rank_below(mym), Ryp = byp + rank_below(myp);
-        const int64_t Rzm = bzm + rank_below(mzm), Rzp = bzp + rank_below(mzp);
-        const int64_t Rmm = bmm + rank_below(mmm);
-        uint64_t fb[6];
-        uint32_t sp = 0;
-        int64_t stot = 0;
-#pragma unroll
-        for (int f = 0; f < 6; ++f) {
-            fb[f] = wave_ballot((p.fmask >> f) & 1u);
-            sp += rank_below(fb[f]);
-            stot += __popcll(fb[f]);
-        }
-        const uint64_t bqx = wave_ballot(p.qx), bqy = wave_ballot(p.qy), bqz = wave_ballot(p.qz);
-        if (p.point) {
-            const int64_t id = R0;
-            float *pt = d.points + 3 * id;
-            pt[0] = (float)(ox + hx * ((double)i + 0.5));
-            pt[1] = py;
-            pt[2] = pz;
-            d.faces[id] = (uint8_t)p.fmask;
-            int64_t s = bs + sp;
-            d.st_off[id] = (int32_t)s;
-            int32_t *ids = d.st_ids;
-            if (p.fmask & 1u) ids[s++] = (int32_t)(R0 - 1);
-            if (p.fmask & 2u) ids[s++] = (int32_t)(R0 + 1);
-            if (p.fmask & 4u) ids[s++] = (int32_t)Rym;
-            if (p.fmask & 8u) ids[s++] = (int32_t)Ryp;
-            if (p.fmask & 16u) ids[s++] = (int32_t)Rzm;
-            if (p.fmask & 32u) ids[s++] = (int32_t)Rzp;
-        }
-        int64_t q = bq + rank_below(bqx) + rank_below(bqy) + rank_below(bqz);
-        if (p.qx) {
-            int32_t *o = d.quads + 4 * q;
-            o[0] = (int32_t)Rmm, o[1] = (int32_t)Rym, o[2] = (int32_t)R0, o[3] = (int32_t)Rzm;
-            pairs[2 * q] = (T)c[0], pairs[2 * q + 1] = (T)c[1];
-            ++q;
-        }
-        if (p.qy) {
-            int32_t *o = d.quads + 4 * q;
-            o[0] = (int32_t)(Rzm - 1), o[1] = (int32_t)Rzm, o[2] = (int32_t)R0,
-            o[3] = (int32_t)(R0 - 1);
-            pairs[2 * q] = (T)c[0], pairs[2 * q + 1] = (T)c[2];
-            ++q;
-        }
-        if (p.qz) {
-            int32_t *o = d.quads + 4 * q;
-            o[0] = (int32_t)(Rym - 1), o[1] = (int32_t)(R0 - 1), o[2] = (int32_t)R0,
-            o[3] = (int32_t)Rym;
-            pairs[2 * q] = (T)c[0], pairs[2 * q + 1] = (T)c[4];
-        }
-        b0 += __popcll(bp);
-        bym += __popcll(mym), byp += __popcll(myp);
-        bzm += __popcll(mzm), bzp += __popcll(mzp), bmm += __popcll(mmm);
-        bq += __popcll(bqx) + __popcll(bqy) + __popcll(bqz);
-        bs += stot;
+    A.wbp = 0, A.pmn = 0, A.wbq = 0, A.wbs = 0;
+    const int n = lane >> 2, u = lane & 3;
+    const bool ym = bp.j >= 1, yp = bp.j + 1 <= g.CN - 1, zm = bp.k >= 1, zp = bp.k + 1 <= g.CO - 1;
+    bool ok = lane < 24 && u < bp.nw;
+    int64_t dr = 0;
+    if (n == 1) ok = ok && ym, dr = -1;
+    if (n == 2) ok = ok && yp, dr = 1;
+    if (n == 3) ok = ok && zm, dr = -g.CN;
+    if (n == 4) ok = ok && zp, dr = g.CN;
+    if (n == 5) ok = ok && ym && zm, dr = -g.CN - 1;
+    if (ok) {
+        const int64_t gw = (bp.r + dr) * g.W + bp.w0 + u;
+        A.wbp = glb(d.wbP)[gw];
+        if (n >= 1) A.pmn = glb(d.pmask)[gw];
+    }
+    if (lane < bp.nw) {
+        A.wbq = glb(d.wbQ)[bp.g0 + lane];
+        A.wbs = glb(d.wbS)[bp.g0 + lane];
     }
 }
 
-__device__ void generate_row_dispatch(const VolDesc &d, int64_t r, int lane)
+__device__ __forceinline__ uint64_t readlane64(uint64_t x, int l)
 {
-    const int m = d.cs.mode;
-    if (d.dtype == 1) {
-        if (m == CLS_IDENT) generate_row<uint8_t, CLS_IDENT>(d, r, lane);
-        else generate_row<uint8_t, CLS_BITMAP>(d, r, lane);
-    } else if (d.dtype == 2) {
-        if (m == CLS_IDENT) generate_row<uint16_t, CLS_IDENT>(d, r, lane);
-        else generate_row<uint16_t, CLS_BITMAP>(d, r, lane);
-    } else {
-        if (m == CLS_IDENT) generate_row<uint32_t, CLS_IDENT>(d, r, lane);
-        else generate_row<uint32_t, CLS_SORTED>(d, r, lane);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, l);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), l);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Outputs of one word (Sec. 2.3 pass 4): its points with their stencil face
+// masks, CSR offsets and neighbour ids, and the quads (with label pairs) of
+// the edges owned by its samples, at the scanned bases of the word.
+template <typename T, int U>
+__device__ __forceinline__ void generate_word(const VolDesc &d, const BatchPos &bp,
+                                              const uint32_t c[8], const GenAux &A, int lane)
+{
+    const int32_t w = bp.w0 + U;
+    const WordMasks m = word_masks(c, w, bp.j, bp.k, d.g);
+    if (m.pt == 0) return;
+    const uint64_t mym = readlane64(A.pmn, 4 + U), myp = readlane64(A.pmn, 8 + U);
+    const uint64_t mzm = readlane64(A.pmn, 12 + U), mzp = readlane64(A.pmn, 16 + U);
+    const uint64_t mmm = readlane64(A.pmn, 20 + U);
+    const int32_t R0 = __builtin_amdgcn_readlane(A.wbp, U) + (int32_t)rank_below(m.pt);
+    const int32_t Rym = __builtin_amdgcn_readlane(A.wbp, 4 + U) + (int32_t)rank_below(mym);
+    const int32_t Ryp = __builtin_amdgcn_readlane(A.wbp, 8 + U) + (int32_t)rank_below(myp);
+    const int32_t Rzm = __builtin_amdgcn_readlane(A.wbp, 12 + U) + (int32_t)rank_below(mzm);
+    const int32_t Rzp = __builtin_amdgcn_readlane(A.wbp, 16 + U) + (int32_t)rank_below(mzp);
+    const int32_t Rmm = __builtin_amdgcn_readlane(A.wbp, 20 + U) + (int32_t)rank_below(mmm);
+    uint32_t fm = 0;
+    int32_t sp = 0;
+#pragma unroll
+    for (int f = 0; f < 6; ++f) {
+        fm |= lane_bit(m.f[f], lane) << f;
+        sp += (int32_t)rank_below(m.f[f]);
+    }
+    if (lane_bit(m.pt, lane)) {
+        const int32_t i = 64 * w + lane;
+        store_point(glb(d.points), R0, (float)(d.origin[0] + d.spacing[0] * ((double)i + 0.5)),
+                    (float)(d.origin[1] + d.spacing[1] * ((double)bp.j + 0.5)),
+                    (float)(d.origin[2] + d.spacing[2] * ((double)bp.k + 0.5)));
+        glb(d.faces)[R0] = (uint8_t)fm;
+        int32_t s = __builtin_amdgcn_readlane(A.wbs, U) + sp;
+        glb(d.st_off)[R0] = s;
+        SN_GLOBAL int32_t *st_ids = glb(d.st_ids);
+        if (fm & 1u) st_ids[s++] = R0 - 1;
+        if (fm & 2u) st_ids[s++] = R0 + 1;
+        if (fm & 4u) st_ids[s++] = Rym;
+        if (fm & 8u) st_ids[s++] = Ryp;
+        if (fm & 16u) st_ids[s++] = Rzm;
+        if (fm & 32u) st_ids[s++] = Rzp;
+    }
+    SN_GLOBAL v4i *quads = glb(reinterpret_cast<v4i *>(d.quads));
+    int32_t q = __builtin_amdgcn_readlane(A.wbq, U) +
+                (int32_t)(rank_below(m.qx) + rank_below(m.qy) + rank_below(m.qz));
+    if (lane_bit(m.qx, lane)) {
+        quads[q] = v4i{Rmm, Rym, R0, Rzm};
+        store_pair<T>(d.pairs, q, c[0], c[1]);
+        ++q;
+    }
+    if (lane_bit(m.qy, lane)) {
+        quads[q] = v4i{Rzm - 1, Rzm, R0, R0 - 1};
+        store_pair<T>(d.pairs, q, c[0], c[2]);
+        ++q;
+    }
+    if (lane_bit(m.qz, lane)) {
+        quads[q] = v4i{Rym - 1, R0 - 1, R0, Rym};
+        store_pair<T>(d.pairs, q, c[0], c[4]);
     }
 }
 
+template <typename T, int MODE>
+__device__ __forceinline__ void generate_process(const VolDesc &d, const BatchPos &bp,
+                                                 const LabelLoads<T> &L, const GenAux &A, int lane)
+{
+    uint32_t c[kU][8];
+    corners<T, MODE>(L, d.cs, lane, c);
+    static_assert(kU == 4, "generate_process unrolls four words");
+    __builtin_amdgcn_sched_barrier(0);
+    generate_word<T, 0>(d, bp, c[0], A, lane);
+    if (bp.nw > 1) {
+        __builtin_amdgcn_sched_barrier(0);
+        generate_word<T, 1>(d, bp, c[1], A, lane);
+    }
+    if (bp.nw > 2) {
+        __builtin_amdgcn_sched_barrier(0);
+        generate_word<T, 2>(d, bp, c[2], A, lane);
+    }
+    if (bp.nw > 3) {
+        __builtin_amdgcn_sched_barrier(0);
+        generate_word<T, 3>(d, bp, c[3], A, lane);
+    }
+}
+
+// nb consecutive batches from b0, two in flight.
+template <typename T, int MODE>
+__device__ void generate_stream(const VolDesc &d, int64_t b0, int nb, int lane)
+{
+    const T *vol = static_cast<const T *>(d.labels);
+    LabelLoads<T> L0, L1;
+    GenAux A0, A1;
+    BatchPos P0 = batch_pos(d.g, b0), P1;
+    issue_labels<T>(vol, d.g, P0, lane, L0);
+    issue_gen_aux(d, P0, lane, A0);
+    for (int q = 0; q < nb; q += 2) {
+        if (q + 1 < nb) {
+            P1 = P0;
+            batch_next(d.g, P1);
+            issue_labels<T>(vol, d.g, P1, lane, L1);
+            issue_gen_aux(d, P1, lane, A1);
+        }
+        generate_process<T, MODE>(d, P0, L0, A0, lane);
+        if (q + 1 >= nb) break;
+        if (q + 2 < nb) {
+            P0 = P1;
+            batch_next(d.g, P0);
+            issue_labels<T>(vol, d.g, P0, lane, L0);
+            issue_gen_aux(d, P0, lane, A0);
+        }
+        generate_process<T, MODE>(d, P1, L1, A1, lane);
+    }
+}
+
+template <typename T, int MODE>
 __global__ __launch_bounds__(kBlock) void k_generate(const VolDesc *__restrict__ descs,
                                                      const int64_t *__restrict__ tile_prefix,
-                                                     int32_t nvol, int32_t rpw)
+                                                     int32_t nvol, int64_t tile_base, int32_t bpw)
 {
-    const int64_t t = blockIdx.x;
+    const int64_t t = tile_base + blockIdx.x;
     const int v = find_seg(tile_prefix, nvol, t);
     const VolDesc &d = descs[v];
-    const int64_t r0 = (t - tile_prefix[v]) * (kWavesPerBlock * rpw);
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    if (threadIdx.x == 0 && t == tile_prefix[v]) d.st_off[d.P] = (int32_t)d.S;
-    for (int q = 0; q < rpw; ++q) {
-        const int64_t r = r0 + wave + kWavesPerBlock * q;
-        if (r < d.g.R) generate_row_dispatch(d, r, lane);
-    }
+    const int64_t nbv = d.g.R * d.g.NB;
+    const int64_t bt0 = (t - tile_prefix[v]) * (kWavesPerBlock * bpw);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (threadIdx.x == 0 && t == tile_prefix[v]) glb(d.st_off)[d.P] = (int32_t)d.S;
+    const int64_t b0 = bt0 + (int64_t)wave * bpw;
+    const int64_t nb = nbv - b0 < bpw ? nbv - b0 : bpw;
+    if (nb > 0) generate_stream<T, MODE>(d, b0, (int)nb, lane);
 }
 
 // ---------------------------------------------------------------------------
 // k_emit: points = origin + spacing * (cell centre + offset)
 // ---------------------------------------------------------------------------
 
+// Own-word data of one batch in lanes u < kU: point bits and first point id.
+struct EmitAux {
+    uint64_t pm;
+    int32_t wbp;
+};
+
+__device__ __forceinline__ void issue_emit_aux(const VolDesc &d, const BatchPos &bp, int lane,
+                                               EmitAux &A)
+{
+    A.pm = 0, A.wbp = 0;
+    if (lane < bp.nw) {
+        A.pm = glb(d.pmask)[bp.g0 + lane];
+        A.wbp = glb(d.wbP)[bp.g0 + lane];
+    }
+}
+
+__device__ __forceinline__ void emit_process(const VolDesc &d, const BatchPos &bp, const EmitAux &A,
+                                             int lane)
+{
+    const SN_GLOBAL float *delta = d.delta ? glb(d.delta) : nullptr;
+    const double y0 = (double)bp.j + 0.5, z0 = (double)bp.k + 0.5;
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+        if (u >= bp.nw) break;
+        const uint64_t m = readlane64(A.pm, u);
+        if (!lane_bit(m, lane)) continue;
+        const int32_t id = __builtin_amdgcn_readlane(A.wbp, u) + (int32_t)rank_below(m);
+        double dx = 0.0, dy = 0.0, dz = 0.0;
+        if (delta) {
+            dx = (double)delta[3 * (int64_t)id];
+            dy = (double)delta[3 * (int64_t)id + 1];
+            dz = (double)delta[3 * (int64_t)id + 2];
+        }
+        const double x0 = (double)(64 * (bp.w0 + u) + lane) + 0.5;
+        store_point(glb(d.points), id, (float)(d.origin[0] + d.spacing[0] * (x0 + dx)),
+                    (float)(d.origin[1] + d.spacing[1] * (y0 + dy)),
+                    (float)(d.origin[2] + d.spacing[2] * (z0 + dz)));
+    }
+}
+
 __global__ __launch_bounds__(kBlock) void k_emit(const VolDesc *__restrict__ descs,
                                                  const int64_t *__restrict__ tile_prefix,
-                                                 int32_t nvol, int32_t rpw)
+                                                 int32_t nvol, int32_t bpw)
 {
     const int64_t t = blockIdx.x;
     const int v = find_seg(tile_prefix, nvol, t);
     const VolDesc &d = descs[v];
-    const Geom &g = d.g;
-    const int64_t r0 = (t - tile_prefix[v]) * (kWavesPerBlock * rpw);
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const float *delta = d.delta;
-    for (int q = 0; q < rpw; ++q) {
-        const int64_t r = r0 + wave + kWavesPerBlock * q;
-        if (r >= g.R) break;
-        const int64_t j = r % g.CN, k = r / g.CN;
-        int64_t b = d.baseP[r];
-        for (int32_t w = 0; w < g.W; ++w) {
-            const uint64_t m = d.pmask[r * g.W + w];
-            if (m == 0) continue;
-            if ((m >> lane) & 1ull) {
-                const int64_t id = b + rank_below(m);
-                double dx = 0.0, dy = 0.0, dz = 0.0;
-                if (delta) {
-                    dx = (double)delta[3 * id], dy = (double)delta[3 * id + 1];
-                    dz = (double)delta[3 * id + 2];
-                }
-                const int64_t i = 64 * (int64_t)w + lane;
-                float *pt = d.points + 3 * id;
-                pt[0] = (float)(d.origin[0] + d.spacing[0] * ((double)i + 0.5 + dx));
-                pt[1] = (float)(d.origin[1] + d.spacing[1] * ((double)j + 0.5 + dy));
-                pt[2] = (float)(d.origin[2] + d.spacing[2] * ((double)k + 0.5 + dz));
-            }
-            b += __popcll(m);
+    const int64_t nbv = d.g.R * d.g.NB;
+    const int64_t bt0 = (t - tile_prefix[v]) * (kWavesPerBlock * bpw);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int64_t b0 = bt0 + (int64_t)wave * bpw;
+    const int64_t nb = nbv - b0 < bpw ? nbv - b0 : bpw;
+    if (nb <= 0) return;
+    EmitAux A0, A1;
+    BatchPos P0 = batch_pos(d.g, b0), P1;
+    issue_emit_aux(d, P0, lane, A0);
+    for (int q = 0; q < nb; q += 2) {
+        if (q + 1 < nb) {
+            P1 = P0;
+            batch_next(d.g, P1);
+            issue_emit_aux(d, P1, lane, A1);
         }
+        emit_process(d, P0, A0, lane);
+        if (q + 1 >= nb) break;
+        if (q + 2 < nb) {
+            P0 = P1;
+            batch_next(d.g, P0);
+            issue_emit_aux(d, P0, lane, A0);
+        }
+        emit_process(d, P1, A1, lane);
     }
 }
 
@@ -419,22 +728,23 @@ __global__ __launch_bounds__(256) void k_jacobi(const SmoothDesc *__restrict__ s
     if (it >= s.iters) return;  // this mesh has finished its sweeps
     const int64_t p = (b - block_prefix[v]) * 256 + threadIdx.x;
     if (p >= s.P) return;
-    const float *din = (it & 1) ? s.db : s.da;
-    float *dout = (it & 1) ? s.da : s.db;
+    const SN_GLOBAL float *din = glb((it & 1) ? s.db : s.da);
+    SN_GLOBAL float *dout = glb((it & 1) ? s.da : s.db);
     const bool zero_in = (it == 0);
-    const uint32_t f = s.faces[p];
+    const uint32_t f = glb(s.faces)[p];
     double x = 0.0, y = 0.0, z = 0.0;
     if (!zero_in) {
         x = (double)din[3 * p], y = (double)din[3 * p + 1], z = (double)din[3 * p + 2];
     }
     const int n = __popc(f);
     if (n > 0) {
+        const SN_GLOBAL int32_t *ids = glb(s.ids);
         double sx = 0.0, sy = 0.0, sz = 0.0;
-        int64_t e = s.off[p];
+        int64_t e = glb(s.off)[p];
 #pragma unroll
         for (int face = 0; face < 6; ++face) {
             if (!((f >> face) & 1u)) continue;
-            const int64_t q = s.ids[e++];
+            const int64_t q = ids[e++];
             double nx = 0.0, ny = 0.0, nz = 0.0;
             if (!zero_in) {
                 nx = (double)din[3 * q], ny = (double)din[3 * q + 1], nz = (double)din[3 * q + 2];
@@ -466,8 +776,8 @@ __global__ __launch_bounds__(256) void k_jacobi(const SmoothDesc *__restrict__ s
 template <typename T>
 __device__ __forceinline__ void tri_pairs(const VolDesc &d, int64_t q)
 {
-    const T *src = static_cast<const T *>(d.pairs);
-    T *dst = static_cast<T *>(d.tri_pairs);
+    const SN_GLOBAL T *src = glb(static_cast<const T *>(d.pairs));
+    SN_GLOBAL T *dst = glb(static_cast<T *>(d.tri_pairs));
     const T f = src[2 * q], b = src[2 * q + 1];
     dst[4 * q] = f, dst[4 * q + 1] = b, dst[4 * q + 2] = f, dst[4 * q + 3] = b;
 }
@@ -481,10 +791,9 @@ __global__ __launch_bounds__(256) void k_tri(const VolDesc *__restrict__ descs,
     const VolDesc &d = descs[v];
     const int64_t q = (b - block_prefix[v]) * 256 + threadIdx.x;
     if (q >= d.Q || d.prim != 3) return;
-    const int32_t *s = d.quads + 4 * q;
-    const int32_t A = s[0], B = s[1], C = s[2], D = s[3];
-    int32_t *o = d.tris + 6 * q;
-    o[0] = A, o[1] = B, o[2] = C, o[3] = A, o[4] = C, o[5] = D;
+    const v4i s = glb(reinterpret_cast<const v4i *>(d.quads))[q];
+    SN_GLOBAL int32_t *o = glb(d.tris) + 6 * q;
+    o[0] = s.x, o[1] = s.y, o[2] = s.z, o[3] = s.x, o[4] = s.z, o[5] = s.w;
     if (d.dtype == 1) tri_pairs<uint8_t>(d, q);
     else if (d.dtype == 2) tri_pairs<uint16_t>(d, q);
     else tri_pairs<uint32_t>(d, q);
@@ -494,31 +803,46 @@ __global__ __launch_bounds__(256) void k_tri(const VolDesc *__restrict__ descs,
 // launchers
 // ---------------------------------------------------------------------------
 
-hipError_t launch_count(const VolDesc *d_descs, const int64_t *d_tile_prefix, int32_t nvol,
-                        int64_t ntiles, int32_t rpw, uint64_t *d_status, uint32_t *d_ticket,
+// One instantiation per (label type, classification mode); every volume of a
+// launch has that key.
+#define SN_KEY_SWITCH(KERNEL, ...)                                                          \
+    switch (dtype * 4 + mode) {                                                             \
+    case 1 * 4 + CLS_IDENT: hipLaunchKernelGGL((KERNEL<uint8_t, CLS_IDENT>), __VA_ARGS__); break; \
+    case 1 * 4 + CLS_BITMAP: hipLaunchKernelGGL((KERNEL<uint8_t, CLS_BITMAP>), __VA_ARGS__); break; \
+    case 2 * 4 + CLS_IDENT: hipLaunchKernelGGL((KERNEL<uint16_t, CLS_IDENT>), __VA_ARGS__); break; \
+    case 2 * 4 + CLS_BITMAP: hipLaunchKernelGGL((KERNEL<uint16_t, CLS_BITMAP>), __VA_ARGS__); break; \
+    case 4 * 4 + CLS_IDENT: hipLaunchKernelGGL((KERNEL<uint32_t, CLS_IDENT>), __VA_ARGS__); break; \
+    case 4 * 4 + CLS_SORTED: hipLaunchKernelGGL((KERNEL<uint32_t, CLS_SORTED>), __VA_ARGS__); break; \
+    default: return hipErrorInvalidValue;                                                   \
+    }
+
+hipError_t launch_count(int32_t dtype, int32_t mode, const VolDesc *d_descs,
+                        const int64_t *d_tile_prefix, int32_t nvol, int64_t tile_base,
+                        int64_t ntiles, int32_t bpw, uint64_t *d_status, uint32_t *d_ticket,
                         int64_t *d_totals, hipStream_t s)
 {
     if (ntiles <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_count, dim3((uint32_t)ntiles), dim3(kBlock), 0, s, d_descs,
-                       d_tile_prefix, nvol, rpw, d_status, d_ticket, d_totals);
+    SN_KEY_SWITCH(k_count, dim3((uint32_t)ntiles), dim3(kBlock), 0, s, d_descs, d_tile_prefix, nvol,
+                  tile_base, bpw, d_status, d_ticket, d_totals)
     return hipGetLastError();
 }
 
-hipError_t launch_generate(const VolDesc *d_descs, const int64_t *d_tile_prefix, int32_t nvol,
-                           int64_t ntiles, int32_t rpw, hipStream_t s)
+hipError_t launch_generate(int32_t dtype, int32_t mode, const VolDesc *d_descs,
+                           const int64_t *d_tile_prefix, int32_t nvol, int64_t tile_base,
+                           int64_t ntiles, int32_t bpw, hipStream_t s)
 {
     if (ntiles <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_generate, dim3((uint32_t)ntiles), dim3(kBlock), 0, s, d_descs,
-                       d_tile_prefix, nvol, rpw);
+    SN_KEY_SWITCH(k_generate, dim3((uint32_t)ntiles), dim3(kBlock), 0, s, d_descs, d_tile_prefix,
+                  nvol, tile_base, bpw)
     return hipGetLastError();
 }
 
 hipError_t launch_emit(const VolDesc *d_descs, const int64_t *d_tile_prefix, int32_t nvol,
-                       int64_t ntiles, int32_t rpw, hipStream_t s)
+                       int64_t ntiles, int32_t bpw, hipStream_t s)
 {
     if (ntiles <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_emit, dim3((uint32_t)ntiles), dim3(kBlock), 0, s, d_descs, d_tile_prefix,
-                       nvol, rpw);
+                       nvol, bpw);
     return hipGetLastError();
 }
 

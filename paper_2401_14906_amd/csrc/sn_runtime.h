@@ -71,12 +71,12 @@ struct sn_ctx {
     std::mutex prof_mu;
     std::vector<ProfEv> prof_pending;
     std::map<std::string, std::pair<int64_t, double>> prof_stats;
-    // schedule table: size class -> rows per wave
+    // schedule table: size class -> batches per wave
     mutable std::mutex tune_mu;
     std::map<std::string, int32_t> tune;
     std::string tune_path;
-    int32_t forced_rpw = 0;
-    int32_t rows_per_wave(const std::string &cls) const;
+    int32_t forced_bpw = 0;
+    int32_t batches_per_wave(const std::string &cls) const;
     void load_tune_cache();
     void save_tune_cache() const;
 };
@@ -86,7 +86,7 @@ struct sn_mesh {
     sn_ctx *ctx = nullptr;
     sn::VolDesc d{};            // host copy (device pointers inside)
     int64_t P = 0, Q = 0, S = 0, voxels = 0, ntiles = 0;
-    int32_t rpw = 2;
+    int32_t bpw = 2;
     std::vector<void *> blocks;  // every device block owned by the mesh
     float *da = nullptr, *db = nullptr;
     const float *final_delta = nullptr;
@@ -116,7 +116,7 @@ sn_status validate_smooth(const sn_smooth_params *p);
 Geom make_geom(const sn_volume &v);
 std::string size_class(const sn_volume &v);
 sn_status extract_many(sn_ctx *c, const sn_volume *vols, int32_t n, hipStream_t s,
-                       int32_t rpw_override, sn_mesh **out);
+                       int32_t bpw_override, sn_mesh **out);
 sn_status smooth_many(sn_ctx *c, sn_mesh **ms, const sn_smooth_params *pv, int32_t n,
                       hipStream_t s);
 sn_status ensure_smooth_buffers(sn_mesh *m);

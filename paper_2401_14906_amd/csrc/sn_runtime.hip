@@ -319,11 +319,11 @@ extern "C" sn_status sn_profile_read(sn_ctx *c, sn_kernel_stat *out, int32_t cap
     return SN_OK;
 }
 
-// ---- schedule table ----------------------------------------------------------
+// ---- schedule table (size class -> batches per wave) ----------------------------------------------------------
 
 std::string sn::size_class(const sn_volume &v)
 {
-    // rows-per-wave matters through the number of rows and their length
+    // the schedule matters through the number of rows and their length
     const int64_t M = v.dims[0], R = std::max<int64_t>(1, (v.dims[1] - 1) * (v.dims[2] - 1));
     int lm = 0, lr = 0;
     while ((int64_t(1) << (lm + 1)) <= M) ++lm;
@@ -333,10 +333,10 @@ std::string sn::size_class(const sn_volume &v)
     return os.str();
 }
 
-int32_t sn_ctx::rows_per_wave(const std::string &cls) const
+int32_t sn_ctx::batches_per_wave(const std::string &cls) const
 {
     std::lock_guard<std::mutex> g(tune_mu);
-    if (forced_rpw > 0) return forced_rpw;
+    if (forced_bpw > 0) return forced_bpw;
     auto it = tune.find(cls);
     if (it != tune.end()) return it->second;
     return 2;
@@ -346,7 +346,7 @@ void sn_ctx::load_tune_cache()
 {
     std::ifstream f(tune_path);
     if (!f) return;
-    // flat JSON object {"class": rpw, ...}
+    // flat JSON object {"class": batches_per_wave, ...}
     std::string s((std::istreambuf_iterator<char>(f)), std::istreambuf_iterator<char>());
     size_t p = 0;
     while ((p = s.find('"', p)) != std::string::npos) {
@@ -356,7 +356,7 @@ void sn_ctx::load_tune_cache()
         size_t colon = s.find(':', q);
         if (colon == std::string::npos) break;
         int v = std::atoi(s.c_str() + colon + 1);
-        if (v >= 1 && v <= kMaxRowsPerWave) tune[key] = v;
+        if (v >= 1 && v <= kMaxBatchesPerWave) tune[key] = v;
         p = colon + 1;
     }
 }
@@ -389,9 +389,9 @@ sn_status sn::validate_volume(const sn_volume *v)
             return fail(SN_EINVAL, "spacing must be positive and finite");
         if (!std::isfinite(v->origin[a])) return fail(SN_EINVAL, "origin must be finite");
     }
-    if (v->dims[0] > (int64_t(1) << 31) || v->dims[1] > (int64_t(1) << 31) ||
-        v->dims[2] > (int64_t(1) << 31))
-        return fail(SN_ETOOBIG, "a dimension exceeds 2^31");
+    if (v->dims[0] > (int64_t(1) << 30) || v->dims[1] > (int64_t(1) << 30) ||
+        v->dims[2] > (int64_t(1) << 30))
+        return fail(SN_ETOOBIG, "a dimension exceeds 2^30");
     if (v->prim != SN_QUADS && v->prim != SN_TRIS) return fail(SN_EINVAL, "prim must be SN_QUADS or SN_TRIS");
     const uint64_t vmax = v->dtype == 4 ? 0xFFFFFFFFull : ((1ull << (8 * v->dtype)) - 1);
     if (v->background > vmax) return fail(SN_EINVAL, "background does not fit the dtype");
@@ -404,6 +404,12 @@ sn_status sn::validate_volume(const sn_volume *v)
     }
     const bool empty = v->dims[0] < 2 || v->dims[1] < 2 || v->dims[2] < 2;
     if (!v->labels && !empty) return fail(SN_EINVAL, "labels is NULL");
+    {
+        // the kernels index rows, words and batches of one volume with int32
+        const Geom g = make_geom(*v);
+        if (g.R * g.W >= INT32_MAX || g.R * g.NB >= INT32_MAX)
+            return fail(SN_ETOOBIG, "volume has more than 2^31 cell words");
+    }
     return SN_OK;
 }
 
@@ -417,6 +423,7 @@ Geom sn::make_geom(const sn_volume &v)
     g.CO = empty ? 0 : g.O - 1;
     g.R = g.CN * g.CO;
     g.W = (int32_t)((g.CM + 63) / 64);
+    g.NB = (g.W + kU - 1) / kU;
     return g;
 }
 
@@ -570,7 +577,7 @@ T *dalloc(sn_mesh *m, int64_t count)
 }  // namespace
 
 sn_status sn::extract_many(sn_ctx *c, const sn_volume *vols, int32_t n, hipStream_t s,
-                           int32_t rpw_override, sn_mesh **out)
+                           int32_t bpw_override, sn_mesh **out)
 {
     if (!c || !vols || !out || n < 1) return fail(SN_EINVAL, "extract: bad arguments");
     for (int32_t v = 0; v < n; ++v) {
@@ -579,7 +586,9 @@ sn_status sn::extract_many(sn_ctx *c, const sn_volume *vols, int32_t n, hipStrea
     }
     HIP_TRY(hipSetDevice(c->device));
     std::vector<sn_mesh *> meshes(n, nullptr);
+    Scratch scr(c);
     auto cleanup = [&](sn_status st) {
+        scr.retire(s);
         for (auto *m : meshes)
             if (m) {
                 m->ctx->pool.release_all(m->blocks, s);
@@ -588,7 +597,6 @@ sn_status sn::extract_many(sn_ctx *c, const sn_volume *vols, int32_t n, hipStrea
             }
         return st;
     };
-    Scratch scr(c);
     // one schedule for the launch: the one tuned for the largest volume
     int64_t big = 0;
     int32_t vb = 0;
@@ -596,16 +604,29 @@ sn_status sn::extract_many(sn_ctx *c, const sn_volume *vols, int32_t n, hipStrea
         const int64_t vox = vols[v].dims[0] * vols[v].dims[1] * vols[v].dims[2];
         if (vox > big) big = vox, vb = v;
     }
-    const int32_t rpw = rpw_override > 0 ? rpw_override : c->rows_per_wave(size_class(vols[vb]));
-    const int TR = kWavesPerBlock * rpw;
+    const int32_t bpw = bpw_override > 0 ? bpw_override : c->batches_per_wave(size_class(vols[vb]));
+    const int TB = kWavesPerBlock * bpw;
+
+    // Volumes are processed grouped by (label type, classification mode): one
+    // kernel instantiation per group.  Position k of the launch arrays holds
+    // volume order[k].
+    std::vector<int32_t> mode(n), order(n);
+    std::vector<std::vector<uint32_t>> tabs(n);
+    for (int32_t v = 0; v < n; ++v) {
+        class_table(vols[v], &mode[v], &tabs[v]);
+        order[v] = v;
+    }
+    auto key = [&](int32_t v) { return vols[v].dtype * 4 + mode[v]; };
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return key(a) < key(b); });
 
     std::vector<int64_t> tile_prefix(n + 1, 0);
-    for (int32_t v = 0; v < n; ++v) {
+    for (int32_t k = 0; k < n; ++k) {
+        const int32_t v = order[k];
         const sn_volume &vol = vols[v];
         sn_mesh *m = new sn_mesh();
         meshes[v] = m;
         m->ctx = c;
-        m->rpw = rpw;
+        m->bpw = bpw;
         VolDesc &d = m->d;
         std::memset(&d, 0, sizeof d);
         d.labels = vol.labels;
@@ -613,34 +634,38 @@ sn_status sn::extract_many(sn_ctx *c, const sn_volume *vols, int32_t n, hipStrea
         d.prim = vol.prim;
         d.g = make_geom(vol);
         for (int a = 0; a < 3; ++a) d.origin[a] = vol.origin[a], d.spacing[a] = vol.spacing[a];
-        std::vector<uint32_t> tab;
-        class_table(vol, &d.cs.mode, &tab);
+        d.cs.mode = mode[v];
         d.cs.bg = vol.background;
-        d.cs.n = (int32_t)tab.size();
-        if (!tab.empty()) {
-            uint32_t *t = dalloc<uint32_t>(m, (int64_t)tab.size());
-            uint32_t *ht = static_cast<uint32_t *>(scr.h(sizeof(uint32_t) * tab.size()));
-            if (!t || !ht) {
-                scr.retire(s);
-                return cleanup(fail(SN_ENOMEM, "extract: classification table"));
-            }
-            std::memcpy(ht, tab.data(), sizeof(uint32_t) * tab.size());
-            HIP_TRY(hipMemcpyAsync(t, ht, sizeof(uint32_t) * tab.size(), hipMemcpyHostToDevice, s));
+        d.cs.n = (int32_t)tabs[v].size();
+        if (!tabs[v].empty()) {
+            const size_t nb = sizeof(uint32_t) * tabs[v].size();
+            uint32_t *t = dalloc<uint32_t>(m, (int64_t)tabs[v].size());
+            uint32_t *ht = static_cast<uint32_t *>(scr.h(nb));
+            if (!t || !ht) return cleanup(fail(SN_ENOMEM, "extract: classification table"));
+            std::memcpy(ht, tabs[v].data(), nb);
+            HIP_TRY(hipMemcpyAsync(t, ht, nb, hipMemcpyHostToDevice, s));
             d.cs.table = t;
         }
-        const int64_t R = d.g.R;
-        d.pmask = dalloc<uint64_t>(m, R * d.g.W);
-        d.baseP = dalloc<int64_t>(m, R + 1);
-        d.baseQ = dalloc<int64_t>(m, R + 1);
-        d.baseS = dalloc<int64_t>(m, R + 1);
-        if (!d.pmask || !d.baseP || !d.baseQ || !d.baseS)
-            return cleanup(fail(SN_ENOMEM, "extract: row metadata"));
-        m->ntiles = (R + TR - 1) / TR;
-        tile_prefix[v + 1] = tile_prefix[v] + m->ntiles;
+        const int64_t words = d.g.R * d.g.W;
+        d.pmask = dalloc<uint64_t>(m, words);
+        d.wbP = dalloc<int32_t>(m, words);
+        d.wbQ = dalloc<int32_t>(m, words);
+        d.wbS = dalloc<int32_t>(m, words);
+        if (!d.pmask || !d.wbP || !d.wbQ || !d.wbS)
+            return cleanup(fail(SN_ENOMEM, "extract: word metadata"));
+        const int64_t nbatch = d.g.R * d.g.NB;
+        m->ntiles = (nbatch + TB - 1) / TB;
+        tile_prefix[k + 1] = tile_prefix[k] + m->ntiles;
         m->voxels = vol.dims[0] * vol.dims[1] * vol.dims[2];
     }
+    // groups: [gbeg[i], gbeg[i+1]) of the launch order share a key
+    std::vector<int32_t> gbeg;
+    for (int32_t k = 0; k < n; ++k)
+        if (k == 0 || key(order[k]) != key(order[k - 1])) gbeg.push_back(k);
+    gbeg.push_back(n);
+    const int32_t ngroups = (int32_t)gbeg.size() - 1;
+
     const int64_t ntiles = tile_prefix[n];
-    // device copies of descriptors, tile map and scan state
     VolDesc *h_desc = static_cast<VolDesc *>(scr.h(sizeof(VolDesc) * n));
     int64_t *h_tp = static_cast<int64_t *>(scr.h(sizeof(int64_t) * (n + 1)));
     int64_t *h_tot = static_cast<int64_t *>(scr.h(sizeof(int64_t) * 3 * n));
@@ -648,37 +673,38 @@ sn_status sn::extract_many(sn_ctx *c, const sn_volume *vols, int32_t n, hipStrea
     int64_t *d_tp = static_cast<int64_t *>(scr.d(sizeof(int64_t) * (n + 1)));
     int64_t *d_tot = static_cast<int64_t *>(scr.d(sizeof(int64_t) * 3 * n));
     const size_t status_bytes = sizeof(uint64_t) * 3 * (size_t)std::max<int64_t>(ntiles, 1);
-    uint8_t *d_status = static_cast<uint8_t *>(scr.d(status_bytes + 256));
-    if (!h_desc || !h_tp || !h_tot || !d_desc || !d_tp || !d_tot || !d_status) {
-        scr.retire(s);
+    const size_t ticket_bytes = sizeof(uint32_t) * (size_t)ngroups;
+    uint8_t *d_status = static_cast<uint8_t *>(scr.d(status_bytes + ticket_bytes));
+    if (!h_desc || !h_tp || !h_tot || !d_desc || !d_tp || !d_tot || !d_status)
         return cleanup(fail(SN_ENOMEM, "extract: scratch"));
-    }
-    for (int32_t v = 0; v < n; ++v) h_desc[v] = meshes[v]->d;
+    for (int32_t k = 0; k < n; ++k) h_desc[k] = meshes[order[k]]->d;
     std::memcpy(h_tp, tile_prefix.data(), sizeof(int64_t) * (n + 1));
-    std::memset(h_tot, 0, sizeof(int64_t) * 3 * n);
     HIP_TRY(hipMemcpyAsync(d_desc, h_desc, sizeof(VolDesc) * n, hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(d_tp, h_tp, sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemsetAsync(d_tot, 0, sizeof(int64_t) * 3 * n, s));
-    HIP_TRY(hipMemsetAsync(d_status, 0, status_bytes + 256, s));
+    HIP_TRY(hipMemsetAsync(d_status, 0, status_bytes + ticket_bytes, s));
     {
         ProfScope ps(c, "k_count", s);
-        HIP_TRY(launch_count(d_desc, d_tp, n, ntiles, rpw, reinterpret_cast<uint64_t *>(d_status),
-                             reinterpret_cast<uint32_t *>(d_status + status_bytes), d_tot, s));
+        for (int32_t gi = 0; gi < ngroups; ++gi) {
+            const int32_t k0 = gbeg[gi], k1 = gbeg[gi + 1];
+            const VolDesc &d0 = h_desc[k0];
+            HIP_TRY(launch_count(d0.dtype, d0.cs.mode, d_desc + k0, d_tp + k0, k1 - k0,
+                                 tile_prefix[k0], tile_prefix[k1] - tile_prefix[k0], bpw,
+                                 reinterpret_cast<uint64_t *>(d_status),
+                                 reinterpret_cast<uint32_t *>(d_status + status_bytes) + gi,
+                                 d_tot + 3 * k0, s));
+        }
     }
     HIP_TRY(hipMemcpyAsync(h_tot, d_tot, sizeof(int64_t) * 3 * n, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
 
     // exact allocation of every output (Sec. 2.3: no incremental allocation)
-    int64_t qblocks = 0;
-    std::vector<int64_t> qprefix(n + 1, 0);
-    for (int32_t v = 0; v < n; ++v) {
-        sn_mesh *m = meshes[v];
+    for (int32_t k = 0; k < n; ++k) {
+        sn_mesh *m = meshes[order[k]];
         VolDesc &d = m->d;
-        m->P = h_tot[3 * v], m->Q = h_tot[3 * v + 1], m->S = h_tot[3 * v + 2];
-        if (m->P >= INT32_MAX || m->Q >= INT32_MAX / 2 || m->S >= INT32_MAX) {
-            scr.retire(s);
+        m->P = h_tot[3 * k], m->Q = h_tot[3 * k + 1], m->S = h_tot[3 * k + 2];
+        if (m->P >= INT32_MAX || m->Q >= INT32_MAX / 2 || m->S >= INT32_MAX)
             return cleanup(fail(SN_ETOOBIG, "extract: mesh indices exceed int32"));
-        }
         d.P = m->P, d.Q = m->Q, d.S = m->S;
         d.points = dalloc<float>(m, 3 * m->P);
         d.faces = dalloc<uint8_t>(m, m->P);
@@ -686,41 +712,40 @@ sn_status sn::extract_many(sn_ctx *c, const sn_volume *vols, int32_t n, hipStrea
         d.st_ids = dalloc<int32_t>(m, m->S);
         d.quads = dalloc<int32_t>(m, 4 * m->Q);
         d.pairs = dalloc<uint8_t>(m, 2 * m->Q * d.dtype);
-        if (!d.points || !d.faces || !d.st_off || !d.st_ids || !d.quads || !d.pairs) {
-            scr.retire(s);
+        if (!d.points || !d.faces || !d.st_off || !d.st_ids || !d.quads || !d.pairs)
             return cleanup(fail(SN_ENOMEM, "extract: outputs"));
-        }
         if (d.prim == SN_TRIS) {
             d.tris = dalloc<int32_t>(m, 6 * m->Q);
             d.tri_pairs = dalloc<uint8_t>(m, 4 * m->Q * d.dtype);
-            if (!d.tris || !d.tri_pairs) {
-                scr.retire(s);
-                return cleanup(fail(SN_ENOMEM, "extract: triangles"));
-            }
-            qblocks += (m->Q + 255) / 256;
+            if (!d.tris || !d.tri_pairs) return cleanup(fail(SN_ENOMEM, "extract: triangles"));
         }
-        qprefix[v + 1] = qblocks;
-        h_desc[v] = d;
+        h_desc[k] = d;
     }
     HIP_TRY(hipMemcpyAsync(d_desc, h_desc, sizeof(VolDesc) * n, hipMemcpyHostToDevice, s));
-    for (int32_t v = 0; v < n; ++v)  // volumes without cell rows still get st_off[0] = 0
-        if (meshes[v]->ntiles == 0) HIP_TRY(hipMemsetAsync(meshes[v]->d.st_off, 0, sizeof(int32_t), s));
+    for (int32_t k = 0; k < n; ++k)  // volumes without cell rows still get st_off[0] = 0
+        if (meshes[order[k]]->ntiles == 0)
+            HIP_TRY(hipMemsetAsync(h_desc[k].st_off, 0, sizeof(int32_t), s));
     {
         ProfScope ps(c, "k_generate", s);
-        HIP_TRY(launch_generate(d_desc, d_tp, n, ntiles, rpw, s));
+        for (int32_t gi = 0; gi < ngroups; ++gi) {
+            const int32_t k0 = gbeg[gi], k1 = gbeg[gi + 1];
+            const VolDesc &d0 = h_desc[k0];
+            HIP_TRY(launch_generate(d0.dtype, d0.cs.mode, d_desc + k0, d_tp + k0, k1 - k0,
+                                    tile_prefix[k0], tile_prefix[k1] - tile_prefix[k0], bpw, s));
+        }
     }
+    int64_t qblocks = 0;
+    for (int32_t k = 0; k < n; ++k)
+        if (h_desc[k].prim == SN_TRIS) qblocks += (h_desc[k].Q + 255) / 256;
     if (qblocks > 0) {
         int64_t *h_qp = static_cast<int64_t *>(scr.h(sizeof(int64_t) * (n + 1)));
         int64_t *d_qp = static_cast<int64_t *>(scr.d(sizeof(int64_t) * (n + 1)));
-        if (!h_qp || !d_qp) {
-            scr.retire(s);
-            return cleanup(fail(SN_ENOMEM, "extract: triangle scratch"));
-        }
+        if (!h_qp || !d_qp) return cleanup(fail(SN_ENOMEM, "extract: triangle scratch"));
         // volumes without triangles keep an empty block range
         int64_t acc = 0;
-        for (int32_t v = 0; v < n; ++v) {
-            h_qp[v] = acc;
-            if (meshes[v]->d.prim == SN_TRIS) acc += (meshes[v]->Q + 255) / 256;
+        for (int32_t k = 0; k < n; ++k) {
+            h_qp[k] = acc;
+            if (h_desc[k].prim == SN_TRIS) acc += (h_desc[k].Q + 255) / 256;
         }
         h_qp[n] = acc;
         HIP_TRY(hipMemcpyAsync(d_qp, h_qp, sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice, s));
@@ -728,30 +753,21 @@ sn_status sn::extract_many(sn_ctx *c, const sn_volume *vols, int32_t n, hipStrea
         HIP_TRY(launch_triangulate(d_desc, d_qp, n, acc, s));
     }
     // per-mesh device descriptors for later emit/smoothing launches
-    for (int32_t v = 0; v < n; ++v) {
-        sn_mesh *m = meshes[v];
+    for (int32_t k = 0; k < n; ++k) {
+        sn_mesh *m = meshes[order[k]];
         m->dd = dalloc<VolDesc>(m, 1);
         m->dtp = dalloc<int64_t>(m, 2);
         m->dsd = dalloc<SmoothDesc>(m, 1);
         m->dbp = dalloc<int64_t>(m, 2);
-        if (!m->dd || !m->dtp || !m->dsd || !m->dbp) {
-            scr.retire(s);
-            return cleanup(fail(SN_ENOMEM, "extract: descriptors"));
-        }
-        HIP_TRY(hipMemcpyAsync(m->dd, &h_desc[v], sizeof(VolDesc), hipMemcpyHostToDevice, s));
         int64_t *tp = static_cast<int64_t *>(scr.h(sizeof(int64_t) * 4));
-        if (!tp) {
-            scr.retire(s);
-            return cleanup(fail(SN_ENOMEM, "extract: staging"));
-        }
+        if (!m->dd || !m->dtp || !m->dsd || !m->dbp || !tp)
+            return cleanup(fail(SN_ENOMEM, "extract: descriptors"));
+        HIP_TRY(hipMemcpyAsync(m->dd, &h_desc[k], sizeof(VolDesc), hipMemcpyHostToDevice, s));
         tp[0] = 0, tp[1] = m->ntiles, tp[2] = 0, tp[3] = (m->P + 255) / 256;
         HIP_TRY(hipMemcpyAsync(m->dtp, tp, sizeof(int64_t) * 2, hipMemcpyHostToDevice, s));
         HIP_TRY(hipMemcpyAsync(m->dbp, tp + 2, sizeof(int64_t) * 2, hipMemcpyHostToDevice, s));
         sn_status st = mesh_mark(m, s);
-        if (st != SN_OK) {
-            scr.retire(s);
-            return cleanup(st);
-        }
+        if (st != SN_OK) return cleanup(st);
     }
     scr.retire(s);
     for (int32_t v = 0; v < n; ++v) out[v] = meshes[v];
@@ -872,7 +888,7 @@ extern "C" sn_status sn_smooth(sn_ctx *c, sn_mesh *m, const sn_smooth_params *p,
     HIP_TRY(hipMemcpyAsync(m->dd, hv, sizeof(VolDesc), hipMemcpyHostToDevice, s));
     {
         ProfScope ps(c, "k_emit", s);
-        HIP_TRY(launch_emit(m->dd, m->dtp, 1, m->ntiles, m->rpw, s));
+        HIP_TRY(launch_emit(m->dd, m->dtp, 1, m->ntiles, m->bpw, s));
     }
     c->pinned.release(h, s);
     c->pinned.release(hv, s);
@@ -931,16 +947,16 @@ sn_status sn::smooth_many(sn_ctx *c, sn_mesh **ms, const sn_smooth_params *pv, i
         scr.retire(s);
         return st;
     }
-    bool same_rpw = true;
-    for (int32_t v = 1; v < n; ++v) same_rpw &= ms[v]->rpw == ms[0]->rpw;
+    bool same_bpw = true;
+    for (int32_t v = 1; v < n; ++v) same_bpw &= ms[v]->bpw == ms[0]->bpw;
     {
         ProfScope ps(c, "k_emit", s);
-        if (same_rpw) {
-            HIP_TRY(launch_emit(d_vd, d_p + n + 1, n, tp[n], ms[0]->rpw, s));
+        if (same_bpw) {
+            HIP_TRY(launch_emit(d_vd, d_p + n + 1, n, tp[n], ms[0]->bpw, s));
         } else {
             for (int32_t v = 0; v < n; ++v) {
                 HIP_TRY(hipMemcpyAsync(ms[v]->dd, &h_vd[v], sizeof(VolDesc), hipMemcpyHostToDevice, s));
-                HIP_TRY(launch_emit(ms[v]->dd, ms[v]->dtp, 1, ms[v]->ntiles, ms[v]->rpw, s));
+                HIP_TRY(launch_emit(ms[v]->dd, ms[v]->dtp, 1, ms[v]->ntiles, ms[v]->bpw, s));
             }
         }
     }
@@ -981,7 +997,7 @@ extern "C" sn_status sn_batch_submit(sn_ctx *c, const sn_volume *vols,
 }
 
 // ---------------------------------------------------------------------------
-// schedule tuner: time k_count + k_generate for each rows-per-wave candidate
+// schedule tuner: time k_count + k_generate for each batches-per-wave candidate
 // ---------------------------------------------------------------------------
 
 extern "C" sn_status sn_autotune(sn_ctx *c, const sn_volume *vol, void *stream, int32_t *chosen)
@@ -996,13 +1012,13 @@ extern "C" sn_status sn_autotune(sn_ctx *c, const sn_volume *vol, void *stream, 
     int32_t arg = 2;
     const bool was = c->profiling;
     c->profiling = false;
-    for (int32_t rpw : cands) {
+    for (int32_t bpw : cands) {
         double tbest = 1e30;
         for (int rep = 0; rep < 4; ++rep) {
             HIP_TRY(hipStreamSynchronize(s));
             auto t0 = std::chrono::steady_clock::now();
             sn_mesh *m = nullptr;
-            st = extract_many(c, vol, 1, s, rpw, &m);
+            st = extract_many(c, vol, 1, s, bpw, &m);
             if (st != SN_OK) {
                 c->profiling = was;
                 return st;
@@ -1012,7 +1028,7 @@ extern "C" sn_status sn_autotune(sn_ctx *c, const sn_volume *vol, void *stream, 
             mesh_release(m);
             if (rep > 0) tbest = std::min(tbest, std::chrono::duration<double>(t1 - t0).count());
         }
-        if (tbest < best) best = tbest, arg = rpw;
+        if (tbest < best) best = tbest, arg = bpw;
     }
     c->profiling = was;
     {
@@ -1024,10 +1040,11 @@ extern "C" sn_status sn_autotune(sn_ctx *c, const sn_volume *vol, void *stream, 
     return SN_OK;
 }
 
-extern "C" sn_status sn_set_rows_per_wave(sn_ctx *c, int32_t rpw)
+extern "C" sn_status sn_set_batches_per_wave(sn_ctx *c, int32_t bpw)
 {
-    if (!c || rpw < 0 || rpw > kMaxRowsPerWave) return fail(SN_EINVAL, "sn_set_rows_per_wave: bad arguments");
+    if (!c || bpw < 0 || bpw > kMaxBatchesPerWave)
+        return fail(SN_EINVAL, "sn_set_batches_per_wave: bad arguments");
     std::lock_guard<std::mutex> g(c->tune_mu);
-    c->forced_rpw = rpw;
+    c->forced_bpw = bpw;
     return SN_OK;
 }

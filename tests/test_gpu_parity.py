@@ -120,17 +120,19 @@ def test_tiny_random_cases(ctx, sn):
         run_case(ctx, sn, vol, sel, bg, iters, lam, d, sp, org, prim)
 
 
-@pytest.mark.parametrize("rpw", [1, 2, 4, 8, 16])
-def test_schedule_invariance(ctx, sn, rpw):
-    """Every rows-per-wave schedule gives the same bytes."""
+@pytest.mark.parametrize("bpw", [1, 2, 4, 8, 16])
+def test_schedule_invariance(ctx, sn, bpw):
+    """Every batches-per-wave schedule gives the same bytes (rows of 3, 4, 5
+    and 7 words: ragged batches and tiles that straddle rows)."""
     rng = np.random.default_rng(77)
-    vol = synth.blocky_tiny(rng, (130, 41, 19), 6, np.uint16)
-    announce(f"schedule rpw={rpw}")
-    ctx.set_rows_per_wave(rpw)
+    announce(f"schedule bpw={bpw}")
+    ctx.set_batches_per_wave(bpw)
     try:
-        run_case(ctx, sn, vol, iters=7)
+        for M in (130, 250, 300, 420):
+            vol = synth.blocky_tiny(rng, (M, 21, 9), 6, np.uint16)
+            run_case(ctx, sn, vol, iters=7)
     finally:
-        ctx.set_rows_per_wave(0)
+        ctx.set_batches_per_wave(0)
 
 
 def test_dtype_edge_values(ctx, sn):
