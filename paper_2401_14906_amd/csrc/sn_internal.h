@@ -33,15 +33,19 @@ constexpr int kU = 4;
 constexpr int kWavesPerBlock = 4;
 constexpr int kBlock = 64 * kWavesPerBlock;
 constexpr int kMaxBatchesPerWave = 16;
-constexpr int kMaxTileWords = kWavesPerBlock * kMaxBatchesPerWave * kU;
+constexpr int kSegmentsPerTile = 16;  // k_edges: 4 waves x 4 segments of 256 samples
 
 // Sample lattice M x N x O; cell grid CM x CN x CO = (M-1)(N-1)(O-1).
+// Cut-edge planes (k_edges) hold one bit per sample, WS words per sample row,
+// computed in segments of 256 samples (NSEG per sample row).
 struct Geom {
     int64_t M, N, O;
     int64_t CM, CN, CO;
-    int64_t R;    // rows
-    int32_t W;    // words per row
-    int32_t NB;   // batches per row
+    int64_t R;     // cell rows
+    int32_t W;     // words per cell row
+    int32_t NB;    // batches per cell row
+    int64_t WS;    // words per sample row
+    int64_t NSEG;  // 256-sample segments per sample row
 };
 
 // Everything the word kernels need for one volume.
@@ -51,6 +55,8 @@ struct VolDesc {
     int32_t prim;   // 3 or 4
     Geom g;
     ClassSpec cs;
+    // cut-edge planes X, Y, Z: [3][O*N][WS]
+    uint64_t *planes;
     // word metadata (kept with the mesh)
     uint64_t *pmask;  // [R*W] point bit per cell
     int32_t *wbP;     // [R*W] id of the first point of each word
@@ -89,15 +95,20 @@ constexpr uint64_t kFlagPrefix = 2ull << 62;
 constexpr uint64_t kValMask = (1ull << 62) - 1;
 
 // ---- launchers (sn_kernels.hip) ----------------------------------------------
-// tile_prefix[v] = first tile of volume v, tile_prefix[nvol] = end; tile
-// indices are global across the launches of one extraction, and a launch
-// covers tiles tile_base .. tile_base + ntiles - 1.  bpw = batches per wave
-// (a tile is 4*bpw batches of one volume).  Every volume of a count/generate
-// launch has the given label type (bytes) and classification mode.
-hipError_t launch_count(int32_t dtype, int32_t mode, const VolDesc *d_descs,
+// Each launch covers tiles tile_base .. tile_base + ntiles - 1 of a global
+// tile numbering over the volumes of one extraction; tile_prefix[v] is the
+// first tile of volume v and tile_prefix[nvol] the end.
+//   k_edges   : a tile is 4*4 segments of 256 samples; every volume of a launch has
+//               the given label type (bytes), classification mode and `wide`
+//               (rows 16-byte aligned and M % 4 == 0: one wide load per lane).
+//   k_count   : a tile is 256 cell words.
+//   k_generate: a tile is 4*bpw batches; label type and mode as for k_edges.
+hipError_t launch_edges(int32_t dtype, int32_t mode, bool wide, const VolDesc *d_descs,
                         const int64_t *d_tile_prefix, int32_t nvol, int64_t tile_base,
-                        int64_t ntiles, int32_t bpw, uint64_t *d_status, uint32_t *d_ticket,
-                        int64_t *d_totals, hipStream_t s);
+                        int64_t ntiles, hipStream_t s);
+hipError_t launch_count(const VolDesc *d_descs, const int64_t *d_tile_prefix, int32_t nvol,
+                        int64_t ntiles, uint64_t *d_status, uint32_t *d_ticket, int64_t *d_totals,
+                        hipStream_t s);
 hipError_t launch_generate(int32_t dtype, int32_t mode, const VolDesc *d_descs,
                            const int64_t *d_tile_prefix, int32_t nvol, int64_t tile_base,
                            int64_t ntiles, int32_t bpw, hipStream_t s);

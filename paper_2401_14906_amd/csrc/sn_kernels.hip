@@ -191,27 +191,52 @@ __device__ __forceinline__ void corners(const LabelLoads<T> &L, const ClassSpec 
     }
 }
 
-// Wave-wide masks of one word (bit L = cell 64w + L): a point where any of
-// the twelve edges is cut (Sec. 2.2), a stencil face where one of its four
-// edges is cut and the neighbour cell exists (Sec. 3.3), a quad per cut edge
-// owned by the cell's origin sample whose four cells exist (Sec. 2.2, open
-// boundary of Sec. 4.2).
+// Masks of one 64-cell word (bit L = cell 64w + L) from the cut-edge planes:
+// a point where any of the twelve edges is cut (Sec. 2.2), a stencil face
+// where one of its four edges is cut and the neighbour cell exists
+// (Sec. 3.3), a quad per cut edge owned by the cell's origin sample whose
+// four cells exist (Sec. 2.2, open boundary of Sec. 4.2).  The same algebra
+// runs per lane (one word per lane, vector registers) in k_count and per wave
+// (scalar registers) in k_generate.
 struct WordMasks {
     uint64_t pt, qx, qy, qz;
     uint64_t f[6];  // -x, +x, -y, +y, -z, +z
 };
 
-__device__ __forceinline__ WordMasks word_masks(const uint32_t c[8], int32_t w, int64_t j, int64_t k,
+// Plane words around cell word w of cell row (j,k): X of sample rows
+// (j,k) (j+1,k) (j,k+1) (j+1,k+1); Y of (j,k), (j,k+1) and Z of (j,k), (j+1,k),
+// each with the following word for the sample at i+1.
+struct PlaneWords {
+    uint64_t x00, x10, x01, x11;
+    uint64_t y00, y00n, y01, y01n;
+    uint64_t z00, z00n, z10, z10n;
+};
+
+template <typename P>
+__device__ __forceinline__ PlaneWords plane_words(const P *planes, int64_t plane_stride, int64_t WS,
+                                                  int64_t s00, int64_t N, int32_t w)
+{
+    const P *X = planes, *Y = planes + plane_stride, *Z = planes + 2 * plane_stride;
+    const int64_t s10 = s00 + 1, s01 = s00 + N, s11 = s01 + 1;
+    const bool nx = w + 1 < WS;
+    PlaneWords p;
+    p.x00 = X[s00 * WS + w], p.x10 = X[s10 * WS + w];
+    p.x01 = X[s01 * WS + w], p.x11 = X[s11 * WS + w];
+    p.y00 = Y[s00 * WS + w], p.y01 = Y[s01 * WS + w];
+    p.z00 = Z[s00 * WS + w], p.z10 = Z[s10 * WS + w];
+    p.y00n = nx ? Y[s00 * WS + w + 1] : 0ull, p.y01n = nx ? Y[s01 * WS + w + 1] : 0ull;
+    p.z00n = nx ? Z[s00 * WS + w + 1] : 0ull, p.z10n = nx ? Z[s10 * WS + w + 1] : 0ull;
+    return p;
+}
+
+__device__ __forceinline__ uint64_t next_bit(uint64_t a, uint64_t an) { return (a >> 1) | (an << 63); }
+
+__device__ __forceinline__ WordMasks word_masks(const PlaneWords &p, int32_t w, int32_t j, int32_t k,
                                                 const Geom &g)
 {
-    const uint32_t c000 = c[0], c100 = c[1], c010 = c[2], c110 = c[3];
-    const uint32_t c001 = c[4], c101 = c[5], c011 = c[6], c111 = c[7];
-    const uint64_t x0 = __ballot(c000 != c100), x1 = __ballot(c010 != c110);
-    const uint64_t x2 = __ballot(c001 != c101), x3 = __ballot(c011 != c111);
-    const uint64_t y0 = __ballot(c000 != c010), y1 = __ballot(c100 != c110);
-    const uint64_t y2 = __ballot(c001 != c011), y3 = __ballot(c101 != c111);
-    const uint64_t z0 = __ballot(c000 != c001), z1 = __ballot(c100 != c101);
-    const uint64_t z2 = __ballot(c010 != c011), z3 = __ballot(c110 != c111);
+    const uint64_t x0 = p.x00, x1 = p.x10, x2 = p.x01, x3 = p.x11;
+    const uint64_t y0 = p.y00, y1 = next_bit(p.y00, p.y00n), y2 = p.y01, y3 = next_bit(p.y01, p.y01n);
+    const uint64_t z0 = p.z00, z1 = next_bit(p.z00, p.z00n), z2 = p.z10, z3 = next_bit(p.z10, p.z10n);
     const int64_t rem = g.CM - 64 * (int64_t)w;       // cells of the row from this word on (>= 1)
     const uint64_t valid = rem >= 64 ? ~0ull : ((1ull << rem) - 1);
     const uint64_t hasprev = w == 0 ? ~1ull : ~0ull;  // i >= 1
@@ -252,64 +277,150 @@ __device__ __forceinline__ int64_t wave_excl_scan(int64_t x, int lane)
 }
 
 // ---------------------------------------------------------------------------
-// k_count
+// k_edges: cut-edge planes X, Y, Z (Sec. 2.2): bit i of word m of sample row
+// (j,k) of plane X is set iff C(i,j,k) != C(i+1,j,k) (Y: C(i,j+1,k), Z:
+// C(i,j,k+1)).  A wave takes 256 samples of a row, four per lane, with one
+// wide load per sample row (rows (j,k), (j+1,k), (j,k+1)); nibbles are merged
+// into 64-bit words across 16 lanes.
 // ---------------------------------------------------------------------------
 
-template <typename T, int MODE>
-__device__ __forceinline__ void count_process(const VolDesc &d, const BatchPos &bp,
-                                              const LabelLoads<T> &L, int lane, int64_t gt0,
-                                              int32_t (*s_wc)[kMaxTileWords])
+constexpr int kSegPerWave = 4;  // 256-sample segments per wave
+
+typedef uint32_t v4u __attribute__((ext_vector_type(4)));
+typedef uint32_t v2u __attribute__((ext_vector_type(2)));
+
+template <typename T, bool WIDE>
+__device__ __forceinline__ void load_quad(const T *row_, int32_t i0, int32_t M1, T (&v)[4])
 {
-    uint32_t c[kU][8];
-    corners<T, MODE>(L, d.cs, lane, c);
-    SN_GLOBAL uint64_t *pmask = glb(d.pmask);
-    const int32_t local = (int32_t)(bp.g0 - gt0);
-#pragma unroll
-    for (int u = 0; u < kU; ++u) {
-        if (u >= bp.nw) break;
-        __builtin_amdgcn_sched_barrier(0);
-        const WordMasks m = word_masks(c[u], bp.w0 + u, bp.j, bp.k, d.g);
-        int32_t nP = 0, nQ = 0, nS = 0;
-        if (m.pt != 0) {  // no cut edge: no quad and no stencil face either
-            nP = __popcll(m.pt);
-            nQ = __popcll(m.qx) + __popcll(m.qy) + __popcll(m.qz);
-#pragma unroll
-            for (int f = 0; f < 6; ++f) nS += __popcll(m.f[f]);
+    const SN_GLOBAL T *row = glb(row_);
+    if constexpr (WIDE) {
+        // rows are 16-byte aligned and M % 4 == 0, so a quad never straddles the row end
+        const int32_t ic = i0 <= M1 ? i0 : M1 - 3;
+        if constexpr (sizeof(T) == 4) {
+            const v4u q = *reinterpret_cast<const SN_GLOBAL v4u *>(row + ic);
+            v[0] = q.x, v[1] = q.y, v[2] = q.z, v[3] = q.w;
+        } else if constexpr (sizeof(T) == 2) {
+            const v2u q = *reinterpret_cast<const SN_GLOBAL v2u *>(row + ic);
+            v[0] = (T)(q.x & 0xffffu), v[1] = (T)(q.x >> 16), v[2] = (T)(q.y & 0xffffu),
+            v[3] = (T)(q.y >> 16);
+        } else {
+            const uint32_t q = *reinterpret_cast<const SN_GLOBAL uint32_t *>(row + ic);
+            v[0] = (T)(q & 0xffu), v[1] = (T)((q >> 8) & 0xffu), v[2] = (T)((q >> 16) & 0xffu),
+            v[3] = (T)(q >> 24);
         }
-        if (lane == 0) {
-            pmask[bp.g0 + u] = m.pt;
-            s_wc[0][local + u] = nP;
-            s_wc[1][local + u] = nQ;
-            s_wc[2][local + u] = nS;
-        }
+    } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) v[e] = row[(uint32_t)(i0 + e <= M1 ? i0 + e : M1)];
     }
 }
 
-// nb consecutive batches from b0, two in flight.
-template <typename T, int MODE>
-__device__ void count_stream(const VolDesc &d, int64_t b0, int nb, int lane, int64_t gt0,
-                             int32_t (*s_wc)[kMaxTileWords])
+// OR of a 4-bit nibble per lane into the 64-bit word of each group of 16 lanes
+// (lane 16g + l contributes bits 4l..4l+3); valid in lane 16g.
+__device__ __forceinline__ uint64_t merge_nibbles(uint32_t nib, int lane)
 {
-    const T *vol = static_cast<const T *>(d.labels);
-    LabelLoads<T> L0, L1;
-    BatchPos P0 = batch_pos(d.g, b0), P1;
-    issue_labels<T>(vol, d.g, P0, lane, L0);
-    for (int q = 0; q < nb; q += 2) {
-        if (q + 1 < nb) {
-            P1 = P0;
-            batch_next(d.g, P1);
-            issue_labels<T>(vol, d.g, P1, lane, L1);
-        }
-        count_process<T, MODE>(d, P0, L0, lane, gt0, s_wc);
-        if (q + 1 >= nb) break;
-        if (q + 2 < nb) {
-            P0 = P1;
-            batch_next(d.g, P0);
-            issue_labels<T>(vol, d.g, P0, lane, L0);
-        }
-        count_process<T, MODE>(d, P1, L1, lane, gt0, s_wc);
+    uint32_t v = nib << (4 * (lane & 7));
+    v |= __shfl_xor(v, 1u);
+    v |= __shfl_xor(v, 2u);
+    v |= __shfl_xor(v, 4u);
+    const uint32_t hi = __shfl_down(v, 8u);
+    return (uint64_t)v | ((uint64_t)hi << 32);
+}
+
+template <typename T, int MODE, bool WIDE>
+__device__ __forceinline__ void edges_segment(const VolDesc &d, int64_t seg, int lane)
+{
+    const Geom &g = d.g;
+    const uint32_t NSEG = (uint32_t)g.NSEG, N = (uint32_t)g.N;
+    const uint32_t srow = (uint32_t)seg / NSEG;
+    const int32_t m = (int32_t)((uint32_t)seg - srow * NSEG);
+    const int32_t j = (int32_t)(srow % N), k = (int32_t)(srow / N);
+    const int32_t M1 = (int32_t)(g.M - 1);
+    const int32_t i0 = 256 * m + 4 * lane;
+    const T *ra = static_cast<const T *>(d.labels) + (int64_t)srow * g.M;
+    const bool hasy = j + 1 < (int32_t)g.N, hasz = k + 1 < (int32_t)g.O;
+    T a[4], b[4] = {0, 0, 0, 0}, c[4] = {0, 0, 0, 0};
+    load_quad<T, WIDE>(ra, i0, M1, a);
+    if (hasy) load_quad<T, WIDE>(ra + g.M, i0, M1, b);
+    if (hasz) load_quad<T, WIDE>(ra + g.M * g.N, i0, M1, c);
+    T an = 0;
+    if (lane == 63) an = glb(ra)[(uint32_t)(256 * (m + 1) <= M1 ? 256 * (m + 1) : M1)];
+    uint32_t ca[5], cb[4], cc[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        ca[e] = classify<MODE>((uint32_t)a[e], d.cs);
+        cb[e] = classify<MODE>((uint32_t)b[e], d.cs);
+        cc[e] = classify<MODE>((uint32_t)c[e], d.cs);
+    }
+    ca[4] = __shfl_down(ca[0], 1u);
+    if (lane == 63) ca[4] = classify<MODE>((uint32_t)an, d.cs);
+    uint32_t xn = 0, yn = 0, zn = 0;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int32_t i = i0 + e;
+        xn |= ((ca[e] != ca[e + 1]) && i <= M1 - 1 ? 1u : 0u) << e;
+        yn |= (hasy && (ca[e] != cb[e]) && i <= M1 ? 1u : 0u) << e;
+        zn |= (hasz && (ca[e] != cc[e]) && i <= M1 ? 1u : 0u) << e;
+    }
+    const uint64_t X = merge_nibbles(xn, lane), Y = merge_nibbles(yn, lane), Z = merge_nibbles(zn, lane);
+    const int64_t wi = 4 * (int64_t)m + (lane >> 4);
+    if ((lane & 15) == 0 && wi < g.WS) {
+        SN_GLOBAL uint64_t *P = glb(d.planes);
+        const int64_t ps = (int64_t)g.N * g.O * g.WS;
+        const int64_t o = (int64_t)srow * g.WS + wi;
+        P[o] = X;
+        P[ps + o] = Y;
+        P[2 * ps + o] = Z;
     }
 }
+
+template <typename T, int MODE, bool WIDE>
+__device__ __forceinline__ void edges_tile(const VolDesc *__restrict__ descs,
+                                           const int64_t *__restrict__ tile_prefix, int32_t nvol,
+                                           int64_t tile_base)
+{
+    const int64_t t = tile_base + blockIdx.x;
+    const int v = find_seg(tile_prefix, nvol, t);
+    const VolDesc &d = descs[v];
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int64_t nseg = d.g.N * d.g.O * d.g.NSEG;
+    int64_t seg = (t - tile_prefix[v]) * (kWavesPerBlock * kSegPerWave) + (int64_t)wave * kSegPerWave;
+    for (int q = 0; q < kSegPerWave; ++q, ++seg) {
+        if (seg >= nseg) break;
+        edges_segment<T, MODE, WIDE>(d, seg, lane);
+    }
+}
+
+template <typename T, int MODE>
+__global__ __launch_bounds__(kBlock) void k_edges_wide(const VolDesc *__restrict__ descs,
+                                                       const int64_t *__restrict__ tile_prefix,
+                                                       int32_t nvol, int64_t tile_base)
+{
+    edges_tile<T, MODE, true>(descs, tile_prefix, nvol, tile_base);
+}
+
+template <typename T, int MODE>
+__global__ __launch_bounds__(kBlock) void k_edges_narrow(const VolDesc *__restrict__ descs,
+                                                         const int64_t *__restrict__ tile_prefix,
+                                                         int32_t nvol, int64_t tile_base)
+{
+    edges_tile<T, MODE, false>(descs, tile_prefix, nvol, tile_base);
+}
+
+template <typename T, int MODE>
+__global__ __launch_bounds__(kBlock) void k_edges_wide(const VolDesc *__restrict__ descs,
+                                                       const int64_t *__restrict__ tile_prefix,
+                                                       int32_t nvol, int64_t tile_base);
+template <typename T, int MODE>
+__global__ __launch_bounds__(kBlock) void k_edges_narrow(const VolDesc *__restrict__ descs,
+                                                         const int64_t *__restrict__ tile_prefix,
+                                                         int32_t nvol, int64_t tile_base);
+
+// ---------------------------------------------------------------------------
+// k_count: one lane per 64-cell word.  Point / quad / stencil counts of every
+// word and the point-bit plane, then a fused single-pass (decoupled
+// look-back) scan over words that gives every word its first point id, quad
+// index and stencil index (Sec. 2.3 passes 1-3 and the prefix sum).
+// ---------------------------------------------------------------------------
 
 // Exclusive prefixes of tile t for the three counts, by one whole wave: lane L
 // inspects tile top-L of each count's window.  Tiles before `first` (the
@@ -356,43 +467,53 @@ __device__ void look_back3(const uint64_t *status, int64_t t, int64_t first, int
     }
 }
 
-template <typename T, int MODE>
 __global__ __launch_bounds__(kBlock) void k_count(const VolDesc *__restrict__ descs,
                                                   const int64_t *__restrict__ tile_prefix,
-                                                  int32_t nvol, int64_t tile_base, int32_t bpw,
-                                                  uint64_t *status, uint32_t *ticket,
+                                                  int32_t nvol, uint64_t *status, uint32_t *ticket,
                                                   int64_t *totals)
 {
     __shared__ int64_t s_tile;
-    __shared__ int32_t s_wc[3][kMaxTileWords];
+    __shared__ int64_t s_wtot[3][kWavesPerBlock];
     __shared__ int64_t s_excl[3];
-    if (threadIdx.x == 0) s_tile = tile_base + (int64_t)atomicAdd(ticket, 1u);
+    if (threadIdx.x == 0) s_tile = (int64_t)atomicAdd(ticket, 1u);
     __syncthreads();
     const int64_t t = s_tile;  // tiles are handed out in order: predecessors are running
     const int v = find_seg(tile_prefix, nvol, t);
     const VolDesc &d = descs[v];
+    const Geom &g = d.g;
     const int64_t first = tile_prefix[v];
-    const int64_t nbv = d.g.R * d.g.NB;  // batches of this volume
-    const int TB = kWavesPerBlock * bpw;
-    const int64_t bt0 = (t - first) * TB;
-    const int64_t bt1 = bt0 + TB < nbv ? bt0 + TB : nbv;
-    const BatchPos pfirst = batch_pos(d.g, bt0), plast = batch_pos(d.g, bt1 - 1);
-    const int64_t gt0 = pfirst.g0;
-    const int32_t ntw = (int32_t)(plast.g0 + plast.nw - gt0);  // words in this tile
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
-    {
-        const int64_t b0 = bt0 + (int64_t)wave * bpw;
-        const int64_t nb = bt1 - b0 < bpw ? bt1 - b0 : bpw;
-        if (nb > 0) count_stream<T, MODE>(d, b0, (int)nb, lane, gt0, s_wc);
+    const int64_t words = g.R * g.W;
+    const int64_t gw = (t - first) * kBlock + threadIdx.x;
+    int64_t cnt[3] = {0, 0, 0};
+    if (gw < words) {
+        const uint32_t r = (uint32_t)gw / (uint32_t)g.W;
+        const int32_t w = (int32_t)((uint32_t)gw - r * (uint32_t)g.W);
+        const int32_t j = (int32_t)(r % (uint32_t)g.CN), k = (int32_t)(r / (uint32_t)g.CN);
+        const int64_t ps = g.N * g.O * g.WS;
+        const PlaneWords p = plane_words(glb(d.planes), ps, g.WS, j + g.N * (int64_t)k, g.N, w);
+        const WordMasks m = word_masks(p, w, j, k, g);
+        glb(d.pmask)[gw] = m.pt;
+        cnt[0] = __popcll(m.pt);
+        cnt[1] = __popcll(m.qx) + __popcll(m.qy) + __popcll(m.qz);
+        cnt[2] = __popcll(m.f[0]) + __popcll(m.f[1]) + __popcll(m.f[2]) + __popcll(m.f[3]) +
+                 __popcll(m.f[4]) + __popcll(m.f[5]);
+    }
+    // block-wide exclusive scan of the three counts
+    int64_t ex[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        ex[c] = wave_excl_scan(cnt[c], lane);
+        if (lane == 63) s_wtot[c][wave] = ex[c] + cnt[c];
     }
     __syncthreads();
     if (wave == 0) {
         int64_t agg[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            int64_t x = 0;
-            for (int32_t i = lane; i < ntw; i += 64) x += s_wc[c][i];
-            agg[c] = wave_sum(x);
+            agg[c] = 0;
+#pragma unroll
+            for (int q = 0; q < kWavesPerBlock; ++q) agg[c] += s_wtot[c][q];
             if (lane == 0)
                 __hip_atomic_store(status + 3 * t + c,
                                    (t == first ? kFlagPrefix : kFlagAgg) | (uint64_t)agg[c],
@@ -416,25 +537,16 @@ __global__ __launch_bounds__(kBlock) void k_count(const VolDesc *__restrict__ de
         }
     }
     __syncthreads();
-    // per-word bases: tile prefix + exclusive scan of the tile's word counts
-    if (wave < 3) {
-        const int c = wave;
-        SN_GLOBAL int32_t *wb = glb(c == 0 ? d.wbP : (c == 1 ? d.wbQ : d.wbS));
-        constexpr int PER = kMaxTileWords / 64;
-        int64_t loc[PER];
-        int64_t sum = 0;
+    if (gw < words) {
+        int64_t before[3] = {0, 0, 0};
 #pragma unroll
-        for (int m = 0; m < PER; ++m) {
-            const int32_t i = lane * PER + m;
-            loc[m] = sum;
-            sum += i < ntw ? s_wc[c][i] : 0;
-        }
-        const int64_t base = s_excl[c] + wave_excl_scan(sum, lane);
+        for (int q = 0; q < kWavesPerBlock; ++q)
+            if (q < wave)
 #pragma unroll
-        for (int m = 0; m < PER; ++m) {
-            const int32_t i = lane * PER + m;
-            if (i < ntw) wb[gt0 + i] = (int32_t)(base + loc[m]);
-        }
+                for (int c = 0; c < 3; ++c) before[c] += s_wtot[c][q];
+        glb(d.wbP)[gw] = (int32_t)(s_excl[0] + before[0] + ex[0]);
+        glb(d.wbQ)[gw] = (int32_t)(s_excl[1] + before[1] + ex[1]);
+        glb(d.wbS)[gw] = (int32_t)(s_excl[2] + before[2] + ex[2]);
     }
 }
 
@@ -466,9 +578,9 @@ __device__ __forceinline__ void store_point(SN_GLOBAL float *points, int32_t id,
 
 // Word data of the own row and its five neighbour rows for one batch, loaded
 // into lanes with one vector load each: lane l < 24 holds the first point id
-// of word (l & 3) of row n = l >> 2 (own, -y, +y, -z, +z, -y-z), lanes 4..23
-// also that word's point bits; lanes u < kU hold the own word's first quad
-// and stencil index.  Read back with readlane.
+// and the point bits of word (l & 3) of row n = l >> 2 (own, -y, +y, -z, +z,
+// -y-z); lanes u < kU hold the own word's first quad and stencil index.  Read
+// back with readlane.
 struct GenAux {
     int32_t wbp;
     uint64_t pmn;
@@ -492,7 +604,7 @@ __device__ __forceinline__ void issue_gen_aux(const VolDesc &d, const BatchPos &
     if (ok) {
         const int64_t gw = (bp.r + dr) * g.W + bp.w0 + u;
         A.wbp = glb(d.wbP)[gw];
-        if (n >= 1) A.pmn = glb(d.pmask)[gw];
+        A.pmn = glb(d.pmask)[gw];
     }
     if (lane < bp.nw) {
         A.wbq = glb(d.wbQ)[bp.g0 + lane];
@@ -514,9 +626,13 @@ template <typename T, int U>
 __device__ __forceinline__ void generate_word(const VolDesc &d, const BatchPos &bp,
                                               const uint32_t c[8], const GenAux &A, int lane)
 {
+    const Geom &g = d.g;
     const int32_t w = bp.w0 + U;
-    const WordMasks m = word_masks(c, w, bp.j, bp.k, d.g);
-    if (m.pt == 0) return;
+    const uint64_t own = readlane64(A.pmn, U);
+    if (own == 0) return;  // no point: no quad and no stencil face either
+    const PlaneWords p = plane_words(cst(d.planes), g.N * g.O * g.WS, g.WS,
+                                     bp.j + g.N * (int64_t)bp.k, g.N, w);
+    const WordMasks m = word_masks(p, w, bp.j, bp.k, g);
     const uint64_t mym = readlane64(A.pmn, 4 + U), myp = readlane64(A.pmn, 8 + U);
     const uint64_t mzm = readlane64(A.pmn, 12 + U), mzp = readlane64(A.pmn, 16 + U);
     const uint64_t mmm = readlane64(A.pmn, 20 + U);
@@ -816,14 +932,28 @@ __global__ __launch_bounds__(256) void k_tri(const VolDesc *__restrict__ descs,
     default: return hipErrorInvalidValue;                                                   \
     }
 
-hipError_t launch_count(int32_t dtype, int32_t mode, const VolDesc *d_descs,
+hipError_t launch_edges(int32_t dtype, int32_t mode, bool wide, const VolDesc *d_descs,
                         const int64_t *d_tile_prefix, int32_t nvol, int64_t tile_base,
-                        int64_t ntiles, int32_t bpw, uint64_t *d_status, uint32_t *d_ticket,
-                        int64_t *d_totals, hipStream_t s)
+                        int64_t ntiles, hipStream_t s)
 {
     if (ntiles <= 0) return hipSuccess;
-    SN_KEY_SWITCH(k_count, dim3((uint32_t)ntiles), dim3(kBlock), 0, s, d_descs, d_tile_prefix, nvol,
-                  tile_base, bpw, d_status, d_ticket, d_totals)
+    if (wide) {
+        SN_KEY_SWITCH(k_edges_wide, dim3((uint32_t)ntiles), dim3(kBlock), 0, s, d_descs,
+                      d_tile_prefix, nvol, tile_base)
+    } else {
+        SN_KEY_SWITCH(k_edges_narrow, dim3((uint32_t)ntiles), dim3(kBlock), 0, s, d_descs,
+                      d_tile_prefix, nvol, tile_base)
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_count(const VolDesc *d_descs, const int64_t *d_tile_prefix, int32_t nvol,
+                        int64_t ntiles, uint64_t *d_status, uint32_t *d_ticket, int64_t *d_totals,
+                        hipStream_t s)
+{
+    if (ntiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_count, dim3((uint32_t)ntiles), dim3(kBlock), 0, s, d_descs, d_tile_prefix,
+                       nvol, d_status, d_ticket, d_totals);
     return hipGetLastError();
 }
 

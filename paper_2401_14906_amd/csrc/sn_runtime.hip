@@ -407,8 +407,8 @@ sn_status sn::validate_volume(const sn_volume *v)
     {
         // the kernels index rows, words and batches of one volume with int32
         const Geom g = make_geom(*v);
-        if (g.R * g.W >= INT32_MAX || g.R * g.NB >= INT32_MAX)
-            return fail(SN_ETOOBIG, "volume has more than 2^31 cell words");
+        if (g.R * g.W >= INT32_MAX || g.R * g.NB >= INT32_MAX || g.N * g.O * g.NSEG >= INT32_MAX)
+            return fail(SN_ETOOBIG, "volume has more than 2^31 cell words or sample segments");
     }
     return SN_OK;
 }
@@ -424,6 +424,8 @@ Geom sn::make_geom(const sn_volume &v)
     g.R = g.CN * g.CO;
     g.W = (int32_t)((g.CM + 63) / 64);
     g.NB = (g.W + kU - 1) / kU;
+    g.WS = empty ? 0 : (g.M + 63) / 64;
+    g.NSEG = empty ? 0 : (g.M + 255) / 256;
     return g;
 }
 
@@ -616,10 +618,15 @@ sn_status sn::extract_many(sn_ctx *c, const sn_volume *vols, int32_t n, hipStrea
         class_table(vols[v], &mode[v], &tabs[v]);
         order[v] = v;
     }
-    auto key = [&](int32_t v) { return vols[v].dtype * 4 + mode[v]; };
+    // wide: rows start 16-byte aligned and hold a multiple of 4 samples
+    auto wide = [&](int32_t v) {
+        return vols[v].dims[0] % 4 == 0 && (reinterpret_cast<uintptr_t>(vols[v].labels) & 15) == 0;
+    };
+    auto key = [&](int32_t v) { return vols[v].dtype * 8 + mode[v] * 2 + (wide(v) ? 1 : 0); };
     std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return key(a) < key(b); });
 
-    std::vector<int64_t> tile_prefix(n + 1, 0);
+    std::vector<int64_t> tile_prefix(n + 1, 0), etile_prefix(n + 1, 0), ctile_prefix(n + 1, 0);
+    std::vector<void *> planes_blocks;
     for (int32_t k = 0; k < n; ++k) {
         const int32_t v = order[k];
         const sn_volume &vol = vols[v];
@@ -649,13 +656,19 @@ sn_status sn::extract_many(sn_ctx *c, const sn_volume *vols, int32_t n, hipStrea
         const int64_t words = d.g.R * d.g.W;
         d.pmask = dalloc<uint64_t>(m, words);
         d.wbP = dalloc<int32_t>(m, words);
-        d.wbQ = dalloc<int32_t>(m, words);
-        d.wbS = dalloc<int32_t>(m, words);
-        if (!d.pmask || !d.wbP || !d.wbQ || !d.wbS)
+        // extraction-only metadata: cut-edge planes and quad/stencil word bases
+        d.wbQ = static_cast<int32_t *>(scr.d(sizeof(int32_t) * (size_t)std::max<int64_t>(words, 1)));
+        d.wbS = static_cast<int32_t *>(scr.d(sizeof(int32_t) * (size_t)std::max<int64_t>(words, 1)));
+        const int64_t pwords = 3 * d.g.N * d.g.O * d.g.WS;
+        d.planes = static_cast<uint64_t *>(scr.d(sizeof(uint64_t) * (size_t)std::max<int64_t>(pwords, 1)));
+        if (!d.pmask || !d.wbP || !d.wbQ || !d.wbS || !d.planes)
             return cleanup(fail(SN_ENOMEM, "extract: word metadata"));
         const int64_t nbatch = d.g.R * d.g.NB;
         m->ntiles = (nbatch + TB - 1) / TB;
         tile_prefix[k + 1] = tile_prefix[k] + m->ntiles;
+        const int64_t nseg = d.g.N * d.g.O * d.g.NSEG;
+        etile_prefix[k + 1] = etile_prefix[k] + (nseg + kSegmentsPerTile - 1) / kSegmentsPerTile;
+        ctile_prefix[k + 1] = ctile_prefix[k] + (words + kBlock - 1) / kBlock;
         m->voxels = vol.dims[0] * vol.dims[1] * vol.dims[2];
     }
     // groups: [gbeg[i], gbeg[i+1]) of the launch order share a key
@@ -665,35 +678,40 @@ sn_status sn::extract_many(sn_ctx *c, const sn_volume *vols, int32_t n, hipStrea
     gbeg.push_back(n);
     const int32_t ngroups = (int32_t)gbeg.size() - 1;
 
-    const int64_t ntiles = tile_prefix[n];
+    const int64_t nctiles = ctile_prefix[n];
     VolDesc *h_desc = static_cast<VolDesc *>(scr.h(sizeof(VolDesc) * n));
-    int64_t *h_tp = static_cast<int64_t *>(scr.h(sizeof(int64_t) * (n + 1)));
+    int64_t *h_tp = static_cast<int64_t *>(scr.h(sizeof(int64_t) * 3 * (n + 1)));
     int64_t *h_tot = static_cast<int64_t *>(scr.h(sizeof(int64_t) * 3 * n));
     VolDesc *d_desc = static_cast<VolDesc *>(scr.d(sizeof(VolDesc) * n));
-    int64_t *d_tp = static_cast<int64_t *>(scr.d(sizeof(int64_t) * (n + 1)));
+    int64_t *d_tp = static_cast<int64_t *>(scr.d(sizeof(int64_t) * 3 * (n + 1)));
     int64_t *d_tot = static_cast<int64_t *>(scr.d(sizeof(int64_t) * 3 * n));
-    const size_t status_bytes = sizeof(uint64_t) * 3 * (size_t)std::max<int64_t>(ntiles, 1);
-    const size_t ticket_bytes = sizeof(uint32_t) * (size_t)ngroups;
-    uint8_t *d_status = static_cast<uint8_t *>(scr.d(status_bytes + ticket_bytes));
+    const size_t status_bytes = sizeof(uint64_t) * 3 * (size_t)std::max<int64_t>(nctiles, 1);
+    uint8_t *d_status = static_cast<uint8_t *>(scr.d(status_bytes + 256));
     if (!h_desc || !h_tp || !h_tot || !d_desc || !d_tp || !d_tot || !d_status)
         return cleanup(fail(SN_ENOMEM, "extract: scratch"));
     for (int32_t k = 0; k < n; ++k) h_desc[k] = meshes[order[k]]->d;
+    // three tile maps: generation batches, edge segments, count words
     std::memcpy(h_tp, tile_prefix.data(), sizeof(int64_t) * (n + 1));
+    std::memcpy(h_tp + (n + 1), etile_prefix.data(), sizeof(int64_t) * (n + 1));
+    std::memcpy(h_tp + 2 * (n + 1), ctile_prefix.data(), sizeof(int64_t) * (n + 1));
+    int64_t *d_etp = d_tp + (n + 1), *d_ctp = d_tp + 2 * (n + 1);
     HIP_TRY(hipMemcpyAsync(d_desc, h_desc, sizeof(VolDesc) * n, hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(d_tp, h_tp, sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(d_tp, h_tp, sizeof(int64_t) * 3 * (n + 1), hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemsetAsync(d_tot, 0, sizeof(int64_t) * 3 * n, s));
-    HIP_TRY(hipMemsetAsync(d_status, 0, status_bytes + ticket_bytes, s));
+    HIP_TRY(hipMemsetAsync(d_status, 0, status_bytes + 256, s));
     {
-        ProfScope ps(c, "k_count", s);
+        ProfScope ps(c, "k_edges", s);
         for (int32_t gi = 0; gi < ngroups; ++gi) {
             const int32_t k0 = gbeg[gi], k1 = gbeg[gi + 1];
             const VolDesc &d0 = h_desc[k0];
-            HIP_TRY(launch_count(d0.dtype, d0.cs.mode, d_desc + k0, d_tp + k0, k1 - k0,
-                                 tile_prefix[k0], tile_prefix[k1] - tile_prefix[k0], bpw,
-                                 reinterpret_cast<uint64_t *>(d_status),
-                                 reinterpret_cast<uint32_t *>(d_status + status_bytes) + gi,
-                                 d_tot + 3 * k0, s));
+            HIP_TRY(launch_edges(d0.dtype, d0.cs.mode, wide(order[k0]), d_desc + k0, d_etp + k0,
+                                 k1 - k0, etile_prefix[k0], etile_prefix[k1] - etile_prefix[k0], s));
         }
+    }
+    {
+        ProfScope ps(c, "k_count", s);
+        HIP_TRY(launch_count(d_desc, d_ctp, n, nctiles, reinterpret_cast<uint64_t *>(d_status),
+                             reinterpret_cast<uint32_t *>(d_status + status_bytes), d_tot, s));
     }
     HIP_TRY(hipMemcpyAsync(h_tot, d_tot, sizeof(int64_t) * 3 * n, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
