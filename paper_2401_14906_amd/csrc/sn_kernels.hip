@@ -129,66 +129,14 @@ __device__ __forceinline__ void batch_next(const Geom &g, BatchPos &p)
     p.g0 = (int64_t)p.r * g.W + p.w0;
 }
 
-// Raw label loads of one batch: word u, sample row q = dj + 2*dk, plus (lane
-// 63 only) the sample just after the batch.  Issued early, consumed later:
-// the kernels keep the loads of the next batch in flight while they work on
-// the current one.
-template <typename T>
-struct LabelLoads {
-    T a[kU][4];
-    T e[4];
-};
+typedef int v4i __attribute__((ext_vector_type(4)));
 
-template <typename T>
-__device__ __forceinline__ void issue_labels(const T *vol_, const Geom &g, const BatchPos &bp,
-                                             int lane, LabelLoads<T> &L)
+// One point's world coordinates (three consecutive floats).
+__device__ __forceinline__ void store_point(SN_GLOBAL float *points, int32_t id, float x, float y,
+                                            float z)
 {
-    const SN_GLOBAL T *vol = glb(vol_);
-    const int32_t M1 = (int32_t)(g.M - 1);
-    const SN_GLOBAL T *rows[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-        rows[q] = vol + g.M * ((int64_t)(bp.j + (q & 1)) + g.N * (int64_t)(bp.k + (q >> 1)));
-#pragma unroll
-    for (int u = 0; u < kU; ++u) {
-        const int32_t i = 64 * (bp.w0 + u) + lane;
-        const int32_t ic = i < M1 ? i : M1;  // lanes past the row end read the last sample
-#pragma unroll
-        for (int q = 0; q < 4; ++q) L.a[u][q] = rows[q][(uint32_t)ic];
-    }
-#pragma unroll
-    for (int q = 0; q < 4; ++q) L.e[q] = 0;
-    if (lane == 63) {
-        const int32_t in = 64 * (bp.w0 + kU) < M1 ? 64 * (bp.w0 + kU) : M1;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) L.e[q] = rows[q][(uint32_t)in];
-    }
-}
-
-// Classified values at the 8 corners of the cells 64(w0+u) + lane of the
-// batch; index di + 2*dj + 4*dk.  The +x corner comes from the next lane,
-// from lane 0 of the next word, or (last word) from the extra load of lane 63.
-template <typename T, int MODE>
-__device__ __forceinline__ void corners(const LabelLoads<T> &L, const ClassSpec &cs, int lane,
-                                        uint32_t (&c)[kU][8])
-{
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int slot = 2 * (q & 1) + 4 * (q >> 1);
-        uint32_t x[kU];
-#pragma unroll
-        for (int u = 0; u < kU; ++u) x[u] = classify<MODE>((uint32_t)L.a[u][q], cs);
-        const uint32_t xe = classify<MODE>((uint32_t)L.e[q], cs);
-#pragma unroll
-        for (int u = 0; u < kU; ++u) {
-            uint32_t y = __shfl_down(x[u], 1u);
-            const uint32_t nxt =
-                (u + 1 < kU) ? (uint32_t)__builtin_amdgcn_readlane((int)x[(u + 1) % kU], 0) : xe;
-            if (lane == 63) y = nxt;
-            c[u][slot] = x[u];
-            c[u][slot + 1] = y;
-        }
-    }
+    SN_GLOBAL float *p = points + 3 * (int64_t)id;
+    p[0] = x, p[1] = y, p[2] = z;
 }
 
 // Masks of one 64-cell word (bit L = cell 64w + L) from the cut-edge planes:
@@ -551,7 +499,13 @@ __global__ __launch_bounds__(kBlock) void k_count(const VolDesc *__restrict__ de
 }
 
 // ---------------------------------------------------------------------------
-// k_generate
+// k_generate: points, stencil CSR, quads and label pairs (Sec. 2.3 pass 4).
+// A wave takes batches of kU words.  Per batch, one vector load each brings
+// the batch's word data into lanes (cut-edge plane words, neighbour-row point
+// bits and first ids, own quad/stencil bases) and three more bring the label
+// rows needed for label pairs; the next batch's loads are in flight while the
+// current one is processed.  A word's outputs are first placed in LDS in
+// final order and then written out with consecutive-address stores.
 // ---------------------------------------------------------------------------
 
 template <typename T> struct Pair;
@@ -559,52 +513,61 @@ template <> struct Pair<uint8_t> { using type = uint16_t; static constexpr int s
 template <> struct Pair<uint16_t> { using type = uint32_t; static constexpr int sh = 16; };
 template <> struct Pair<uint32_t> { using type = uint64_t; static constexpr int sh = 32; };
 
-template <typename T>
-__device__ __forceinline__ void store_pair(void *pairs, int32_t q, uint32_t front, uint32_t back)
-{
-    using P = typename Pair<T>::type;
-    glb(static_cast<P *>(pairs))[q] = (P)(T)front | ((P)(T)back << Pair<T>::sh);
-}
+// Per-wave LDS staging of one word's outputs (worst case: 64 points, 384
+// stencil entries, 192 quads).
+struct Stage {
+    float pts[64 * 3];
+    int32_t off[64];
+    int32_t ids[384];
+    v4i quads[192];
+    uint64_t pairs[192];  // Pair<T>::type values (the first 2*sizeof(T) bytes of each slot)
+    uint8_t faces[64];
+};
 
-typedef int v4i __attribute__((ext_vector_type(4)));
-
-// One point's world coordinates (three consecutive floats).
-__device__ __forceinline__ void store_point(SN_GLOBAL float *points, int32_t id, float x, float y,
-                                            float z)
-{
-    SN_GLOBAL float *p = points + 3 * (int64_t)id;
-    p[0] = x, p[1] = y, p[2] = z;
-}
-
-// Word data of the own row and its five neighbour rows for one batch, loaded
-// into lanes with one vector load each: lane l < 24 holds the first point id
-// and the point bits of word (l & 3) of row n = l >> 2 (own, -y, +y, -z, +z,
-// -y-z); lanes u < kU hold the own word's first quad and stencil index.  Read
-// back with readlane.
+// Word data of one batch in lanes.  Lane l < 48: plane word p = l >> 2 of word
+// u = l & 3, in the order of PlaneWords (x00 x10 x01 x11 y00 y00n y01 y01n
+// z00 z00n z10 z10n).  Lane l < 24: first point id and point bits of word
+// (l & 3) of cell row n = l >> 2 (own, -y, +y, -z, +z, -y-z).  Lane u < kU:
+// first quad and stencil index of own word u.
 struct GenAux {
-    int32_t wbp;
+    uint64_t pw;
     uint64_t pmn;
-    int32_t wbq, wbs;
+    int32_t wbp, wbq, wbs;
 };
 
 __device__ __forceinline__ void issue_gen_aux(const VolDesc &d, const BatchPos &bp, int lane,
                                               GenAux &A)
 {
     const Geom &g = d.g;
-    A.wbp = 0, A.pmn = 0, A.wbq = 0, A.wbs = 0;
-    const int n = lane >> 2, u = lane & 3;
-    const bool ym = bp.j >= 1, yp = bp.j + 1 <= g.CN - 1, zm = bp.k >= 1, zp = bp.k + 1 <= g.CO - 1;
-    bool ok = lane < 24 && u < bp.nw;
-    int64_t dr = 0;
-    if (n == 1) ok = ok && ym, dr = -1;
-    if (n == 2) ok = ok && yp, dr = 1;
-    if (n == 3) ok = ok && zm, dr = -g.CN;
-    if (n == 4) ok = ok && zp, dr = g.CN;
-    if (n == 5) ok = ok && ym && zm, dr = -g.CN - 1;
-    if (ok) {
-        const int64_t gw = (bp.r + dr) * g.W + bp.w0 + u;
-        A.wbp = glb(d.wbP)[gw];
-        A.pmn = glb(d.pmask)[gw];
+    A.pw = 0, A.pmn = 0, A.wbp = 0, A.wbq = 0, A.wbs = 0;
+    {
+        const int p = lane >> 2, u = lane & 3;
+        const int32_t w = bp.w0 + u;
+        const int64_t s00 = bp.j + g.N * (int64_t)bp.k;
+        const int64_t ps = g.N * g.O * g.WS;
+        // sample row and plane of each of the twelve words
+        const int64_t srow = (p == 1 || p == 3 || p == 10 || p == 11) ? 1 : 0;
+        const int64_t srowk = (p == 2 || p == 3 || p == 6 || p == 7) ? g.N : 0;
+        const int64_t plane = p < 4 ? 0 : (p < 8 ? 1 : 2);
+        const int32_t wn = (p == 5 || p == 7 || p == 9 || p == 11) ? w + 1 : w;
+        if (lane < 48 && u < bp.nw && wn < g.WS)
+            A.pw = glb(d.planes)[plane * ps + (s00 + srow + srowk) * g.WS + wn];
+    }
+    {
+        const int n = lane >> 2, u = lane & 3;
+        const bool ym = bp.j >= 1, yp = bp.j + 1 <= g.CN - 1, zm = bp.k >= 1, zp = bp.k + 1 <= g.CO - 1;
+        bool ok = lane < 24 && u < bp.nw;
+        int64_t dr = 0;
+        if (n == 1) ok = ok && ym, dr = -1;
+        if (n == 2) ok = ok && yp, dr = 1;
+        if (n == 3) ok = ok && zm, dr = -g.CN;
+        if (n == 4) ok = ok && zp, dr = g.CN;
+        if (n == 5) ok = ok && ym && zm, dr = -g.CN - 1;
+        if (ok) {
+            const int64_t gw = (bp.r + dr) * g.W + bp.w0 + u;
+            A.wbp = glb(d.wbP)[gw];
+            A.pmn = glb(d.pmask)[gw];
+        }
     }
     if (lane < bp.nw) {
         A.wbq = glb(d.wbQ)[bp.g0 + lane];
@@ -619,120 +582,191 @@ __device__ __forceinline__ uint64_t readlane64(uint64_t x, int l)
     return ((uint64_t)hi << 32) | lo;
 }
 
-// Outputs of one word (Sec. 2.3 pass 4): its points with their stencil face
-// masks, CSR offsets and neighbour ids, and the quads (with label pairs) of
-// the edges owned by its samples, at the scanned bases of the word.
-template <typename T, int U>
-__device__ __forceinline__ void generate_word(const VolDesc &d, const BatchPos &bp,
-                                              const uint32_t c[8], const GenAux &A, int lane)
+// Label rows for the label pairs: samples 64(w0+u) + lane of rows (j,k),
+// (j+1,k), (j,k+1), plus (lane 63) the sample just after the batch in row (j,k).
+template <typename T>
+struct PairLoads {
+    T a[kU], b[kU], c[kU];
+    T e;
+};
+
+template <typename T>
+__device__ __forceinline__ void issue_pair_loads(const T *vol_, const Geom &g, const BatchPos &bp,
+                                                 int lane, PairLoads<T> &L)
 {
-    const Geom &g = d.g;
+    const SN_GLOBAL T *ra = glb(vol_) + g.M * ((int64_t)bp.j + g.N * (int64_t)bp.k);
+    const SN_GLOBAL T *rb = ra + g.M, *rc = ra + g.M * g.N;
+    const int32_t M1 = (int32_t)(g.M - 1);
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+        const int32_t i = 64 * (bp.w0 + u) + lane;
+        const uint32_t ic = (uint32_t)(i < M1 ? i : M1);
+        L.a[u] = ra[ic], L.b[u] = rb[ic], L.c[u] = rc[ic];
+    }
+    L.e = 0;
+    if (lane == 63) L.e = ra[(uint32_t)(64 * (bp.w0 + kU) < M1 ? 64 * (bp.w0 + kU) : M1)];
+}
+
+template <typename T, int MODE, int U>
+__device__ __forceinline__ void generate_word(const VolDesc &d, const BatchPos &bp, const GenAux &A,
+                                              const PairLoads<T> &L, Stage &st, int lane)
+{
     const int32_t w = bp.w0 + U;
     const uint64_t own = readlane64(A.pmn, U);
     if (own == 0) return;  // no point: no quad and no stencil face either
-    const PlaneWords p = plane_words(cst(d.planes), g.N * g.O * g.WS, g.WS,
-                                     bp.j + g.N * (int64_t)bp.k, g.N, w);
-    const WordMasks m = word_masks(p, w, bp.j, bp.k, g);
+    PlaneWords p;
+    p.x00 = readlane64(A.pw, 0 * 4 + U), p.x10 = readlane64(A.pw, 1 * 4 + U);
+    p.x01 = readlane64(A.pw, 2 * 4 + U), p.x11 = readlane64(A.pw, 3 * 4 + U);
+    p.y00 = readlane64(A.pw, 4 * 4 + U), p.y00n = readlane64(A.pw, 5 * 4 + U);
+    p.y01 = readlane64(A.pw, 6 * 4 + U), p.y01n = readlane64(A.pw, 7 * 4 + U);
+    p.z00 = readlane64(A.pw, 8 * 4 + U), p.z00n = readlane64(A.pw, 9 * 4 + U);
+    p.z10 = readlane64(A.pw, 10 * 4 + U), p.z10n = readlane64(A.pw, 11 * 4 + U);
+    const WordMasks m = word_masks(p, w, bp.j, bp.k, d.g);
     const uint64_t mym = readlane64(A.pmn, 4 + U), myp = readlane64(A.pmn, 8 + U);
     const uint64_t mzm = readlane64(A.pmn, 12 + U), mzp = readlane64(A.pmn, 16 + U);
     const uint64_t mmm = readlane64(A.pmn, 20 + U);
-    const int32_t R0 = __builtin_amdgcn_readlane(A.wbp, U) + (int32_t)rank_below(m.pt);
+    const int32_t b0 = __builtin_amdgcn_readlane(A.wbp, U);
+    const int32_t bq = __builtin_amdgcn_readlane(A.wbq, U);
+    const int32_t bs = __builtin_amdgcn_readlane(A.wbs, U);
+    const int32_t r0 = (int32_t)rank_below(m.pt);
+    const int32_t R0 = b0 + r0;
     const int32_t Rym = __builtin_amdgcn_readlane(A.wbp, 4 + U) + (int32_t)rank_below(mym);
     const int32_t Ryp = __builtin_amdgcn_readlane(A.wbp, 8 + U) + (int32_t)rank_below(myp);
     const int32_t Rzm = __builtin_amdgcn_readlane(A.wbp, 12 + U) + (int32_t)rank_below(mzm);
     const int32_t Rzp = __builtin_amdgcn_readlane(A.wbp, 16 + U) + (int32_t)rank_below(mzp);
     const int32_t Rmm = __builtin_amdgcn_readlane(A.wbp, 20 + U) + (int32_t)rank_below(mmm);
     uint32_t fm = 0;
-    int32_t sp = 0;
+    int32_t sp = 0, ns = 0;
 #pragma unroll
     for (int f = 0; f < 6; ++f) {
         fm |= lane_bit(m.f[f], lane) << f;
         sp += (int32_t)rank_below(m.f[f]);
+        ns += __popcll(m.f[f]);
     }
+    const int32_t np = __popcll(m.pt);
+    // --- stage in LDS, in output order
     if (lane_bit(m.pt, lane)) {
         const int32_t i = 64 * w + lane;
-        store_point(glb(d.points), R0, (float)(d.origin[0] + d.spacing[0] * ((double)i + 0.5)),
-                    (float)(d.origin[1] + d.spacing[1] * ((double)bp.j + 0.5)),
-                    (float)(d.origin[2] + d.spacing[2] * ((double)bp.k + 0.5)));
-        glb(d.faces)[R0] = (uint8_t)fm;
-        int32_t s = __builtin_amdgcn_readlane(A.wbs, U) + sp;
-        glb(d.st_off)[R0] = s;
-        SN_GLOBAL int32_t *st_ids = glb(d.st_ids);
-        if (fm & 1u) st_ids[s++] = R0 - 1;
-        if (fm & 2u) st_ids[s++] = R0 + 1;
-        if (fm & 4u) st_ids[s++] = Rym;
-        if (fm & 8u) st_ids[s++] = Ryp;
-        if (fm & 16u) st_ids[s++] = Rzm;
-        if (fm & 32u) st_ids[s++] = Rzp;
+        st.pts[3 * r0 + 0] = (float)(d.origin[0] + d.spacing[0] * ((double)i + 0.5));
+        st.pts[3 * r0 + 1] = (float)(d.origin[1] + d.spacing[1] * ((double)bp.j + 0.5));
+        st.pts[3 * r0 + 2] = (float)(d.origin[2] + d.spacing[2] * ((double)bp.k + 0.5));
+        st.faces[r0] = (uint8_t)fm;
+        st.off[r0] = bs + sp;
+        int32_t e = sp;
+        if (fm & 1u) st.ids[e++] = R0 - 1;
+        if (fm & 2u) st.ids[e++] = R0 + 1;
+        if (fm & 4u) st.ids[e++] = Rym;
+        if (fm & 8u) st.ids[e++] = Ryp;
+        if (fm & 16u) st.ids[e++] = Rzm;
+        if (fm & 32u) st.ids[e++] = Rzp;
     }
-    SN_GLOBAL v4i *quads = glb(reinterpret_cast<v4i *>(d.quads));
-    int32_t q = __builtin_amdgcn_readlane(A.wbq, U) +
-                (int32_t)(rank_below(m.qx) + rank_below(m.qy) + rank_below(m.qz));
-    if (lane_bit(m.qx, lane)) {
-        quads[q] = v4i{Rmm, Rym, R0, Rzm};
-        store_pair<T>(d.pairs, q, c[0], c[1]);
-        ++q;
+    const uint64_t anyq = m.qx | m.qy | m.qz;
+    int32_t nq = 0;
+    if (anyq) {
+        nq = __popcll(m.qx) + __popcll(m.qy) + __popcll(m.qz);
+        using P = typename Pair<T>::type;
+        const uint32_t ca = classify<MODE>((uint32_t)L.a[U], d.cs);
+        uint32_t cn = __shfl_down(ca, 1u);
+        // computed in every lane: readlane must read a value lane 0 has produced
+        const uint32_t cnext = classify<MODE>((uint32_t)L.a[(U + 1) % kU], d.cs);
+        const uint32_t after = (U + 1 < kU) ? (uint32_t)__builtin_amdgcn_readlane((int)cnext, 0)
+                                            : classify<MODE>((uint32_t)L.e, d.cs);
+        if (lane == 63) cn = after;
+        const uint32_t cb = classify<MODE>((uint32_t)L.b[U], d.cs);
+        const uint32_t cc = classify<MODE>((uint32_t)L.c[U], d.cs);
+        int32_t q = (int32_t)(rank_below(m.qx) + rank_below(m.qy) + rank_below(m.qz));
+        P *pairs = reinterpret_cast<P *>(st.pairs);
+        auto pack = [](uint32_t f, uint32_t bk) { return (P)(T)f | ((P)(T)bk << Pair<T>::sh); };
+        if (lane_bit(m.qx, lane)) {
+            st.quads[q] = v4i{Rmm, Rym, R0, Rzm};
+            pairs[q] = pack(ca, cn);
+            ++q;
+        }
+        if (lane_bit(m.qy, lane)) {
+            st.quads[q] = v4i{Rzm - 1, Rzm, R0, R0 - 1};
+            pairs[q] = pack(ca, cb);
+            ++q;
+        }
+        if (lane_bit(m.qz, lane)) {
+            st.quads[q] = v4i{Rym - 1, R0 - 1, R0, Rym};
+            pairs[q] = pack(ca, cc);
+        }
     }
-    if (lane_bit(m.qy, lane)) {
-        quads[q] = v4i{Rzm - 1, Rzm, R0, R0 - 1};
-        store_pair<T>(d.pairs, q, c[0], c[2]);
-        ++q;
+    // LDS operations of one wave complete in order; this only stops the
+    // compiler from moving the copies above the staging writes.
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // --- consecutive-address copies to the output arrays
+    {
+        SN_GLOBAL float *gp = glb(d.points) + 3 * (int64_t)b0;
+        for (int32_t e = lane; e < 3 * np; e += 64) gp[e] = st.pts[e];
+        SN_GLOBAL int32_t *go = glb(d.st_off) + b0;
+        SN_GLOBAL uint8_t *gf = glb(d.faces) + b0;
+        if (lane < np) go[lane] = st.off[lane], gf[lane] = st.faces[lane];
+        SN_GLOBAL int32_t *gi = glb(d.st_ids) + bs;
+        for (int32_t e = lane; e < ns; e += 64) gi[e] = st.ids[e];
     }
-    if (lane_bit(m.qz, lane)) {
-        quads[q] = v4i{Rym - 1, R0 - 1, R0, Rym};
-        store_pair<T>(d.pairs, q, c[0], c[4]);
+    if (nq) {
+        using P = typename Pair<T>::type;
+        SN_GLOBAL v4i *gq = glb(reinterpret_cast<v4i *>(d.quads)) + bq;
+        SN_GLOBAL P *gpp = glb(static_cast<P *>(d.pairs)) + bq;
+        const P *pairs = reinterpret_cast<const P *>(st.pairs);
+        for (int32_t e = lane; e < nq; e += 64) gq[e] = st.quads[e], gpp[e] = pairs[e];
     }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 template <typename T, int MODE>
 __device__ __forceinline__ void generate_process(const VolDesc &d, const BatchPos &bp,
-                                                 const LabelLoads<T> &L, const GenAux &A, int lane)
+                                                 const GenAux &A, const PairLoads<T> &L, Stage &st,
+                                                 int lane)
 {
-    uint32_t c[kU][8];
-    corners<T, MODE>(L, d.cs, lane, c);
     static_assert(kU == 4, "generate_process unrolls four words");
     __builtin_amdgcn_sched_barrier(0);
-    generate_word<T, 0>(d, bp, c[0], A, lane);
+    generate_word<T, MODE, 0>(d, bp, A, L, st, lane);
     if (bp.nw > 1) {
         __builtin_amdgcn_sched_barrier(0);
-        generate_word<T, 1>(d, bp, c[1], A, lane);
+        generate_word<T, MODE, 1>(d, bp, A, L, st, lane);
     }
     if (bp.nw > 2) {
         __builtin_amdgcn_sched_barrier(0);
-        generate_word<T, 2>(d, bp, c[2], A, lane);
+        generate_word<T, MODE, 2>(d, bp, A, L, st, lane);
     }
     if (bp.nw > 3) {
         __builtin_amdgcn_sched_barrier(0);
-        generate_word<T, 3>(d, bp, c[3], A, lane);
+        generate_word<T, MODE, 3>(d, bp, A, L, st, lane);
     }
 }
 
 // nb consecutive batches from b0, two in flight.
 template <typename T, int MODE>
-__device__ void generate_stream(const VolDesc &d, int64_t b0, int nb, int lane)
+__device__ void generate_stream(const VolDesc &d, int64_t b0, int nb, int lane, Stage &st)
 {
     const T *vol = static_cast<const T *>(d.labels);
-    LabelLoads<T> L0, L1;
+    PairLoads<T> L0, L1;
     GenAux A0, A1;
     BatchPos P0 = batch_pos(d.g, b0), P1;
-    issue_labels<T>(vol, d.g, P0, lane, L0);
     issue_gen_aux(d, P0, lane, A0);
+    issue_pair_loads<T>(vol, d.g, P0, lane, L0);
     for (int q = 0; q < nb; q += 2) {
         if (q + 1 < nb) {
             P1 = P0;
             batch_next(d.g, P1);
-            issue_labels<T>(vol, d.g, P1, lane, L1);
             issue_gen_aux(d, P1, lane, A1);
+            issue_pair_loads<T>(vol, d.g, P1, lane, L1);
         }
-        generate_process<T, MODE>(d, P0, L0, A0, lane);
+        generate_process<T, MODE>(d, P0, A0, L0, st, lane);
         if (q + 1 >= nb) break;
         if (q + 2 < nb) {
             P0 = P1;
             batch_next(d.g, P0);
-            issue_labels<T>(vol, d.g, P0, lane, L0);
             issue_gen_aux(d, P0, lane, A0);
+            issue_pair_loads<T>(vol, d.g, P0, lane, L0);
         }
-        generate_process<T, MODE>(d, P1, L1, A1, lane);
+        generate_process<T, MODE>(d, P1, A1, L1, st, lane);
     }
 }
 
@@ -741,6 +775,7 @@ __global__ __launch_bounds__(kBlock) void k_generate(const VolDesc *__restrict__
                                                      const int64_t *__restrict__ tile_prefix,
                                                      int32_t nvol, int64_t tile_base, int32_t bpw)
 {
+    __shared__ Stage stage[kWavesPerBlock];
     const int64_t t = tile_base + blockIdx.x;
     const int v = find_seg(tile_prefix, nvol, t);
     const VolDesc &d = descs[v];
@@ -750,7 +785,7 @@ __global__ __launch_bounds__(kBlock) void k_generate(const VolDesc *__restrict__
     if (threadIdx.x == 0 && t == tile_prefix[v]) glb(d.st_off)[d.P] = (int32_t)d.S;
     const int64_t b0 = bt0 + (int64_t)wave * bpw;
     const int64_t nb = nbv - b0 < bpw ? nbv - b0 : bpw;
-    if (nb > 0) generate_stream<T, MODE>(d, b0, (int)nb, lane);
+    if (nb > 0) generate_stream<T, MODE>(d, b0, (int)nb, lane, stage[wave]);
 }
 
 // ---------------------------------------------------------------------------
