@@ -40,30 +40,43 @@ def log(*a):
 
 
 # --------------------------------------------------------------------------
-# algorithmic bytes (what the method must move; metadata is overhead)
+# algorithmic bytes: what the method itself must move.  Input labels, the
+# output mesh and, per sweep, the offsets and the stencil.  Metadata of this
+# design (cut-edge bit planes, point masks, word bases, the per-point face
+# byte) is overhead and is not counted; `design_bytes` adds it back as the
+# bytes each kernel reads or writes once in this implementation.
 # --------------------------------------------------------------------------
 
-def bytes_count(V, b):
-    """k_count: read the label volume once."""
-    return V * b
+def words_of(dims):
+    M, N, O = dims
+    R = max(N - 1, 0) * max(O - 1, 0)
+    W = (max(M - 1, 0) + 63) // 64
+    WS = (M + 63) // 64
+    return R * W, 3 * N * O * WS * 8  # cell words, plane bytes
 
 
-def bytes_generate(V, b, P, Q, S):
-    """k_generate: read the volume, write points (12 B), stencil offsets (4 B),
-    quads (16 B), label pairs (2b B) and stencil ids (4 B)."""
-    return V * b + 12 * P + 4 * (P + 1) + Q * (16 + 2 * b) + 4 * S
+def bytes_extract(V, b, P, Q, S):
+    """Whole extraction: read the labels once; write points (12 B) and CSR
+    offsets (4 B) per point, quads (16 B) and label pairs (2b B) per quad,
+    4 B per stencil id."""
+    return V * b + 16 * P + 4 + Q * (16 + 2 * b) + 4 * S
 
 
-def bytes_jacobi_avg(P, S, n):
-    """k_jacobi, averaged over n sweeps: read own offset (all but the first
-    sweep), faces byte, CSR offset, stencil ids; write the new offset.
-    Neighbour offsets are re-reads of the same array (reuse, not counted)."""
-    return P * (12.0 * (n - 1) / n + 12 + 1 + 4) + 4 * S
-
-
-def bytes_emit(P):
-    """k_emit: read the final offsets, write world points."""
-    return 24 * P
+def alg_bytes(dims, b, P, Q, S, n):
+    V = dims[0] * dims[1] * dims[2]
+    words, planes = words_of(dims)
+    out_gen = 16 * P + 4 + Q * (16 + 2 * b) + 4 * S
+    return {
+        # kernel: (algorithmic, design)
+        "k_edges": (V * b, V * b + planes),
+        "k_count": (0, planes + 20 * words),
+        "k_generate": (out_gen, out_gen + P + planes + 20 * words + V * b),
+        # per sweep: read own offset and CSR offset, stencil ids, write offset;
+        # neighbour offsets are re-reads of the array being read (not counted)
+        "k_jacobi": (P * (12 + 12 + 4) + 4 * S, P * (12 + 12 + 4 + 1) + 4 * S),
+        # read the final offsets, write world points
+        "k_emit": (24 * P, 24 * P),
+    }
 
 
 # --------------------------------------------------------------------------
@@ -102,15 +115,19 @@ def measure_workload(ctx, sn, torch, vol, steps, warmup):
     for name, (launches, ms) in prof.items():
         per[name] = {"launches": launches, "avg_us": 1e3 * ms / max(launches, 1),
                      "total_ms": ms}
-    alg = {"k_count": bytes_count(V, b), "k_generate": bytes_generate(V, b, P, Q, S),
-           "k_jacobi": bytes_jacobi_avg(P, S, n), "k_emit": bytes_emit(P)}
+    alg = alg_bytes(vol.dims, b, P, Q, S, n)
     for name, d in per.items():
         if name in alg:
-            d["alg_bytes"] = alg[name]
-            d["achieved_GBs"] = alg[name] / (d["avg_us"] * 1e-6) / 1e9
+            a, dsg = alg[name]
+            d["alg_bytes"] = a
+            d["design_bytes"] = dsg
+            d["achieved_GBs"] = a / (d["avg_us"] * 1e-6) / 1e9
             d["frac_hbm"] = d["achieved_GBs"] / HBM_PEAK_GBS
-    ext_ms = sum(per.get(k, {}).get("total_ms", 0.0) for k in ("k_count", "k_generate")) / steps
+            d["design_GBs"] = dsg / (d["avg_us"] * 1e-6) / 1e9
+    ext_ms = sum(per.get(k, {}).get("total_ms", 0.0)
+                 for k in ("k_edges", "k_count", "k_generate")) / steps
     smo_ms = sum(per.get(k, {}).get("total_ms", 0.0) for k in ("k_jacobi", "k_emit")) / steps
+    bx = bytes_extract(V, b, P, Q, S)
     res = {
         "voxels": V, "points": P, "quads": Q, "stencil": S, "iterations": n,
         "ms_per_step": 1e3 * wall / steps,
@@ -119,7 +136,9 @@ def measure_workload(ctx, sn, torch, vol, steps, warmup):
         "smooth_kernel_ms": smo_ms,
         "extract_gvox_per_s": V / (ext_ms * 1e-3) / 1e9 if ext_ms > 0 else None,
         "smooth_gptit_per_s": P * n / (smo_ms * 1e-3) / 1e9 if smo_ms > 0 else None,
-        "extract_alg_GBs": (bytes_generate(V, b, P, Q, S)) / (ext_ms * 1e-3) / 1e9 if ext_ms > 0 else None,
+        "extract_alg_bytes": bx,
+        "extract_alg_GBs": bx / (ext_ms * 1e-3) / 1e9 if ext_ms > 0 else None,
+        "extract_frac_hbm": bx / (ext_ms * 1e-3) / 1e9 / HBM_PEAK_GBS if ext_ms > 0 else None,
         "kernels": per,
     }
     del t
@@ -128,7 +147,7 @@ def measure_workload(ctx, sn, torch, vol, steps, warmup):
 
 def roofline_of(res, traffic=None):
     per = res["kernels"]
-    dom = max((k for k in per if "alg_bytes" in per[k]), key=lambda k: per[k]["total_ms"])
+    dom = max((k for k in per if per[k].get("alg_bytes")), key=lambda k: per[k]["total_ms"])
     d = per[dom]
     return {"kernel": dom, "bound": "hbm", "achieved": round(d["achieved_GBs"], 1),
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(d["frac_hbm"], 4),
@@ -282,6 +301,77 @@ def bench_served(ctx, sn, torch, n_requests=240, pool=16, seed=5):
             "p99_speedup": round(plain["p99_ms"] / max(served["p99_ms"], 1e-9), 3)}
 
 
+COPY_PROBE_BYTES = 256 << 20
+
+
+def copy_probe(torch, reps=5):
+    """A plain streaming kernel of known size (int32 bitwise_not: reads and
+    writes COPY_PROBE_BYTES each), timed with events; under rocprofv3 --pmc its
+    FETCH_SIZE / WRITE_SIZE calibrate the counters of the library's kernels."""
+    n = COPY_PROBE_BYTES // 4
+    src = torch.arange(n, dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.bitwise_not(src, out=dst)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        torch.bitwise_not(src, out=dst)
+    e1.record()
+    torch.cuda.synchronize()
+    us = e0.elapsed_time(e1) * 1e3 / reps
+    assert int(dst[12345]) == ~12345
+    return {"bytes_read": COPY_PROBE_BYTES, "bytes_written": COPY_PROBE_BYTES,
+            "avg_us": round(us, 2), "GBs": round(2 * COPY_PROBE_BYTES / (us * 1e-6) / 1e9, 1)}
+
+
+def pmc_summary(pmc_dir, out_path, workload):
+    """Reduce rocprofv3 --pmc runs (FETCH_SIZE in one, WRITE_SIZE in another,
+    CSV output) of `bench.py --copy-probe` to HBM bytes per dispatch of each
+    library kernel, each counter scaled by what it reads for the copy probe
+    (known bytes / counted bytes).  Merged into the JSON file under
+    `workload`."""
+    import csv
+    import glob
+
+    acc = {}
+    for f in sorted(glob.glob(os.path.join(pmc_dir, "**", "*counter_collection.csv"),
+                              recursive=True)):
+        for row in csv.DictReader(open(f)):
+            name = row["Kernel_Name"]
+            if "bitwise_not" in name:
+                key = "copy_probe"
+            else:
+                key = name.split("(")[0].split("<")[0].replace("void ", "").replace("sn::", "")
+                key = key.strip()
+            c = row["Counter_Name"]
+            d = acc.setdefault(key, {}).setdefault(c, {})
+            disp = row.get("Dispatch_Id") or row.get("Correlation_Id") or str(len(d))
+            d[disp] = d.get(disp, 0.0) + float(row["Counter_Value"])
+    mean = {k: {c: sum(v.values()) / len(v) for c, v in cs.items()} for k, cs in acc.items()}
+    if "copy_probe" not in mean:
+        raise SystemExit("pmc summary: no copy probe dispatches found")
+    cp = mean["copy_probe"]
+    f_rd = COPY_PROBE_BYTES / (cp["FETCH_SIZE"] * 1024.0)
+    f_wr = COPY_PROBE_BYTES / (cp["WRITE_SIZE"] * 1024.0)
+    res = {"calibration": {"copy_bytes": COPY_PROBE_BYTES, "fetch_kib": cp["FETCH_SIZE"],
+                           "write_kib": cp["WRITE_SIZE"], "read_factor": round(f_rd, 4),
+                           "write_factor": round(f_wr, 4)}}
+    for k, cs in mean.items():
+        if k == "copy_probe" or "FETCH_SIZE" not in cs or "WRITE_SIZE" not in cs:
+            continue
+        res[k] = {"fetch_kib": round(cs["FETCH_SIZE"], 1), "write_kib": round(cs["WRITE_SIZE"], 1),
+                  "bytes": int(cs["FETCH_SIZE"] * 1024 * f_rd + cs["WRITE_SIZE"] * 1024 * f_wr)}
+    allj = {}
+    if os.path.exists(out_path):
+        allj = json.load(open(out_path))
+    allj[workload] = res
+    with open(out_path, "w") as fh:
+        json.dump(allj, fh, indent=1, sort_keys=True)
+        fh.write("\n")
+    print(json.dumps(res, indent=1))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -292,7 +382,14 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"),
                     help="HBM traffic per launch from rocprofv3 counters, if measured")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a plain streaming kernel of known size (counter calibration)")
+    ap.add_argument("--pmc-summary", metavar="DIR",
+                    help="no GPU work: reduce rocprofv3 --pmc output in DIR into --traffic-json")
     args = ap.parse_args()
+    if args.pmc_summary:
+        pmc_summary(args.pmc_summary, args.traffic_json, args.workload)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (the method here has no multi-GPU path); "
               f"--gpus {args.gpus} is not supported", file=sys.stderr)
@@ -315,14 +412,14 @@ def main():
     res = measure_workload(ctx, sn, torch, vol, args.steps, args.warmup)
     log(f"[bench] {vol.name}: {res['ms_per_step']:.3f} ms/step, {res['gvox_per_s']:.2f} Gvox/s")
 
+    probe = copy_probe(torch) if args.copy_probe else None
     traffic = None
+    dom = roofline_of(res)["kernel"]
     if os.path.exists(args.traffic_json):
-        try:
-            tj = json.load(open(args.traffic_json))
-            traffic = tj.get(vol.name)
-        except Exception:
-            traffic = None
-    roof = roofline_of(res, (traffic or {}).get(roofline_of(res)["kernel"]) if traffic else None)
+        tj = json.load(open(args.traffic_json)).get(args.workload, {})
+        if dom in tj:
+            traffic = tj[dom]["bytes"]
+    roof = roofline_of(res, traffic)
 
     extra = {}
     if not args.no_extra:
@@ -333,6 +430,8 @@ def main():
                 "name": cvol.name, "ms_per_step": round(r3["ms_per_step"], 3),
                 "gvox_per_s": round(r3["gvox_per_s"], 3),
                 "extract_gvox_per_s": round(r3["extract_gvox_per_s"], 3),
+                "extract_alg_GBs": round(r3["extract_alg_GBs"], 1),
+                "extract_frac_hbm": round(r3["extract_frac_hbm"], 4),
                 "smooth_gptit_per_s": round(r3["smooth_gptit_per_s"], 3),
                 "points": r3["points"], "quads": r3["quads"],
                 "roofline": roofline_of(r3),
@@ -361,9 +460,13 @@ def main():
         "kernels": {k: {kk: (round(vv, 3) if isinstance(vv, float) else vv) for kk, vv in d.items()}
                     for k, d in res["kernels"].items()},
         "roofline": roof,
+        "extract_alg_GBs": round(res["extract_alg_GBs"], 1),
+        "extract_frac_hbm": round(res["extract_frac_hbm"], 4),
         "cpu_baseline": cpu,
         "extra": extra,
     }
+    if probe:
+        line["copy_probe"] = probe
     print(json.dumps(line), flush=True)
     ctx.close()
 

@@ -122,6 +122,9 @@ typedef struct sn_mesh_view {
  * of schedule choices) and SN_TEST_MEM_LIMIT (a byte cap on the library's
  * device pool, used by tests to force SN_ENOMEM) from the environment. */
 sn_status sn_ctx_create(int device, sn_ctx **out);
+/* Release the caller's handle.  Meshes and servers made by the context hold
+ * it alive: its device memory and streams go when the last of them is freed
+ * (sn_mesh_free, sn_serve_stop), so meshes may be freed in any order. */
 void sn_ctx_destroy(sn_ctx *ctx);
 const char *sn_strerror(sn_status s);
 /* Text of the last error raised on this host thread ("" if none). */
@@ -214,7 +217,7 @@ sn_status sn_autotune(sn_ctx *ctx, const sn_volume *vol, void *stream, int32_t *
 sn_status sn_set_batches_per_wave(sn_ctx *ctx, int32_t batches_per_wave);
 
 /* Per-kernel timing: with on = 1 every library kernel launch is bracketed by
- * HIP events on the stream it runs on, and a replay of the captured sweep
+ * HIP events on the stream it runs on, and a replay of the sweep
  * graph is bracketed as a whole (counted as `iterations` launches of
  * k_jacobi); with on = 2 the sweeps are launched one by one instead, each with
  * its own events.  on = 0 turns timing off.  sn_profile_read synchronises,

@@ -76,18 +76,27 @@ struct VolDesc {
     int64_t P, Q, S;
 };
 
-// One mesh's smoothing job.
+// One mesh's smoothing job.  Sweep 0 reads the CSR stencil (off, ids) and
+// writes nbr: per point the ids of its -y, +y, -z, +z stencil neighbours
+// (-1 where absent); later sweeps read nbr and take the -x / +x neighbours,
+// which are always points p-1 / p+1, from the neighbouring lanes.
 struct SmoothDesc {
     int64_t P;
     const uint8_t *faces;
     const int32_t *off;
     const int32_t *ids;
+    int32_t *nbr;  // [P][4]
     float *da;
     float *db;
     int32_t iters;
     double lam;
     double dist;
 };
+
+// A smoothing block covers kSweepPoints consecutive points: each wave holds
+// kSweepChunks chunks of 64 points.
+constexpr int kSweepChunks = 2;
+constexpr int kSweepPoints = kBlock * kSweepChunks;
 
 // Scan tile status word: [63:62] flag, [61:0] value.
 constexpr uint64_t kFlagAgg = 1ull << 62;
@@ -114,9 +123,14 @@ hipError_t launch_generate(int32_t dtype, int32_t mode, const VolDesc *d_descs,
                            int64_t ntiles, int32_t bpw, hipStream_t s);
 hipError_t launch_emit(const VolDesc *d_descs, const int64_t *d_tile_prefix, int32_t nvol,
                        int64_t ntiles, int32_t bpw, hipStream_t s);
-// block_prefix[v] = first block of volume v (256 points per block)
+// block_prefix[v] = first block of volume v (kSweepPoints points per block);
+// it = 0 runs the first sweep (zero input offsets, builds nbr)
 hipError_t launch_jacobi(const SmoothDesc *d_sd, const int64_t *d_block_prefix, int32_t nvol,
                          int64_t nblocks, int32_t it, hipStream_t s);
+// the same n sweeps as kernel nodes of `graph`, each depending on the one before
+hipError_t add_jacobi_nodes(hipGraph_t graph, const SmoothDesc *d_sd,
+                            const int64_t *d_block_prefix, int32_t nvol, int64_t nblocks,
+                            int32_t iters);
 // quad blocks (256 quads per block) of the volumes with prim 3
 hipError_t launch_triangulate(const VolDesc *d_descs, const int64_t *d_block_prefix, int32_t nvol,
                               int64_t nblocks, hipStream_t s);

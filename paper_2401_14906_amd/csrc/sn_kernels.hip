@@ -1,23 +1,26 @@
 // SurfaceNets extraction and smoothing kernels for gfx950 (MI355X).
 //
-// Word kernels.  Cells are enumerated in linear order and cut into 64-cell
-// words (see sn_internal.h); lane L of a wavefront owns cell 64w + L of word
-// w and the sample at its origin.  A wavefront takes a batch of kU words of
-// one row and issues all 4*kU sample-row loads of the batch before using any
-// (the +x corner comes from the next lane).  The twelve edge cuts of a cell
-// are twelve compares whose wave ballots are 64-bit masks; points, stencil
-// faces and quads are mask algebra on scalar registers, and every rank inside
-// a word is an mbcnt.  This replaces the paper's triad byte volume, trim
-// intervals, checkerboarded PRODUCE_POINT bits and 3x3 row iterator
-// (Sec. 3.2-3.6) with a 1-bit point plane and per-word prefix bases.
+// Extraction works on bit planes and 64-cell words.  k_edges reads the label
+// volume once, with wide coalesced row loads, and writes three cut-edge bit
+// planes X, Y, Z (one bit per lattice sample and axis: the edge from the
+// sample to its +x, +y or +z neighbour is cut).  Cells are enumerated in
+// linear order and cut into 64-cell words (see sn_internal.h); every later
+// step is mask algebra on 64-bit words of those planes: a cell's twelve edges
+// are bits of four plane rows, its point bit is their OR, a face's cut test
+// is the OR of four, and every rank inside a word is an mbcnt.  This replaces
+// the paper's triad byte volume, trim intervals, checkerboarded point bits
+// and 3x3 row iterator (Sec. 3.2-3.6) with bit planes, a 1-bit point plane
+// and per-word prefix bases.
 //
-//   k_count    : classify, cut edges, per-word point/quad/stencil counts and the
-//                point-bit plane; a fused single-pass (decoupled look-back) scan
-//                of the word counts gives every word its first point id, quad
-//                index and stencil index (Sec. 2.3 passes 1-3 and the prefix sum).
+//   k_edges    : classification and cut-edge planes (Sec. 2.3 passes 1-2).
+//   k_count    : per-word point / quad / stencil counts and the point-bit
+//                plane, with a fused single-pass (decoupled look-back) scan
+//                that gives every word its first point id, quad index and
+//                stencil index (Sec. 2.3 pass 3 and the prefix sum).
 //   k_generate : points, stencil CSR, quads and label pairs written at those
 //                bases, without atomics (Sec. 2.3 pass 4).
-//   k_jacobi   : one double-buffered sweep of Eq. (1) with the box constraint
+//   k_jacobi_first, k_jacobi
+//              : double-buffered sweeps of Eq. (1) with the box constraint
 //                (Sec. 2.2, 2.4), on cell-relative offsets.
 //   k_emit     : world coordinates of the points from the offsets.
 //   k_tri      : two triangles per quad (Sec. 2.5).
@@ -868,56 +871,198 @@ __global__ __launch_bounds__(kBlock) void k_emit(const VolDesc *__restrict__ des
 // ---------------------------------------------------------------------------
 // k_jacobi: one sweep of Eq. (1) on the offsets, FP64 arithmetic, FP32 storage
 // ---------------------------------------------------------------------------
+// The offset of point p moves by lambda times the mean over its stencil
+// neighbours q of (p_q - p_p) = (unit face step) + (delta_q - delta_p), then
+// is clamped to the box [-d, d]^3 (Sec. 2.4, Eq. (1)).  Neighbours are summed
+// in face order -x, +x, -y, +y, -z, +z.
 
-__global__ __launch_bounds__(256) void k_jacobi(const SmoothDesc *__restrict__ sds,
-                                                const int64_t *__restrict__ block_prefix,
-                                                int32_t nvol, int32_t it)
+// Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
+// contiguous range of logical blocks so that stencil neighbours (a row or a
+// slice of points away) are mostly in its own L2.
+__device__ __forceinline__ int64_t xcd_block(uint32_t b, uint32_t nb)
 {
-    const int64_t b = blockIdx.x;
-    const int v = find_seg(block_prefix, nvol, b);
-    const SmoothDesc &s = sds[v];
-    if (it >= s.iters) return;  // this mesh has finished its sweeps
-    const int64_t p = (b - block_prefix[v]) * 256 + threadIdx.x;
-    if (p >= s.P) return;
-    const SN_GLOBAL float *din = glb((it & 1) ? s.db : s.da);
-    SN_GLOBAL float *dout = glb((it & 1) ? s.da : s.db);
-    const bool zero_in = (it == 0);
-    const uint32_t f = glb(s.faces)[p];
-    double x = 0.0, y = 0.0, z = 0.0;
-    if (!zero_in) {
-        x = (double)din[3 * p], y = (double)din[3 * p + 1], z = (double)din[3 * p + 2];
-    }
-    const int n = __popc(f);
-    if (n > 0) {
-        const SN_GLOBAL int32_t *ids = glb(s.ids);
-        double sx = 0.0, sy = 0.0, sz = 0.0;
-        int64_t e = glb(s.off)[p];
-#pragma unroll
-        for (int face = 0; face < 6; ++face) {
-            if (!((f >> face) & 1u)) continue;
-            const int64_t q = ids[e++];
-            double nx = 0.0, ny = 0.0, nz = 0.0;
-            if (!zero_in) {
-                nx = (double)din[3 * q], ny = (double)din[3 * q + 1], nz = (double)din[3 * q + 2];
-            }
-            // p_q - p_p = unit face step + offset difference
-            const double step = (face & 1) ? 1.0 : -1.0;
-            sx += (face >> 1) == 0 ? step + nx - x : nx - x;
-            sy += (face >> 1) == 1 ? step + ny - y : ny - y;
-            sz += (face >> 1) == 2 ? step + nz - z : nz - z;
-        }
-        const double inv = 1.0 / (double)n;
-        x = x + s.lam * (sx * inv);
-        y = y + s.lam * (sy * inv);
-        z = z + s.lam * (sz * inv);
-    }
-    const double c = s.dist;
+    const uint32_t x = b & 7u, i = b >> 3, q = nb >> 3, r = nb & 7u;
+    return (int64_t)x * q + (x < r ? x : r) + i;
+}
+
+__device__ __forceinline__ double face_term(int face, int axis, double n, double own)
+{
+    // component `axis` of p_q - p_p for the neighbour across `face`
+    const double step = (face & 1) ? 1.0 : -1.0;
+    return (face >> 1) == axis ? step + n - own : n - own;
+}
+
+__device__ __forceinline__ void store_offset(SN_GLOBAL float *dout, int64_t p, double x, double y,
+                                             double z, double c)
+{
     x = fmin(fmax(x, -c), c);
     y = fmin(fmax(y, -c), c);
     z = fmin(fmax(z, -c), c);
     dout[3 * p] = (float)x;
     dout[3 * p + 1] = (float)y;
     dout[3 * p + 2] = (float)z;
+}
+
+// Sweep 0: every input offset is zero, so p_q - p_p is the face step alone.
+// Reads the CSR stencil once and writes the y/z neighbour table.
+__global__ __launch_bounds__(256) void k_jacobi_first(const SmoothDesc *__restrict__ sds,
+                                                      const int64_t *__restrict__ block_prefix,
+                                                      int32_t nvol)
+{
+    const int64_t b = xcd_block(blockIdx.x, gridDim.x);
+    const int v = find_seg(block_prefix, nvol, b);
+    const SmoothDesc &s = sds[v];
+    if (s.iters < 1) return;
+    SN_GLOBAL float *dout = glb(s.db);
+#pragma unroll
+    for (int c = 0; c < kSweepChunks; ++c) {
+        const int64_t p = (b - block_prefix[v]) * kSweepPoints + c * kBlock + threadIdx.x;
+        if (p >= s.P) break;
+        const uint32_t f = glb(s.faces)[p];
+        const int n = __popc(f);
+        int64_t e = glb(s.off)[p];
+        v4i q = {-1, -1, -1, -1};
+        double sx = 0.0, sy = 0.0, sz = 0.0;
+#pragma unroll
+        for (int face = 0; face < 6; ++face) {
+            if (!((f >> face) & 1u)) continue;
+            const int32_t id = glb(s.ids)[e++];
+            if (face == 2) q.x = id;
+            if (face == 3) q.y = id;
+            if (face == 4) q.z = id;
+            if (face == 5) q.w = id;
+            sx += face_term(face, 0, 0.0, 0.0);
+            sy += face_term(face, 1, 0.0, 0.0);
+            sz += face_term(face, 2, 0.0, 0.0);
+        }
+        glb(reinterpret_cast<v4i *>(s.nbr))[p] = q;
+        double x = 0.0, y = 0.0, z = 0.0;
+        if (n > 0) {
+            const double inv = 1.0 / (double)n;
+            x = x + s.lam * (sx * inv);
+            y = y + s.lam * (sy * inv);
+            z = z + s.lam * (sz * inv);
+        }
+        store_offset(dout, p, x, y, z, s.dist);
+    }
+}
+
+__device__ __forceinline__ float shfl_up1(float x)
+{
+    return __shfl_up(x, 1u);
+}
+
+__device__ __forceinline__ float shfl_down1(float x)
+{
+    return __shfl_down(x, 1u);
+}
+
+__device__ __forceinline__ float readlane_f(float x, int l)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
+}
+
+// Sweeps 1..n-1.  Each wave holds kSweepChunks chunks of 64 consecutive
+// points, one point per lane and chunk; all loads of the wave are issued
+// before any use.  The -x / +x neighbours of point p are points p - 1 / p + 1
+// (consecutive cells of a row get consecutive ids), read from the adjacent
+// lane; only the first and the last point of the wave load them.
+__global__ __launch_bounds__(256) void k_jacobi(const SmoothDesc *__restrict__ sds,
+                                                const int64_t *__restrict__ block_prefix,
+                                                int32_t nvol, int32_t it)
+{
+    constexpr int K = kSweepChunks;
+    const int64_t b = xcd_block(blockIdx.x, gridDim.x);
+    const int v = find_seg(block_prefix, nvol, b);
+    const SmoothDesc &s = sds[v];
+    if (it >= s.iters) return;  // this mesh has finished its sweeps
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int64_t p0 = (b - block_prefix[v]) * kSweepPoints + (int64_t)wave * (64 * K);
+    const int64_t P = s.P;
+    if (p0 >= P) return;
+    const SN_GLOBAL float *din = glb((it & 1) ? s.db : s.da);
+    SN_GLOBAL float *dout = glb((it & 1) ? s.da : s.db);
+    const SN_GLOBAL v4i *nbr = glb(reinterpret_cast<const v4i *>(s.nbr));
+
+    uint32_t f[K];
+    v4i nb[K];
+    float ox[K], oy[K], oz[K];
+#pragma unroll
+    for (int c = 0; c < K; ++c) {
+        const int64_t p = p0 + 64 * c + lane;
+        f[c] = 0, nb[c] = v4i{-1, -1, -1, -1}, ox[c] = oy[c] = oz[c] = 0.f;
+        if (p < P) {
+            f[c] = glb(s.faces)[p];
+            nb[c] = nbr[p];
+            ox[c] = din[3 * p], oy[c] = din[3 * p + 1], oz[c] = din[3 * p + 2];
+        }
+    }
+    // wave halo: -x of the first point, +x of the last one (p0 + 64K - 1)
+    float hmx = 0.f, hmy = 0.f, hmz = 0.f, hpx = 0.f, hpy = 0.f, hpz = 0.f;
+    if (lane == 0 && (f[0] & 1u)) {
+        hmx = din[3 * (p0 - 1)], hmy = din[3 * (p0 - 1) + 1], hmz = din[3 * (p0 - 1) + 2];
+    }
+    if (lane == 63 && (f[K - 1] & 2u)) {
+        const int64_t q = p0 + 64 * K;
+        hpx = din[3 * q], hpy = din[3 * q + 1], hpz = din[3 * q + 2];
+    }
+    // y / z neighbours
+    float gx[K][4], gy[K][4], gz[K][4];
+#pragma unroll
+    for (int c = 0; c < K; ++c) {
+        const int32_t id[4] = {nb[c].x, nb[c].y, nb[c].z, nb[c].w};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            gx[c][e] = gy[c][e] = gz[c][e] = 0.f;
+            if (id[e] >= 0) {
+                const int64_t q = id[e];
+                gx[c][e] = din[3 * q], gy[c][e] = din[3 * q + 1], gz[c][e] = din[3 * q + 2];
+            }
+        }
+    }
+    // x neighbours, exchanged with every lane of the wave active:
+    // -x from lane - 1 (lane 0: the previous chunk's lane 63, or the halo),
+    // +x from lane + 1 (lane 63: the next chunk's lane 0, or the halo)
+    float mx[K], my[K], mz[K], px[K], py[K], pz[K];
+#pragma unroll
+    for (int c = 0; c < K; ++c) {
+        mx[c] = shfl_up1(ox[c]), my[c] = shfl_up1(oy[c]), mz[c] = shfl_up1(oz[c]);
+        px[c] = shfl_down1(ox[c]), py[c] = shfl_down1(oy[c]), pz[c] = shfl_down1(oz[c]);
+        const float lmx = c > 0 ? readlane_f(ox[c > 0 ? c - 1 : 0], 63) : hmx;
+        const float lmy = c > 0 ? readlane_f(oy[c > 0 ? c - 1 : 0], 63) : hmy;
+        const float lmz = c > 0 ? readlane_f(oz[c > 0 ? c - 1 : 0], 63) : hmz;
+        const float lpx = c + 1 < K ? readlane_f(ox[c + 1 < K ? c + 1 : 0], 0) : hpx;
+        const float lpy = c + 1 < K ? readlane_f(oy[c + 1 < K ? c + 1 : 0], 0) : hpy;
+        const float lpz = c + 1 < K ? readlane_f(oz[c + 1 < K ? c + 1 : 0], 0) : hpz;
+        if (lane == 0) mx[c] = lmx, my[c] = lmy, mz[c] = lmz;
+        if (lane == 63) px[c] = lpx, py[c] = lpy, pz[c] = lpz;
+    }
+#pragma unroll
+    for (int c = 0; c < K; ++c) {
+        const int64_t p = p0 + 64 * c + lane;
+        if (p >= P) continue;
+        const uint32_t fc = f[c];
+        double x = (double)ox[c], y = (double)oy[c], z = (double)oz[c];
+        const int n = __popc(fc);
+        if (n > 0) {
+            const float nx[6] = {mx[c], px[c], gx[c][0], gx[c][1], gx[c][2], gx[c][3]};
+            const float ny[6] = {my[c], py[c], gy[c][0], gy[c][1], gy[c][2], gy[c][3]};
+            const float nz[6] = {mz[c], pz[c], gz[c][0], gz[c][1], gz[c][2], gz[c][3]};
+            double sx = 0.0, sy = 0.0, sz = 0.0;
+#pragma unroll
+            for (int face = 0; face < 6; ++face) {
+                if (!((fc >> face) & 1u)) continue;
+                sx += face_term(face, 0, (double)nx[face], x);
+                sy += face_term(face, 1, (double)ny[face], y);
+                sz += face_term(face, 2, (double)nz[face], z);
+            }
+            const double inv = 1.0 / (double)n;
+            x = x + s.lam * (sx * inv);
+            y = y + s.lam * (sy * inv);
+            z = z + s.lam * (sz * inv);
+        }
+        store_offset(dout, p, x, y, z, s.dist);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1015,9 +1160,38 @@ hipError_t launch_jacobi(const SmoothDesc *d_sd, const int64_t *d_block_prefix, 
                          int64_t nblocks, int32_t it, hipStream_t s)
 {
     if (nblocks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_jacobi, dim3((uint32_t)nblocks), dim3(256), 0, s, d_sd, d_block_prefix,
-                       nvol, it);
+    if (it == 0)
+        hipLaunchKernelGGL(k_jacobi_first, dim3((uint32_t)nblocks), dim3(256), 0, s, d_sd,
+                           d_block_prefix, nvol);
+    else
+        hipLaunchKernelGGL(k_jacobi, dim3((uint32_t)nblocks), dim3(256), 0, s, d_sd,
+                           d_block_prefix, nvol, it);
     return hipGetLastError();
+}
+
+hipError_t add_jacobi_nodes(hipGraph_t graph, const SmoothDesc *d_sd,
+                            const int64_t *d_block_prefix, int32_t nvol, int64_t nblocks,
+                            int32_t iters)
+{
+    hipGraphNode_t prev = nullptr;
+    for (int32_t it = 0; it < iters && nblocks > 0; ++it) {
+        void *args_first[] = {&d_sd, &d_block_prefix, &nvol};
+        void *args[] = {&d_sd, &d_block_prefix, &nvol, &it};
+        hipKernelNodeParams kp{};
+        kp.func = it == 0 ? reinterpret_cast<void *>(&k_jacobi_first)
+                          : reinterpret_cast<void *>(&k_jacobi);
+        kp.gridDim = dim3((uint32_t)nblocks);
+        kp.blockDim = dim3(256);
+        kp.sharedMemBytes = 0;
+        kp.kernelParams = it == 0 ? args_first : args;
+        kp.extra = nullptr;
+        hipGraphNode_t node;
+        const hipError_t e =
+            hipGraphAddKernelNode(&node, graph, prev ? &prev : nullptr, prev ? 1 : 0, &kp);
+        if (e != hipSuccess) return e;
+        prev = node;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_triangulate(const VolDesc *d_descs, const int64_t *d_block_prefix, int32_t nvol,

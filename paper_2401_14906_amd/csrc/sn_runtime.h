@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <map>
 #include <mutex>
 #include <string>
@@ -56,10 +57,11 @@ struct sn_ctx {
     explicit sn_ctx(int dev);
     ~sn_ctx();
     int device;
+    // one reference for the caller's handle and one per live mesh or server
+    std::atomic<int64_t> refs{1};
     sn::Pool pool;    // device blocks
     sn::Pool pinned;  // pinned host staging
-    hipStream_t capture_stream = nullptr;
-    std::mutex capture_mu;
+    hipStream_t copy_stream = nullptr;  // non-blocking, for copies to the host
     // profiling
     bool profiling = false;
     bool profile_eager = false;  // sweeps launched one by one instead of a graph
@@ -89,12 +91,13 @@ struct sn_mesh {
     int32_t bpw = 2;
     std::vector<void *> blocks;  // every device block owned by the mesh
     float *da = nullptr, *db = nullptr;
+    int32_t *nbr = nullptr;  // [P][4] y/z stencil neighbours, written by sweep 0
     const float *final_delta = nullptr;
     sn::VolDesc *dd = nullptr;     // device copy of d
     int64_t *dtp = nullptr;        // device tile prefix {0, ntiles}
     sn::SmoothDesc *dsd = nullptr; // device smoothing descriptor
     int64_t *dbp = nullptr;        // device block prefix {0, point blocks}
-    std::map<int32_t, hipGraphExec_t> graphs;  // sweeps -> captured graph
+    std::map<int32_t, hipGraphExec_t> graphs;  // sweeps -> instantiated sweep graph
     hipEvent_t done_ev = nullptr;
     bool last_stream_valid = false;
 };
@@ -125,5 +128,7 @@ sn_status run_sweeps(sn_ctx *c, const SmoothDesc *d_sd, const int64_t *d_bp, int
                      std::map<int32_t, hipGraphExec_t> *cache);
 sn_status mesh_mark(sn_mesh *m, hipStream_t s);
 void mesh_release(sn_mesh *m);
+void ctx_retain(sn_ctx *c);
+void ctx_release(sn_ctx *c);  // frees the context with its last reference
 
 }  // namespace sn

@@ -214,7 +214,7 @@ extern "C" sn_status sn_ctx_create(int device, sn_ctx **out)
     }
     HIP_TRY(hipSetDevice(device));
     sn_ctx *c = new sn_ctx(device);
-    if (hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking) != hipSuccess) {
+    if (hipStreamCreateWithFlags(&c->copy_stream, hipStreamNonBlocking) != hipSuccess) {
         delete c;
         return fail(SN_EDEVICE, "sn_ctx_create: stream creation failed");
     }
@@ -227,13 +227,20 @@ extern "C" sn_status sn_ctx_create(int device, sn_ctx **out)
     return SN_OK;
 }
 
+void sn::ctx_retain(sn_ctx *c) { c->refs.fetch_add(1, std::memory_order_relaxed); }
+
+void sn::ctx_release(sn_ctx *c)
+{
+    if (c->refs.fetch_sub(1, std::memory_order_acq_rel) != 1) return;
+    (void)hipSetDevice(c->device);
+    (void)hipStreamSynchronize(c->copy_stream);
+    (void)hipStreamDestroy(c->copy_stream);
+    delete c;
+}
+
 extern "C" void sn_ctx_destroy(sn_ctx *c)
 {
-    if (!c) return;
-    (void)hipSetDevice(c->device);
-    (void)hipDeviceSynchronize();
-    (void)hipStreamDestroy(c->capture_stream);
-    delete c;
+    if (c) ctx_release(c);
 }
 
 sn_ctx::sn_ctx(int dev) : device(dev), pool(dev, false), pinned(dev, true) {}
@@ -470,8 +477,10 @@ void sn::mesh_release(sn_mesh *m)
         if (m->done_ev) (void)hipEventSynchronize(m->done_ev);
     }
     if (m->done_ev) (void)hipEventDestroy(m->done_ev);
-    m->ctx->pool.release_all(m->blocks, Pool::kNoWait);
+    sn_ctx *c = m->ctx;
+    c->pool.release_all(m->blocks, Pool::kNoWait);
     delete m;
+    ctx_release(c);
 }
 
 extern "C" void sn_mesh_free(sn_mesh *m) { mesh_release(m); }
@@ -518,10 +527,14 @@ extern "C" sn_status sn_mesh_copy_to_host(const sn_mesh *m, float *points, int32
     if (m->done_ev) HIP_TRY(hipEventSynchronize(m->done_ev));
     sn_mesh_view v;
     sn_mesh_view_get(m, &v);
-    auto cp = [](void *dst, const void *src, size_t n) -> hipError_t {
+    // a non-blocking stream of the context: no implicit ordering with the
+    // legacy stream or with other threads' streams (the mesh's own work is
+    // complete after the event wait above)
+    hipStream_t cs = m->ctx->copy_stream;
+    auto cp = [cs](void *dst, const void *src, size_t n) -> hipError_t {
         if (!dst || n == 0) return hipSuccess;
         if (!src) return hipErrorInvalidValue;
-        return hipMemcpy(dst, src, n, hipMemcpyDeviceToHost);
+        return hipMemcpyAsync(dst, src, n, hipMemcpyDeviceToHost, cs);
     };
     HIP_TRY(cp(points, v.points, sizeof(float) * 3 * v.n_points));
     HIP_TRY(cp(polys, v.polys, sizeof(int32_t) * v.prim * v.n_polys));
@@ -534,6 +547,7 @@ extern "C" sn_status sn_mesh_copy_to_host(const sn_mesh *m, float *points, int32
         else
             std::memset(offsets, 0, sizeof(float) * 3 * v.n_points);
     }
+    HIP_TRY(hipStreamSynchronize(cs));
     return SN_OK;
 }
 
@@ -596,6 +610,7 @@ sn_status sn::extract_many(sn_ctx *c, const sn_volume *vols, int32_t n, hipStrea
                 m->ctx->pool.release_all(m->blocks, s);
                 m->blocks.clear();
                 delete m;
+                ctx_release(c);
             }
         return st;
     };
@@ -633,6 +648,7 @@ sn_status sn::extract_many(sn_ctx *c, const sn_volume *vols, int32_t n, hipStrea
         sn_mesh *m = new sn_mesh();
         meshes[v] = m;
         m->ctx = c;
+        ctx_retain(c);
         m->bpw = bpw;
         VolDesc &d = m->d;
         std::memset(&d, 0, sizeof d);
@@ -781,7 +797,7 @@ sn_status sn::extract_many(sn_ctx *c, const sn_volume *vols, int32_t n, hipStrea
         if (!m->dd || !m->dtp || !m->dsd || !m->dbp || !tp)
             return cleanup(fail(SN_ENOMEM, "extract: descriptors"));
         HIP_TRY(hipMemcpyAsync(m->dd, &h_desc[k], sizeof(VolDesc), hipMemcpyHostToDevice, s));
-        tp[0] = 0, tp[1] = m->ntiles, tp[2] = 0, tp[3] = (m->P + 255) / 256;
+        tp[0] = 0, tp[1] = m->ntiles, tp[2] = 0, tp[3] = (m->P + kSweepPoints - 1) / kSweepPoints;
         HIP_TRY(hipMemcpyAsync(m->dtp, tp, sizeof(int64_t) * 2, hipMemcpyHostToDevice, s));
         HIP_TRY(hipMemcpyAsync(m->dbp, tp + 2, sizeof(int64_t) * 2, hipMemcpyHostToDevice, s));
         sn_status st = mesh_mark(m, s);
@@ -818,11 +834,12 @@ sn_status sn::ensure_smooth_buffers(sn_mesh *m)
     if (m->d.P == 0 || m->da) return SN_OK;
     m->da = dalloc<float>(m, 3 * m->P);
     m->db = dalloc<float>(m, 3 * m->P);
-    if (!m->da || !m->db) return fail(SN_ENOMEM, "smooth: offset buffers");
+    m->nbr = dalloc<int32_t>(m, 4 * m->P);
+    if (!m->da || !m->db || !m->nbr) return fail(SN_ENOMEM, "smooth: offset buffers");
     return SN_OK;
 }
 
-// n sweeps of k_jacobi over `nvol` meshes, replayed from a captured graph
+// n sweeps over `nvol` meshes, replayed from a HIP graph of kernel nodes
 sn_status sn::run_sweeps(sn_ctx *c, const SmoothDesc *d_sd, const int64_t *d_bp, int32_t nvol,
                          int64_t nblocks, int32_t iters, hipStream_t s,
                          std::map<int32_t, hipGraphExec_t> *cache)
@@ -844,20 +861,16 @@ sn_status sn::run_sweeps(sn_ctx *c, const SmoothDesc *d_sd, const int64_t *d_bp,
         if (it != cache->end()) exec = it->second;
     }
     if (!exec) {
-        std::lock_guard<std::mutex> g(c->capture_mu);
+        // built node by node rather than by stream capture: no stream of the
+        // process is ever in capture mode, so other threads' work on the
+        // legacy stream cannot collide with it
         hipGraph_t graph;
-        HIP_TRY(hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal));
-        hipError_t e = hipSuccess;
-        for (int32_t it = 0; it < iters && e == hipSuccess; ++it)
-            e = launch_jacobi(d_sd, d_bp, nvol, nblocks, it, c->capture_stream);
-        hipError_t e2 = hipStreamEndCapture(c->capture_stream, &graph);
-        if (e != hipSuccess || e2 != hipSuccess)
-            return fail(SN_EDEVICE, std::string("smooth: graph capture failed: ") +
-                                        hipGetErrorString(e != hipSuccess ? e : e2));
-        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        HIP_TRY(hipGraphCreate(&graph, 0));
+        hipError_t e = add_jacobi_nodes(graph, d_sd, d_bp, nvol, nblocks, iters);
+        if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
         (void)hipGraphDestroy(graph);
         if (e != hipSuccess)
-            return fail(SN_EDEVICE, std::string("smooth: graph instantiate: ") + hipGetErrorString(e));
+            return fail(SN_EDEVICE, std::string("smooth: sweep graph: ") + hipGetErrorString(e));
         if (cache) (*cache)[iters] = exec;
     }
     hipError_t e = hipGraphLaunch(exec, s);
@@ -889,10 +902,10 @@ extern "C" sn_status sn_smooth(sn_ctx *c, sn_mesh *m, const sn_smooth_params *p,
         return fail(SN_ENOMEM, "smooth: staging");
     }
     h->P = m->P, h->faces = m->d.faces, h->off = m->d.st_off, h->ids = m->d.st_ids;
-    h->da = m->da, h->db = m->db, h->iters = p->iterations;
+    h->nbr = m->nbr, h->da = m->da, h->db = m->db, h->iters = p->iterations;
     h->lam = (double)p->relaxation, h->dist = (double)p->constraint;
     HIP_TRY(hipMemcpyAsync(m->dsd, h, sizeof(SmoothDesc), hipMemcpyHostToDevice, s));
-    const int64_t nblocks = (m->P + 255) / 256;
+    const int64_t nblocks = (m->P + kSweepPoints - 1) / kSweepPoints;
     st = run_sweeps(c, m->dsd, m->dbp, 1, nblocks, p->iterations, s, &m->graphs);
     if (st != SN_OK) {
         c->pinned.release(h, s);
@@ -930,7 +943,7 @@ sn_status sn::smooth_many(sn_ctx *c, sn_mesh **ms, const sn_smooth_params *pv, i
             st = ensure_smooth_buffers(ms[v]);
             if (st != SN_OK) return st;
         }
-        bp[v + 1] = bp[v] + (ms[v]->P + 255) / 256;
+        bp[v + 1] = bp[v] + (ms[v]->P + kSweepPoints - 1) / kSweepPoints;
         tp[v + 1] = tp[v] + ms[v]->ntiles;
         maxit = std::max(maxit, pv[v].iterations);
     }
@@ -948,7 +961,7 @@ sn_status sn::smooth_many(sn_ctx *c, sn_mesh **ms, const sn_smooth_params *pv, i
         sn_mesh *m = ms[v];
         SmoothDesc &h = h_sd[v];
         h.P = m->P, h.faces = m->d.faces, h.off = m->d.st_off, h.ids = m->d.st_ids;
-        h.da = m->da, h.db = m->db, h.iters = m->P > 0 ? pv[v].iterations : 0;
+        h.nbr = m->nbr, h.da = m->da, h.db = m->db, h.iters = m->P > 0 ? pv[v].iterations : 0;
         h.lam = (double)pv[v].relaxation, h.dist = (double)pv[v].constraint;
         m->final_delta =
             h.iters == 0 ? nullptr : (((h.iters - 1) & 1) ? m->da : m->db);

@@ -5,7 +5,7 @@
 // order while (a) the sum of device-footprint estimates of everything in
 // flight stays within the budget and (b) fewer than max_inflight requests are
 // in flight, fuses the admitted requests into one batch (one counting launch,
-// one generation launch, one captured-graph replay of the sweeps for the whole
+// one generation launch, one HIP-graph replay of the sweeps for the whole
 // batch) and runs it on its stream.  Requests arriving meanwhile join the next
 // batch of whichever worker frees first, so device work of different batches
 // overlaps.  Finished meshes stay device-resident until claimed.
@@ -77,7 +77,27 @@ struct sn_server {
     int32_t busy_count = 0;
 
     void worker(int w);
+    // extract + smooth n requests as one fused batch on stream s and wait for
+    // it; on failure every ms[k] is null
+    sn_status run_fused(const sn_volume *vols, const sn_smooth_params *ps, int32_t n,
+                        hipStream_t s, sn_mesh **ms);
 };
+
+sn_status sn_server::run_fused(const sn_volume *vols, const sn_smooth_params *ps, int32_t n,
+                               hipStream_t s, sn_mesh **ms)
+{
+    std::fill(ms, ms + n, nullptr);
+    sn_status st = extract_many(ctx, vols, n, s, 0, ms);
+    if (st == SN_OK) {
+        st = smooth_many(ctx, ms, ps, n, s);
+        if (st == SN_OK && hipStreamSynchronize(s) != hipSuccess) st = SN_EDEVICE;
+        if (st != SN_OK) {
+            for (int32_t k = 0; k < n; ++k) mesh_release(ms[k]);
+            std::fill(ms, ms + n, nullptr);
+        }
+    }
+    return st;
+}
 
 void sn_server::worker(int w)
 {
@@ -119,20 +139,21 @@ void sn_server::worker(int w)
             ps[k] = batch[k]->p;
         }
         std::vector<sn_mesh *> ms(n, nullptr);
-        sn_status st = extract_many(ctx, vols.data(), n, s, 0, ms.data());
-        if (st == SN_OK) {
-            st = smooth_many(ctx, ms.data(), ps.data(), n, s);
-            if (st == SN_OK && hipStreamSynchronize(s) != hipSuccess) st = SN_EDEVICE;
-            if (st != SN_OK) {
-                for (auto *m : ms) mesh_release(m);
-                std::fill(ms.begin(), ms.end(), nullptr);
-            }
+        std::vector<sn_status> sts(n, SN_OK);
+        const sn_status st = run_fused(vols.data(), ps.data(), n, s, ms.data());
+        if (st == SN_ENOMEM && n > 1) {
+            // the fused batch did not fit next to what the other streams hold:
+            // run its requests one at a time instead of failing all of them
+            for (int32_t k = 0; k < n; ++k) sts[k] = run_fused(&vols[k], &ps[k], 1, s, &ms[k]);
+        } else {
+            std::fill(sts.begin(), sts.end(), st);
         }
         const auto now = Clock::now();
         {
             std::lock_guard<std::mutex> lk(mu);
             for (int32_t k = 0; k < n; ++k) {
                 Request *r = batch[k];
+                const sn_status st = sts[k];
                 r->done = true;
                 r->status = st;
                 r->mesh = ms[k];
@@ -169,12 +190,14 @@ extern "C" sn_status sn_serve_start(sn_ctx *ctx, const sn_serve_config *cfg, sn_
     HIP_TRY(hipSetDevice(ctx->device));
     sn_server *srv = new sn_server();
     srv->ctx = ctx;
+    ctx_retain(ctx);
     srv->cfg = *cfg;
     for (int w = 0; w < cfg->n_streams; ++w) {
         hipStream_t s;
         if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
             for (auto x : srv->streams) (void)hipStreamDestroy(x);
             delete srv;
+            ctx_release(ctx);
             return fail(SN_EDEVICE, "sn_serve_start: stream creation failed");
         }
         srv->streams.push_back(s);
@@ -299,7 +322,6 @@ extern "C" sn_status sn_serve_stats_get(sn_server *srv, sn_serve_stats *out)
 extern "C" sn_status sn_serve_stop(sn_server *srv)
 {
     if (!srv) return fail(SN_EINVAL, "sn_serve_stop: NULL server");
-    std::vector<Request *> rejected;
     {
         std::lock_guard<std::mutex> lk(srv->mu);
         srv->stopping = true;
@@ -324,6 +346,8 @@ extern "C" sn_status sn_serve_stop(sn_server *srv)
         if (kv.second->mesh) mesh_release(kv.second->mesh);
         delete kv.second;
     }
+    sn_ctx *ctx = srv->ctx;
     delete srv;
+    ctx_release(ctx);
     return SN_OK;
 }

@@ -201,8 +201,8 @@ def test_resmooth_restarts_from_cache(ctx, sn, torch):
 
 
 def test_graph_replays_match_eager(ctx, sn, torch):
-    """The captured sweep graph, replayed many times with other device work and
-    synchronisations in between, gives the eager (profiled, uncaptured) result
+    """The sweep graph, replayed many times with other device work and
+    synchronisations in between, gives the eager (profiled, one launch per sweep) result
     every time."""
     rng = np.random.default_rng(9)
     vol = synth.blocky_tiny(rng, (70, 50, 30), 7, np.uint16)
