@@ -154,7 +154,11 @@ sn_status sn_mesh_view_get(const sn_mesh *mesh, sn_mesh_view *out);
  * labels 2*n_polys*dtype bytes, stencil_off P+1, stencil_ids S int32. */
 sn_status sn_mesh_copy_to_host(const sn_mesh *mesh, float *points, int32_t *polys, void *labels,
                                int32_t *stencil_off, int32_t *stencil_ids, float *offsets);
-/* Waits for the mesh's outstanding work, then releases it. */
+/* Releases the mesh without waiting: its device memory returns to the
+ * context's pool and is handed out again only after the library's own work
+ * on the mesh (on whatever stream it ran) has completed.  Device work of the
+ * caller that still reads the mesh's arrays must be complete (or ordered
+ * before the library's next use of the memory) when the mesh is freed. */
 void sn_mesh_free(sn_mesh *mesh);
 
 /* ---- batched path ---------------------------------------------------------- */

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 namespace sn {
 
 // ---- classification (Sec. 2.1) ---------------------------------------------
@@ -71,7 +73,6 @@ struct VolDesc {
     void *pairs;       // [Q*2] dtype
     int32_t *tris;     // [2Q*3] (prim 3)
     void *tri_pairs;   // [2Q*2] dtype (prim 3)
-    const float *delta;  // emit: final offsets or nullptr (zero)
     double origin[3], spacing[3];
     int64_t P, Q, S;
 };
@@ -112,17 +113,20 @@ constexpr uint64_t kValMask = (1ull << 62) - 1;
 //               (rows 16-byte aligned and M % 4 == 0: one wide load per lane).
 //   k_count   : a tile is 256 cell words.
 //   k_generate: a tile is 4*bpw batches; label type and mode as for k_edges.
+//               The launch also zeroes d_zero[0 .. nzero) (the count pass's scan
+//               status), so the extraction needs no separate memset.
 hipError_t launch_edges(int32_t dtype, int32_t mode, bool wide, const VolDesc *d_descs,
                         const int64_t *d_tile_prefix, int32_t nvol, int64_t tile_base,
-                        int64_t ntiles, hipStream_t s);
+                        int64_t ntiles, uint64_t *d_zero, int64_t nzero, hipStream_t s);
 hipError_t launch_count(const VolDesc *d_descs, const int64_t *d_tile_prefix, int32_t nvol,
                         int64_t ntiles, uint64_t *d_status, uint32_t *d_ticket, int64_t *d_totals,
                         hipStream_t s);
 hipError_t launch_generate(int32_t dtype, int32_t mode, const VolDesc *d_descs,
                            const int64_t *d_tile_prefix, int32_t nvol, int64_t tile_base,
                            int64_t ntiles, int32_t bpw, hipStream_t s);
-hipError_t launch_emit(const VolDesc *d_descs, const int64_t *d_tile_prefix, int32_t nvol,
-                       int64_t ntiles, int32_t bpw, hipStream_t s);
+// k_emit: d_sds[v] (iterations, ping-pong buffers) names volume v's final offsets
+hipError_t launch_emit(const VolDesc *d_descs, const SmoothDesc *d_sds, const int64_t *d_tile_prefix,
+                       int32_t nvol, int64_t ntiles, int32_t bpw, hipStream_t s);
 // block_prefix[v] = first block of volume v (kSweepPoints points per block);
 // it = 0 runs the first sweep (zero input offsets, builds nbr)
 hipError_t launch_jacobi(const SmoothDesc *d_sd, const int64_t *d_block_prefix, int32_t nvol,
@@ -131,6 +135,22 @@ hipError_t launch_jacobi(const SmoothDesc *d_sd, const int64_t *d_block_prefix, 
 hipError_t add_jacobi_nodes(hipGraph_t graph, const SmoothDesc *d_sd,
                             const int64_t *d_block_prefix, int32_t nvol, int64_t nblocks,
                             int32_t iters);
+// Single-volume forms: the descriptor travels by value in the kernel
+// arguments (no upload, no prefix array; tiles and blocks start at 0).
+hipError_t launch_edges_one(const VolDesc &d, bool wide, int64_t ntiles, uint64_t *d_zero,
+                            int64_t nzero, hipStream_t s);
+hipError_t launch_count_one(const VolDesc &d, int64_t ntiles, uint64_t *d_status, uint32_t *d_ticket,
+                            int64_t *d_totals, hipStream_t s);
+hipError_t launch_generate_one(const VolDesc &d, int64_t ntiles, int32_t bpw, hipStream_t s);
+hipError_t launch_emit_one(const VolDesc &d, const SmoothDesc &sd, int64_t ntiles, int32_t bpw,
+                           hipStream_t s);
+hipError_t launch_jacobi_one(const SmoothDesc &sd, int64_t nblocks, int32_t it, hipStream_t s);
+hipError_t add_jacobi_nodes_one(hipGraph_t graph, const SmoothDesc &sd, int64_t nblocks,
+                                int32_t iters, std::vector<hipGraphNode_t> *nodes);
+// new descriptor for the nodes of an instantiated graph made by add_jacobi_nodes_one
+hipError_t set_jacobi_nodes_one(hipGraphExec_t exec, const std::vector<hipGraphNode_t> &nodes,
+                                const SmoothDesc &sd, int64_t nblocks);
+hipError_t launch_triangulate_one(const VolDesc &d, hipStream_t s);
 // quad blocks (256 quads per block) of the volumes with prim 3
 hipError_t launch_triangulate(const VolDesc *d_descs, const int64_t *d_block_prefix, int32_t nvol,
                               int64_t nblocks, hipStream_t s);

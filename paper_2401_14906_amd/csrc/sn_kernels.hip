@@ -76,6 +76,61 @@ __device__ __forceinline__ int find_seg(const int64_t *prefix, int n, int64_t t)
     return lo;
 }
 
+// Where a launch finds its volume: an array of descriptors in device memory
+// with a prefix of tiles (or blocks) per volume, for launches over many
+// volumes; or a single descriptor passed by value in the kernel arguments,
+// which needs no upload before the launch.
+struct ManyVols {
+    const VolDesc *descs;
+    const int64_t *prefix;
+    int32_t nvol;
+};
+struct OneVol {
+    VolDesc d;
+};
+struct ManySmooth {
+    const SmoothDesc *sds;
+    const int64_t *prefix;
+    int32_t nvol;
+};
+struct OneSmooth {
+    SmoothDesc s;
+};
+struct ManyEmit {
+    const VolDesc *descs;
+    const SmoothDesc *sds;
+    const int64_t *prefix;
+    int32_t nvol;
+};
+struct OneEmit {
+    VolDesc d;
+    SmoothDesc s;
+};
+
+// Volume of global tile t, its index and its first tile.
+__device__ __forceinline__ const VolDesc &vol_of(const ManyVols &a, int64_t t, int &v, int64_t &first)
+{
+    v = find_seg(a.prefix, a.nvol, t);
+    first = cst(a.prefix)[v];
+    return a.descs[v];
+}
+__device__ __forceinline__ const VolDesc &vol_of(const OneVol &a, int64_t, int &v, int64_t &first)
+{
+    v = 0, first = 0;
+    return a.d;
+}
+__device__ __forceinline__ const SmoothDesc &smooth_of(const ManySmooth &a, int64_t b, int64_t &first)
+{
+    const int v = find_seg(a.prefix, a.nvol, b);
+    first = cst(a.prefix)[v];
+    return a.sds[v];
+}
+__device__ __forceinline__ const SmoothDesc &smooth_of(const OneSmooth &a, int64_t, int64_t &first)
+{
+    first = 0;
+    return a.s;
+}
+
 template <int MODE>
 __device__ __forceinline__ uint32_t classify(uint32_t v, const ClassSpec &cs)
 {
@@ -324,47 +379,40 @@ __device__ __forceinline__ void edges_segment(const VolDesc &d, int64_t seg, int
     }
 }
 
-template <typename T, int MODE, bool WIDE>
-__device__ __forceinline__ void edges_tile(const VolDesc *__restrict__ descs,
-                                           const int64_t *__restrict__ tile_prefix, int32_t nvol,
-                                           int64_t tile_base)
+template <typename T, int MODE, bool WIDE, class Src>
+__device__ __forceinline__ void edges_tile(const Src &a, int64_t tile_base, uint64_t *zero,
+                                           int64_t nzero)
 {
+    // clear the scan status words of the counting pass that follows
+    for (int64_t z = (int64_t)blockIdx.x * kBlock + threadIdx.x; z < nzero;
+         z += (int64_t)gridDim.x * kBlock)
+        glb(zero)[z] = 0;
     const int64_t t = tile_base + blockIdx.x;
-    const int v = find_seg(tile_prefix, nvol, t);
-    const VolDesc &d = descs[v];
+    int v;
+    int64_t first;
+    const VolDesc &d = vol_of(a, t, v, first);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int64_t nseg = d.g.N * d.g.O * d.g.NSEG;
-    int64_t seg = (t - tile_prefix[v]) * (kWavesPerBlock * kSegPerWave) + (int64_t)wave * kSegPerWave;
+    int64_t seg = (t - first) * (kWavesPerBlock * kSegPerWave) + (int64_t)wave * kSegPerWave;
     for (int q = 0; q < kSegPerWave; ++q, ++seg) {
         if (seg >= nseg) break;
         edges_segment<T, MODE, WIDE>(d, seg, lane);
     }
 }
 
-template <typename T, int MODE>
-__global__ __launch_bounds__(kBlock) void k_edges_wide(const VolDesc *__restrict__ descs,
-                                                       const int64_t *__restrict__ tile_prefix,
-                                                       int32_t nvol, int64_t tile_base)
+template <typename T, int MODE, class Src>
+__global__ __launch_bounds__(kBlock) void k_edges_wide(Src a, int64_t tile_base, uint64_t *zero,
+                                                       int64_t nzero)
 {
-    edges_tile<T, MODE, true>(descs, tile_prefix, nvol, tile_base);
+    edges_tile<T, MODE, true>(a, tile_base, zero, nzero);
 }
 
-template <typename T, int MODE>
-__global__ __launch_bounds__(kBlock) void k_edges_narrow(const VolDesc *__restrict__ descs,
-                                                         const int64_t *__restrict__ tile_prefix,
-                                                         int32_t nvol, int64_t tile_base)
+template <typename T, int MODE, class Src>
+__global__ __launch_bounds__(kBlock) void k_edges_narrow(Src a, int64_t tile_base, uint64_t *zero,
+                                                         int64_t nzero)
 {
-    edges_tile<T, MODE, false>(descs, tile_prefix, nvol, tile_base);
+    edges_tile<T, MODE, false>(a, tile_base, zero, nzero);
 }
-
-template <typename T, int MODE>
-__global__ __launch_bounds__(kBlock) void k_edges_wide(const VolDesc *__restrict__ descs,
-                                                       const int64_t *__restrict__ tile_prefix,
-                                                       int32_t nvol, int64_t tile_base);
-template <typename T, int MODE>
-__global__ __launch_bounds__(kBlock) void k_edges_narrow(const VolDesc *__restrict__ descs,
-                                                         const int64_t *__restrict__ tile_prefix,
-                                                         int32_t nvol, int64_t tile_base);
 
 // ---------------------------------------------------------------------------
 // k_count: one lane per 64-cell word.  Point / quad / stencil counts of every
@@ -418,9 +466,18 @@ __device__ void look_back3(const uint64_t *status, int64_t t, int64_t first, int
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_count(const VolDesc *__restrict__ descs,
-                                                  const int64_t *__restrict__ tile_prefix,
-                                                  int32_t nvol, uint64_t *status, uint32_t *ticket,
+// Last tile of volume v (a launch over one volume has exactly its tiles).
+__device__ __forceinline__ int64_t last_tile(const ManyVols &a, int v)
+{
+    return cst(a.prefix)[v + 1] - 1;
+}
+__device__ __forceinline__ int64_t last_tile(const OneVol &, int)
+{
+    return (int64_t)gridDim.x - 1;
+}
+
+template <class Src>
+__global__ __launch_bounds__(kBlock) void k_count(Src a, uint64_t *status, uint32_t *ticket,
                                                   int64_t *totals)
 {
     __shared__ int64_t s_tile;
@@ -429,10 +486,10 @@ __global__ __launch_bounds__(kBlock) void k_count(const VolDesc *__restrict__ de
     if (threadIdx.x == 0) s_tile = (int64_t)atomicAdd(ticket, 1u);
     __syncthreads();
     const int64_t t = s_tile;  // tiles are handed out in order: predecessors are running
-    const int v = find_seg(tile_prefix, nvol, t);
-    const VolDesc &d = descs[v];
+    int v;
+    int64_t first;
+    const VolDesc &d = vol_of(a, t, v, first);
     const Geom &g = d.g;
-    const int64_t first = tile_prefix[v];
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int64_t words = g.R * g.W;
     const int64_t gw = (t - first) * kBlock + threadIdx.x;
@@ -483,7 +540,7 @@ __global__ __launch_bounds__(kBlock) void k_count(const VolDesc *__restrict__ de
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 s_excl[c] = excl[c];
-                if (t == tile_prefix[v + 1] - 1) totals[3 * v + c] = excl[c] + agg[c];
+                if (t == last_tile(a, v)) totals[3 * v + c] = excl[c] + agg[c];
             }
         }
     }
@@ -746,7 +803,7 @@ __device__ __forceinline__ void generate_process(const VolDesc &d, const BatchPo
 
 // nb consecutive batches from b0, two in flight.
 template <typename T, int MODE>
-__device__ void generate_stream(const VolDesc &d, int64_t b0, int nb, int lane, Stage &st)
+__device__ __forceinline__ void generate_stream(const VolDesc &d, int64_t b0, int nb, int lane, Stage &st)
 {
     const T *vol = static_cast<const T *>(d.labels);
     PairLoads<T> L0, L1;
@@ -773,19 +830,18 @@ __device__ void generate_stream(const VolDesc &d, int64_t b0, int nb, int lane, 
     }
 }
 
-template <typename T, int MODE>
-__global__ __launch_bounds__(kBlock) void k_generate(const VolDesc *__restrict__ descs,
-                                                     const int64_t *__restrict__ tile_prefix,
-                                                     int32_t nvol, int64_t tile_base, int32_t bpw)
+template <typename T, int MODE, class Src>
+__global__ __launch_bounds__(kBlock) void k_generate(Src a, int64_t tile_base, int32_t bpw)
 {
     __shared__ Stage stage[kWavesPerBlock];
     const int64_t t = tile_base + blockIdx.x;
-    const int v = find_seg(tile_prefix, nvol, t);
-    const VolDesc &d = descs[v];
+    int v;
+    int64_t first;
+    const VolDesc &d = vol_of(a, t, v, first);
     const int64_t nbv = d.g.R * d.g.NB;
-    const int64_t bt0 = (t - tile_prefix[v]) * (kWavesPerBlock * bpw);
+    const int64_t bt0 = (t - first) * (kWavesPerBlock * bpw);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
-    if (threadIdx.x == 0 && t == tile_prefix[v]) glb(d.st_off)[d.P] = (int32_t)d.S;
+    if (threadIdx.x == 0 && t == first) glb(d.st_off)[d.P] = (int32_t)d.S;
     const int64_t b0 = bt0 + (int64_t)wave * bpw;
     const int64_t nb = nbv - b0 < bpw ? nbv - b0 : bpw;
     if (nb > 0) generate_stream<T, MODE>(d, b0, (int)nb, lane, stage[wave]);
@@ -811,10 +867,10 @@ __device__ __forceinline__ void issue_emit_aux(const VolDesc &d, const BatchPos 
     }
 }
 
-__device__ __forceinline__ void emit_process(const VolDesc &d, const BatchPos &bp, const EmitAux &A,
-                                             int lane)
+__device__ __forceinline__ void emit_process(const VolDesc &d, const float *delta_, const BatchPos &bp,
+                                             const EmitAux &A, int lane)
 {
-    const SN_GLOBAL float *delta = d.delta ? glb(d.delta) : nullptr;
+    const SN_GLOBAL float *delta = delta_ ? glb(delta_) : nullptr;
     const double y0 = (double)bp.j + 0.5, z0 = (double)bp.k + 0.5;
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
@@ -835,15 +891,34 @@ __device__ __forceinline__ void emit_process(const VolDesc &d, const BatchPos &b
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_emit(const VolDesc *__restrict__ descs,
-                                                 const int64_t *__restrict__ tile_prefix,
-                                                 int32_t nvol, int32_t bpw)
+__device__ __forceinline__ const VolDesc &emit_of(const ManyEmit &a, int64_t t, const SmoothDesc *&sd,
+                                                  int64_t &first)
+{
+    const int v = find_seg(a.prefix, a.nvol, t);
+    first = cst(a.prefix)[v];
+    sd = &a.sds[v];
+    return a.descs[v];
+}
+__device__ __forceinline__ const VolDesc &emit_of(const OneEmit &a, int64_t, const SmoothDesc *&sd,
+                                                  int64_t &first)
+{
+    first = 0;
+    sd = &a.s;
+    return a.d;
+}
+
+template <class Src>
+__global__ __launch_bounds__(kBlock) void k_emit(Src a, int32_t bpw)
 {
     const int64_t t = blockIdx.x;
-    const int v = find_seg(tile_prefix, nvol, t);
-    const VolDesc &d = descs[v];
+    const SmoothDesc *sdp;
+    int64_t first;
+    const VolDesc &d = emit_of(a, t, sdp, first);
+    // the last of n sweeps wrote buffer ((n - 1) odd ? da : db); no sweep: centres
+    const SmoothDesc &sd = *sdp;
+    const float *delta = sd.iters <= 0 ? nullptr : (((sd.iters - 1) & 1) ? sd.da : sd.db);
     const int64_t nbv = d.g.R * d.g.NB;
-    const int64_t bt0 = (t - tile_prefix[v]) * (kWavesPerBlock * bpw);
+    const int64_t bt0 = (t - first) * (kWavesPerBlock * bpw);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int64_t b0 = bt0 + (int64_t)wave * bpw;
     const int64_t nb = nbv - b0 < bpw ? nbv - b0 : bpw;
@@ -857,14 +932,14 @@ __global__ __launch_bounds__(kBlock) void k_emit(const VolDesc *__restrict__ des
             batch_next(d.g, P1);
             issue_emit_aux(d, P1, lane, A1);
         }
-        emit_process(d, P0, A0, lane);
+        emit_process(d, delta, P0, A0, lane);
         if (q + 1 >= nb) break;
         if (q + 2 < nb) {
             P0 = P1;
             batch_next(d.g, P0);
             issue_emit_aux(d, P0, lane, A0);
         }
-        emit_process(d, P1, A1, lane);
+        emit_process(d, delta, P1, A1, lane);
     }
 }
 
@@ -905,18 +980,17 @@ __device__ __forceinline__ void store_offset(SN_GLOBAL float *dout, int64_t p, d
 
 // Sweep 0: every input offset is zero, so p_q - p_p is the face step alone.
 // Reads the CSR stencil once and writes the y/z neighbour table.
-__global__ __launch_bounds__(256) void k_jacobi_first(const SmoothDesc *__restrict__ sds,
-                                                      const int64_t *__restrict__ block_prefix,
-                                                      int32_t nvol)
+template <class Src>
+__global__ __launch_bounds__(256) void k_jacobi_first(Src a)
 {
     const int64_t b = xcd_block(blockIdx.x, gridDim.x);
-    const int v = find_seg(block_prefix, nvol, b);
-    const SmoothDesc &s = sds[v];
+    int64_t first;
+    const SmoothDesc &s = smooth_of(a, b, first);
     if (s.iters < 1) return;
     SN_GLOBAL float *dout = glb(s.db);
 #pragma unroll
     for (int c = 0; c < kSweepChunks; ++c) {
-        const int64_t p = (b - block_prefix[v]) * kSweepPoints + c * kBlock + threadIdx.x;
+        const int64_t p = (b - first) * kSweepPoints + c * kBlock + threadIdx.x;
         if (p >= s.P) break;
         const uint32_t f = glb(s.faces)[p];
         const int n = __popc(f);
@@ -967,17 +1041,16 @@ __device__ __forceinline__ float readlane_f(float x, int l)
 // before any use.  The -x / +x neighbours of point p are points p - 1 / p + 1
 // (consecutive cells of a row get consecutive ids), read from the adjacent
 // lane; only the first and the last point of the wave load them.
-__global__ __launch_bounds__(256) void k_jacobi(const SmoothDesc *__restrict__ sds,
-                                                const int64_t *__restrict__ block_prefix,
-                                                int32_t nvol, int32_t it)
+template <class Src>
+__global__ __launch_bounds__(256) void k_jacobi(Src a, int32_t it)
 {
     constexpr int K = kSweepChunks;
     const int64_t b = xcd_block(blockIdx.x, gridDim.x);
-    const int v = find_seg(block_prefix, nvol, b);
-    const SmoothDesc &s = sds[v];
+    int64_t first;
+    const SmoothDesc &s = smooth_of(a, b, first);
     if (it >= s.iters) return;  // this mesh has finished its sweeps
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
-    const int64_t p0 = (b - block_prefix[v]) * kSweepPoints + (int64_t)wave * (64 * K);
+    const int64_t p0 = (b - first) * kSweepPoints + (int64_t)wave * (64 * K);
     const int64_t P = s.P;
     if (p0 >= P) return;
     const SN_GLOBAL float *din = glb((it & 1) ? s.db : s.da);
@@ -1078,14 +1151,14 @@ __device__ __forceinline__ void tri_pairs(const VolDesc &d, int64_t q)
     dst[4 * q] = f, dst[4 * q + 1] = b, dst[4 * q + 2] = f, dst[4 * q + 3] = b;
 }
 
-__global__ __launch_bounds__(256) void k_tri(const VolDesc *__restrict__ descs,
-                                             const int64_t *__restrict__ block_prefix,
-                                             int32_t nvol)
+template <class Src>
+__global__ __launch_bounds__(256) void k_tri(Src a)
 {
     const int64_t b = blockIdx.x;
-    const int v = find_seg(block_prefix, nvol, b);
-    const VolDesc &d = descs[v];
-    const int64_t q = (b - block_prefix[v]) * 256 + threadIdx.x;
+    int v;
+    int64_t first;
+    const VolDesc &d = vol_of(a, b, v, first);
+    const int64_t q = (b - first) * 256 + threadIdx.x;
     if (q >= d.Q || d.prim != 3) return;
     const v4i s = glb(reinterpret_cast<const v4i *>(d.quads))[q];
     SN_GLOBAL int32_t *o = glb(d.tris) + 6 * q;
@@ -1099,32 +1172,46 @@ __global__ __launch_bounds__(256) void k_tri(const VolDesc *__restrict__ descs,
 // launchers
 // ---------------------------------------------------------------------------
 
-// One instantiation per (label type, classification mode); every volume of a
-// launch has that key.
-#define SN_KEY_SWITCH(KERNEL, ...)                                                          \
-    switch (dtype * 4 + mode) {                                                             \
-    case 1 * 4 + CLS_IDENT: hipLaunchKernelGGL((KERNEL<uint8_t, CLS_IDENT>), __VA_ARGS__); break; \
-    case 1 * 4 + CLS_BITMAP: hipLaunchKernelGGL((KERNEL<uint8_t, CLS_BITMAP>), __VA_ARGS__); break; \
-    case 2 * 4 + CLS_IDENT: hipLaunchKernelGGL((KERNEL<uint16_t, CLS_IDENT>), __VA_ARGS__); break; \
-    case 2 * 4 + CLS_BITMAP: hipLaunchKernelGGL((KERNEL<uint16_t, CLS_BITMAP>), __VA_ARGS__); break; \
-    case 4 * 4 + CLS_IDENT: hipLaunchKernelGGL((KERNEL<uint32_t, CLS_IDENT>), __VA_ARGS__); break; \
-    case 4 * 4 + CLS_SORTED: hipLaunchKernelGGL((KERNEL<uint32_t, CLS_SORTED>), __VA_ARGS__); break; \
-    default: return hipErrorInvalidValue;                                                   \
+// One instantiation per (label type, classification mode, source); every
+// volume of a launch has that key.
+#define SN_KEY_SWITCH(KERNEL, SRC, ...)                                                              \
+    switch (dtype * 4 + mode) {                                                                      \
+    case 1 * 4 + CLS_IDENT: hipLaunchKernelGGL((KERNEL<uint8_t, CLS_IDENT, SRC>), __VA_ARGS__); break;   \
+    case 1 * 4 + CLS_BITMAP: hipLaunchKernelGGL((KERNEL<uint8_t, CLS_BITMAP, SRC>), __VA_ARGS__); break; \
+    case 2 * 4 + CLS_IDENT: hipLaunchKernelGGL((KERNEL<uint16_t, CLS_IDENT, SRC>), __VA_ARGS__); break;  \
+    case 2 * 4 + CLS_BITMAP: hipLaunchKernelGGL((KERNEL<uint16_t, CLS_BITMAP, SRC>), __VA_ARGS__); break; \
+    case 4 * 4 + CLS_IDENT: hipLaunchKernelGGL((KERNEL<uint32_t, CLS_IDENT, SRC>), __VA_ARGS__); break;  \
+    case 4 * 4 + CLS_SORTED: hipLaunchKernelGGL((KERNEL<uint32_t, CLS_SORTED, SRC>), __VA_ARGS__); break; \
+    default: return hipErrorInvalidValue;                                                            \
     }
 
-hipError_t launch_edges(int32_t dtype, int32_t mode, bool wide, const VolDesc *d_descs,
-                        const int64_t *d_tile_prefix, int32_t nvol, int64_t tile_base,
-                        int64_t ntiles, hipStream_t s)
+template <class Src>
+static hipError_t edges_impl(int32_t dtype, int32_t mode, bool wide, const Src &a, int64_t tile_base,
+                             int64_t ntiles, uint64_t *d_zero, int64_t nzero, hipStream_t s)
 {
     if (ntiles <= 0) return hipSuccess;
     if (wide) {
-        SN_KEY_SWITCH(k_edges_wide, dim3((uint32_t)ntiles), dim3(kBlock), 0, s, d_descs,
-                      d_tile_prefix, nvol, tile_base)
+        SN_KEY_SWITCH(k_edges_wide, Src, dim3((uint32_t)ntiles), dim3(kBlock), 0, s, a, tile_base,
+                      d_zero, nzero)
     } else {
-        SN_KEY_SWITCH(k_edges_narrow, dim3((uint32_t)ntiles), dim3(kBlock), 0, s, d_descs,
-                      d_tile_prefix, nvol, tile_base)
+        SN_KEY_SWITCH(k_edges_narrow, Src, dim3((uint32_t)ntiles), dim3(kBlock), 0, s, a, tile_base,
+                      d_zero, nzero)
     }
     return hipGetLastError();
+}
+
+hipError_t launch_edges(int32_t dtype, int32_t mode, bool wide, const VolDesc *d_descs,
+                        const int64_t *d_tile_prefix, int32_t nvol, int64_t tile_base,
+                        int64_t ntiles, uint64_t *d_zero, int64_t nzero, hipStream_t s)
+{
+    return edges_impl(dtype, mode, wide, ManyVols{d_descs, d_tile_prefix, nvol}, tile_base, ntiles,
+                      d_zero, nzero, s);
+}
+
+hipError_t launch_edges_one(const VolDesc &d, bool wide, int64_t ntiles, uint64_t *d_zero,
+                            int64_t nzero, hipStream_t s)
+{
+    return edges_impl(d.dtype, d.cs.mode, wide, OneVol{d}, 0, ntiles, d_zero, nzero, s);
 }
 
 hipError_t launch_count(const VolDesc *d_descs, const int64_t *d_tile_prefix, int32_t nvol,
@@ -1132,8 +1219,17 @@ hipError_t launch_count(const VolDesc *d_descs, const int64_t *d_tile_prefix, in
                         hipStream_t s)
 {
     if (ntiles <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_count, dim3((uint32_t)ntiles), dim3(kBlock), 0, s, d_descs, d_tile_prefix,
-                       nvol, d_status, d_ticket, d_totals);
+    hipLaunchKernelGGL(k_count<ManyVols>, dim3((uint32_t)ntiles), dim3(kBlock), 0, s,
+                       ManyVols{d_descs, d_tile_prefix, nvol}, d_status, d_ticket, d_totals);
+    return hipGetLastError();
+}
+
+hipError_t launch_count_one(const VolDesc &d, int64_t ntiles, uint64_t *d_status, uint32_t *d_ticket,
+                            int64_t *d_totals, hipStream_t s)
+{
+    if (ntiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_count<OneVol>, dim3((uint32_t)ntiles), dim3(kBlock), 0, s, OneVol{d},
+                       d_status, d_ticket, d_totals);
     return hipGetLastError();
 }
 
@@ -1142,17 +1238,35 @@ hipError_t launch_generate(int32_t dtype, int32_t mode, const VolDesc *d_descs,
                            int64_t ntiles, int32_t bpw, hipStream_t s)
 {
     if (ntiles <= 0) return hipSuccess;
-    SN_KEY_SWITCH(k_generate, dim3((uint32_t)ntiles), dim3(kBlock), 0, s, d_descs, d_tile_prefix,
-                  nvol, tile_base, bpw)
+    SN_KEY_SWITCH(k_generate, ManyVols, dim3((uint32_t)ntiles), dim3(kBlock), 0, s,
+                  ManyVols{d_descs, d_tile_prefix, nvol}, tile_base, bpw)
     return hipGetLastError();
 }
 
-hipError_t launch_emit(const VolDesc *d_descs, const int64_t *d_tile_prefix, int32_t nvol,
-                       int64_t ntiles, int32_t bpw, hipStream_t s)
+hipError_t launch_generate_one(const VolDesc &d, int64_t ntiles, int32_t bpw, hipStream_t s)
 {
     if (ntiles <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_emit, dim3((uint32_t)ntiles), dim3(kBlock), 0, s, d_descs, d_tile_prefix,
-                       nvol, bpw);
+    const int32_t dtype = d.dtype, mode = d.cs.mode;
+    SN_KEY_SWITCH(k_generate, OneVol, dim3((uint32_t)ntiles), dim3(kBlock), 0, s, OneVol{d},
+                  (int64_t)0, bpw)
+    return hipGetLastError();
+}
+
+hipError_t launch_emit(const VolDesc *d_descs, const SmoothDesc *d_sds, const int64_t *d_tile_prefix,
+                       int32_t nvol, int64_t ntiles, int32_t bpw, hipStream_t s)
+{
+    if (ntiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_emit<ManyEmit>, dim3((uint32_t)ntiles), dim3(kBlock), 0, s,
+                       ManyEmit{d_descs, d_sds, d_tile_prefix, nvol}, bpw);
+    return hipGetLastError();
+}
+
+hipError_t launch_emit_one(const VolDesc &d, const SmoothDesc &sd, int64_t ntiles, int32_t bpw,
+                           hipStream_t s)
+{
+    if (ntiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_emit<OneEmit>, dim3((uint32_t)ntiles), dim3(kBlock), 0, s, OneEmit{d, sd},
+                       bpw);
     return hipGetLastError();
 }
 
@@ -1160,26 +1274,38 @@ hipError_t launch_jacobi(const SmoothDesc *d_sd, const int64_t *d_block_prefix, 
                          int64_t nblocks, int32_t it, hipStream_t s)
 {
     if (nblocks <= 0) return hipSuccess;
+    const ManySmooth a{d_sd, d_block_prefix, nvol};
     if (it == 0)
-        hipLaunchKernelGGL(k_jacobi_first, dim3((uint32_t)nblocks), dim3(256), 0, s, d_sd,
-                           d_block_prefix, nvol);
+        hipLaunchKernelGGL(k_jacobi_first<ManySmooth>, dim3((uint32_t)nblocks), dim3(256), 0, s, a);
     else
-        hipLaunchKernelGGL(k_jacobi, dim3((uint32_t)nblocks), dim3(256), 0, s, d_sd,
-                           d_block_prefix, nvol, it);
+        hipLaunchKernelGGL(k_jacobi<ManySmooth>, dim3((uint32_t)nblocks), dim3(256), 0, s, a, it);
     return hipGetLastError();
 }
 
-hipError_t add_jacobi_nodes(hipGraph_t graph, const SmoothDesc *d_sd,
-                            const int64_t *d_block_prefix, int32_t nvol, int64_t nblocks,
-                            int32_t iters)
+hipError_t launch_jacobi_one(const SmoothDesc &sd, int64_t nblocks, int32_t it, hipStream_t s)
+{
+    if (nblocks <= 0) return hipSuccess;
+    const OneSmooth a{sd};
+    if (it == 0)
+        hipLaunchKernelGGL(k_jacobi_first<OneSmooth>, dim3((uint32_t)nblocks), dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL(k_jacobi<OneSmooth>, dim3((uint32_t)nblocks), dim3(256), 0, s, a, it);
+    return hipGetLastError();
+}
+
+// Kernel nodes of n sweeps, each depending on the one before.  Arguments are
+// copied into the nodes, so `a` may be a temporary.
+template <class Src>
+static hipError_t add_sweep_nodes(hipGraph_t graph, const Src &a, int64_t nblocks, int32_t iters)
 {
     hipGraphNode_t prev = nullptr;
+    Src arg = a;
     for (int32_t it = 0; it < iters && nblocks > 0; ++it) {
-        void *args_first[] = {&d_sd, &d_block_prefix, &nvol};
-        void *args[] = {&d_sd, &d_block_prefix, &nvol, &it};
+        void *args_first[] = {&arg};
+        void *args[] = {&arg, &it};
         hipKernelNodeParams kp{};
-        kp.func = it == 0 ? reinterpret_cast<void *>(&k_jacobi_first)
-                          : reinterpret_cast<void *>(&k_jacobi);
+        kp.func = it == 0 ? reinterpret_cast<void *>(&k_jacobi_first<Src>)
+                          : reinterpret_cast<void *>(&k_jacobi<Src>);
         kp.gridDim = dim3((uint32_t)nblocks);
         kp.blockDim = dim3(256);
         kp.sharedMemBytes = 0;
@@ -1194,12 +1320,80 @@ hipError_t add_jacobi_nodes(hipGraph_t graph, const SmoothDesc *d_sd,
     return hipSuccess;
 }
 
+hipError_t add_jacobi_nodes(hipGraph_t graph, const SmoothDesc *d_sd,
+                            const int64_t *d_block_prefix, int32_t nvol, int64_t nblocks,
+                            int32_t iters)
+{
+    return add_sweep_nodes(graph, ManySmooth{d_sd, d_block_prefix, nvol}, nblocks, iters);
+}
+
+// Node parameters of sweep `it` of one mesh; `arg` and `itv` must outlive the
+// API call that consumes the parameters.
+static void sweep_params_one(OneSmooth &arg, int32_t &itv, void **args, int64_t nblocks,
+                             hipKernelNodeParams &kp)
+{
+    args[0] = &arg;
+    args[1] = &itv;
+    kp = hipKernelNodeParams{};
+    kp.func = itv == 0 ? reinterpret_cast<void *>(&k_jacobi_first<OneSmooth>)
+                       : reinterpret_cast<void *>(&k_jacobi<OneSmooth>);
+    kp.gridDim = dim3((uint32_t)nblocks);
+    kp.blockDim = dim3(256);
+    kp.sharedMemBytes = 0;
+    kp.kernelParams = args;
+    kp.extra = nullptr;
+}
+
+hipError_t add_jacobi_nodes_one(hipGraph_t graph, const SmoothDesc &sd, int64_t nblocks,
+                                int32_t iters, std::vector<hipGraphNode_t> *nodes)
+{
+    OneSmooth arg{sd};
+    hipGraphNode_t prev = nullptr;
+    nodes->clear();
+    for (int32_t it = 0; it < iters && nblocks > 0; ++it) {
+        void *args[2];
+        hipKernelNodeParams kp;
+        int32_t itv = it;
+        sweep_params_one(arg, itv, args, nblocks, kp);
+        hipGraphNode_t node;
+        const hipError_t e =
+            hipGraphAddKernelNode(&node, graph, prev ? &prev : nullptr, prev ? 1 : 0, &kp);
+        if (e != hipSuccess) return e;
+        nodes->push_back(node);
+        prev = node;
+    }
+    return hipSuccess;
+}
+
+hipError_t set_jacobi_nodes_one(hipGraphExec_t exec, const std::vector<hipGraphNode_t> &nodes,
+                                const SmoothDesc &sd, int64_t nblocks)
+{
+    OneSmooth arg{sd};
+    for (size_t it = 0; it < nodes.size(); ++it) {
+        void *args[2];
+        hipKernelNodeParams kp;
+        int32_t itv = (int32_t)it;
+        sweep_params_one(arg, itv, args, nblocks, kp);
+        const hipError_t e = hipGraphExecKernelNodeSetParams(exec, nodes[it], &kp);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 hipError_t launch_triangulate(const VolDesc *d_descs, const int64_t *d_block_prefix, int32_t nvol,
                               int64_t nblocks, hipStream_t s)
 {
     if (nblocks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_tri, dim3((uint32_t)nblocks), dim3(256), 0, s, d_descs, d_block_prefix,
-                       nvol);
+    hipLaunchKernelGGL(k_tri<ManyVols>, dim3((uint32_t)nblocks), dim3(256), 0, s,
+                       ManyVols{d_descs, d_block_prefix, nvol});
+    return hipGetLastError();
+}
+
+hipError_t launch_triangulate_one(const VolDesc &d, hipStream_t s)
+{
+    const int64_t nblocks = (d.Q + 255) / 256;
+    if (nblocks <= 0 || d.prim != 3) return hipSuccess;
+    hipLaunchKernelGGL(k_tri<OneVol>, dim3((uint32_t)nblocks), dim3(256), 0, s, OneVol{d});
     return hipGetLastError();
 }
 

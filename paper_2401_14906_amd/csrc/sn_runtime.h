@@ -4,9 +4,11 @@
 #include <hip/hip_runtime.h>
 
 #include <atomic>
+#include <deque>
 #include <map>
 #include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "sn.h"
@@ -22,6 +24,20 @@ sn_status fail(sn_status s, const std::string &msg);
         if (_e != hipSuccess)                                                           \
             return ::sn::fail(SN_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(_e)); \
     } while (0)
+
+// Recycled HIP events of one kind (timing or not).
+class EventCache {
+  public:
+    explicit EventCache(unsigned flags) : flags_(flags) {}
+    ~EventCache();
+    hipEvent_t get();  // nullptr on failure
+    void put(hipEvent_t e);
+
+  private:
+    unsigned flags_;
+    std::mutex mu_;
+    std::vector<hipEvent_t> free_;
+};
 
 class Pool {
   public:
@@ -47,7 +63,8 @@ class Pool {
     mutable std::mutex mu_;
     std::multimap<size_t, void *> free_;
     std::map<void *, size_t> sizes_;
-    std::vector<Pending> pending_;
+    std::deque<Pending> pending_;  // in release order
+    EventCache events_{hipEventDisableTiming};
     int64_t in_use_ = 0, peak_ = 0, limit_ = -1;
 };
 
@@ -62,6 +79,23 @@ struct sn_ctx {
     sn::Pool pool;    // device blocks
     sn::Pool pinned;  // pinned host staging
     hipStream_t copy_stream = nullptr;  // non-blocking, for copies to the host
+    // Freed meshes: the retire stream waits for each mesh's completion event
+    // and their pool blocks are released behind an event recorded on it.
+    hipStream_t retire_stream = nullptr;
+    // Sweep graphs of single meshes by (iterations, bucketed block count).
+    // The smoothing descriptor is a kernel-node argument; a new mesh of a
+    // similar size reuses an instantiated graph by rewriting those arguments
+    // once the graph's previous launch has completed.
+    struct SweepGraph {
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        std::vector<hipGraphNode_t> nodes;
+        sn::SmoothDesc args{};
+        hipEvent_t last = nullptr;  // after the last launch of the graph
+    };
+    std::mutex sweep_mu;
+    std::map<std::pair<int32_t, int64_t>, SweepGraph> sweep_graphs;
+    sn::EventCache timing_events{hipEventDefault};
     // profiling
     bool profiling = false;
     bool profile_eager = false;  // sweeps launched one by one instead of a graph
@@ -93,13 +127,9 @@ struct sn_mesh {
     float *da = nullptr, *db = nullptr;
     int32_t *nbr = nullptr;  // [P][4] y/z stencil neighbours, written by sweep 0
     const float *final_delta = nullptr;
-    sn::VolDesc *dd = nullptr;     // device copy of d
-    int64_t *dtp = nullptr;        // device tile prefix {0, ntiles}
-    sn::SmoothDesc *dsd = nullptr; // device smoothing descriptor
-    int64_t *dbp = nullptr;        // device block prefix {0, point blocks}
-    std::map<int32_t, hipGraphExec_t> graphs;  // sweeps -> instantiated sweep graph
-    hipEvent_t done_ev = nullptr;
-    bool last_stream_valid = false;
+
+
+    hipEvent_t done_ev = nullptr;  // recorded after the last library work on the mesh
 };
 
 namespace sn {
@@ -124,8 +154,8 @@ sn_status smooth_many(sn_ctx *c, sn_mesh **ms, const sn_smooth_params *pv, int32
                       hipStream_t s);
 sn_status ensure_smooth_buffers(sn_mesh *m);
 sn_status run_sweeps(sn_ctx *c, const SmoothDesc *d_sd, const int64_t *d_bp, int32_t nvol,
-                     int64_t nblocks, int32_t iters, hipStream_t s,
-                     std::map<int32_t, hipGraphExec_t> *cache);
+                     int64_t nblocks, int32_t iters, hipStream_t s);
+sn_status run_sweeps_one(sn_ctx *c, const SmoothDesc &sd, int64_t nblocks, hipStream_t s);
 sn_status mesh_mark(sn_mesh *m, hipStream_t s);
 void mesh_release(sn_mesh *m);
 void ctx_retain(sn_ctx *c);

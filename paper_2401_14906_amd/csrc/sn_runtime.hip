@@ -62,6 +62,37 @@ extern "C" const char *sn_version(void) { return "libsn gfx950 " __DATE__; }
 // block freed while a stream still uses it is never handed out early.
 // ---------------------------------------------------------------------------
 
+EventCache::~EventCache()
+{
+    for (auto e : free_) (void)hipEventDestroy(e);
+}
+
+hipEvent_t EventCache::get()
+{
+    {
+        std::lock_guard<std::mutex> g(mu_);
+        if (!free_.empty()) {
+            hipEvent_t e = free_.back();
+            free_.pop_back();
+            return e;
+        }
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreateWithFlags(&e, flags_) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    return e;
+}
+
+// Only events whose recorded work has completed come back here.
+void EventCache::put(hipEvent_t e)
+{
+    if (!e) return;
+    std::lock_guard<std::mutex> g(mu_);
+    free_.push_back(e);
+}
+
 static size_t round_size(size_t n)
 {
     if (n == 0) n = 1;
@@ -94,19 +125,20 @@ void Pool::raw_free(void *p)
         (void)hipFree(p);
 }
 
+// Deferred blocks come back in release order; without `wait` the scan stops
+// at the first release whose event has not completed.
 void Pool::reclaim_locked(bool wait)
 {
-    for (size_t k = 0; k < pending_.size();) {
-        Pending &pd = pending_[k];
-        hipError_t q = wait ? hipEventSynchronize(pd.ev) : hipEventQuery(pd.ev);
-        if (q == hipSuccess || (q != hipErrorNotReady)) {
-            for (void *p : pd.blocks) free_.emplace(sizes_[p], p);
+    while (!pending_.empty()) {
+        Pending &pd = pending_.front();
+        const hipError_t q = wait ? hipEventSynchronize(pd.ev) : hipEventQuery(pd.ev);
+        if (q == hipErrorNotReady) break;
+        for (void *p : pd.blocks) free_.emplace(sizes_[p], p);
+        if (q == hipSuccess)
+            events_.put(pd.ev);
+        else
             (void)hipEventDestroy(pd.ev);
-            pending_[k] = std::move(pending_.back());
-            pending_.pop_back();
-        } else {
-            ++k;
-        }
+        pending_.pop_front();
     }
 }
 
@@ -154,10 +186,10 @@ void Pool::release(void *p, hipStream_t after)
         free_.emplace(it->second, p);
         return;
     }
-    hipEvent_t ev;
-    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess ||
-        hipEventRecord(ev, after) != hipSuccess) {
+    hipEvent_t ev = events_.get();
+    if (!ev || hipEventRecord(ev, after) != hipSuccess) {
         (void)hipGetLastError();
+        if (ev) (void)hipEventDestroy(ev);
         (void)hipStreamSynchronize(after);
         free_.emplace(it->second, p);
         return;
@@ -177,10 +209,10 @@ void Pool::release_all(const std::vector<void *> &ps, hipStream_t after)
         live.push_back(p);
     }
     if (live.empty()) return;
-    hipEvent_t ev;
-    if (after == kNoWait || hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess ||
-        hipEventRecord(ev, after) != hipSuccess) {
+    hipEvent_t ev = after == kNoWait ? nullptr : events_.get();
+    if (after == kNoWait || !ev || hipEventRecord(ev, after) != hipSuccess) {
         (void)hipGetLastError();
+        if (ev) (void)hipEventDestroy(ev);
         if (after != kNoWait) (void)hipStreamSynchronize(after);
         for (void *p : live) free_.emplace(sizes_[p], p);
         return;
@@ -214,7 +246,9 @@ extern "C" sn_status sn_ctx_create(int device, sn_ctx **out)
     }
     HIP_TRY(hipSetDevice(device));
     sn_ctx *c = new sn_ctx(device);
-    if (hipStreamCreateWithFlags(&c->copy_stream, hipStreamNonBlocking) != hipSuccess) {
+    if (hipStreamCreateWithFlags(&c->copy_stream, hipStreamNonBlocking) != hipSuccess ||
+        hipStreamCreateWithFlags(&c->retire_stream, hipStreamNonBlocking) != hipSuccess) {
+        if (c->copy_stream) (void)hipStreamDestroy(c->copy_stream);
         delete c;
         return fail(SN_EDEVICE, "sn_ctx_create: stream creation failed");
     }
@@ -234,7 +268,16 @@ void sn::ctx_release(sn_ctx *c)
     if (c->refs.fetch_sub(1, std::memory_order_acq_rel) != 1) return;
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->copy_stream);
+    (void)hipStreamSynchronize(c->retire_stream);
+    for (auto &kv : c->sweep_graphs) {
+        (void)hipEventSynchronize(kv.second.last);
+        (void)hipEventDestroy(kv.second.last);
+        (void)hipGraphExecDestroy(kv.second.exec);
+        (void)hipGraphDestroy(kv.second.graph);
+    }
+    c->sweep_graphs.clear();
     (void)hipStreamDestroy(c->copy_stream);
+    (void)hipStreamDestroy(c->retire_stream);
     delete c;
 }
 
@@ -259,8 +302,11 @@ ProfScope::ProfScope(sn_ctx *c, const char *name, hipStream_t s, int64_t launche
     : c_(c), name_(name), s_(s), launches_(launches)
 {
     if (!c_ || !c_->profiling) return;
-    if (hipEventCreate(&a_) != hipSuccess || hipEventCreate(&b_) != hipSuccess) {
-        (void)hipGetLastError();
+    a_ = c_->timing_events.get();
+    b_ = c_->timing_events.get();
+    if (!a_ || !b_) {
+        c_->timing_events.put(a_);
+        c_->timing_events.put(b_);
         a_ = b_ = nullptr;
         return;
     }
@@ -308,8 +354,8 @@ extern "C" sn_status sn_profile_read(sn_ctx *c, sn_kernel_stat *out, int32_t cap
         auto &st = c->prof_stats[p.name];
         st.first += p.launches;
         st.second += ms;
-        (void)hipEventDestroy(p.a);
-        (void)hipEventDestroy(p.b);
+        c->timing_events.put(p.a);
+        c->timing_events.put(p.b);
     }
     c->prof_pending.clear();
     int32_t k = 0;
@@ -463,22 +509,25 @@ static void class_table(const sn_volume &v, int32_t *mode, std::vector<uint32_t>
 // meshes
 // ---------------------------------------------------------------------------
 
-sn_mesh::~sn_mesh()
-{
-    for (auto &kv : graphs) (void)hipGraphExecDestroy(kv.second);
-}
+sn_mesh::~sn_mesh() {}
 
 void sn::mesh_release(sn_mesh *m)
 {
     if (!m) return;
-    (void)hipSetDevice(m->ctx->device);
-    if (m->last_stream_valid) {
-        // wait only for the work this mesh has enqueued
-        if (m->done_ev) (void)hipEventSynchronize(m->done_ev);
+    sn_ctx *c = m->ctx;
+    (void)hipSetDevice(c->device);
+    // everything the library enqueued for this mesh precedes done_ev; the
+    // retire stream waits for it, and the blocks are released behind an event
+    // on the retire stream, without blocking the host
+    hipStream_t rs = c->retire_stream;
+    bool ordered = true;
+    if (m->done_ev && hipStreamWaitEvent(rs, m->done_ev, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipEventSynchronize(m->done_ev);
+        ordered = false;
     }
     if (m->done_ev) (void)hipEventDestroy(m->done_ev);
-    sn_ctx *c = m->ctx;
-    c->pool.release_all(m->blocks, Pool::kNoWait);
+    c->pool.release_all(m->blocks, ordered ? rs : Pool::kNoWait);
     delete m;
     ctx_release(c);
 }
@@ -489,7 +538,6 @@ sn_status sn::mesh_mark(sn_mesh *m, hipStream_t s)
 {
     if (!m->done_ev) HIP_TRY(hipEventCreateWithFlags(&m->done_ev, hipEventDisableTiming));
     HIP_TRY(hipEventRecord(m->done_ev, s));
-    m->last_stream_valid = true;
     return SN_OK;
 }
 
@@ -582,6 +630,18 @@ struct Scratch {
     }
 };
 
+// Sub-allocation of several arrays from one pool block: each array starts on
+// a 256-byte boundary.
+struct Carve {
+    size_t bytes = 0;
+    size_t add(int64_t n)
+    {
+        const size_t at = bytes;
+        bytes += ((size_t)std::max<int64_t>(n, 1) + 255) & ~size_t(255);
+        return at;
+    }
+};
+
 template <typename T>
 T *dalloc(sn_mesh *m, int64_t count)
 {
@@ -641,7 +701,27 @@ sn_status sn::extract_many(sn_ctx *c, const sn_volume *vols, int32_t n, hipStrea
     std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return key(a) < key(b); });
 
     std::vector<int64_t> tile_prefix(n + 1, 0), etile_prefix(n + 1, 0), ctile_prefix(n + 1, 0);
-    std::vector<void *> planes_blocks;
+    // A single volume travels to its kernels by value (kernel arguments); a
+    // batch uploads its descriptor array and tile maps once.  Classification
+    // tables are uploaded in the same block (read by k_edges and k_generate
+    // only, so they live as long as this call's scratch).
+    const bool one = (n == 1);
+    size_t tab_words = 0;
+    for (int32_t v = 0; v < n; ++v) tab_words += (tabs[v].size() + 1) / 2;
+    const size_t arr_bytes = one ? 0 : sizeof(VolDesc) * n + sizeof(int64_t) * 3 * (n + 1);
+    const size_t up_a = arr_bytes + 8 * tab_words;
+    uint8_t *h_up = nullptr, *d_up = nullptr;
+    if (up_a > 0) {
+        h_up = static_cast<uint8_t *>(scr.h(up_a));
+        d_up = static_cast<uint8_t *>(scr.d(up_a));
+        if (!h_up || !d_up) return cleanup(fail(SN_ENOMEM, "extract: descriptor staging"));
+    }
+    std::vector<VolDesc> hd(n);  // host descriptors in launch order
+    VolDesc *d_desc = one ? nullptr : reinterpret_cast<VolDesc *>(d_up);
+    int64_t *d_tp = one ? nullptr : reinterpret_cast<int64_t *>(d_up + sizeof(VolDesc) * n);
+    uint32_t *h_tab = h_up ? reinterpret_cast<uint32_t *>(h_up + arr_bytes) : nullptr;
+    uint32_t *d_tab = d_up ? reinterpret_cast<uint32_t *>(d_up + arr_bytes) : nullptr;
+    size_t tab_at = 0;  // in uint32 units, kept 8-byte aligned
     for (int32_t k = 0; k < n; ++k) {
         const int32_t v = order[k];
         const sn_volume &vol = vols[v];
@@ -661,17 +741,18 @@ sn_status sn::extract_many(sn_ctx *c, const sn_volume *vols, int32_t n, hipStrea
         d.cs.bg = vol.background;
         d.cs.n = (int32_t)tabs[v].size();
         if (!tabs[v].empty()) {
-            const size_t nb = sizeof(uint32_t) * tabs[v].size();
-            uint32_t *t = dalloc<uint32_t>(m, (int64_t)tabs[v].size());
-            uint32_t *ht = static_cast<uint32_t *>(scr.h(nb));
-            if (!t || !ht) return cleanup(fail(SN_ENOMEM, "extract: classification table"));
-            std::memcpy(ht, tabs[v].data(), nb);
-            HIP_TRY(hipMemcpyAsync(t, ht, nb, hipMemcpyHostToDevice, s));
-            d.cs.table = t;
+            std::memcpy(h_tab + tab_at, tabs[v].data(), sizeof(uint32_t) * tabs[v].size());
+            d.cs.table = d_tab + tab_at;
+            tab_at += 2 * ((tabs[v].size() + 1) / 2);
         }
         const int64_t words = d.g.R * d.g.W;
-        d.pmask = dalloc<uint64_t>(m, words);
-        d.wbP = dalloc<int32_t>(m, words);
+        {
+            Carve cv;
+            const size_t o_pm = cv.add(8 * words), o_wb = cv.add(4 * words);
+            uint8_t *blk = dalloc<uint8_t>(m, (int64_t)cv.bytes);
+            d.pmask = blk ? reinterpret_cast<uint64_t *>(blk + o_pm) : nullptr;
+            d.wbP = blk ? reinterpret_cast<int32_t *>(blk + o_wb) : nullptr;
+        }
         // extraction-only metadata: cut-edge planes and quad/stencil word bases
         d.wbQ = static_cast<int32_t *>(scr.d(sizeof(int32_t) * (size_t)std::max<int64_t>(words, 1)));
         d.wbS = static_cast<int32_t *>(scr.d(sizeof(int32_t) * (size_t)std::max<int64_t>(words, 1)));
@@ -680,12 +761,15 @@ sn_status sn::extract_many(sn_ctx *c, const sn_volume *vols, int32_t n, hipStrea
         if (!d.pmask || !d.wbP || !d.wbQ || !d.wbS || !d.planes)
             return cleanup(fail(SN_ENOMEM, "extract: word metadata"));
         const int64_t nbatch = d.g.R * d.g.NB;
-        m->ntiles = (nbatch + TB - 1) / TB;
+        // every volume has at least one generation tile: its first tile writes
+        // st_off[P] = S (st_off[0] = 0 for an empty mesh)
+        m->ntiles = std::max<int64_t>(1, (nbatch + TB - 1) / TB);
         tile_prefix[k + 1] = tile_prefix[k] + m->ntiles;
         const int64_t nseg = d.g.N * d.g.O * d.g.NSEG;
         etile_prefix[k + 1] = etile_prefix[k] + (nseg + kSegmentsPerTile - 1) / kSegmentsPerTile;
         ctile_prefix[k + 1] = ctile_prefix[k] + (words + kBlock - 1) / kBlock;
         m->voxels = vol.dims[0] * vol.dims[1] * vol.dims[2];
+        hd[k] = d;
     }
     // groups: [gbeg[i], gbeg[i+1]) of the launch order share a key
     std::vector<int32_t> gbeg;
@@ -695,112 +779,126 @@ sn_status sn::extract_many(sn_ctx *c, const sn_volume *vols, int32_t n, hipStrea
     const int32_t ngroups = (int32_t)gbeg.size() - 1;
 
     const int64_t nctiles = ctile_prefix[n];
-    VolDesc *h_desc = static_cast<VolDesc *>(scr.h(sizeof(VolDesc) * n));
-    int64_t *h_tp = static_cast<int64_t *>(scr.h(sizeof(int64_t) * 3 * (n + 1)));
     int64_t *h_tot = static_cast<int64_t *>(scr.h(sizeof(int64_t) * 3 * n));
-    VolDesc *d_desc = static_cast<VolDesc *>(scr.d(sizeof(VolDesc) * n));
-    int64_t *d_tp = static_cast<int64_t *>(scr.d(sizeof(int64_t) * 3 * (n + 1)));
     int64_t *d_tot = static_cast<int64_t *>(scr.d(sizeof(int64_t) * 3 * n));
     const size_t status_bytes = sizeof(uint64_t) * 3 * (size_t)std::max<int64_t>(nctiles, 1);
     uint8_t *d_status = static_cast<uint8_t *>(scr.d(status_bytes + 256));
-    if (!h_desc || !h_tp || !h_tot || !d_desc || !d_tp || !d_tot || !d_status)
-        return cleanup(fail(SN_ENOMEM, "extract: scratch"));
-    for (int32_t k = 0; k < n; ++k) h_desc[k] = meshes[order[k]]->d;
-    // three tile maps: generation batches, edge segments, count words
-    std::memcpy(h_tp, tile_prefix.data(), sizeof(int64_t) * (n + 1));
-    std::memcpy(h_tp + (n + 1), etile_prefix.data(), sizeof(int64_t) * (n + 1));
-    std::memcpy(h_tp + 2 * (n + 1), ctile_prefix.data(), sizeof(int64_t) * (n + 1));
-    int64_t *d_etp = d_tp + (n + 1), *d_ctp = d_tp + 2 * (n + 1);
-    HIP_TRY(hipMemcpyAsync(d_desc, h_desc, sizeof(VolDesc) * n, hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(d_tp, h_tp, sizeof(int64_t) * 3 * (n + 1), hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemsetAsync(d_tot, 0, sizeof(int64_t) * 3 * n, s));
-    HIP_TRY(hipMemsetAsync(d_status, 0, status_bytes + 256, s));
+    if (!h_tot || !d_tot || !d_status) return cleanup(fail(SN_ENOMEM, "extract: scratch"));
+    uint64_t *status = reinterpret_cast<uint64_t *>(d_status);
+    uint32_t *ticket = reinterpret_cast<uint32_t *>(d_status + status_bytes);
+    if (!one) {
+        // descriptors and the three tile maps: generation batches, edge segments, count words
+        std::memcpy(h_up, hd.data(), sizeof(VolDesc) * n);
+        int64_t *h_tp = reinterpret_cast<int64_t *>(h_up + sizeof(VolDesc) * n);
+        std::memcpy(h_tp, tile_prefix.data(), sizeof(int64_t) * (n + 1));
+        std::memcpy(h_tp + (n + 1), etile_prefix.data(), sizeof(int64_t) * (n + 1));
+        std::memcpy(h_tp + 2 * (n + 1), ctile_prefix.data(), sizeof(int64_t) * (n + 1));
+    }
+    if (up_a > 0) HIP_TRY(hipMemcpyAsync(d_up, h_up, up_a, hipMemcpyHostToDevice, s));
+    // the first edges launch clears the count pass's status words and ticket
+    const int64_t nzero = (int64_t)((status_bytes + 256) / 8);
     {
         ProfScope ps(c, "k_edges", s);
-        for (int32_t gi = 0; gi < ngroups; ++gi) {
-            const int32_t k0 = gbeg[gi], k1 = gbeg[gi + 1];
-            const VolDesc &d0 = h_desc[k0];
-            HIP_TRY(launch_edges(d0.dtype, d0.cs.mode, wide(order[k0]), d_desc + k0, d_etp + k0,
-                                 k1 - k0, etile_prefix[k0], etile_prefix[k1] - etile_prefix[k0], s));
+        if (one) {
+            HIP_TRY(launch_edges_one(hd[0], wide(order[0]), etile_prefix[1], status, nzero, s));
+        } else {
+            bool zeroed = false;
+            for (int32_t gi = 0; gi < ngroups; ++gi) {
+                const int32_t k0 = gbeg[gi], k1 = gbeg[gi + 1];
+                const int64_t nt = etile_prefix[k1] - etile_prefix[k0];
+                HIP_TRY(launch_edges(hd[k0].dtype, hd[k0].cs.mode, wide(order[k0]), d_desc + k0,
+                                     d_tp + (n + 1) + k0, k1 - k0, etile_prefix[k0], nt, status,
+                                     (nt > 0 && !zeroed) ? nzero : 0, s));
+                zeroed = zeroed || nt > 0;
+            }
         }
     }
     {
         ProfScope ps(c, "k_count", s);
-        HIP_TRY(launch_count(d_desc, d_ctp, n, nctiles, reinterpret_cast<uint64_t *>(d_status),
-                             reinterpret_cast<uint32_t *>(d_status + status_bytes), d_tot, s));
+        if (one)
+            HIP_TRY(launch_count_one(hd[0], nctiles, status, ticket, d_tot, s));
+        else
+            HIP_TRY(launch_count(d_desc, d_tp + 2 * (n + 1), n, nctiles, status, ticket, d_tot, s));
     }
     HIP_TRY(hipMemcpyAsync(h_tot, d_tot, sizeof(int64_t) * 3 * n, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
 
     // exact allocation of every output (Sec. 2.3: no incremental allocation)
+    int64_t qblocks = 0;
     for (int32_t k = 0; k < n; ++k) {
         sn_mesh *m = meshes[order[k]];
         VolDesc &d = m->d;
-        m->P = h_tot[3 * k], m->Q = h_tot[3 * k + 1], m->S = h_tot[3 * k + 2];
+        // a volume without cell words has no count tile and no totals written
+        const bool counted = ctile_prefix[k + 1] > ctile_prefix[k];
+        m->P = counted ? h_tot[3 * k] : 0;
+        m->Q = counted ? h_tot[3 * k + 1] : 0;
+        m->S = counted ? h_tot[3 * k + 2] : 0;
         if (m->P >= INT32_MAX || m->Q >= INT32_MAX / 2 || m->S >= INT32_MAX)
             return cleanup(fail(SN_ETOOBIG, "extract: mesh indices exceed int32"));
         d.P = m->P, d.Q = m->Q, d.S = m->S;
-        d.points = dalloc<float>(m, 3 * m->P);
-        d.faces = dalloc<uint8_t>(m, m->P);
-        d.st_off = dalloc<int32_t>(m, m->P + 1);
-        d.st_ids = dalloc<int32_t>(m, m->S);
-        d.quads = dalloc<int32_t>(m, 4 * m->Q);
-        d.pairs = dalloc<uint8_t>(m, 2 * m->Q * d.dtype);
-        if (!d.points || !d.faces || !d.st_off || !d.st_ids || !d.quads || !d.pairs)
-            return cleanup(fail(SN_ENOMEM, "extract: outputs"));
-        if (d.prim == SN_TRIS) {
-            d.tris = dalloc<int32_t>(m, 6 * m->Q);
-            d.tri_pairs = dalloc<uint8_t>(m, 4 * m->Q * d.dtype);
-            if (!d.tris || !d.tri_pairs) return cleanup(fail(SN_ENOMEM, "extract: triangles"));
+        // every output of the mesh in one block, sized exactly
+        Carve cv;
+        const size_t o_pts = cv.add(12 * m->P), o_fc = cv.add(m->P), o_off = cv.add(4 * (m->P + 1));
+        const size_t o_ids = cv.add(4 * m->S), o_q = cv.add(16 * m->Q), o_pr = cv.add(2 * m->Q * d.dtype);
+        const bool tris = d.prim == SN_TRIS;
+        const size_t o_t = tris ? cv.add(24 * m->Q) : 0, o_tp = tris ? cv.add(4 * m->Q * d.dtype) : 0;
+        uint8_t *blk = dalloc<uint8_t>(m, (int64_t)cv.bytes);
+        if (!blk) return cleanup(fail(SN_ENOMEM, "extract: outputs"));
+        d.points = reinterpret_cast<float *>(blk + o_pts);
+        d.faces = blk + o_fc;
+        d.st_off = reinterpret_cast<int32_t *>(blk + o_off);
+        d.st_ids = reinterpret_cast<int32_t *>(blk + o_ids);
+        d.quads = reinterpret_cast<int32_t *>(blk + o_q);
+        d.pairs = blk + o_pr;
+        if (tris) {
+            d.tris = reinterpret_cast<int32_t *>(blk + o_t);
+            d.tri_pairs = blk + o_tp;
+            qblocks += (m->Q + 255) / 256;
         }
-        h_desc[k] = d;
+        hd[k] = d;
     }
-    HIP_TRY(hipMemcpyAsync(d_desc, h_desc, sizeof(VolDesc) * n, hipMemcpyHostToDevice, s));
-    for (int32_t k = 0; k < n; ++k)  // volumes without cell rows still get st_off[0] = 0
-        if (meshes[order[k]]->ntiles == 0)
-            HIP_TRY(hipMemsetAsync(h_desc[k].st_off, 0, sizeof(int32_t), s));
-    {
-        ProfScope ps(c, "k_generate", s);
-        for (int32_t gi = 0; gi < ngroups; ++gi) {
-            const int32_t k0 = gbeg[gi], k1 = gbeg[gi + 1];
-            const VolDesc &d0 = h_desc[k0];
-            HIP_TRY(launch_generate(d0.dtype, d0.cs.mode, d_desc + k0, d_tp + k0, k1 - k0,
-                                    tile_prefix[k0], tile_prefix[k1] - tile_prefix[k0], bpw, s));
+    if (one) {
+        {
+            ProfScope ps(c, "k_generate", s);
+            HIP_TRY(launch_generate_one(hd[0], tile_prefix[1], bpw, s));
         }
-    }
-    int64_t qblocks = 0;
-    for (int32_t k = 0; k < n; ++k)
-        if (h_desc[k].prim == SN_TRIS) qblocks += (h_desc[k].Q + 255) / 256;
-    if (qblocks > 0) {
-        int64_t *h_qp = static_cast<int64_t *>(scr.h(sizeof(int64_t) * (n + 1)));
-        int64_t *d_qp = static_cast<int64_t *>(scr.d(sizeof(int64_t) * (n + 1)));
-        if (!h_qp || !d_qp) return cleanup(fail(SN_ENOMEM, "extract: triangle scratch"));
-        // volumes without triangles keep an empty block range
+        if (qblocks > 0) {
+            ProfScope ps(c, "k_tri", s);
+            HIP_TRY(launch_triangulate_one(hd[0], s));
+        }
+    } else {
+        // second upload: descriptors with the output arrays, and the triangle
+        // block map (volumes without triangles keep an empty range)
+        const size_t up_b = sizeof(VolDesc) * n + sizeof(int64_t) * (n + 1);
+        uint8_t *h_b = static_cast<uint8_t *>(scr.h(up_b));
+        uint8_t *d_b = static_cast<uint8_t *>(scr.d(up_b));
+        if (!h_b || !d_b) return cleanup(fail(SN_ENOMEM, "extract: descriptor staging"));
+        std::memcpy(h_b, hd.data(), sizeof(VolDesc) * n);
+        int64_t *h_qp = reinterpret_cast<int64_t *>(h_b + sizeof(VolDesc) * n);
         int64_t acc = 0;
         for (int32_t k = 0; k < n; ++k) {
             h_qp[k] = acc;
-            if (h_desc[k].prim == SN_TRIS) acc += (h_desc[k].Q + 255) / 256;
+            if (hd[k].prim == SN_TRIS) acc += (hd[k].Q + 255) / 256;
         }
         h_qp[n] = acc;
-        HIP_TRY(hipMemcpyAsync(d_qp, h_qp, sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice, s));
-        ProfScope ps(c, "k_tri", s);
-        HIP_TRY(launch_triangulate(d_desc, d_qp, n, acc, s));
+        HIP_TRY(hipMemcpyAsync(d_b, h_b, up_b, hipMemcpyHostToDevice, s));
+        VolDesc *d_desc2 = reinterpret_cast<VolDesc *>(d_b);
+        {
+            ProfScope ps(c, "k_generate", s);
+            for (int32_t gi = 0; gi < ngroups; ++gi) {
+                const int32_t k0 = gbeg[gi], k1 = gbeg[gi + 1];
+                HIP_TRY(launch_generate(hd[k0].dtype, hd[k0].cs.mode, d_desc2 + k0, d_tp + k0, k1 - k0,
+                                        tile_prefix[k0], tile_prefix[k1] - tile_prefix[k0], bpw, s));
+            }
+        }
+        if (qblocks > 0) {
+            ProfScope ps(c, "k_tri", s);
+            HIP_TRY(launch_triangulate(d_desc2, reinterpret_cast<int64_t *>(d_b + sizeof(VolDesc) * n),
+                                       n, acc, s));
+        }
     }
-    // per-mesh device descriptors for later emit/smoothing launches
     for (int32_t k = 0; k < n; ++k) {
-        sn_mesh *m = meshes[order[k]];
-        m->dd = dalloc<VolDesc>(m, 1);
-        m->dtp = dalloc<int64_t>(m, 2);
-        m->dsd = dalloc<SmoothDesc>(m, 1);
-        m->dbp = dalloc<int64_t>(m, 2);
-        int64_t *tp = static_cast<int64_t *>(scr.h(sizeof(int64_t) * 4));
-        if (!m->dd || !m->dtp || !m->dsd || !m->dbp || !tp)
-            return cleanup(fail(SN_ENOMEM, "extract: descriptors"));
-        HIP_TRY(hipMemcpyAsync(m->dd, &h_desc[k], sizeof(VolDesc), hipMemcpyHostToDevice, s));
-        tp[0] = 0, tp[1] = m->ntiles, tp[2] = 0, tp[3] = (m->P + kSweepPoints - 1) / kSweepPoints;
-        HIP_TRY(hipMemcpyAsync(m->dtp, tp, sizeof(int64_t) * 2, hipMemcpyHostToDevice, s));
-        HIP_TRY(hipMemcpyAsync(m->dbp, tp + 2, sizeof(int64_t) * 2, hipMemcpyHostToDevice, s));
-        sn_status st = mesh_mark(m, s);
+        sn_status st = mesh_mark(meshes[order[k]], s);
         if (st != SN_OK) return cleanup(st);
     }
     scr.retire(s);
@@ -832,17 +930,20 @@ sn_status sn::validate_smooth(const sn_smooth_params *p)
 sn_status sn::ensure_smooth_buffers(sn_mesh *m)
 {
     if (m->d.P == 0 || m->da) return SN_OK;
-    m->da = dalloc<float>(m, 3 * m->P);
-    m->db = dalloc<float>(m, 3 * m->P);
-    m->nbr = dalloc<int32_t>(m, 4 * m->P);
-    if (!m->da || !m->db || !m->nbr) return fail(SN_ENOMEM, "smooth: offset buffers");
+    Carve cv;
+    const size_t o_a = cv.add(12 * m->P), o_b = cv.add(12 * m->P), o_n = cv.add(16 * m->P);
+    uint8_t *blk = dalloc<uint8_t>(m, (int64_t)cv.bytes);
+    if (!blk) return fail(SN_ENOMEM, "smooth: offset buffers");
+    m->da = reinterpret_cast<float *>(blk + o_a);
+    m->db = reinterpret_cast<float *>(blk + o_b);
+    m->nbr = reinterpret_cast<int32_t *>(blk + o_n);
     return SN_OK;
 }
 
-// n sweeps over `nvol` meshes, replayed from a HIP graph of kernel nodes
+// n sweeps over `nvol` meshes (descriptor array), replayed from a HIP graph of
+// kernel nodes built for this call
 sn_status sn::run_sweeps(sn_ctx *c, const SmoothDesc *d_sd, const int64_t *d_bp, int32_t nvol,
-                         int64_t nblocks, int32_t iters, hipStream_t s,
-                         std::map<int32_t, hipGraphExec_t> *cache)
+                         int64_t nblocks, int32_t iters, hipStream_t s)
 {
     if (iters <= 0 || nblocks <= 0) return SN_OK;
     if (c->profile_eager) {
@@ -855,26 +956,84 @@ sn_status sn::run_sweeps(sn_ctx *c, const SmoothDesc *d_sd, const int64_t *d_bp,
     }
     // one event pair around the whole graph replay: `iters` launches
     ProfScope ps(c, "k_jacobi", s, iters);
+    // built node by node rather than by stream capture: no stream of the
+    // process is ever in capture mode, so other threads' work on the legacy
+    // stream cannot collide with it
+    hipGraph_t graph;
     hipGraphExec_t exec = nullptr;
-    if (cache) {
-        auto it = cache->find(iters);
-        if (it != cache->end()) exec = it->second;
+    HIP_TRY(hipGraphCreate(&graph, 0));
+    hipError_t e = add_jacobi_nodes(graph, d_sd, d_bp, nvol, nblocks, iters);
+    if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e == hipSuccess) e = hipGraphLaunch(exec, s);
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (e != hipSuccess) return fail(SN_EDEVICE, std::string("smooth: sweep graph: ") + hipGetErrorString(e));
+    return SN_OK;
+}
+
+// Launch-grid size of a cached sweep graph: the block count rounded up to
+// three significant bits (at most 1/8 of the blocks find no points and exit).
+static int64_t sweep_bucket(int64_t n)
+{
+    if (n <= 8) return n;
+    const int sh = 63 - __builtin_clzll((uint64_t)n) - 2;
+    return ((n + (int64_t(1) << sh) - 1) >> sh) << sh;
+}
+
+// n sweeps of one mesh from the context's cache of sweep graphs
+sn_status sn::run_sweeps_one(sn_ctx *c, const SmoothDesc &sd, int64_t nblocks, hipStream_t s)
+{
+    const int32_t iters = sd.iters;
+    if (iters <= 0 || nblocks <= 0) return SN_OK;
+    if (c->profile_eager) {
+        for (int32_t it = 0; it < iters; ++it) {
+            ProfScope ps(c, "k_jacobi", s);
+            HIP_TRY(launch_jacobi_one(sd, nblocks, it, s));
+        }
+        return SN_OK;
     }
-    if (!exec) {
-        // built node by node rather than by stream capture: no stream of the
-        // process is ever in capture mode, so other threads' work on the
-        // legacy stream cannot collide with it
-        hipGraph_t graph;
-        HIP_TRY(hipGraphCreate(&graph, 0));
-        hipError_t e = add_jacobi_nodes(graph, d_sd, d_bp, nvol, nblocks, iters);
-        if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(graph);
-        if (e != hipSuccess)
+    const int64_t nb = sweep_bucket(nblocks);
+    std::lock_guard<std::mutex> g(c->sweep_mu);
+    auto key = std::make_pair(iters, nb);
+    auto it = c->sweep_graphs.find(key);
+    if (it == c->sweep_graphs.end()) {
+        if (c->sweep_graphs.size() >= 32) {
+            // drop one cached graph once its last launch has completed
+            auto victim = c->sweep_graphs.begin();
+            (void)hipEventSynchronize(victim->second.last);
+            (void)hipEventDestroy(victim->second.last);
+            (void)hipGraphExecDestroy(victim->second.exec);
+            (void)hipGraphDestroy(victim->second.graph);
+            c->sweep_graphs.erase(victim);
+        }
+        sn_ctx::SweepGraph sg;
+        hipError_t e = hipGraphCreate(&sg.graph, 0);
+        if (e == hipSuccess) e = add_jacobi_nodes_one(sg.graph, sd, nb, iters, &sg.nodes);
+        if (e == hipSuccess) e = hipGraphInstantiate(&sg.exec, sg.graph, nullptr, nullptr, 0);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&sg.last, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            if (sg.exec) (void)hipGraphExecDestroy(sg.exec);
+            if (sg.graph) (void)hipGraphDestroy(sg.graph);
             return fail(SN_EDEVICE, std::string("smooth: sweep graph: ") + hipGetErrorString(e));
-        if (cache) (*cache)[iters] = exec;
+        }
+        sg.args = sd;
+        it = c->sweep_graphs.emplace(key, std::move(sg)).first;
     }
-    hipError_t e = hipGraphLaunch(exec, s);
-    if (!cache) (void)hipGraphExecDestroy(exec);
+    sn_ctx::SweepGraph &sg = it->second;
+    if (std::memcmp(&sg.args, &sd, sizeof(SmoothDesc)) != 0) {
+        // arguments of a launch still pending must not change under it
+        hipError_t e = hipEventSynchronize(sg.last);
+        if (e == hipSuccess) e = set_jacobi_nodes_one(sg.exec, sg.nodes, sd, nb);
+        if (e != hipSuccess) return fail(SN_EDEVICE, std::string("smooth: graph update: ") + hipGetErrorString(e));
+        sg.args = sd;
+    }
+    hipError_t e;
+    {
+        // one event pair around the whole graph replay: `iters` launches
+        ProfScope ps(c, "k_jacobi", s, iters);
+        e = hipGraphLaunch(sg.exec, s);
+    }
+    if (e == hipSuccess) e = hipEventRecord(sg.last, s);
     if (e != hipSuccess) return fail(SN_EDEVICE, std::string("smooth: graph launch: ") + hipGetErrorString(e));
     return SN_OK;
 }
@@ -894,35 +1053,20 @@ extern "C" sn_status sn_smooth(sn_ctx *c, sn_mesh *m, const sn_smooth_params *p,
         st = ensure_smooth_buffers(m);
         if (st != SN_OK) return st;
     }
-    SmoothDesc *h = static_cast<SmoothDesc *>(c->pinned.alloc(sizeof(SmoothDesc)));
-    VolDesc *hv = static_cast<VolDesc *>(c->pinned.alloc(sizeof(VolDesc)));
-    if (!h || !hv) {
-        c->pinned.release(h, Pool::kNoWait);
-        c->pinned.release(hv, Pool::kNoWait);
-        return fail(SN_ENOMEM, "smooth: staging");
-    }
-    h->P = m->P, h->faces = m->d.faces, h->off = m->d.st_off, h->ids = m->d.st_ids;
-    h->nbr = m->nbr, h->da = m->da, h->db = m->db, h->iters = p->iterations;
-    h->lam = (double)p->relaxation, h->dist = (double)p->constraint;
-    HIP_TRY(hipMemcpyAsync(m->dsd, h, sizeof(SmoothDesc), hipMemcpyHostToDevice, s));
+    SmoothDesc sd;
+    std::memset(&sd, 0, sizeof sd);
+    sd.P = m->P, sd.faces = m->d.faces, sd.off = m->d.st_off, sd.ids = m->d.st_ids;
+    sd.nbr = m->nbr, sd.da = m->da, sd.db = m->db, sd.iters = p->iterations;
+    sd.lam = (double)p->relaxation, sd.dist = (double)p->constraint;
     const int64_t nblocks = (m->P + kSweepPoints - 1) / kSweepPoints;
-    st = run_sweeps(c, m->dsd, m->dbp, 1, nblocks, p->iterations, s, &m->graphs);
-    if (st != SN_OK) {
-        c->pinned.release(h, s);
-        c->pinned.release(hv, s);
-        return st;
-    }
+    st = run_sweeps_one(c, sd, nblocks, s);
+    if (st != SN_OK) return st;
     // the last sweep `it` wrote buffer (it odd ? da : db)
     m->final_delta = p->iterations == 0 ? nullptr : (((p->iterations - 1) & 1) ? m->da : m->db);
-    m->d.delta = m->final_delta;
-    *hv = m->d;
-    HIP_TRY(hipMemcpyAsync(m->dd, hv, sizeof(VolDesc), hipMemcpyHostToDevice, s));
     {
         ProfScope ps(c, "k_emit", s);
-        HIP_TRY(launch_emit(m->dd, m->dtp, 1, m->ntiles, m->bpw, s));
+        HIP_TRY(launch_emit_one(m->d, sd, m->ntiles, m->bpw, s));
     }
-    c->pinned.release(h, s);
-    c->pinned.release(hv, s);
     return mesh_mark(m, s);
 }
 
@@ -947,16 +1091,21 @@ sn_status sn::smooth_many(sn_ctx *c, sn_mesh **ms, const sn_smooth_params *pv, i
         tp[v + 1] = tp[v] + ms[v]->ntiles;
         maxit = std::max(maxit, pv[v].iterations);
     }
-    SmoothDesc *h_sd = static_cast<SmoothDesc *>(scr.h(sizeof(SmoothDesc) * n));
-    VolDesc *h_vd = static_cast<VolDesc *>(scr.h(sizeof(VolDesc) * n));
-    int64_t *h_p = static_cast<int64_t *>(scr.h(sizeof(int64_t) * 2 * (n + 1)));
-    SmoothDesc *d_sd = static_cast<SmoothDesc *>(scr.d(sizeof(SmoothDesc) * n));
-    VolDesc *d_vd = static_cast<VolDesc *>(scr.d(sizeof(VolDesc) * n));
-    int64_t *d_p = static_cast<int64_t *>(scr.d(sizeof(int64_t) * 2 * (n + 1)));
-    if (!h_sd || !h_vd || !h_p || !d_sd || !d_vd || !d_p) {
+    // one upload: smoothing and volume descriptors, sweep-block map, emit tile
+    // map and per-mesh emit maps {0, ntiles}
+    const size_t up = sizeof(SmoothDesc) * n + sizeof(VolDesc) * n + sizeof(int64_t) * (4 * n + 2);
+    uint8_t *h_up = static_cast<uint8_t *>(scr.h(up));
+    uint8_t *d_up = static_cast<uint8_t *>(scr.d(up));
+    if (!h_up || !d_up) {
         scr.retire(s);
         return fail(SN_ENOMEM, "batch smooth: scratch");
     }
+    SmoothDesc *h_sd = reinterpret_cast<SmoothDesc *>(h_up);
+    VolDesc *h_vd = reinterpret_cast<VolDesc *>(h_up + sizeof(SmoothDesc) * n);
+    int64_t *h_p = reinterpret_cast<int64_t *>(h_up + (sizeof(SmoothDesc) + sizeof(VolDesc)) * n);
+    SmoothDesc *d_sd = reinterpret_cast<SmoothDesc *>(d_up);
+    VolDesc *d_vd = reinterpret_cast<VolDesc *>(d_up + sizeof(SmoothDesc) * n);
+    int64_t *d_p = reinterpret_cast<int64_t *>(d_up + (sizeof(SmoothDesc) + sizeof(VolDesc)) * n);
     for (int32_t v = 0; v < n; ++v) {
         sn_mesh *m = ms[v];
         SmoothDesc &h = h_sd[v];
@@ -965,15 +1114,14 @@ sn_status sn::smooth_many(sn_ctx *c, sn_mesh **ms, const sn_smooth_params *pv, i
         h.lam = (double)pv[v].relaxation, h.dist = (double)pv[v].constraint;
         m->final_delta =
             h.iters == 0 ? nullptr : (((h.iters - 1) & 1) ? m->da : m->db);
-        m->d.delta = m->final_delta;
         h_vd[v] = m->d;
+        h_p[2 * (n + 1) + 2 * v] = 0;
+        h_p[2 * (n + 1) + 2 * v + 1] = m->ntiles;
     }
     std::memcpy(h_p, bp.data(), sizeof(int64_t) * (n + 1));
     std::memcpy(h_p + n + 1, tp.data(), sizeof(int64_t) * (n + 1));
-    HIP_TRY(hipMemcpyAsync(d_sd, h_sd, sizeof(SmoothDesc) * n, hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(d_vd, h_vd, sizeof(VolDesc) * n, hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(d_p, h_p, sizeof(int64_t) * 2 * (n + 1), hipMemcpyHostToDevice, s));
-    sn_status st = run_sweeps(c, d_sd, d_p, n, bp[n], maxit, s, nullptr);
+    HIP_TRY(hipMemcpyAsync(d_up, h_up, up, hipMemcpyHostToDevice, s));
+    sn_status st = run_sweeps(c, d_sd, d_p, n, bp[n], maxit, s);
     if (st != SN_OK) {
         scr.retire(s);
         return st;
@@ -983,17 +1131,13 @@ sn_status sn::smooth_many(sn_ctx *c, sn_mesh **ms, const sn_smooth_params *pv, i
     {
         ProfScope ps(c, "k_emit", s);
         if (same_bpw) {
-            HIP_TRY(launch_emit(d_vd, d_p + n + 1, n, tp[n], ms[0]->bpw, s));
+            HIP_TRY(launch_emit(d_vd, d_sd, d_p + n + 1, n, tp[n], ms[0]->bpw, s));
         } else {
-            for (int32_t v = 0; v < n; ++v) {
-                HIP_TRY(hipMemcpyAsync(ms[v]->dd, &h_vd[v], sizeof(VolDesc), hipMemcpyHostToDevice, s));
-                HIP_TRY(launch_emit(ms[v]->dd, ms[v]->dtp, 1, ms[v]->ntiles, ms[v]->bpw, s));
-            }
+            for (int32_t v = 0; v < n; ++v)
+                HIP_TRY(launch_emit(d_vd + v, d_sd + v, d_p + 2 * (n + 1) + 2 * v, 1, ms[v]->ntiles,
+                                    ms[v]->bpw, s));
         }
     }
-    // keep each mesh's own descriptor current for later per-mesh calls
-    for (int32_t v = 0; v < n; ++v)
-        HIP_TRY(hipMemcpyAsync(ms[v]->dd, &h_vd[v], sizeof(VolDesc), hipMemcpyHostToDevice, s));
     scr.retire(s);
     for (int32_t v = 0; v < n; ++v) {
         st = mesh_mark(ms[v], s);
