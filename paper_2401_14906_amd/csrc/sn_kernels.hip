@@ -79,7 +79,10 @@ __device__ __forceinline__ int find_seg(const int64_t *prefix, int n, int64_t t)
 // Where a launch finds its volume: an array of descriptors in device memory
 // with a prefix of tiles (or blocks) per volume, for launches over many
 // volumes; or a single descriptor passed by value in the kernel arguments,
-// which needs no upload before the launch.
+// which needs no upload before the launch.  Kernels over many volumes take
+// the array as __restrict__ parameters (so descriptor loads are known not to
+// alias the kernel's stores) and wrap them in these structs for the shared
+// bodies.
 struct ManyVols {
     const VolDesc *descs;
     const int64_t *prefix;
@@ -400,18 +403,34 @@ __device__ __forceinline__ void edges_tile(const Src &a, int64_t tile_base, uint
     }
 }
 
-template <typename T, int MODE, class Src>
-__global__ __launch_bounds__(kBlock) void k_edges_wide(Src a, int64_t tile_base, uint64_t *zero,
-                                                       int64_t nzero)
+template <typename T, int MODE>
+__global__ __launch_bounds__(kBlock) void k_edges_wide(const VolDesc *__restrict__ descs,
+                                                       const int64_t *__restrict__ prefix,
+                                                       int32_t nvol, int64_t tile_base,
+                                                       uint64_t *zero, int64_t nzero)
 {
-    edges_tile<T, MODE, true>(a, tile_base, zero, nzero);
+    edges_tile<T, MODE, true>(ManyVols{descs, prefix, nvol}, tile_base, zero, nzero);
 }
 
-template <typename T, int MODE, class Src>
-__global__ __launch_bounds__(kBlock) void k_edges_narrow(Src a, int64_t tile_base, uint64_t *zero,
-                                                         int64_t nzero)
+template <typename T, int MODE>
+__global__ __launch_bounds__(kBlock) void k_edges_narrow(const VolDesc *__restrict__ descs,
+                                                         const int64_t *__restrict__ prefix,
+                                                         int32_t nvol, int64_t tile_base,
+                                                         uint64_t *zero, int64_t nzero)
 {
-    edges_tile<T, MODE, false>(a, tile_base, zero, nzero);
+    edges_tile<T, MODE, false>(ManyVols{descs, prefix, nvol}, tile_base, zero, nzero);
+}
+
+template <typename T, int MODE>
+__global__ __launch_bounds__(kBlock) void k_edges_wide_one(OneVol a, uint64_t *zero, int64_t nzero)
+{
+    edges_tile<T, MODE, true>(a, 0, zero, nzero);
+}
+
+template <typename T, int MODE>
+__global__ __launch_bounds__(kBlock) void k_edges_narrow_one(OneVol a, uint64_t *zero, int64_t nzero)
+{
+    edges_tile<T, MODE, false>(a, 0, zero, nzero);
 }
 
 // ---------------------------------------------------------------------------
@@ -477,8 +496,8 @@ __device__ __forceinline__ int64_t last_tile(const OneVol &, int)
 }
 
 template <class Src>
-__global__ __launch_bounds__(kBlock) void k_count(Src a, uint64_t *status, uint32_t *ticket,
-                                                  int64_t *totals)
+__device__ __forceinline__ void count_body(const Src &a, uint64_t *status, uint32_t *ticket,
+                                           int64_t *totals)
 {
     __shared__ int64_t s_tile;
     __shared__ int64_t s_wtot[3][kWavesPerBlock];
@@ -556,6 +575,19 @@ __global__ __launch_bounds__(kBlock) void k_count(Src a, uint64_t *status, uint3
         glb(d.wbQ)[gw] = (int32_t)(s_excl[1] + before[1] + ex[1]);
         glb(d.wbS)[gw] = (int32_t)(s_excl[2] + before[2] + ex[2]);
     }
+}
+
+__global__ __launch_bounds__(kBlock) void k_count(const VolDesc *__restrict__ descs,
+                                                  const int64_t *__restrict__ prefix, int32_t nvol,
+                                                  uint64_t *status, uint32_t *ticket, int64_t *totals)
+{
+    count_body(ManyVols{descs, prefix, nvol}, status, ticket, totals);
+}
+
+__global__ __launch_bounds__(kBlock) void k_count_one(OneVol a, uint64_t *status, uint32_t *ticket,
+                                                      int64_t *totals)
+{
+    count_body(a, status, ticket, totals);
 }
 
 // ---------------------------------------------------------------------------
@@ -830,14 +862,16 @@ __device__ __forceinline__ void generate_stream(const VolDesc &d, int64_t b0, in
     }
 }
 
-template <typename T, int MODE, class Src>
-__global__ __launch_bounds__(kBlock) void k_generate(Src a, int64_t tile_base, int32_t bpw)
+template <typename T, int MODE>
+__global__ __launch_bounds__(kBlock) void k_generate(const VolDesc *__restrict__ descs,
+                                                     const int64_t *__restrict__ prefix,
+                                                     int32_t nvol, int64_t tile_base, int32_t bpw)
 {
     __shared__ Stage stage[kWavesPerBlock];
     const int64_t t = tile_base + blockIdx.x;
     int v;
     int64_t first;
-    const VolDesc &d = vol_of(a, t, v, first);
+    const VolDesc &d = vol_of(ManyVols{descs, prefix, nvol}, t, v, first);
     const int64_t nbv = d.g.R * d.g.NB;
     const int64_t bt0 = (t - first) * (kWavesPerBlock * bpw);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
@@ -908,7 +942,7 @@ __device__ __forceinline__ const VolDesc &emit_of(const OneEmit &a, int64_t, con
 }
 
 template <class Src>
-__global__ __launch_bounds__(kBlock) void k_emit(Src a, int32_t bpw)
+__device__ __forceinline__ void emit_body(const Src &a, int32_t bpw)
 {
     const int64_t t = blockIdx.x;
     const SmoothDesc *sdp;
@@ -941,6 +975,19 @@ __global__ __launch_bounds__(kBlock) void k_emit(Src a, int32_t bpw)
         }
         emit_process(d, delta, P1, A1, lane);
     }
+}
+
+__global__ __launch_bounds__(kBlock) void k_emit(const VolDesc *__restrict__ descs,
+                                                 const SmoothDesc *__restrict__ sds,
+                                                 const int64_t *__restrict__ prefix, int32_t nvol,
+                                                 int32_t bpw)
+{
+    emit_body(ManyEmit{descs, sds, prefix, nvol}, bpw);
+}
+
+__global__ __launch_bounds__(kBlock) void k_emit_one(OneEmit a, int32_t bpw)
+{
+    emit_body(a, bpw);
 }
 
 // ---------------------------------------------------------------------------
@@ -980,10 +1027,21 @@ __device__ __forceinline__ void store_offset(SN_GLOBAL float *dout, int64_t p, d
 
 // Sweep 0: every input offset is zero, so p_q - p_p is the face step alone.
 // Reads the CSR stencil once and writes the y/z neighbour table.
-template <class Src>
-__global__ __launch_bounds__(256) void k_jacobi_first(Src a)
+// Blocks of a sweep launch that carry points: a launch over many meshes has
+// exactly those; a single mesh may run on a larger cached grid whose extra
+// blocks leave at once (and must not take part in the XCD remap).
+__device__ __forceinline__ uint32_t sweep_blocks(const ManySmooth &) { return gridDim.x; }
+__device__ __forceinline__ uint32_t sweep_blocks(const OneSmooth &a)
 {
-    const int64_t b = xcd_block(blockIdx.x, gridDim.x);
+    return (uint32_t)((a.s.P + kSweepPoints - 1) / kSweepPoints);
+}
+
+template <class Src>
+__device__ __forceinline__ void jacobi_first_body(const Src &a)
+{
+    const uint32_t nb = sweep_blocks(a);
+    if (blockIdx.x >= nb) return;
+    const int64_t b = xcd_block(blockIdx.x, nb);
     int64_t first;
     const SmoothDesc &s = smooth_of(a, b, first);
     if (s.iters < 1) return;
@@ -1021,6 +1079,18 @@ __global__ __launch_bounds__(256) void k_jacobi_first(Src a)
     }
 }
 
+__global__ __launch_bounds__(256) void k_jacobi_first(const SmoothDesc *__restrict__ sds,
+                                                      const int64_t *__restrict__ prefix,
+                                                      int32_t nvol)
+{
+    jacobi_first_body(ManySmooth{sds, prefix, nvol});
+}
+
+__global__ __launch_bounds__(256) void k_jacobi_first_one(OneSmooth a)
+{
+    jacobi_first_body(a);
+}
+
 __device__ __forceinline__ float shfl_up1(float x)
 {
     return __shfl_up(x, 1u);
@@ -1042,10 +1112,12 @@ __device__ __forceinline__ float readlane_f(float x, int l)
 // (consecutive cells of a row get consecutive ids), read from the adjacent
 // lane; only the first and the last point of the wave load them.
 template <class Src>
-__global__ __launch_bounds__(256) void k_jacobi(Src a, int32_t it)
+__device__ __forceinline__ void jacobi_body(const Src &a, int32_t it)
 {
     constexpr int K = kSweepChunks;
-    const int64_t b = xcd_block(blockIdx.x, gridDim.x);
+    const uint32_t nbl = sweep_blocks(a);
+    if (blockIdx.x >= nbl) return;
+    const int64_t b = xcd_block(blockIdx.x, nbl);
     int64_t first;
     const SmoothDesc &s = smooth_of(a, b, first);
     if (it >= s.iters) return;  // this mesh has finished its sweeps
@@ -1138,6 +1210,18 @@ __global__ __launch_bounds__(256) void k_jacobi(Src a, int32_t it)
     }
 }
 
+__global__ __launch_bounds__(256) void k_jacobi(const SmoothDesc *__restrict__ sds,
+                                                const int64_t *__restrict__ prefix, int32_t nvol,
+                                                int32_t it)
+{
+    jacobi_body(ManySmooth{sds, prefix, nvol}, it);
+}
+
+__global__ __launch_bounds__(256) void k_jacobi_one(OneSmooth a, int32_t it)
+{
+    jacobi_body(a, it);
+}
+
 // ---------------------------------------------------------------------------
 // k_tri: quad (A,B,C,D) -> (A,B,C), (A,C,D)
 // ---------------------------------------------------------------------------
@@ -1152,7 +1236,7 @@ __device__ __forceinline__ void tri_pairs(const VolDesc &d, int64_t q)
 }
 
 template <class Src>
-__global__ __launch_bounds__(256) void k_tri(Src a)
+__device__ __forceinline__ void tri_body(const Src &a)
 {
     const int64_t b = blockIdx.x;
     int v;
@@ -1168,50 +1252,62 @@ __global__ __launch_bounds__(256) void k_tri(Src a)
     else tri_pairs<uint32_t>(d, q);
 }
 
+__global__ __launch_bounds__(256) void k_tri(const VolDesc *__restrict__ descs,
+                                             const int64_t *__restrict__ prefix, int32_t nvol)
+{
+    tri_body(ManyVols{descs, prefix, nvol});
+}
+
+__global__ __launch_bounds__(256) void k_tri_one(OneVol a)
+{
+    tri_body(a);
+}
+
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
 
-// One instantiation per (label type, classification mode, source); every
-// volume of a launch has that key.
-#define SN_KEY_SWITCH(KERNEL, SRC, ...)                                                              \
-    switch (dtype * 4 + mode) {                                                                      \
-    case 1 * 4 + CLS_IDENT: hipLaunchKernelGGL((KERNEL<uint8_t, CLS_IDENT, SRC>), __VA_ARGS__); break;   \
-    case 1 * 4 + CLS_BITMAP: hipLaunchKernelGGL((KERNEL<uint8_t, CLS_BITMAP, SRC>), __VA_ARGS__); break; \
-    case 2 * 4 + CLS_IDENT: hipLaunchKernelGGL((KERNEL<uint16_t, CLS_IDENT, SRC>), __VA_ARGS__); break;  \
-    case 2 * 4 + CLS_BITMAP: hipLaunchKernelGGL((KERNEL<uint16_t, CLS_BITMAP, SRC>), __VA_ARGS__); break; \
-    case 4 * 4 + CLS_IDENT: hipLaunchKernelGGL((KERNEL<uint32_t, CLS_IDENT, SRC>), __VA_ARGS__); break;  \
-    case 4 * 4 + CLS_SORTED: hipLaunchKernelGGL((KERNEL<uint32_t, CLS_SORTED, SRC>), __VA_ARGS__); break; \
-    default: return hipErrorInvalidValue;                                                            \
+// One instantiation per (label type, classification mode); every volume of a
+// launch has that key.
+#define SN_KEY_SWITCH(KERNEL, ...)                                                          \
+    switch (dtype * 4 + mode) {                                                             \
+    case 1 * 4 + CLS_IDENT: hipLaunchKernelGGL((KERNEL<uint8_t, CLS_IDENT>), __VA_ARGS__); break; \
+    case 1 * 4 + CLS_BITMAP: hipLaunchKernelGGL((KERNEL<uint8_t, CLS_BITMAP>), __VA_ARGS__); break; \
+    case 2 * 4 + CLS_IDENT: hipLaunchKernelGGL((KERNEL<uint16_t, CLS_IDENT>), __VA_ARGS__); break; \
+    case 2 * 4 + CLS_BITMAP: hipLaunchKernelGGL((KERNEL<uint16_t, CLS_BITMAP>), __VA_ARGS__); break; \
+    case 4 * 4 + CLS_IDENT: hipLaunchKernelGGL((KERNEL<uint32_t, CLS_IDENT>), __VA_ARGS__); break; \
+    case 4 * 4 + CLS_SORTED: hipLaunchKernelGGL((KERNEL<uint32_t, CLS_SORTED>), __VA_ARGS__); break; \
+    default: return hipErrorInvalidValue;                                                   \
     }
-
-template <class Src>
-static hipError_t edges_impl(int32_t dtype, int32_t mode, bool wide, const Src &a, int64_t tile_base,
-                             int64_t ntiles, uint64_t *d_zero, int64_t nzero, hipStream_t s)
-{
-    if (ntiles <= 0) return hipSuccess;
-    if (wide) {
-        SN_KEY_SWITCH(k_edges_wide, Src, dim3((uint32_t)ntiles), dim3(kBlock), 0, s, a, tile_base,
-                      d_zero, nzero)
-    } else {
-        SN_KEY_SWITCH(k_edges_narrow, Src, dim3((uint32_t)ntiles), dim3(kBlock), 0, s, a, tile_base,
-                      d_zero, nzero)
-    }
-    return hipGetLastError();
-}
 
 hipError_t launch_edges(int32_t dtype, int32_t mode, bool wide, const VolDesc *d_descs,
                         const int64_t *d_tile_prefix, int32_t nvol, int64_t tile_base,
                         int64_t ntiles, uint64_t *d_zero, int64_t nzero, hipStream_t s)
 {
-    return edges_impl(dtype, mode, wide, ManyVols{d_descs, d_tile_prefix, nvol}, tile_base, ntiles,
-                      d_zero, nzero, s);
+    if (ntiles <= 0) return hipSuccess;
+    if (wide) {
+        SN_KEY_SWITCH(k_edges_wide, dim3((uint32_t)ntiles), dim3(kBlock), 0, s, d_descs,
+                      d_tile_prefix, nvol, tile_base, d_zero, nzero)
+    } else {
+        SN_KEY_SWITCH(k_edges_narrow, dim3((uint32_t)ntiles), dim3(kBlock), 0, s, d_descs,
+                      d_tile_prefix, nvol, tile_base, d_zero, nzero)
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_edges_one(const VolDesc &d, bool wide, int64_t ntiles, uint64_t *d_zero,
                             int64_t nzero, hipStream_t s)
 {
-    return edges_impl(d.dtype, d.cs.mode, wide, OneVol{d}, 0, ntiles, d_zero, nzero, s);
+    if (ntiles <= 0) return hipSuccess;
+    const int32_t dtype = d.dtype, mode = d.cs.mode;
+    if (wide) {
+        SN_KEY_SWITCH(k_edges_wide_one, dim3((uint32_t)ntiles), dim3(kBlock), 0, s, OneVol{d},
+                      d_zero, nzero)
+    } else {
+        SN_KEY_SWITCH(k_edges_narrow_one, dim3((uint32_t)ntiles), dim3(kBlock), 0, s, OneVol{d},
+                      d_zero, nzero)
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_count(const VolDesc *d_descs, const int64_t *d_tile_prefix, int32_t nvol,
@@ -1219,8 +1315,8 @@ hipError_t launch_count(const VolDesc *d_descs, const int64_t *d_tile_prefix, in
                         hipStream_t s)
 {
     if (ntiles <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_count<ManyVols>, dim3((uint32_t)ntiles), dim3(kBlock), 0, s,
-                       ManyVols{d_descs, d_tile_prefix, nvol}, d_status, d_ticket, d_totals);
+    hipLaunchKernelGGL(k_count, dim3((uint32_t)ntiles), dim3(kBlock), 0, s, d_descs, d_tile_prefix,
+                       nvol, d_status, d_ticket, d_totals);
     return hipGetLastError();
 }
 
@@ -1228,8 +1324,8 @@ hipError_t launch_count_one(const VolDesc &d, int64_t ntiles, uint64_t *d_status
                             int64_t *d_totals, hipStream_t s)
 {
     if (ntiles <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_count<OneVol>, dim3((uint32_t)ntiles), dim3(kBlock), 0, s, OneVol{d},
-                       d_status, d_ticket, d_totals);
+    hipLaunchKernelGGL(k_count_one, dim3((uint32_t)ntiles), dim3(kBlock), 0, s, OneVol{d}, d_status,
+                       d_ticket, d_totals);
     return hipGetLastError();
 }
 
@@ -1238,17 +1334,8 @@ hipError_t launch_generate(int32_t dtype, int32_t mode, const VolDesc *d_descs,
                            int64_t ntiles, int32_t bpw, hipStream_t s)
 {
     if (ntiles <= 0) return hipSuccess;
-    SN_KEY_SWITCH(k_generate, ManyVols, dim3((uint32_t)ntiles), dim3(kBlock), 0, s,
-                  ManyVols{d_descs, d_tile_prefix, nvol}, tile_base, bpw)
-    return hipGetLastError();
-}
-
-hipError_t launch_generate_one(const VolDesc &d, int64_t ntiles, int32_t bpw, hipStream_t s)
-{
-    if (ntiles <= 0) return hipSuccess;
-    const int32_t dtype = d.dtype, mode = d.cs.mode;
-    SN_KEY_SWITCH(k_generate, OneVol, dim3((uint32_t)ntiles), dim3(kBlock), 0, s, OneVol{d},
-                  (int64_t)0, bpw)
+    SN_KEY_SWITCH(k_generate, dim3((uint32_t)ntiles), dim3(kBlock), 0, s, d_descs, d_tile_prefix,
+                  nvol, tile_base, bpw)
     return hipGetLastError();
 }
 
@@ -1256,8 +1343,8 @@ hipError_t launch_emit(const VolDesc *d_descs, const SmoothDesc *d_sds, const in
                        int32_t nvol, int64_t ntiles, int32_t bpw, hipStream_t s)
 {
     if (ntiles <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_emit<ManyEmit>, dim3((uint32_t)ntiles), dim3(kBlock), 0, s,
-                       ManyEmit{d_descs, d_sds, d_tile_prefix, nvol}, bpw);
+    hipLaunchKernelGGL(k_emit, dim3((uint32_t)ntiles), dim3(kBlock), 0, s, d_descs, d_sds,
+                       d_tile_prefix, nvol, bpw);
     return hipGetLastError();
 }
 
@@ -1265,8 +1352,7 @@ hipError_t launch_emit_one(const VolDesc &d, const SmoothDesc &sd, int64_t ntile
                            hipStream_t s)
 {
     if (ntiles <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_emit<OneEmit>, dim3((uint32_t)ntiles), dim3(kBlock), 0, s, OneEmit{d, sd},
-                       bpw);
+    hipLaunchKernelGGL(k_emit_one, dim3((uint32_t)ntiles), dim3(kBlock), 0, s, OneEmit{d, sd}, bpw);
     return hipGetLastError();
 }
 
@@ -1274,38 +1360,37 @@ hipError_t launch_jacobi(const SmoothDesc *d_sd, const int64_t *d_block_prefix, 
                          int64_t nblocks, int32_t it, hipStream_t s)
 {
     if (nblocks <= 0) return hipSuccess;
-    const ManySmooth a{d_sd, d_block_prefix, nvol};
     if (it == 0)
-        hipLaunchKernelGGL(k_jacobi_first<ManySmooth>, dim3((uint32_t)nblocks), dim3(256), 0, s, a);
+        hipLaunchKernelGGL(k_jacobi_first, dim3((uint32_t)nblocks), dim3(256), 0, s, d_sd,
+                           d_block_prefix, nvol);
     else
-        hipLaunchKernelGGL(k_jacobi<ManySmooth>, dim3((uint32_t)nblocks), dim3(256), 0, s, a, it);
+        hipLaunchKernelGGL(k_jacobi, dim3((uint32_t)nblocks), dim3(256), 0, s, d_sd, d_block_prefix,
+                           nvol, it);
     return hipGetLastError();
 }
 
 hipError_t launch_jacobi_one(const SmoothDesc &sd, int64_t nblocks, int32_t it, hipStream_t s)
 {
     if (nblocks <= 0) return hipSuccess;
-    const OneSmooth a{sd};
     if (it == 0)
-        hipLaunchKernelGGL(k_jacobi_first<OneSmooth>, dim3((uint32_t)nblocks), dim3(256), 0, s, a);
+        hipLaunchKernelGGL(k_jacobi_first_one, dim3((uint32_t)nblocks), dim3(256), 0, s, OneSmooth{sd});
     else
-        hipLaunchKernelGGL(k_jacobi<OneSmooth>, dim3((uint32_t)nblocks), dim3(256), 0, s, a, it);
+        hipLaunchKernelGGL(k_jacobi_one, dim3((uint32_t)nblocks), dim3(256), 0, s, OneSmooth{sd}, it);
     return hipGetLastError();
 }
 
-// Kernel nodes of n sweeps, each depending on the one before.  Arguments are
-// copied into the nodes, so `a` may be a temporary.
-template <class Src>
-static hipError_t add_sweep_nodes(hipGraph_t graph, const Src &a, int64_t nblocks, int32_t iters)
+// Kernel nodes of n sweeps over many meshes, each depending on the one before.
+hipError_t add_jacobi_nodes(hipGraph_t graph, const SmoothDesc *d_sd,
+                            const int64_t *d_block_prefix, int32_t nvol, int64_t nblocks,
+                            int32_t iters)
 {
     hipGraphNode_t prev = nullptr;
-    Src arg = a;
     for (int32_t it = 0; it < iters && nblocks > 0; ++it) {
-        void *args_first[] = {&arg};
-        void *args[] = {&arg, &it};
+        void *args_first[] = {&d_sd, &d_block_prefix, &nvol};
+        void *args[] = {&d_sd, &d_block_prefix, &nvol, &it};
         hipKernelNodeParams kp{};
-        kp.func = it == 0 ? reinterpret_cast<void *>(&k_jacobi_first<Src>)
-                          : reinterpret_cast<void *>(&k_jacobi<Src>);
+        kp.func = it == 0 ? reinterpret_cast<void *>(&k_jacobi_first)
+                          : reinterpret_cast<void *>(&k_jacobi);
         kp.gridDim = dim3((uint32_t)nblocks);
         kp.blockDim = dim3(256);
         kp.sharedMemBytes = 0;
@@ -1320,13 +1405,6 @@ static hipError_t add_sweep_nodes(hipGraph_t graph, const Src &a, int64_t nblock
     return hipSuccess;
 }
 
-hipError_t add_jacobi_nodes(hipGraph_t graph, const SmoothDesc *d_sd,
-                            const int64_t *d_block_prefix, int32_t nvol, int64_t nblocks,
-                            int32_t iters)
-{
-    return add_sweep_nodes(graph, ManySmooth{d_sd, d_block_prefix, nvol}, nblocks, iters);
-}
-
 // Node parameters of sweep `it` of one mesh; `arg` and `itv` must outlive the
 // API call that consumes the parameters.
 static void sweep_params_one(OneSmooth &arg, int32_t &itv, void **args, int64_t nblocks,
@@ -1335,8 +1413,8 @@ static void sweep_params_one(OneSmooth &arg, int32_t &itv, void **args, int64_t 
     args[0] = &arg;
     args[1] = &itv;
     kp = hipKernelNodeParams{};
-    kp.func = itv == 0 ? reinterpret_cast<void *>(&k_jacobi_first<OneSmooth>)
-                       : reinterpret_cast<void *>(&k_jacobi<OneSmooth>);
+    kp.func = itv == 0 ? reinterpret_cast<void *>(&k_jacobi_first_one)
+                       : reinterpret_cast<void *>(&k_jacobi_one);
     kp.gridDim = dim3((uint32_t)nblocks);
     kp.blockDim = dim3(256);
     kp.sharedMemBytes = 0;
@@ -1384,8 +1462,8 @@ hipError_t launch_triangulate(const VolDesc *d_descs, const int64_t *d_block_pre
                               int64_t nblocks, hipStream_t s)
 {
     if (nblocks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_tri<ManyVols>, dim3((uint32_t)nblocks), dim3(256), 0, s,
-                       ManyVols{d_descs, d_block_prefix, nvol});
+    hipLaunchKernelGGL(k_tri, dim3((uint32_t)nblocks), dim3(256), 0, s, d_descs, d_block_prefix,
+                       nvol);
     return hipGetLastError();
 }
 
@@ -1393,7 +1471,7 @@ hipError_t launch_triangulate_one(const VolDesc &d, hipStream_t s)
 {
     const int64_t nblocks = (d.Q + 255) / 256;
     if (nblocks <= 0 || d.prim != 3) return hipSuccess;
-    hipLaunchKernelGGL(k_tri<OneVol>, dim3((uint32_t)nblocks), dim3(256), 0, s, OneVol{d});
+    hipLaunchKernelGGL(k_tri_one, dim3((uint32_t)nblocks), dim3(256), 0, s, OneVol{d});
     return hipGetLastError();
 }
 

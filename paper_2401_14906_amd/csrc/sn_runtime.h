@@ -152,6 +152,8 @@ sn_status extract_many(sn_ctx *c, const sn_volume *vols, int32_t n, hipStream_t 
                        int32_t bpw_override, sn_mesh **out);
 sn_status smooth_many(sn_ctx *c, sn_mesh **ms, const sn_smooth_params *pv, int32_t n,
                       hipStream_t s);
+// the plain path of one mesh (cached sweep graph, descriptors by value)
+sn_status smooth_one(sn_ctx *c, sn_mesh *m, const sn_smooth_params *p, hipStream_t s);
 sn_status ensure_smooth_buffers(sn_mesh *m);
 sn_status run_sweeps(sn_ctx *c, const SmoothDesc *d_sd, const int64_t *d_bp, int32_t nvol,
                      int64_t nblocks, int32_t iters, hipStream_t s);

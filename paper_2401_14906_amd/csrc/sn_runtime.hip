@@ -858,9 +858,21 @@ sn_status sn::extract_many(sn_ctx *c, const sn_volume *vols, int32_t n, hipStrea
         hd[k] = d;
     }
     if (one) {
+        // k_generate reads its descriptor from device memory even for one
+        // volume: as a kernel argument it would be held in scalar registers,
+        // which this kernel needs for its word masks
+        uint8_t *h_b = static_cast<uint8_t *>(scr.h(sizeof(VolDesc) + 2 * sizeof(int64_t)));
+        uint8_t *d_b = static_cast<uint8_t *>(scr.d(sizeof(VolDesc) + 2 * sizeof(int64_t)));
+        if (!h_b || !d_b) return cleanup(fail(SN_ENOMEM, "extract: descriptor staging"));
+        std::memcpy(h_b, &hd[0], sizeof(VolDesc));
+        const int64_t tp1[2] = {0, tile_prefix[1]};
+        std::memcpy(h_b + sizeof(VolDesc), tp1, sizeof tp1);
+        HIP_TRY(hipMemcpyAsync(d_b, h_b, sizeof(VolDesc) + sizeof tp1, hipMemcpyHostToDevice, s));
         {
             ProfScope ps(c, "k_generate", s);
-            HIP_TRY(launch_generate_one(hd[0], tile_prefix[1], bpw, s));
+            HIP_TRY(launch_generate(hd[0].dtype, hd[0].cs.mode, reinterpret_cast<VolDesc *>(d_b),
+                                    reinterpret_cast<int64_t *>(d_b + sizeof(VolDesc)), 1, 0,
+                                    tile_prefix[1], bpw, s));
         }
         if (qblocks > 0) {
             ProfScope ps(c, "k_tri", s);
@@ -1041,9 +1053,13 @@ sn_status sn::run_sweeps_one(sn_ctx *c, const SmoothDesc &sd, int64_t nblocks, h
 extern "C" sn_status sn_smooth(sn_ctx *c, sn_mesh *m, const sn_smooth_params *p, void *stream)
 {
     if (!c || !m) return fail(SN_EINVAL, "sn_smooth: NULL argument");
+    return smooth_one(c, m, p, static_cast<hipStream_t>(stream));
+}
+
+sn_status sn::smooth_one(sn_ctx *c, sn_mesh *m, const sn_smooth_params *p, hipStream_t s)
+{
     sn_status st = validate_smooth(p);
     if (st != SN_OK) return st;
-    hipStream_t s = static_cast<hipStream_t>(stream);
     HIP_TRY(hipSetDevice(c->device));
     if (m->P == 0) {
         m->final_delta = nullptr;

@@ -18,6 +18,8 @@
 #include <deque>
 #include <mutex>
 #include <thread>
+
+#include <atomic>
 #include <unordered_map>
 #include <vector>
 
@@ -52,6 +54,21 @@ int64_t footprint_of(const sn_volume &v, double out_bytes_per_voxel)
     return meta + (int64_t)(out_bytes_per_voxel * vox);
 }
 
+// Worker threads spin this long for new work before sleeping, and poll their
+// stream for this long before blocking on it.
+constexpr int64_t kSpinUs = 200;
+
+hipError_t wait_stream(hipStream_t s)
+{
+    const auto until = Clock::now() + std::chrono::microseconds(kSpinUs);
+    while (Clock::now() < until) {
+        const hipError_t e = hipStreamQuery(s);
+        if (e != hipErrorNotReady) return e;
+        std::this_thread::yield();
+    }
+    return hipStreamSynchronize(s);
+}
+
 }  // namespace
 
 struct sn_server {
@@ -76,6 +93,7 @@ struct sn_server {
     double busy_s = 0.0;
     int32_t busy_count = 0;
 
+    std::atomic<int64_t> queued{0};  // queue length, read without the lock by spinning workers
     void worker(int w);
     // extract + smooth n requests as one fused batch on stream s and wait for
     // it; on failure every ms[k] is null
@@ -89,8 +107,9 @@ sn_status sn_server::run_fused(const sn_volume *vols, const sn_smooth_params *ps
     std::fill(ms, ms + n, nullptr);
     sn_status st = extract_many(ctx, vols, n, s, 0, ms);
     if (st == SN_OK) {
-        st = smooth_many(ctx, ms, ps, n, s);
-        if (st == SN_OK && hipStreamSynchronize(s) != hipSuccess) st = SN_EDEVICE;
+        // a batch of one takes the plain path (its sweep graph is cached)
+        st = n == 1 ? smooth_one(ctx, ms[0], ps, s) : smooth_many(ctx, ms, ps, n, s);
+        if (st == SN_OK && wait_stream(s) != hipSuccess) st = SN_EDEVICE;
         if (st != SN_OK) {
             for (int32_t k = 0; k < n; ++k) mesh_release(ms[k]);
             std::fill(ms, ms + n, nullptr);
@@ -105,6 +124,11 @@ void sn_server::worker(int w)
     hipStream_t s = streams[w];
     while (true) {
         std::vector<Request *> batch;
+        // a request arriving shortly after the last one is picked up without
+        // a sleep/wake round trip
+        const auto spin_until = Clock::now() + std::chrono::microseconds(kSpinUs);
+        while (queued.load(std::memory_order_acquire) == 0 && Clock::now() < spin_until)
+            std::this_thread::yield();
         {
             std::unique_lock<std::mutex> lk(mu);
             cv_work.wait(lk, [&] {
@@ -121,6 +145,7 @@ void sn_server::worker(int w)
                 const bool fits = reserved + h->footprint <= cfg.hbm_budget_bytes;
                 if (!fits && !(batch.empty() && inflight == 0)) break;
                 queue.pop_front();
+                queued.fetch_sub(1, std::memory_order_release);
                 reserved += h->footprint;
                 ++inflight;
                 batch.push_back(h);
@@ -235,6 +260,7 @@ extern "C" sn_status sn_serve_submit(sn_server *srv, const sn_volume *vol, const
         r->ticket = srv->next_ticket++;
         srv->reqs[r->ticket] = r;
         srv->queue.push_back(r);
+        srv->queued.fetch_add(1, std::memory_order_release);
         ++srv->n_submitted;
         *ticket = r->ticket;
     }
@@ -329,6 +355,7 @@ extern "C" sn_status sn_serve_stop(sn_server *srv)
         while (!srv->queue.empty()) {
             Request *r = srv->queue.front();
             srv->queue.pop_front();
+            srv->queued.fetch_sub(1, std::memory_order_release);
             r->done = true;
             r->status = SN_ESHUTDOWN;
             ++srv->n_rejected;
