@@ -119,8 +119,10 @@ typedef struct sn_mesh_view {
 /* ---- context -------------------------------------------------------------- */
 
 /* Bind a context to HIP device `device`.  Reads SN_AUTOTUNE_CACHE (a JSON file
- * of schedule choices) and SN_TEST_MEM_LIMIT (a byte cap on the library's
- * device pool, used by tests to force SN_ENOMEM) from the environment. */
+ * of schedule choices) from the environment, and two test knobs:
+ * SN_TEST_MEM_LIMIT (a byte cap on the library's device pool, to force
+ * SN_ENOMEM) and SN_TEST_COUNT_WIDE_WORDS (the number of cell words from which
+ * an extraction counts four words per thread; results do not depend on it). */
 sn_status sn_ctx_create(int device, sn_ctx **out);
 /* Release the caller's handle.  Meshes and servers made by the context hold
  * it alive: its device memory and streams go when the last of them is freed

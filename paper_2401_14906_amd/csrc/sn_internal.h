@@ -36,6 +36,13 @@ constexpr int kWavesPerBlock = 4;
 constexpr int kBlock = 64 * kWavesPerBlock;
 constexpr int kMaxBatchesPerWave = 16;
 constexpr int kSegmentsPerTile = 16;  // k_edges: 4 waves x 4 segments of 256 samples
+// k_count: 1024 threads per workgroup, one or kCountWideV words per thread
+// (the wide form for launches of at least kCountWideWords words: fewer scan
+// tiles, and fewer of the ordered tile tickets every workgroup takes)
+constexpr int kCountWaves = 16;
+constexpr int kCountBlock = 64 * kCountWaves;
+constexpr int kCountWideV = 4;
+constexpr int64_t kCountWideWords = int64_t(1) << 22;
 
 // Sample lattice M x N x O; cell grid CM x CN x CO = (M-1)(N-1)(O-1).
 // Cut-edge planes (k_edges) hold one bit per sample, WS words per sample row,
@@ -67,6 +74,7 @@ struct VolDesc {
     // outputs
     float *points;     // [P*3]
     uint8_t *faces;    // [P] stencil face mask, bit f = face f (-x,+x,-y,+y,-z,+z)
+    uint32_t *pcell;   // [P] cell linear index of each point, or nullptr (>= 2^32 cells)
     int32_t *st_off;   // [P+1]
     int32_t *st_ids;   // [S]
     int32_t *quads;    // [Q*4]
@@ -76,6 +84,24 @@ struct VolDesc {
     double origin[3], spacing[3];
     int64_t P, Q, S;
 };
+
+// Division of 32-bit values by an invariant divisor d >= 1 (Granlund and
+// Montgomery's method): with t = umulhi(n, m), n / d = (t + ((n - t) >> s1)) >> s2.
+struct UDiv {
+    uint32_t d, m, s1, s2;
+};
+
+inline UDiv make_udiv(uint32_t d)
+{
+    uint32_t l = 0;
+    while (l < 32 && (uint64_t(1) << l) < d) ++l;  // l = ceil(log2 d)
+    UDiv u;
+    u.d = d;
+    u.m = (uint32_t)(((uint64_t(1) << 32) * ((uint64_t(1) << l) - d)) / d + 1);
+    u.s1 = l < 1 ? l : 1;
+    u.s2 = l > 1 ? l - 1 : 0;
+    return u;
+}
 
 // One mesh's smoothing job.  Sweep 0 reads the CSR stencil (off, ids) and
 // writes nbr: per point the ids of its -y, +y, -z, +z stencil neighbours
@@ -92,6 +118,12 @@ struct SmoothDesc {
     int32_t iters;
     double lam;
     double dist;
+    // the last sweep also writes world points when pcell is set:
+    // origin + spacing * (cell centre + offset)
+    const uint32_t *pcell;
+    float *points;
+    UDiv CM, CN;  // cells per row, rows per slice
+    double origin[3], spacing[3];
 };
 
 // A smoothing block covers kSweepPoints consecutive points: each wave holds
@@ -111,7 +143,7 @@ constexpr uint64_t kValMask = (1ull << 62) - 1;
 //   k_edges   : a tile is 4*4 segments of 256 samples; every volume of a launch has
 //               the given label type (bytes), classification mode and `wide`
 //               (rows 16-byte aligned and M % 4 == 0: one wide load per lane).
-//   k_count   : a tile is 256 cell words.
+//   k_count   : a tile is kCountBlock or kCountWideV * kCountBlock cell words.
 //   k_generate: a tile is 4*bpw batches; label type and mode as for k_edges.
 //               The launch also zeroes d_zero[0 .. nzero) (the count pass's scan
 //               status), so the extraction needs no separate memset.
@@ -119,8 +151,8 @@ hipError_t launch_edges(int32_t dtype, int32_t mode, bool wide, const VolDesc *d
                         const int64_t *d_tile_prefix, int32_t nvol, int64_t tile_base,
                         int64_t ntiles, uint64_t *d_zero, int64_t nzero, hipStream_t s);
 hipError_t launch_count(const VolDesc *d_descs, const int64_t *d_tile_prefix, int32_t nvol,
-                        int64_t ntiles, uint64_t *d_status, uint32_t *d_ticket, int64_t *d_totals,
-                        hipStream_t s);
+                        int64_t ntiles, int32_t words_per_thread, uint64_t *d_status,
+                        uint32_t *d_ticket, int64_t *d_totals, hipStream_t s);
 hipError_t launch_generate(int32_t dtype, int32_t mode, const VolDesc *d_descs,
                            const int64_t *d_tile_prefix, int32_t nvol, int64_t tile_base,
                            int64_t ntiles, int32_t bpw, hipStream_t s);
@@ -139,8 +171,8 @@ hipError_t add_jacobi_nodes(hipGraph_t graph, const SmoothDesc *d_sd,
 // arguments (no upload, no prefix array; tiles and blocks start at 0).
 hipError_t launch_edges_one(const VolDesc &d, bool wide, int64_t ntiles, uint64_t *d_zero,
                             int64_t nzero, hipStream_t s);
-hipError_t launch_count_one(const VolDesc &d, int64_t ntiles, uint64_t *d_status, uint32_t *d_ticket,
-                            int64_t *d_totals, hipStream_t s);
+hipError_t launch_count_one(const VolDesc &d, int64_t ntiles, int32_t words_per_thread,
+                            uint64_t *d_status, uint32_t *d_ticket, int64_t *d_totals, hipStream_t s);
 hipError_t launch_emit_one(const VolDesc &d, const SmoothDesc &sd, int64_t ntiles, int32_t bpw,
                            hipStream_t s);
 hipError_t launch_jacobi_one(const SmoothDesc &sd, int64_t nblocks, int32_t it, hipStream_t s);

@@ -274,12 +274,12 @@ __device__ __forceinline__ int64_t wave_sum(int64_t x)
     return x;
 }
 
-__device__ __forceinline__ int64_t wave_excl_scan(int64_t x, int lane)
+__device__ __forceinline__ int32_t wave_excl_scan32(int32_t x, int lane)
 {
-    int64_t inc = x;
+    int32_t inc = x;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
-        const int64_t y = __shfl_up(inc, (unsigned)o);
+        const int32_t y = __shfl_up(inc, (unsigned)o);
         if (lane >= o) inc += y;
     }
     return inc - x;
@@ -440,12 +440,15 @@ __global__ __launch_bounds__(kBlock) void k_edges_narrow_one(OneVol a, uint64_t 
 // index and stencil index (Sec. 2.3 passes 1-3 and the prefix sum).
 // ---------------------------------------------------------------------------
 
-// Exclusive prefixes of tile t for the three counts, by one whole wave: lane L
-// inspects tile top-L of each count's window.  Tiles before `first` (the
+// Exclusive prefixes of tile t for the three counts, by one whole wave.  Each
+// round inspects a window of 64 * kLookV tiles below `top`: window position
+// q = L + 64 v (lane L, slot v) is tile top - q.  Tiles before `first` (the
 // volume's first tile) read as an inclusive prefix of zero.  A count waits
-// only while a tile at or after its nearest inclusive prefix has not yet
-// published an aggregate; the nearest such tile was handed out before t, so
-// its workgroup is running and publishes without waiting on anything.
+// only while a tile closer than its nearest inclusive prefix has not yet
+// published an aggregate; such a tile was handed out before t, so its
+// workgroup is running and publishes without waiting on anything.
+constexpr int kLookV = 1;
+
 __device__ void look_back3(const uint64_t *status, int64_t t, int64_t first, int lane,
                            int64_t excl[3])
 {
@@ -453,33 +456,50 @@ __device__ void look_back3(const uint64_t *status, int64_t t, int64_t first, int
     bool done[3] = {false, false, false};
     excl[0] = excl[1] = excl[2] = 0;
     while (!(done[0] && done[1] && done[2])) {
-        uint64_t s[3];
+        uint64_t s[3][kLookV];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            const int64_t p = top[c] - lane;
-            s[c] = kFlagPrefix;
-            if (!done[c] && p >= first)
-                s[c] = __hip_atomic_load(status + 3 * p + c, __ATOMIC_RELAXED,
-                                         __HIP_MEMORY_SCOPE_AGENT);
-        }
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int v = 0; v < kLookV; ++v) {
+                const int64_t p = top[c] - lane - 64 * v;
+                s[c][v] = kFlagPrefix;
+                if (!done[c] && p >= first)
+                    s[c][v] = __hip_atomic_load(status + 3 * p + c, __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_AGENT);
+            }
         bool stalled = false;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             if (done[c]) continue;
-            const uint64_t flag = s[c] & ~kValMask;
-            const uint64_t pm = __ballot(flag == kFlagPrefix);
-            const uint64_t zm = __ballot(flag == 0);
-            const int lp = pm ? __builtin_ctzll(pm) : 64;
-            const uint64_t upto = lp >= 63 ? ~0ull : ((2ull << lp) - 1);
-            if (zm & upto) {
+            // nearest inclusive prefix in the window (qp = 64 * kLookV: none)
+            int qp = 64 * kLookV;
+            bool waiting = false;
+#pragma unroll
+            for (int v = 0; v < kLookV; ++v) {
+                const uint64_t flag = s[c][v] & ~kValMask;
+                const uint64_t pm = __ballot(flag == kFlagPrefix);
+                const uint64_t zm = __ballot(flag == 0);
+                if (qp == 64 * kLookV) {
+                    // slot v is reached: positions 64v .. up to its first prefix
+                    const int lp = pm ? __builtin_ctzll(pm) : 64;
+                    const uint64_t upto = lp >= 63 ? ~0ull : ((2ull << lp) - 1);
+                    if (zm & upto) waiting = true;
+                    if (pm) qp = 64 * v + lp;
+                }
+            }
+            if (waiting) {
                 stalled = true;
                 continue;
             }
-            excl[c] += wave_sum(lane <= lp ? (int64_t)(s[c] & kValMask) : 0);
-            if (pm)
+            int64_t part = 0;
+#pragma unroll
+            for (int v = 0; v < kLookV; ++v)
+                if (64 * v + lane <= qp) part += (int64_t)(s[c][v] & kValMask);
+            excl[c] += wave_sum(part);
+            if (qp < 64 * kLookV)
                 done[c] = true;
             else
-                top[c] -= 64;
+                top[c] -= 64 * kLookV;
         }
         if (stalled) __builtin_amdgcn_s_sleep(1);
     }
@@ -495,43 +515,49 @@ __device__ __forceinline__ int64_t last_tile(const OneVol &, int)
     return (int64_t)gridDim.x - 1;
 }
 
-template <class Src>
+template <int V, class Src>
 __device__ __forceinline__ void count_body(const Src &a, uint64_t *status, uint32_t *ticket,
                                            int64_t *totals)
 {
+    // a tile is V * kCountBlock words; word (v, thread) of the tile is
+    // v * kCountBlock + thread, so each v is one coalesced pass
     __shared__ int64_t s_tile;
-    __shared__ int64_t s_wtot[3][kWavesPerBlock];
+    __shared__ int32_t s_wtot[V][3][kCountWaves];
     __shared__ int64_t s_excl[3];
     if (threadIdx.x == 0) s_tile = (int64_t)atomicAdd(ticket, 1u);
     __syncthreads();
     const int64_t t = s_tile;  // tiles are handed out in order: predecessors are running
-    int v;
+    int vol;
     int64_t first;
-    const VolDesc &d = vol_of(a, t, v, first);
+    const VolDesc &d = vol_of(a, t, vol, first);
     const Geom &g = d.g;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int64_t words = g.R * g.W;
-    const int64_t gw = (t - first) * kBlock + threadIdx.x;
-    int64_t cnt[3] = {0, 0, 0};
-    if (gw < words) {
-        const uint32_t r = (uint32_t)gw / (uint32_t)g.W;
-        const int32_t w = (int32_t)((uint32_t)gw - r * (uint32_t)g.W);
-        const int32_t j = (int32_t)(r % (uint32_t)g.CN), k = (int32_t)(r / (uint32_t)g.CN);
-        const int64_t ps = g.N * g.O * g.WS;
-        const PlaneWords p = plane_words(glb(d.planes), ps, g.WS, j + g.N * (int64_t)k, g.N, w);
-        const WordMasks m = word_masks(p, w, j, k, g);
-        glb(d.pmask)[gw] = m.pt;
-        cnt[0] = __popcll(m.pt);
-        cnt[1] = __popcll(m.qx) + __popcll(m.qy) + __popcll(m.qz);
-        cnt[2] = __popcll(m.f[0]) + __popcll(m.f[1]) + __popcll(m.f[2]) + __popcll(m.f[3]) +
-                 __popcll(m.f[4]) + __popcll(m.f[5]);
-    }
-    // block-wide exclusive scan of the three counts
-    int64_t ex[3];
+    const int64_t gw0 = (t - first) * (int64_t)(V * kCountBlock) + threadIdx.x;
+    int32_t ex[V][3];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        ex[c] = wave_excl_scan(cnt[c], lane);
-        if (lane == 63) s_wtot[c][wave] = ex[c] + cnt[c];
+    for (int v = 0; v < V; ++v) {
+        const int64_t gw = gw0 + v * kCountBlock;
+        int32_t cnt[3] = {0, 0, 0};
+        if (gw < words) {
+            const uint32_t r = (uint32_t)gw / (uint32_t)g.W;
+            const int32_t w = (int32_t)((uint32_t)gw - r * (uint32_t)g.W);
+            const int32_t j = (int32_t)(r % (uint32_t)g.CN), k = (int32_t)(r / (uint32_t)g.CN);
+            const int64_t ps = g.N * g.O * g.WS;
+            const PlaneWords p = plane_words(glb(d.planes), ps, g.WS, j + g.N * (int64_t)k, g.N, w);
+            const WordMasks m = word_masks(p, w, j, k, g);
+            glb(d.pmask)[gw] = m.pt;
+            cnt[0] = __popcll(m.pt);
+            cnt[1] = __popcll(m.qx) + __popcll(m.qy) + __popcll(m.qz);
+            cnt[2] = __popcll(m.f[0]) + __popcll(m.f[1]) + __popcll(m.f[2]) + __popcll(m.f[3]) +
+                     __popcll(m.f[4]) + __popcll(m.f[5]);
+        }
+        // wave-level exclusive scan of the three counts (a tile's counts fit 32 bits)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            ex[v][c] = wave_excl_scan32(cnt[c], lane);
+            if (lane == 63) s_wtot[v][c][wave] = ex[v][c] + cnt[c];
+        }
     }
     __syncthreads();
     if (wave == 0) {
@@ -540,7 +566,9 @@ __device__ __forceinline__ void count_body(const Src &a, uint64_t *status, uint3
         for (int c = 0; c < 3; ++c) {
             agg[c] = 0;
 #pragma unroll
-            for (int q = 0; q < kWavesPerBlock; ++q) agg[c] += s_wtot[c][q];
+            for (int v = 0; v < V; ++v)
+#pragma unroll
+                for (int q = 0; q < kCountWaves; ++q) agg[c] += s_wtot[v][c][q];
             if (lane == 0)
                 __hip_atomic_store(status + 3 * t + c,
                                    (t == first ? kFlagPrefix : kFlagAgg) | (uint64_t)agg[c],
@@ -559,35 +587,45 @@ __device__ __forceinline__ void count_body(const Src &a, uint64_t *status, uint3
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 s_excl[c] = excl[c];
-                if (t == last_tile(a, v)) totals[3 * v + c] = excl[c] + agg[c];
+                if (t == last_tile(a, vol)) totals[3 * vol + c] = excl[c] + agg[c];
             }
         }
     }
     __syncthreads();
-    if (gw < words) {
-        int64_t before[3] = {0, 0, 0};
+    int32_t before[3] = {0, 0, 0};  // counts of the tile's words before (v, this wave)
 #pragma unroll
-        for (int q = 0; q < kWavesPerBlock; ++q)
-            if (q < wave)
+    for (int v = 0; v < V; ++v) {
+        int32_t b[3] = {before[0], before[1], before[2]};
 #pragma unroll
-                for (int c = 0; c < 3; ++c) before[c] += s_wtot[c][q];
-        glb(d.wbP)[gw] = (int32_t)(s_excl[0] + before[0] + ex[0]);
-        glb(d.wbQ)[gw] = (int32_t)(s_excl[1] + before[1] + ex[1]);
-        glb(d.wbS)[gw] = (int32_t)(s_excl[2] + before[2] + ex[2]);
+        for (int q = 0; q < kCountWaves; ++q)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                if (q < wave) b[c] += s_wtot[v][c][q];
+                before[c] += s_wtot[v][c][q];
+            }
+        const int64_t gw = gw0 + v * kCountBlock;
+        if (gw < words) {
+            glb(d.wbP)[gw] = (int32_t)(s_excl[0] + b[0] + ex[v][0]);
+            glb(d.wbQ)[gw] = (int32_t)(s_excl[1] + b[1] + ex[v][1]);
+            glb(d.wbS)[gw] = (int32_t)(s_excl[2] + b[2] + ex[v][2]);
+        }
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_count(const VolDesc *__restrict__ descs,
-                                                  const int64_t *__restrict__ prefix, int32_t nvol,
-                                                  uint64_t *status, uint32_t *ticket, int64_t *totals)
+template <int V>
+__global__ __launch_bounds__(kCountBlock) void k_count(const VolDesc *__restrict__ descs,
+                                                       const int64_t *__restrict__ prefix,
+                                                       int32_t nvol, uint64_t *status,
+                                                       uint32_t *ticket, int64_t *totals)
 {
-    count_body(ManyVols{descs, prefix, nvol}, status, ticket, totals);
+    count_body<V>(ManyVols{descs, prefix, nvol}, status, ticket, totals);
 }
 
-__global__ __launch_bounds__(kBlock) void k_count_one(OneVol a, uint64_t *status, uint32_t *ticket,
-                                                      int64_t *totals)
+template <int V>
+__global__ __launch_bounds__(kCountBlock) void k_count_one(OneVol a, uint64_t *status,
+                                                           uint32_t *ticket, int64_t *totals)
 {
-    count_body(a, status, ticket, totals);
+    count_body<V>(a, status, ticket, totals);
 }
 
 // ---------------------------------------------------------------------------
@@ -614,6 +652,7 @@ struct Stage {
     v4i quads[192];
     uint64_t pairs[192];  // Pair<T>::type values (the first 2*sizeof(T) bytes of each slot)
     uint8_t faces[64];
+    uint32_t cell[64];
 };
 
 // Word data of one batch in lanes.  Lane l < 48: plane word p = l >> 2 of word
@@ -743,6 +782,7 @@ __device__ __forceinline__ void generate_word(const VolDesc &d, const BatchPos &
         st.pts[3 * r0 + 1] = (float)(d.origin[1] + d.spacing[1] * ((double)bp.j + 0.5));
         st.pts[3 * r0 + 2] = (float)(d.origin[2] + d.spacing[2] * ((double)bp.k + 0.5));
         st.faces[r0] = (uint8_t)fm;
+        st.cell[r0] = (uint32_t)i + (uint32_t)d.g.CM * (uint32_t)bp.r;
         st.off[r0] = bs + sp;
         int32_t e = sp;
         if (fm & 1u) st.ids[e++] = R0 - 1;
@@ -796,6 +836,7 @@ __device__ __forceinline__ void generate_word(const VolDesc &d, const BatchPos &
         SN_GLOBAL int32_t *go = glb(d.st_off) + b0;
         SN_GLOBAL uint8_t *gf = glb(d.faces) + b0;
         if (lane < np) go[lane] = st.off[lane], gf[lane] = st.faces[lane];
+        if (d.pcell && lane < np) glb(d.pcell)[b0 + lane] = st.cell[lane];
         SN_GLOBAL int32_t *gi = glb(d.st_ids) + bs;
         for (int32_t e = lane; e < ns; e += 64) gi[e] = st.ids[e];
     }
@@ -950,6 +991,7 @@ __device__ __forceinline__ void emit_body(const Src &a, int32_t bpw)
     const VolDesc &d = emit_of(a, t, sdp, first);
     // the last of n sweeps wrote buffer ((n - 1) odd ? da : db); no sweep: centres
     const SmoothDesc &sd = *sdp;
+    if (sd.iters > 0 && sd.pcell) return;  // the last sweep wrote the world points
     const float *delta = sd.iters <= 0 ? nullptr : (((sd.iters - 1) & 1) ? sd.da : sd.db);
     const int64_t nbv = d.g.R * d.g.NB;
     const int64_t bt0 = (t - first) * (kWavesPerBlock * bpw);
@@ -1014,15 +1056,33 @@ __device__ __forceinline__ double face_term(int face, int axis, double n, double
     return (face >> 1) == axis ? step + n - own : n - own;
 }
 
-__device__ __forceinline__ void store_offset(SN_GLOBAL float *dout, int64_t p, double x, double y,
-                                             double z, double c)
+__device__ __forceinline__ uint32_t udiv(uint32_t n, const UDiv &u)
 {
-    x = fmin(fmax(x, -c), c);
-    y = fmin(fmax(y, -c), c);
-    z = fmin(fmax(z, -c), c);
-    dout[3 * p] = (float)x;
-    dout[3 * p + 1] = (float)y;
-    dout[3 * p + 2] = (float)z;
+    const uint32_t t = __umulhi(n, u.m);
+    return (t + ((n - t) >> u.s1)) >> u.s2;
+}
+
+// Clamp to the box, store the offset, and in the mesh's last sweep also the
+// world point origin + spacing * (cell centre + stored offset), from the
+// point's cell index (the world-coordinate output, fused into the sweep).
+__device__ __forceinline__ void store_offset(const SmoothDesc &s, SN_GLOBAL float *dout, int64_t p,
+                                             double x, double y, double z, bool last, uint32_t cell)
+{
+    const double c = s.dist;
+    const float fx = (float)fmin(fmax(x, -c), c);
+    const float fy = (float)fmin(fmax(y, -c), c);
+    const float fz = (float)fmin(fmax(z, -c), c);
+    dout[3 * p] = fx;
+    dout[3 * p + 1] = fy;
+    dout[3 * p + 2] = fz;
+    if (last) {
+        const uint32_t r = udiv(cell, s.CM), i = cell - r * s.CM.d;
+        const uint32_t k = udiv(r, s.CN), j = r - k * s.CN.d;
+        SN_GLOBAL float *o = glb(s.points) + 3 * p;
+        o[0] = (float)(s.origin[0] + s.spacing[0] * ((double)i + 0.5 + (double)fx));
+        o[1] = (float)(s.origin[1] + s.spacing[1] * ((double)j + 0.5 + (double)fy));
+        o[2] = (float)(s.origin[2] + s.spacing[2] * ((double)k + 0.5 + (double)fz));
+    }
 }
 
 // Sweep 0: every input offset is zero, so p_q - p_p is the face step alone.
@@ -1075,7 +1135,8 @@ __device__ __forceinline__ void jacobi_first_body(const Src &a)
             y = y + s.lam * (sy * inv);
             z = z + s.lam * (sz * inv);
         }
-        store_offset(dout, p, x, y, z, s.dist);
+        const bool last = s.iters == 1 && s.pcell;
+        store_offset(s, dout, p, x, y, z, last, last ? glb(s.pcell)[p] : 0u);
     }
 }
 
@@ -1129,17 +1190,20 @@ __device__ __forceinline__ void jacobi_body(const Src &a, int32_t it)
     SN_GLOBAL float *dout = glb((it & 1) ? s.da : s.db);
     const SN_GLOBAL v4i *nbr = glb(reinterpret_cast<const v4i *>(s.nbr));
 
-    uint32_t f[K];
+    // the mesh's last sweep also writes world points from the cell indices
+    const bool last = it == s.iters - 1 && s.pcell;
+    uint32_t f[K], cell[K];
     v4i nb[K];
     float ox[K], oy[K], oz[K];
 #pragma unroll
     for (int c = 0; c < K; ++c) {
         const int64_t p = p0 + 64 * c + lane;
-        f[c] = 0, nb[c] = v4i{-1, -1, -1, -1}, ox[c] = oy[c] = oz[c] = 0.f;
+        f[c] = 0, cell[c] = 0, nb[c] = v4i{-1, -1, -1, -1}, ox[c] = oy[c] = oz[c] = 0.f;
         if (p < P) {
             f[c] = glb(s.faces)[p];
             nb[c] = nbr[p];
             ox[c] = din[3 * p], oy[c] = din[3 * p + 1], oz[c] = din[3 * p + 2];
+            if (last) cell[c] = glb(s.pcell)[p];
         }
     }
     // wave halo: -x of the first point, +x of the last one (p0 + 64K - 1)
@@ -1206,7 +1270,7 @@ __device__ __forceinline__ void jacobi_body(const Src &a, int32_t it)
             y = y + s.lam * (sy * inv);
             z = z + s.lam * (sz * inv);
         }
-        store_offset(dout, p, x, y, z, s.dist);
+        store_offset(s, dout, p, x, y, z, last, cell[c]);
     }
 }
 
@@ -1311,21 +1375,29 @@ hipError_t launch_edges_one(const VolDesc &d, bool wide, int64_t ntiles, uint64_
 }
 
 hipError_t launch_count(const VolDesc *d_descs, const int64_t *d_tile_prefix, int32_t nvol,
-                        int64_t ntiles, uint64_t *d_status, uint32_t *d_ticket, int64_t *d_totals,
-                        hipStream_t s)
+                        int64_t ntiles, int32_t words_per_thread, uint64_t *d_status,
+                        uint32_t *d_ticket, int64_t *d_totals, hipStream_t s)
 {
     if (ntiles <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_count, dim3((uint32_t)ntiles), dim3(kBlock), 0, s, d_descs, d_tile_prefix,
-                       nvol, d_status, d_ticket, d_totals);
+    if (words_per_thread == kCountWideV)
+        hipLaunchKernelGGL(k_count<kCountWideV>, dim3((uint32_t)ntiles), dim3(kCountBlock), 0, s,
+                           d_descs, d_tile_prefix, nvol, d_status, d_ticket, d_totals);
+    else
+        hipLaunchKernelGGL(k_count<1>, dim3((uint32_t)ntiles), dim3(kCountBlock), 0, s, d_descs,
+                           d_tile_prefix, nvol, d_status, d_ticket, d_totals);
     return hipGetLastError();
 }
 
-hipError_t launch_count_one(const VolDesc &d, int64_t ntiles, uint64_t *d_status, uint32_t *d_ticket,
-                            int64_t *d_totals, hipStream_t s)
+hipError_t launch_count_one(const VolDesc &d, int64_t ntiles, int32_t words_per_thread,
+                            uint64_t *d_status, uint32_t *d_ticket, int64_t *d_totals, hipStream_t s)
 {
     if (ntiles <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_count_one, dim3((uint32_t)ntiles), dim3(kBlock), 0, s, OneVol{d}, d_status,
-                       d_ticket, d_totals);
+    if (words_per_thread == kCountWideV)
+        hipLaunchKernelGGL(k_count_one<kCountWideV>, dim3((uint32_t)ntiles), dim3(kCountBlock), 0, s,
+                           OneVol{d}, d_status, d_ticket, d_totals);
+    else
+        hipLaunchKernelGGL(k_count_one<1>, dim3((uint32_t)ntiles), dim3(kCountBlock), 0, s, OneVol{d},
+                           d_status, d_ticket, d_totals);
     return hipGetLastError();
 }
 

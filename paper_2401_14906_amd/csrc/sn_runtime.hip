@@ -252,6 +252,8 @@ extern "C" sn_status sn_ctx_create(int device, sn_ctx **out)
         delete c;
         return fail(SN_EDEVICE, "sn_ctx_create: stream creation failed");
     }
+    if (const char *cw = std::getenv("SN_TEST_COUNT_WIDE_WORDS"); cw && *cw)
+        c->count_wide_words = std::strtoll(cw, nullptr, 10);
     const char *cache = std::getenv("SN_AUTOTUNE_CACHE");
     if (cache && *cache) {
         c->tune_path = cache;
@@ -767,10 +769,16 @@ sn_status sn::extract_many(sn_ctx *c, const sn_volume *vols, int32_t n, hipStrea
         tile_prefix[k + 1] = tile_prefix[k] + m->ntiles;
         const int64_t nseg = d.g.N * d.g.O * d.g.NSEG;
         etile_prefix[k + 1] = etile_prefix[k] + (nseg + kSegmentsPerTile - 1) / kSegmentsPerTile;
-        ctile_prefix[k + 1] = ctile_prefix[k] + (words + kBlock - 1) / kBlock;
+        ctile_prefix[k + 1] = words;  // words for now; tiles below
         m->voxels = vol.dims[0] * vol.dims[1] * vol.dims[2];
         hd[k] = d;
     }
+    // count tiles: the wide form for launches of many words
+    int64_t total_words = 0;
+    for (int32_t k = 0; k < n; ++k) total_words += ctile_prefix[k + 1];
+    const int32_t cv = total_words >= c->count_wide_words ? kCountWideV : 1;
+    for (int32_t k = 0; k < n; ++k)
+        ctile_prefix[k + 1] = ctile_prefix[k] + (ctile_prefix[k + 1] + cv * kCountBlock - 1) / (cv * kCountBlock);
     // groups: [gbeg[i], gbeg[i+1]) of the launch order share a key
     std::vector<int32_t> gbeg;
     for (int32_t k = 0; k < n; ++k)
@@ -816,9 +824,9 @@ sn_status sn::extract_many(sn_ctx *c, const sn_volume *vols, int32_t n, hipStrea
     {
         ProfScope ps(c, "k_count", s);
         if (one)
-            HIP_TRY(launch_count_one(hd[0], nctiles, status, ticket, d_tot, s));
+            HIP_TRY(launch_count_one(hd[0], nctiles, cv, status, ticket, d_tot, s));
         else
-            HIP_TRY(launch_count(d_desc, d_tp + 2 * (n + 1), n, nctiles, status, ticket, d_tot, s));
+            HIP_TRY(launch_count(d_desc, d_tp + 2 * (n + 1), n, nctiles, cv, status, ticket, d_tot, s));
     }
     HIP_TRY(hipMemcpyAsync(h_tot, d_tot, sizeof(int64_t) * 3 * n, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
@@ -842,6 +850,10 @@ sn_status sn::extract_many(sn_ctx *c, const sn_volume *vols, int32_t n, hipStrea
         const size_t o_ids = cv.add(4 * m->S), o_q = cv.add(16 * m->Q), o_pr = cv.add(2 * m->Q * d.dtype);
         const bool tris = d.prim == SN_TRIS;
         const size_t o_t = tris ? cv.add(24 * m->Q) : 0, o_tp = tris ? cv.add(4 * m->Q * d.dtype) : 0;
+        // cell index per point (for world points written by the last sweep),
+        // when every cell index fits 32 bits
+        const bool cells32 = (uint64_t)d.g.R * (uint64_t)d.g.CM < (uint64_t(1) << 32);
+        const size_t o_pc = cells32 ? cv.add(4 * m->P) : 0;
         uint8_t *blk = dalloc<uint8_t>(m, (int64_t)cv.bytes);
         if (!blk) return cleanup(fail(SN_ENOMEM, "extract: outputs"));
         d.points = reinterpret_cast<float *>(blk + o_pts);
@@ -855,6 +867,7 @@ sn_status sn::extract_many(sn_ctx *c, const sn_volume *vols, int32_t n, hipStrea
             d.tri_pairs = blk + o_tp;
             qblocks += (m->Q + 255) / 256;
         }
+        d.pcell = cells32 ? reinterpret_cast<uint32_t *>(blk + o_pc) : nullptr;
         hd[k] = d;
     }
     if (one) {
@@ -950,6 +963,19 @@ sn_status sn::ensure_smooth_buffers(sn_mesh *m)
     m->db = reinterpret_cast<float *>(blk + o_b);
     m->nbr = reinterpret_cast<int32_t *>(blk + o_n);
     return SN_OK;
+}
+
+// Smoothing descriptor of a mesh for the given parameters.
+static void fill_smooth_desc(const sn_mesh *m, const sn_smooth_params &p, SmoothDesc *sd)
+{
+    std::memset(sd, 0, sizeof *sd);
+    sd->P = m->P, sd->faces = m->d.faces, sd->off = m->d.st_off, sd->ids = m->d.st_ids;
+    sd->nbr = m->nbr, sd->da = m->da, sd->db = m->db, sd->iters = p.iterations;
+    sd->lam = (double)p.relaxation, sd->dist = (double)p.constraint;
+    sd->pcell = m->d.pcell, sd->points = m->d.points;
+    sd->CM = make_udiv((uint32_t)std::max<int64_t>(m->d.g.CM, 1));
+    sd->CN = make_udiv((uint32_t)std::max<int64_t>(m->d.g.CN, 1));
+    for (int a = 0; a < 3; ++a) sd->origin[a] = m->d.origin[a], sd->spacing[a] = m->d.spacing[a];
 }
 
 // n sweeps over `nvol` meshes (descriptor array), replayed from a HIP graph of
@@ -1070,16 +1096,13 @@ sn_status sn::smooth_one(sn_ctx *c, sn_mesh *m, const sn_smooth_params *p, hipSt
         if (st != SN_OK) return st;
     }
     SmoothDesc sd;
-    std::memset(&sd, 0, sizeof sd);
-    sd.P = m->P, sd.faces = m->d.faces, sd.off = m->d.st_off, sd.ids = m->d.st_ids;
-    sd.nbr = m->nbr, sd.da = m->da, sd.db = m->db, sd.iters = p->iterations;
-    sd.lam = (double)p->relaxation, sd.dist = (double)p->constraint;
+    fill_smooth_desc(m, *p, &sd);
     const int64_t nblocks = (m->P + kSweepPoints - 1) / kSweepPoints;
     st = run_sweeps_one(c, sd, nblocks, s);
     if (st != SN_OK) return st;
     // the last sweep `it` wrote buffer (it odd ? da : db)
     m->final_delta = p->iterations == 0 ? nullptr : (((p->iterations - 1) & 1) ? m->da : m->db);
-    {
+    if (p->iterations == 0 || !m->d.pcell) {  // else the last sweep wrote the points
         ProfScope ps(c, "k_emit", s);
         HIP_TRY(launch_emit_one(m->d, sd, m->ntiles, m->bpw, s));
     }
@@ -1122,12 +1145,13 @@ sn_status sn::smooth_many(sn_ctx *c, sn_mesh **ms, const sn_smooth_params *pv, i
     SmoothDesc *d_sd = reinterpret_cast<SmoothDesc *>(d_up);
     VolDesc *d_vd = reinterpret_cast<VolDesc *>(d_up + sizeof(SmoothDesc) * n);
     int64_t *d_p = reinterpret_cast<int64_t *>(d_up + (sizeof(SmoothDesc) + sizeof(VolDesc)) * n);
+    bool need_emit = false;
     for (int32_t v = 0; v < n; ++v) {
         sn_mesh *m = ms[v];
         SmoothDesc &h = h_sd[v];
-        h.P = m->P, h.faces = m->d.faces, h.off = m->d.st_off, h.ids = m->d.st_ids;
-        h.nbr = m->nbr, h.da = m->da, h.db = m->db, h.iters = m->P > 0 ? pv[v].iterations : 0;
-        h.lam = (double)pv[v].relaxation, h.dist = (double)pv[v].constraint;
+        fill_smooth_desc(m, pv[v], &h);
+        if (m->P == 0) h.iters = 0;
+        need_emit = need_emit || h.iters == 0 || !h.pcell;
         m->final_delta =
             h.iters == 0 ? nullptr : (((h.iters - 1) & 1) ? m->da : m->db);
         h_vd[v] = m->d;
@@ -1144,7 +1168,7 @@ sn_status sn::smooth_many(sn_ctx *c, sn_mesh **ms, const sn_smooth_params *pv, i
     }
     bool same_bpw = true;
     for (int32_t v = 1; v < n; ++v) same_bpw &= ms[v]->bpw == ms[0]->bpw;
-    {
+    if (need_emit) {  // meshes whose last sweep wrote the points skip inside k_emit
         ProfScope ps(c, "k_emit", s);
         if (same_bpw) {
             HIP_TRY(launch_emit(d_vd, d_sd, d_p + n + 1, n, tp[n], ms[0]->bpw, s));

@@ -253,3 +253,24 @@ def test_invalid_arguments(ctx, sn, torch):
     with pytest.raises(sn.SNError):
         ctx.smooth(m, relaxation=1.5)
     m.free()
+
+
+def test_wide_count_tiles(sn, torch, monkeypatch):
+    """The counting pass's wide form (four words per thread, taken for large
+    launches) forced on small volumes: same results against the oracle."""
+    monkeypatch.setenv("SN_TEST_COUNT_WIDE_WORDS", "0")
+    c = sn.Context(0)
+    try:
+        rng = np.random.default_rng(4321)
+        for case in range(24):
+            dims = (int(rng.integers(2, 300)), int(rng.integers(2, 40)), int(rng.integers(2, 30)))
+            dt = [np.uint8, np.uint16, np.uint32][case % 3]
+            vol = (synth.blocky_tiny if case % 2 else synth.random_tiny)(rng, dims, 5, dt)
+            announce(f"wide count {case}: dims={dims} {np.dtype(dt).name}")
+            run_case(c, sn, vol, iters=int(rng.integers(0, 8)))
+        v = synth.torso_like()
+        announce("wide count: " + v.name)
+        run_case(c, sn, v.labels, iters=v.iterations, lam=v.relaxation, d=v.constraint,
+                 spacing=v.spacing)
+    finally:
+        c.close()
