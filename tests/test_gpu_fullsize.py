@@ -236,3 +236,97 @@ def test_connectome_full_size(torch):
                   n_points=400, n_quads=1000)
     m.free()
     ctx.close()
+
+
+FIELDS = ("points", "offsets", "polys", "label_pairs", "stencil_off", "stencil_ids")
+
+
+def same_mesh(a, b, what):
+    for f in FIELDS:
+        x, y = getattr(a, f), getattr(b, f)
+        assert x.shape == y.shape and np.array_equal(x, y), f"{what}: {f} differs"
+
+
+def oracle_check(g, labels, iters, lam, d, selected=()):
+    import oracle
+
+    o = oracle.extract(labels, selected)
+    assert g.points.shape[0] == o.n_points
+    np.testing.assert_array_equal(g.polys, o.quads)
+    np.testing.assert_array_equal(g.label_pairs.astype(np.uint32), o.pairs)
+    np.testing.assert_array_equal(g.stencil_off.astype(np.int64), o.st_off)
+    np.testing.assert_array_equal(g.stencil_ids, o.st_ids)
+    if o.n_points:
+        ref = o.smooth(iters, lam, d) - o.centres()
+        assert np.max(np.abs(g.offsets.astype(np.float64) - ref)) <= TOL
+
+
+def test_batched_configuration(torch):
+    """The 64-volume batched workload as the benchmark runs it: every batched
+    mesh equals the plain one byte for byte; four of them against the oracle."""
+    import paper_2401_14906_amd as sn
+
+    sn.load_library()
+    ctx = sn.Context(0)
+    vols = synth.batch_volumes(count=64)
+    ts = [sn.to_device(v.labels) for v in vols]
+    announce("batched configuration: 64 volumes")
+    ms = ctx.batch_submit([dict(labels=t) for t in ts],
+                          [(v.iterations, v.relaxation, v.constraint) for v in vols])
+    got = [m.to_host() for m in ms]
+    for m in ms:
+        m.free()
+    for k, (t, v) in enumerate(zip(ts, vols)):
+        m = ctx.extract(t)
+        ctx.smooth(m, iterations=v.iterations, relaxation=v.relaxation, constraint=v.constraint)
+        same_mesh(got[k], m.to_host(), f"batch volume {k}")
+        m.free()
+    sizes = np.array([v.labels.size for v in vols])
+    for k in np.argsort(sizes)[[0, 1, 31, 63]]:
+        v = vols[int(k)]
+        announce(f"oracle check of batch volume {int(k)} {v.labels.shape}")
+        oracle_check(got[int(k)], v.labels, v.iterations, v.relaxation, v.constraint)
+    ctx.close()
+
+
+def test_served_configuration(torch):
+    """The served workload's volume pool (cubic edges 32..512, u8/u16/u32,
+    label subsets): results served in fused batches equal the plain results
+    for the same requests; two small ones against the oracle."""
+    import paper_2401_14906_amd as sn
+
+    sn.load_library()
+    ctx = sn.Context(0)
+    vols = synth.serve_pool(seed=5, count=16)
+    ts = [sn.to_device(v.labels) for v in vols]
+    present = [np.flatnonzero(np.bincount(v.labels.ravel())) for v in vols]
+    rng = np.random.default_rng(5)
+    reqs = []
+    for _ in range(48):
+        k = int(rng.integers(0, len(vols)))
+        labs = present[k][present[k] != 0]
+        sel = tuple(int(x) for x in rng.choice(labs, size=int(rng.integers(1, min(20, len(labs)) + 1)),
+                                               replace=False))
+        reqs.append((k, sel, int(rng.integers(10, 41))))
+    srv = ctx.serve_start(hbm_budget_bytes=32 << 30, max_inflight=64, n_streams=2, max_batch=16)
+    announce(f"served configuration: {len(reqs)} requests")
+    tks = [srv.submit(ts[k], iterations=it, relaxation=0.5, constraint=1.0, selected=sel)
+           for k, sel, it in reqs]
+    got = []
+    for tk in tks:
+        m = srv.wait(tk, timeout_us=120_000_000)
+        got.append(m.to_host())
+        m.free()
+    assert srv.stats()["n_batches"] < len(reqs)
+    srv.stop()
+    for n, (k, sel, it) in enumerate(reqs):
+        m = ctx.extract(ts[k], selected=sel)
+        ctx.smooth(m, iterations=it, relaxation=0.5, constraint=1.0)
+        same_mesh(got[n], m.to_host(), f"request {n}")
+        m.free()
+    small = sorted(range(len(reqs)), key=lambda n: vols[reqs[n][0]].labels.size)[:2]
+    for n in small:
+        k, sel, it = reqs[n]
+        announce(f"oracle check of request {n} {vols[k].labels.shape} {vols[k].labels.dtype}")
+        oracle_check(got[n], vols[k].labels, it, 0.5, 1.0, sel)
+    ctx.close()
