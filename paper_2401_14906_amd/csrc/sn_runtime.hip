@@ -388,13 +388,16 @@ std::string sn::size_class(const sn_volume &v)
     return os.str();
 }
 
-int32_t sn_ctx::batches_per_wave(const std::string &cls) const
+int32_t sn_ctx::batches_per_wave(const std::string &cls, int64_t nbatch) const
 {
     std::lock_guard<std::mutex> g(tune_mu);
     if (forced_bpw > 0) return forced_bpw;
     auto it = tune.find(cls);
     if (it != tune.end()) return it->second;
-    return 2;
+    // untuned: one batch per wave while that still gives few workgroups per
+    // CU (more waves in flight), three for large volumes (fewer launches of
+    // waves and the next batch's loads in flight behind the current one)
+    return nbatch < (int64_t(1) << 18) ? 1 : 3;
 }
 
 void sn_ctx::load_tune_cache()
@@ -683,7 +686,9 @@ sn_status sn::extract_many(sn_ctx *c, const sn_volume *vols, int32_t n, hipStrea
         const int64_t vox = vols[v].dims[0] * vols[v].dims[1] * vols[v].dims[2];
         if (vox > big) big = vox, vb = v;
     }
-    const int32_t bpw = bpw_override > 0 ? bpw_override : c->batches_per_wave(size_class(vols[vb]));
+    const Geom gb = make_geom(vols[vb]);
+    const int32_t bpw =
+        bpw_override > 0 ? bpw_override : c->batches_per_wave(size_class(vols[vb]), gb.R * gb.NB);
     const int TB = kWavesPerBlock * bpw;
 
     // Volumes are processed grouped by (label type, classification mode): one
@@ -1222,7 +1227,7 @@ extern "C" sn_status sn_autotune(sn_ctx *c, const sn_volume *vol, void *stream, 
     if (st != SN_OK) return st;
     hipStream_t s = static_cast<hipStream_t>(stream);
     HIP_TRY(hipSetDevice(c->device));
-    const int32_t cands[] = {1, 2, 4, 8};
+    const int32_t cands[] = {1, 2, 3, 4, 8};
     double best = 1e30;
     int32_t arg = 2;
     const bool was = c->profiling;
