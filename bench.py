@@ -371,10 +371,18 @@ def pmc_summary(pmc_dir, out_path, workload):
             else:
                 key = name.split("(")[0].split("<")[0].replace("void ", "").replace("sn::", "")
                 key = key.strip()
+                # one entry per kernel as the library's timing names it: the
+                # single-volume forms (_one), the first sweep (k_jacobi_first)
+                # and the row-width forms of k_edges count with their kernel
+                for suf in ("_one", "_wide", "_narrow"):
+                    key = key.replace(suf, "")
+                if key.startswith("k_jacobi"):
+                    key = "k_jacobi"
             c = row["Counter_Name"]
             d = acc.setdefault(key, {}).setdefault(c, {})
             disp = row.get("Dispatch_Id") or row.get("Correlation_Id") or str(len(d))
             d[disp] = d.get(disp, 0.0) + float(row["Counter_Value"])
+    # mean per dispatch over every dispatch of the kernel (all its forms)
     mean = {k: {c: sum(v.values()) / len(v) for c, v in cs.items()} for k, cs in acc.items()}
     if "copy_probe" not in mean:
         raise SystemExit("pmc summary: no copy probe dispatches found")
