@@ -1096,12 +1096,23 @@ __device__ __forceinline__ uint32_t sweep_blocks(const OneSmooth &a)
     return (uint32_t)((a.s.P + kSweepPoints - 1) / kSweepPoints);
 }
 
+// Logical block of a sweep.  A mesh whose sweep data fits the last-level
+// cache gains from XCD-contiguous blocks (stencil neighbours in the same L2);
+// a larger one streams from HBM and is faster with the hardware's
+// round-robin order.
+constexpr uint32_t kSweepXcdBlocks = 8192;
+
+__device__ __forceinline__ int64_t sweep_block(uint32_t b, uint32_t nb)
+{
+    return nb <= kSweepXcdBlocks ? xcd_block(b, nb) : (int64_t)b;
+}
+
 template <class Src>
 __device__ __forceinline__ void jacobi_first_body(const Src &a)
 {
     const uint32_t nb = sweep_blocks(a);
     if (blockIdx.x >= nb) return;
-    const int64_t b = xcd_block(blockIdx.x, nb);
+    const int64_t b = sweep_block(blockIdx.x, nb);
     int64_t first;
     const SmoothDesc &s = smooth_of(a, b, first);
     if (s.iters < 1) return;
@@ -1178,7 +1189,7 @@ __device__ __forceinline__ void jacobi_body(const Src &a, int32_t it)
     constexpr int K = kSweepChunks;
     const uint32_t nbl = sweep_blocks(a);
     if (blockIdx.x >= nbl) return;
-    const int64_t b = xcd_block(blockIdx.x, nbl);
+    const int64_t b = sweep_block(blockIdx.x, nbl);
     int64_t first;
     const SmoothDesc &s = smooth_of(a, b, first);
     if (it >= s.iters) return;  // this mesh has finished its sweeps
