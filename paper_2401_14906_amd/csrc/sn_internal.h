@@ -126,10 +126,17 @@ struct SmoothDesc {
     double origin[3], spacing[3];
 };
 
-// A smoothing block covers kSweepPoints consecutive points: each wave holds
-// kSweepChunks chunks of 64 points.
-constexpr int kSweepChunks = 2;
-constexpr int kSweepPoints = kBlock * kSweepChunks;
+// A smoothing block covers kBlock * K consecutive points: each wave holds K
+// chunks of 64 points.  Meshes of up to kSweepSmallPoints points (their sweep
+// data fits the last-level cache; latency decides) run with K = 1, more and
+// shorter waves, and XCD-contiguous blocks; larger ones (bandwidth decides)
+// with K = 2 and the hardware's round-robin block order.
+constexpr int64_t kSweepSmallPoints = int64_t(1) << 22;
+inline int sweep_chunks(int64_t points) { return points <= kSweepSmallPoints ? 1 : 2; }
+inline int64_t sweep_blocks_for(int64_t points, int K)
+{
+    return (points + (int64_t)kBlock * K - 1) / ((int64_t)kBlock * K);
+}
 
 // Scan tile status word: [63:62] flag, [61:0] value.
 constexpr uint64_t kFlagAgg = 1ull << 62;
@@ -159,14 +166,16 @@ hipError_t launch_generate(int32_t dtype, int32_t mode, const VolDesc *d_descs,
 // k_emit: d_sds[v] (iterations, ping-pong buffers) names volume v's final offsets
 hipError_t launch_emit(const VolDesc *d_descs, const SmoothDesc *d_sds, const int64_t *d_tile_prefix,
                        int32_t nvol, int64_t ntiles, int32_t bpw, hipStream_t s);
-// block_prefix[v] = first block of volume v (kSweepPoints points per block);
-// it = 0 runs the first sweep (zero input offsets, builds nbr)
+// block_prefix[v] = first block of volume v (kBlock * K points per block, K
+// from sweep_chunks of the launch's points); it = 0 runs the first sweep
+// (zero input offsets, builds nbr)
 hipError_t launch_jacobi(const SmoothDesc *d_sd, const int64_t *d_block_prefix, int32_t nvol,
-                         int64_t nblocks, int32_t it, hipStream_t s);
+                         int64_t nblocks, int32_t it, int K, hipStream_t s);
 // the same n sweeps as kernel nodes of `graph`, each depending on the one before
+// (sweep `it` launches grid[it] blocks)
 hipError_t add_jacobi_nodes(hipGraph_t graph, const SmoothDesc *d_sd,
-                            const int64_t *d_block_prefix, int32_t nvol, int64_t nblocks,
-                            int32_t iters);
+                            const int64_t *d_block_prefix, int32_t nvol, const int64_t *grid,
+                            int32_t iters, int K);
 // Single-volume forms: the descriptor travels by value in the kernel
 // arguments (no upload, no prefix array; tiles and blocks start at 0).
 hipError_t launch_edges_one(const VolDesc &d, bool wide, int64_t ntiles, uint64_t *d_zero,
@@ -175,12 +184,12 @@ hipError_t launch_count_one(const VolDesc &d, int64_t ntiles, int32_t words_per_
                             uint64_t *d_status, uint32_t *d_ticket, int64_t *d_totals, hipStream_t s);
 hipError_t launch_emit_one(const VolDesc &d, const SmoothDesc &sd, int64_t ntiles, int32_t bpw,
                            hipStream_t s);
-hipError_t launch_jacobi_one(const SmoothDesc &sd, int64_t nblocks, int32_t it, hipStream_t s);
+hipError_t launch_jacobi_one(const SmoothDesc &sd, int64_t nblocks, int32_t it, int K, hipStream_t s);
 hipError_t add_jacobi_nodes_one(hipGraph_t graph, const SmoothDesc &sd, int64_t nblocks,
-                                int32_t iters, std::vector<hipGraphNode_t> *nodes);
+                                int32_t iters, int K, std::vector<hipGraphNode_t> *nodes);
 // new descriptor for the nodes of an instantiated graph made by add_jacobi_nodes_one
 hipError_t set_jacobi_nodes_one(hipGraphExec_t exec, const std::vector<hipGraphNode_t> &nodes,
-                                const SmoothDesc &sd, int64_t nblocks);
+                                const SmoothDesc &sd, int64_t nblocks, int K);
 hipError_t launch_triangulate_one(const VolDesc &d, hipStream_t s);
 // quad blocks (256 quads per block) of the volumes with prim 3
 hipError_t launch_triangulate(const VolDesc *d_descs, const int64_t *d_block_prefix, int32_t nvol,

@@ -1090,36 +1090,37 @@ __device__ __forceinline__ void store_offset(const SmoothDesc &s, SN_GLOBAL floa
 // Blocks of a sweep launch that carry points: a launch over many meshes has
 // exactly those; a single mesh may run on a larger cached grid whose extra
 // blocks leave at once (and must not take part in the XCD remap).
+template <int K>
 __device__ __forceinline__ uint32_t sweep_blocks(const ManySmooth &) { return gridDim.x; }
+template <int K>
 __device__ __forceinline__ uint32_t sweep_blocks(const OneSmooth &a)
 {
-    return (uint32_t)((a.s.P + kSweepPoints - 1) / kSweepPoints);
+    return (uint32_t)((a.s.P + kBlock * K - 1) / (kBlock * K));
 }
 
-// Logical block of a sweep.  A mesh whose sweep data fits the last-level
-// cache gains from XCD-contiguous blocks (stencil neighbours in the same L2);
-// a larger one streams from HBM and is faster with the hardware's
-// round-robin order.
-constexpr uint32_t kSweepXcdBlocks = 8192;
-
+// Logical block of a sweep.  Small meshes (K = 1), whose sweep data fits the
+// last-level cache, gain from XCD-contiguous blocks (stencil neighbours in
+// the same L2); larger ones stream from HBM and are faster with the
+// hardware's round-robin order.
+template <int K>
 __device__ __forceinline__ int64_t sweep_block(uint32_t b, uint32_t nb)
 {
-    return nb <= kSweepXcdBlocks ? xcd_block(b, nb) : (int64_t)b;
+    return K == 1 ? xcd_block(b, nb) : (int64_t)b;
 }
 
-template <class Src>
+template <int K, class Src>
 __device__ __forceinline__ void jacobi_first_body(const Src &a)
 {
-    const uint32_t nb = sweep_blocks(a);
+    const uint32_t nb = sweep_blocks<K>(a);
     if (blockIdx.x >= nb) return;
-    const int64_t b = sweep_block(blockIdx.x, nb);
+    const int64_t b = sweep_block<K>(blockIdx.x, nb);
     int64_t first;
     const SmoothDesc &s = smooth_of(a, b, first);
     if (s.iters < 1) return;
     SN_GLOBAL float *dout = glb(s.db);
 #pragma unroll
-    for (int c = 0; c < kSweepChunks; ++c) {
-        const int64_t p = (b - first) * kSweepPoints + c * kBlock + threadIdx.x;
+    for (int c = 0; c < K; ++c) {
+        const int64_t p = (b - first) * (kBlock * K) + c * kBlock + threadIdx.x;
         if (p >= s.P) break;
         const uint32_t f = glb(s.faces)[p];
         const int n = __popc(f);
@@ -1151,16 +1152,18 @@ __device__ __forceinline__ void jacobi_first_body(const Src &a)
     }
 }
 
+template <int K>
 __global__ __launch_bounds__(256) void k_jacobi_first(const SmoothDesc *__restrict__ sds,
                                                       const int64_t *__restrict__ prefix,
                                                       int32_t nvol)
 {
-    jacobi_first_body(ManySmooth{sds, prefix, nvol});
+    jacobi_first_body<K>(ManySmooth{sds, prefix, nvol});
 }
 
+template <int K>
 __global__ __launch_bounds__(256) void k_jacobi_first_one(OneSmooth a)
 {
-    jacobi_first_body(a);
+    jacobi_first_body<K>(a);
 }
 
 __device__ __forceinline__ float shfl_up1(float x)
@@ -1178,23 +1181,22 @@ __device__ __forceinline__ float readlane_f(float x, int l)
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
 }
 
-// Sweeps 1..n-1.  Each wave holds kSweepChunks chunks of 64 consecutive
+// Sweeps 1..n-1.  Each wave holds K chunks of 64 consecutive
 // points, one point per lane and chunk; all loads of the wave are issued
 // before any use.  The -x / +x neighbours of point p are points p - 1 / p + 1
 // (consecutive cells of a row get consecutive ids), read from the adjacent
 // lane; only the first and the last point of the wave load them.
-template <class Src>
+template <int K, class Src>
 __device__ __forceinline__ void jacobi_body(const Src &a, int32_t it)
 {
-    constexpr int K = kSweepChunks;
-    const uint32_t nbl = sweep_blocks(a);
+    const uint32_t nbl = sweep_blocks<K>(a);
     if (blockIdx.x >= nbl) return;
-    const int64_t b = sweep_block(blockIdx.x, nbl);
+    const int64_t b = sweep_block<K>(blockIdx.x, nbl);
     int64_t first;
     const SmoothDesc &s = smooth_of(a, b, first);
     if (it >= s.iters) return;  // this mesh has finished its sweeps
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
-    const int64_t p0 = (b - first) * kSweepPoints + (int64_t)wave * (64 * K);
+    const int64_t p0 = (b - first) * (kBlock * K) + (int64_t)wave * (64 * K);
     const int64_t P = s.P;
     if (p0 >= P) return;
     const SN_GLOBAL float *din = glb((it & 1) ? s.db : s.da);
@@ -1285,16 +1287,18 @@ __device__ __forceinline__ void jacobi_body(const Src &a, int32_t it)
     }
 }
 
+template <int K>
 __global__ __launch_bounds__(256) void k_jacobi(const SmoothDesc *__restrict__ sds,
                                                 const int64_t *__restrict__ prefix, int32_t nvol,
                                                 int32_t it)
 {
-    jacobi_body(ManySmooth{sds, prefix, nvol}, it);
+    jacobi_body<K>(ManySmooth{sds, prefix, nvol}, it);
 }
 
+template <int K>
 __global__ __launch_bounds__(256) void k_jacobi_one(OneSmooth a, int32_t it)
 {
-    jacobi_body(a, it);
+    jacobi_body<K>(a, it);
 }
 
 // ---------------------------------------------------------------------------
@@ -1439,41 +1443,65 @@ hipError_t launch_emit_one(const VolDesc &d, const SmoothDesc &sd, int64_t ntile
     return hipGetLastError();
 }
 
-hipError_t launch_jacobi(const SmoothDesc *d_sd, const int64_t *d_block_prefix, int32_t nvol,
-                         int64_t nblocks, int32_t it, hipStream_t s)
+template <int K>
+static void jacobi_k(const SmoothDesc *d_sd, const int64_t *d_block_prefix, int32_t nvol,
+                     int64_t nblocks, int32_t it, hipStream_t s)
 {
-    if (nblocks <= 0) return hipSuccess;
     if (it == 0)
-        hipLaunchKernelGGL(k_jacobi_first, dim3((uint32_t)nblocks), dim3(256), 0, s, d_sd,
+        hipLaunchKernelGGL(k_jacobi_first<K>, dim3((uint32_t)nblocks), dim3(256), 0, s, d_sd,
                            d_block_prefix, nvol);
     else
-        hipLaunchKernelGGL(k_jacobi, dim3((uint32_t)nblocks), dim3(256), 0, s, d_sd, d_block_prefix,
-                           nvol, it);
+        hipLaunchKernelGGL(k_jacobi<K>, dim3((uint32_t)nblocks), dim3(256), 0, s, d_sd,
+                           d_block_prefix, nvol, it);
+}
+
+template <int K>
+static void jacobi_one_k(const SmoothDesc &sd, int64_t nblocks, int32_t it, hipStream_t s)
+{
+    if (it == 0)
+        hipLaunchKernelGGL(k_jacobi_first_one<K>, dim3((uint32_t)nblocks), dim3(256), 0, s,
+                           OneSmooth{sd});
+    else
+        hipLaunchKernelGGL(k_jacobi_one<K>, dim3((uint32_t)nblocks), dim3(256), 0, s, OneSmooth{sd},
+                           it);
+}
+
+hipError_t launch_jacobi(const SmoothDesc *d_sd, const int64_t *d_block_prefix, int32_t nvol,
+                         int64_t nblocks, int32_t it, int K, hipStream_t s)
+{
+    if (nblocks <= 0) return hipSuccess;
+    if (K == 1)
+        jacobi_k<1>(d_sd, d_block_prefix, nvol, nblocks, it, s);
+    else
+        jacobi_k<2>(d_sd, d_block_prefix, nvol, nblocks, it, s);
     return hipGetLastError();
 }
 
-hipError_t launch_jacobi_one(const SmoothDesc &sd, int64_t nblocks, int32_t it, hipStream_t s)
+hipError_t launch_jacobi_one(const SmoothDesc &sd, int64_t nblocks, int32_t it, int K, hipStream_t s)
 {
     if (nblocks <= 0) return hipSuccess;
-    if (it == 0)
-        hipLaunchKernelGGL(k_jacobi_first_one, dim3((uint32_t)nblocks), dim3(256), 0, s, OneSmooth{sd});
+    if (K == 1)
+        jacobi_one_k<1>(sd, nblocks, it, s);
     else
-        hipLaunchKernelGGL(k_jacobi_one, dim3((uint32_t)nblocks), dim3(256), 0, s, OneSmooth{sd}, it);
+        jacobi_one_k<2>(sd, nblocks, it, s);
     return hipGetLastError();
 }
 
 // Kernel nodes of n sweeps over many meshes, each depending on the one before.
 hipError_t add_jacobi_nodes(hipGraph_t graph, const SmoothDesc *d_sd,
-                            const int64_t *d_block_prefix, int32_t nvol, int64_t nblocks,
-                            int32_t iters)
+                            const int64_t *d_block_prefix, int32_t nvol, const int64_t *grid,
+                            int32_t iters, int K)
 {
     hipGraphNode_t prev = nullptr;
-    for (int32_t it = 0; it < iters && nblocks > 0; ++it) {
+    for (int32_t it = 0; it < iters && grid[it] > 0; ++it) {
+        const int64_t nblocks = grid[it];
         void *args_first[] = {&d_sd, &d_block_prefix, &nvol};
         void *args[] = {&d_sd, &d_block_prefix, &nvol, &it};
         hipKernelNodeParams kp{};
-        kp.func = it == 0 ? reinterpret_cast<void *>(&k_jacobi_first)
-                          : reinterpret_cast<void *>(&k_jacobi);
+        kp.func = it == 0 ? (K == 1 ? reinterpret_cast<void *>(&k_jacobi_first<1>)
+                                    : reinterpret_cast<void *>(&k_jacobi_first<2>))
+                          : (K == 1 ? reinterpret_cast<void *>(&k_jacobi<1>)
+                                    : reinterpret_cast<void *>(&k_jacobi<2>));
         kp.gridDim = dim3((uint32_t)nblocks);
         kp.blockDim = dim3(256);
         kp.sharedMemBytes = 0;
@@ -1490,14 +1518,16 @@ hipError_t add_jacobi_nodes(hipGraph_t graph, const SmoothDesc *d_sd,
 
 // Node parameters of sweep `it` of one mesh; `arg` and `itv` must outlive the
 // API call that consumes the parameters.
-static void sweep_params_one(OneSmooth &arg, int32_t &itv, void **args, int64_t nblocks,
+static void sweep_params_one(OneSmooth &arg, int32_t &itv, void **args, int64_t nblocks, int K,
                              hipKernelNodeParams &kp)
 {
     args[0] = &arg;
     args[1] = &itv;
     kp = hipKernelNodeParams{};
-    kp.func = itv == 0 ? reinterpret_cast<void *>(&k_jacobi_first_one)
-                       : reinterpret_cast<void *>(&k_jacobi_one);
+    kp.func = itv == 0 ? (K == 1 ? reinterpret_cast<void *>(&k_jacobi_first_one<1>)
+                                 : reinterpret_cast<void *>(&k_jacobi_first_one<2>))
+                       : (K == 1 ? reinterpret_cast<void *>(&k_jacobi_one<1>)
+                                 : reinterpret_cast<void *>(&k_jacobi_one<2>));
     kp.gridDim = dim3((uint32_t)nblocks);
     kp.blockDim = dim3(256);
     kp.sharedMemBytes = 0;
@@ -1506,7 +1536,7 @@ static void sweep_params_one(OneSmooth &arg, int32_t &itv, void **args, int64_t 
 }
 
 hipError_t add_jacobi_nodes_one(hipGraph_t graph, const SmoothDesc &sd, int64_t nblocks,
-                                int32_t iters, std::vector<hipGraphNode_t> *nodes)
+                                int32_t iters, int K, std::vector<hipGraphNode_t> *nodes)
 {
     OneSmooth arg{sd};
     hipGraphNode_t prev = nullptr;
@@ -1515,7 +1545,7 @@ hipError_t add_jacobi_nodes_one(hipGraph_t graph, const SmoothDesc &sd, int64_t 
         void *args[2];
         hipKernelNodeParams kp;
         int32_t itv = it;
-        sweep_params_one(arg, itv, args, nblocks, kp);
+        sweep_params_one(arg, itv, args, nblocks, K, kp);
         hipGraphNode_t node;
         const hipError_t e =
             hipGraphAddKernelNode(&node, graph, prev ? &prev : nullptr, prev ? 1 : 0, &kp);
@@ -1527,14 +1557,14 @@ hipError_t add_jacobi_nodes_one(hipGraph_t graph, const SmoothDesc &sd, int64_t 
 }
 
 hipError_t set_jacobi_nodes_one(hipGraphExec_t exec, const std::vector<hipGraphNode_t> &nodes,
-                                const SmoothDesc &sd, int64_t nblocks)
+                                const SmoothDesc &sd, int64_t nblocks, int K)
 {
     OneSmooth arg{sd};
     for (size_t it = 0; it < nodes.size(); ++it) {
         void *args[2];
         hipKernelNodeParams kp;
         int32_t itv = (int32_t)it;
-        sweep_params_one(arg, itv, args, nblocks, kp);
+        sweep_params_one(arg, itv, args, nblocks, K, kp);
         const hipError_t e = hipGraphExecKernelNodeSetParams(exec, nodes[it], &kp);
         if (e != hipSuccess) return e;
     }

@@ -82,7 +82,8 @@ struct sn_ctx {
     // Freed meshes: the retire stream waits for each mesh's completion event
     // and their pool blocks are released behind an event recorded on it.
     hipStream_t retire_stream = nullptr;
-    // Sweep graphs of single meshes by (iterations, bucketed block count).
+    // Sweep graphs of single meshes by (iterations, bucketed block count,
+    // chunks per wave).
     // The smoothing descriptor is a kernel-node argument; a new mesh of a
     // similar size reuses an instantiated graph by rewriting those arguments
     // once the graph's previous launch has completed.
@@ -94,7 +95,7 @@ struct sn_ctx {
         hipEvent_t last = nullptr;  // after the last launch of the graph
     };
     std::mutex sweep_mu;
-    std::map<std::pair<int32_t, int64_t>, SweepGraph> sweep_graphs;
+    std::map<std::tuple<int32_t, int64_t, int>, SweepGraph> sweep_graphs;  // (iters, blocks, K)
     sn::EventCache timing_events{hipEventDefault};
     // profiling
     bool profiling = false;
@@ -156,9 +157,10 @@ sn_status smooth_many(sn_ctx *c, sn_mesh **ms, const sn_smooth_params *pv, int32
 // the plain path of one mesh (cached sweep graph, descriptors by value)
 sn_status smooth_one(sn_ctx *c, sn_mesh *m, const sn_smooth_params *p, hipStream_t s);
 sn_status ensure_smooth_buffers(sn_mesh *m);
+// sweep `it` of grid.size() sweeps launches grid[it] blocks
 sn_status run_sweeps(sn_ctx *c, const SmoothDesc *d_sd, const int64_t *d_bp, int32_t nvol,
-                     int64_t nblocks, int32_t iters, hipStream_t s);
-sn_status run_sweeps_one(sn_ctx *c, const SmoothDesc &sd, int64_t nblocks, hipStream_t s);
+                     const std::vector<int64_t> &grid, int K, hipStream_t s);
+sn_status run_sweeps_one(sn_ctx *c, const SmoothDesc &sd, int64_t nblocks, int K, hipStream_t s);
 sn_status mesh_mark(sn_mesh *m, hipStream_t s);
 void mesh_release(sn_mesh *m);
 void ctx_retain(sn_ctx *c);

@@ -983,17 +983,18 @@ static void fill_smooth_desc(const sn_mesh *m, const sn_smooth_params &p, Smooth
     for (int a = 0; a < 3; ++a) sd->origin[a] = m->d.origin[a], sd->spacing[a] = m->d.spacing[a];
 }
 
-// n sweeps over `nvol` meshes (descriptor array), replayed from a HIP graph of
-// kernel nodes built for this call
+// Sweeps over `nvol` meshes (descriptor array), replayed from a HIP graph of
+// kernel nodes built for this call; sweep `it` launches grid[it] blocks
 sn_status sn::run_sweeps(sn_ctx *c, const SmoothDesc *d_sd, const int64_t *d_bp, int32_t nvol,
-                         int64_t nblocks, int32_t iters, hipStream_t s)
+                         const std::vector<int64_t> &grid, int K, hipStream_t s)
 {
-    if (iters <= 0 || nblocks <= 0) return SN_OK;
+    const int32_t iters = (int32_t)grid.size();
+    if (iters <= 0 || grid[0] <= 0) return SN_OK;
     if (c->profile_eager) {
         // eager launches, each sweep bracketed by its own events
         for (int32_t it = 0; it < iters; ++it) {
             ProfScope ps(c, "k_jacobi", s);
-            HIP_TRY(launch_jacobi(d_sd, d_bp, nvol, nblocks, it, s));
+            HIP_TRY(launch_jacobi(d_sd, d_bp, nvol, grid[it], it, K, s));
         }
         return SN_OK;
     }
@@ -1005,7 +1006,7 @@ sn_status sn::run_sweeps(sn_ctx *c, const SmoothDesc *d_sd, const int64_t *d_bp,
     hipGraph_t graph;
     hipGraphExec_t exec = nullptr;
     HIP_TRY(hipGraphCreate(&graph, 0));
-    hipError_t e = add_jacobi_nodes(graph, d_sd, d_bp, nvol, nblocks, iters);
+    hipError_t e = add_jacobi_nodes(graph, d_sd, d_bp, nvol, grid.data(), iters, K);
     if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     if (e == hipSuccess) e = hipGraphLaunch(exec, s);
@@ -1024,20 +1025,20 @@ static int64_t sweep_bucket(int64_t n)
 }
 
 // n sweeps of one mesh from the context's cache of sweep graphs
-sn_status sn::run_sweeps_one(sn_ctx *c, const SmoothDesc &sd, int64_t nblocks, hipStream_t s)
+sn_status sn::run_sweeps_one(sn_ctx *c, const SmoothDesc &sd, int64_t nblocks, int K, hipStream_t s)
 {
     const int32_t iters = sd.iters;
     if (iters <= 0 || nblocks <= 0) return SN_OK;
     if (c->profile_eager) {
         for (int32_t it = 0; it < iters; ++it) {
             ProfScope ps(c, "k_jacobi", s);
-            HIP_TRY(launch_jacobi_one(sd, nblocks, it, s));
+            HIP_TRY(launch_jacobi_one(sd, nblocks, it, K, s));
         }
         return SN_OK;
     }
     const int64_t nb = sweep_bucket(nblocks);
     std::lock_guard<std::mutex> g(c->sweep_mu);
-    auto key = std::make_pair(iters, nb);
+    auto key = std::make_tuple(iters, nb, K);
     auto it = c->sweep_graphs.find(key);
     if (it == c->sweep_graphs.end()) {
         if (c->sweep_graphs.size() >= 32) {
@@ -1051,7 +1052,7 @@ sn_status sn::run_sweeps_one(sn_ctx *c, const SmoothDesc &sd, int64_t nblocks, h
         }
         sn_ctx::SweepGraph sg;
         hipError_t e = hipGraphCreate(&sg.graph, 0);
-        if (e == hipSuccess) e = add_jacobi_nodes_one(sg.graph, sd, nb, iters, &sg.nodes);
+        if (e == hipSuccess) e = add_jacobi_nodes_one(sg.graph, sd, nb, iters, K, &sg.nodes);
         if (e == hipSuccess) e = hipGraphInstantiate(&sg.exec, sg.graph, nullptr, nullptr, 0);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&sg.last, hipEventDisableTiming);
         if (e != hipSuccess) {
@@ -1066,7 +1067,7 @@ sn_status sn::run_sweeps_one(sn_ctx *c, const SmoothDesc &sd, int64_t nblocks, h
     if (std::memcmp(&sg.args, &sd, sizeof(SmoothDesc)) != 0) {
         // arguments of a launch still pending must not change under it
         hipError_t e = hipEventSynchronize(sg.last);
-        if (e == hipSuccess) e = set_jacobi_nodes_one(sg.exec, sg.nodes, sd, nb);
+        if (e == hipSuccess) e = set_jacobi_nodes_one(sg.exec, sg.nodes, sd, nb, K);
         if (e != hipSuccess) return fail(SN_EDEVICE, std::string("smooth: graph update: ") + hipGetErrorString(e));
         sg.args = sd;
     }
@@ -1102,8 +1103,8 @@ sn_status sn::smooth_one(sn_ctx *c, sn_mesh *m, const sn_smooth_params *p, hipSt
     }
     SmoothDesc sd;
     fill_smooth_desc(m, *p, &sd);
-    const int64_t nblocks = (m->P + kSweepPoints - 1) / kSweepPoints;
-    st = run_sweeps_one(c, sd, nblocks, s);
+    const int K = sweep_chunks(m->P);
+    st = run_sweeps_one(c, sd, sweep_blocks_for(m->P, K), K, s);
     if (st != SN_OK) return st;
     // the last sweep `it` wrote buffer (it odd ? da : db)
     m->final_delta = p->iterations == 0 ? nullptr : (((p->iterations - 1) & 1) ? m->da : m->db);
@@ -1122,8 +1123,7 @@ sn_status sn::smooth_many(sn_ctx *c, sn_mesh **ms, const sn_smooth_params *pv, i
                           hipStream_t s)
 {
     Scratch scr(c);
-    std::vector<int64_t> bp(n + 1, 0), tp(n + 1, 0);
-    int32_t maxit = 0;
+    int64_t all_points = 0;
     for (int32_t v = 0; v < n; ++v) {
         sn_status st = validate_smooth(&pv[v]);
         if (st != SN_OK) return st;
@@ -1131,9 +1131,27 @@ sn_status sn::smooth_many(sn_ctx *c, sn_mesh **ms, const sn_smooth_params *pv, i
             st = ensure_smooth_buffers(ms[v]);
             if (st != SN_OK) return st;
         }
-        bp[v + 1] = bp[v] + (ms[v]->P + kSweepPoints - 1) / kSweepPoints;
-        tp[v + 1] = tp[v] + ms[v]->ntiles;
-        maxit = std::max(maxit, pv[v].iterations);
+        all_points += ms[v]->P;
+    }
+    const int K = sweep_chunks(all_points);
+    // meshes in order of descending sweep count: the blocks still sweeping at
+    // sweep `it` are then a prefix of the block map, and each sweep launches
+    // only those
+    auto iters_of = [&](int32_t v) { return ms[v]->P > 0 ? pv[v].iterations : 0; };
+    std::vector<int32_t> ord(n);
+    for (int32_t v = 0; v < n; ++v) ord[v] = v;
+    std::stable_sort(ord.begin(), ord.end(),
+                     [&](int32_t a, int32_t b) { return iters_of(a) > iters_of(b); });
+    std::vector<int64_t> bp(n + 1, 0), tp(n + 1, 0);
+    for (int32_t k = 0; k < n; ++k) {
+        bp[k + 1] = bp[k] + sweep_blocks_for(ms[ord[k]]->P, K);
+        tp[k + 1] = tp[k] + ms[ord[k]]->ntiles;
+    }
+    const int32_t maxit = n > 0 ? iters_of(ord[0]) : 0;
+    std::vector<int64_t> grid(maxit);
+    for (int32_t it = 0, k = n; it < maxit; ++it) {
+        while (k > 0 && iters_of(ord[k - 1]) <= it) --k;
+        grid[it] = bp[k];
     }
     // one upload: smoothing and volume descriptors, sweep-block map, emit tile
     // map and per-mesh emit maps {0, ntiles}
@@ -1151,22 +1169,22 @@ sn_status sn::smooth_many(sn_ctx *c, sn_mesh **ms, const sn_smooth_params *pv, i
     VolDesc *d_vd = reinterpret_cast<VolDesc *>(d_up + sizeof(SmoothDesc) * n);
     int64_t *d_p = reinterpret_cast<int64_t *>(d_up + (sizeof(SmoothDesc) + sizeof(VolDesc)) * n);
     bool need_emit = false;
-    for (int32_t v = 0; v < n; ++v) {
-        sn_mesh *m = ms[v];
-        SmoothDesc &h = h_sd[v];
-        fill_smooth_desc(m, pv[v], &h);
-        if (m->P == 0) h.iters = 0;
+    for (int32_t k = 0; k < n; ++k) {
+        sn_mesh *m = ms[ord[k]];
+        SmoothDesc &h = h_sd[k];
+        fill_smooth_desc(m, pv[ord[k]], &h);
+        h.iters = iters_of(ord[k]);
         need_emit = need_emit || h.iters == 0 || !h.pcell;
         m->final_delta =
             h.iters == 0 ? nullptr : (((h.iters - 1) & 1) ? m->da : m->db);
-        h_vd[v] = m->d;
-        h_p[2 * (n + 1) + 2 * v] = 0;
-        h_p[2 * (n + 1) + 2 * v + 1] = m->ntiles;
+        h_vd[k] = m->d;
+        h_p[2 * (n + 1) + 2 * k] = 0;
+        h_p[2 * (n + 1) + 2 * k + 1] = m->ntiles;
     }
     std::memcpy(h_p, bp.data(), sizeof(int64_t) * (n + 1));
     std::memcpy(h_p + n + 1, tp.data(), sizeof(int64_t) * (n + 1));
     HIP_TRY(hipMemcpyAsync(d_up, h_up, up, hipMemcpyHostToDevice, s));
-    sn_status st = run_sweeps(c, d_sd, d_p, n, bp[n], maxit, s);
+    sn_status st = run_sweeps(c, d_sd, d_p, n, grid, K, s);
     if (st != SN_OK) {
         scr.retire(s);
         return st;
@@ -1178,9 +1196,9 @@ sn_status sn::smooth_many(sn_ctx *c, sn_mesh **ms, const sn_smooth_params *pv, i
         if (same_bpw) {
             HIP_TRY(launch_emit(d_vd, d_sd, d_p + n + 1, n, tp[n], ms[0]->bpw, s));
         } else {
-            for (int32_t v = 0; v < n; ++v)
-                HIP_TRY(launch_emit(d_vd + v, d_sd + v, d_p + 2 * (n + 1) + 2 * v, 1, ms[v]->ntiles,
-                                    ms[v]->bpw, s));
+            for (int32_t k = 0; k < n; ++k)
+                HIP_TRY(launch_emit(d_vd + k, d_sd + k, d_p + 2 * (n + 1) + 2 * k, 1,
+                                    ms[ord[k]]->ntiles, ms[ord[k]]->bpw, s));
         }
     }
     scr.retire(s);
