@@ -36,6 +36,9 @@ constexpr int kWavesPerBlock = 4;
 constexpr int kBlock = 64 * kWavesPerBlock;
 constexpr int kMaxBatchesPerWave = 16;
 constexpr int kSegmentsPerTile = 16;  // k_edges: 4 waves x 4 segments of 256 samples
+// k_generate: a wave takes groups of kGenWords consecutive words (any rows),
+// bpw groups per wave
+constexpr int kGenWords = 32;
 // k_count: 1024 threads per workgroup, one or kCountWideV words per thread
 // (the wide form for launches of at least kCountWideWords words: fewer scan
 // tiles, and fewer of the ordered tile tickets every workgroup takes)

@@ -285,6 +285,26 @@ __device__ __forceinline__ int32_t wave_excl_scan32(int32_t x, int lane)
     return inc - x;
 }
 
+// Inclusive wave scan on DPP row shifts and row broadcasts (no LDS traffic).
+__device__ __forceinline__ int32_t wave_incl_scan_dpp(int32_t v, int lane)
+{
+    const int rl = lane & 15;
+    int32_t t;
+    t = __builtin_amdgcn_mov_dpp(v, 0x111, 0xf, 0xf, false);  // row_shr:1
+    if (rl >= 1) v += t;
+    t = __builtin_amdgcn_mov_dpp(v, 0x112, 0xf, 0xf, false);  // row_shr:2
+    if (rl >= 2) v += t;
+    t = __builtin_amdgcn_mov_dpp(v, 0x114, 0xf, 0xf, false);  // row_shr:4
+    if (rl >= 4) v += t;
+    t = __builtin_amdgcn_mov_dpp(v, 0x118, 0xf, 0xf, false);  // row_shr:8
+    if (rl >= 8) v += t;
+    t = __builtin_amdgcn_mov_dpp(v, 0x142, 0xf, 0xf, false);  // row_bcast:15
+    if ((lane & 31) >= 16) v += t;
+    t = __builtin_amdgcn_mov_dpp(v, 0x143, 0xf, 0xf, false);  // row_bcast:31
+    if (lane >= 32) v += t;
+    return v;
+}
+
 // ---------------------------------------------------------------------------
 // k_edges: cut-edge planes X, Y, Z (Sec. 2.2): bit i of word m of sample row
 // (j,k) of plane X is set iff C(i,j,k) != C(i+1,j,k) (Y: C(i,j+1,k), Z:
@@ -630,12 +650,19 @@ __global__ __launch_bounds__(kCountBlock) void k_count_one(OneVol a, uint64_t *s
 
 // ---------------------------------------------------------------------------
 // k_generate: points, stencil CSR, quads and label pairs (Sec. 2.3 pass 4).
-// A wave takes batches of kU words.  Per batch, one vector load each brings
-// the batch's word data into lanes (cut-edge plane words, neighbour-row point
-// bits and first ids, own quad/stencil bases) and three more bring the label
-// rows needed for label pairs; the next batch's loads are in flight while the
-// current one is processed.  A word's outputs are first placed in LDS in
-// final order and then written out with consecutive-address stores.
+// A wave takes groups of kGenWords consecutive words in cell order (a group
+// may span several rows).
+//   Phase 1, one lane per word: the word's masks from the cut-edge planes
+//   (the algebra of k_count), the point bits and first point ids of the four
+//   neighbouring cell rows, all stored in LDS as two 32-cell halves, and the
+//   group's point list (word, bit) in id order, written by a per-lane loop
+//   over the word's point bits.
+//   Phase 2, one lane per point: 64 list entries per step.  A point's stencil
+//   faces, owned quads and neighbour ids follow from its word's half at its
+//   bit; the group's stencil entries and quads are contiguous and in point
+//   order, so their positions come from a wave scan of per-point counts.
+// Only cells with a point take a lane in phase 2, and each store of a step
+// covers consecutive output addresses.
 // ---------------------------------------------------------------------------
 
 template <typename T> struct Pair;
@@ -643,68 +670,242 @@ template <> struct Pair<uint8_t> { using type = uint16_t; static constexpr int s
 template <> struct Pair<uint16_t> { using type = uint32_t; static constexpr int sh = 16; };
 template <> struct Pair<uint32_t> { using type = uint64_t; static constexpr int sh = 32; };
 
-// Per-wave LDS staging of one word's outputs (worst case: 64 points, 384
-// stencil entries, 192 quads).
-struct Stage {
-    float pts[64 * 3];
-    int32_t off[64];
-    int32_t ids[384];
-    v4i quads[192];
-    uint64_t pairs[192];  // Pair<T>::type values (the first 2*sizeof(T) bytes of each slot)
-    uint8_t faces[64];
-    uint32_t cell[64];
+// One 32-cell half of a word.
+struct GenHalf {
+    uint32_t f[6];  // stencil faces -x, +x, -y, +y, -z, +z
+    uint32_t q[3];  // quads owned along x, y, z
+    uint32_t nm[5];  // point bits of the same cells in rows -y, +y, -z, +z, (-y,-z)
+    int32_t nb[5];   // id of the first point of those rows in this half
+    uint32_t pad;
+};
+struct GenWord {
+    GenHalf h[2];
+    int64_t soff;   // label index of sample (64w, j, k)
+    int32_t ci0;    // 64w
+    uint32_t cell0;  // linear index of the word's first cell (mod 2^32)
+    float py, pz;   // world y and z of the row's cell centres
+};
+constexpr int kGenList = 64 * kGenWords;  // every cell of a group may hold a point
+struct GenLds {
+    GenWord word[kGenWords];
+    uint16_t list[kGenList];  // (word << 6) | bit, in point-id order
 };
 
-// Word data of one batch in lanes.  Lane l < 48: plane word p = l >> 2 of word
-// u = l & 3, in the order of PlaneWords (x00 x10 x01 x11 y00 y00n y01 y01n
-// z00 z00n z10 z10n).  Lane l < 24: first point id and point bits of word
-// (l & 3) of cell row n = l >> 2 (own, -y, +y, -z, +z, -y-z).  Lane u < kU:
-// first quad and stencil index of own word u.
-struct GenAux {
-    uint64_t pw;
-    uint64_t pmn;
-    int32_t wbp, wbq, wbs;
-};
-
-__device__ __forceinline__ void issue_gen_aux(const VolDesc &d, const BatchPos &bp, int lane,
-                                              GenAux &A)
+__device__ __forceinline__ void wave_lds_sync()
 {
-    const Geom &g = d.g;
-    A.pw = 0, A.pmn = 0, A.wbp = 0, A.wbq = 0, A.wbs = 0;
-    {
-        const int p = lane >> 2, u = lane & 3;
-        const int32_t w = bp.w0 + u;
-        const int64_t s00 = bp.j + g.N * (int64_t)bp.k;
-        const int64_t ps = g.N * g.O * g.WS;
-        // sample row and plane of each of the twelve words
-        const int64_t srow = (p == 1 || p == 3 || p == 10 || p == 11) ? 1 : 0;
-        const int64_t srowk = (p == 2 || p == 3 || p == 6 || p == 7) ? g.N : 0;
-        const int64_t plane = p < 4 ? 0 : (p < 8 ? 1 : 2);
-        const int32_t wn = (p == 5 || p == 7 || p == 9 || p == 11) ? w + 1 : w;
-        if (lane < 48 && u < bp.nw && wn < g.WS)
-            A.pw = glb(d.planes)[plane * ps + (s00 + srow + srowk) * g.WS + wn];
-    }
-    {
-        const int n = lane >> 2, u = lane & 3;
-        const bool ym = bp.j >= 1, yp = bp.j + 1 <= g.CN - 1, zm = bp.k >= 1, zp = bp.k + 1 <= g.CO - 1;
-        bool ok = lane < 24 && u < bp.nw;
-        int64_t dr = 0;
-        if (n == 1) ok = ok && ym, dr = -1;
-        if (n == 2) ok = ok && yp, dr = 1;
-        if (n == 3) ok = ok && zm, dr = -g.CN;
-        if (n == 4) ok = ok && zp, dr = g.CN;
-        if (n == 5) ok = ok && ym && zm, dr = -g.CN - 1;
-        if (ok) {
-            const int64_t gw = (bp.r + dr) * g.W + bp.w0 + u;
-            A.wbp = glb(d.wbP)[gw];
-            A.pmn = glb(d.pmask)[gw];
+    // LDS operations of one wave complete in order; this keeps the compiler
+    // from moving LDS accesses of one phase across the other
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// One phase-2 step of a lane: its point (list entry), stencil faces, owned
+// quads, neighbour ids and the labels its quads need.
+template <typename T>
+struct GenStep {
+    int32_t act;      // the lane holds a point this step
+    int32_t R0;       // own point id
+    int32_t R[5];     // ids of the cells -y, +y, -z, +z, (-y,-z)
+    uint32_t ent;     // list entry
+    uint32_t fm, qa;  // face and quad-axis bits (0: no point)
+    uint32_t la, lx, ly, lz;  // labels at the sample and at +x, +y, +z
+};
+
+template <typename T>
+__device__ __forceinline__ void generate_front(const VolDesc &d, const GenLds &L, int32_t npg,
+                                               int32_t pbase, int32_t base, int lane, int64_t sy,
+                                               int64_t sz, GenStep<T> &x)
+{
+    const int32_t e = base + lane;
+    const bool act = e < npg;
+    x.act = act;
+    x.ent = act ? (uint32_t)L.list[e] : 0u;
+    const int u = (int)(x.ent >> 6), i = (int)(x.ent & 63u), ib = i & 31;
+    const GenWord &W = L.word[u];
+    const GenHalf &H = W.h[i >> 5];
+    uint32_t fm = 0;
+#pragma unroll
+    for (int f = 0; f < 6; ++f) fm |= ((H.f[f] >> ib) & 1u) << f;
+    const uint32_t qa =
+        ((H.q[0] >> ib) & 1u) | (((H.q[1] >> ib) & 1u) << 1) | (((H.q[2] >> ib) & 1u) << 2);
+    x.fm = act ? fm : 0u;
+    x.qa = act ? qa : 0u;
+    // loaded by every lane (a fixed number of loads per step, so waits for
+    // them need not wait for the stores issued since): the sample of a lane
+    // without a point is the first cell of the group's first word, whose +x,
+    // +y and +z samples exist
+    const SN_GLOBAL T *s0 = glb(static_cast<const T *>(d.labels)) + W.soff + (W.ci0 + i);
+    x.la = s0[0], x.lx = s0[1], x.ly = s0[sy], x.lz = s0[sz];
+    const uint32_t below = (1u << ib) - 1u;
+#pragma unroll
+    for (int n = 0; n < 5; ++n) x.R[n] = H.nb[n] + __popc(H.nm[n] & below);
+    x.R0 = pbase + e;
+}
+
+template <typename T, int MODE>
+__device__ __forceinline__ void generate_back(const VolDesc &d, const GenLds &L, const GenStep<T> &x,
+                                              int32_t sbase, int32_t qbase, int32_t &scarry,
+                                              int32_t &qcarry, int lane)
+{
+    using P = typename Pair<T>::type;
+    const int32_t ns = __popc(x.fm), nq = __popc(x.qa);
+    const int32_t inc = wave_incl_scan_dpp((ns << 16) | nq, lane);
+    const int32_t tot = __builtin_amdgcn_readlane(inc, 63);
+    const int32_t ex = inc - ((ns << 16) | nq);
+    const int32_t so = sbase + scarry + (ex >> 16);
+    int32_t q = qbase + qcarry + (ex & 0xffff);
+    scarry += tot >> 16;
+    qcarry += tot & 0xffff;
+    // the bounds hold by construction; checked so that no store can leave
+    // the mesh's arrays
+    if (!x.act || x.R0 >= d.P || so + ns > d.S || q + nq > d.Q) return;
+    const int u = (int)(x.ent >> 6), i = (int)(x.ent & 63u);
+    const GenWord &W = L.word[u];
+    const int32_t R0 = x.R0;
+    store_point(glb(d.points), R0, (float)(d.origin[0] + d.spacing[0] * ((double)(W.ci0 + i) + 0.5)),
+                W.py, W.pz);
+    glb(d.faces)[R0] = (uint8_t)x.fm;
+    glb(d.st_off)[R0] = so;
+    if (d.pcell) glb(d.pcell)[R0] = W.cell0 + (uint32_t)i;
+    SN_GLOBAL int32_t *ids = glb(d.st_ids) + so;
+    int32_t s = 0;
+    if (x.fm & 1u) ids[s++] = R0 - 1;
+    if (x.fm & 2u) ids[s++] = R0 + 1;
+    if (x.fm & 4u) ids[s++] = x.R[0];
+    if (x.fm & 8u) ids[s++] = x.R[1];
+    if (x.fm & 16u) ids[s++] = x.R[2];
+    if (x.fm & 32u) ids[s++] = x.R[3];
+    if (x.qa) {
+        SN_GLOBAL v4i *gq = glb(reinterpret_cast<v4i *>(d.quads));
+        SN_GLOBAL P *gp = glb(static_cast<P *>(d.pairs));
+        const uint32_t ca = classify<MODE>(x.la, d.cs);
+        auto pack = [](uint32_t f, uint32_t bk) { return (P)(T)f | ((P)(T)bk << Pair<T>::sh); };
+        if (x.qa & 1u) {
+            gq[q] = v4i{x.R[4], x.R[0], R0, x.R[2]};
+            gp[q] = pack(ca, classify<MODE>(x.lx, d.cs));
+            ++q;
+        }
+        if (x.qa & 2u) {
+            gq[q] = v4i{x.R[2] - 1, x.R[2], R0, R0 - 1};
+            gp[q] = pack(ca, classify<MODE>(x.ly, d.cs));
+            ++q;
+        }
+        if (x.qa & 4u) {
+            gq[q] = v4i{x.R[0] - 1, R0 - 1, R0, x.R[0]};
+            gp[q] = pack(ca, classify<MODE>(x.lz, d.cs));
         }
     }
-    if (lane < bp.nw) {
-        A.wbq = glb(d.wbQ)[bp.g0 + lane];
-        A.wbs = glb(d.wbS)[bp.g0 + lane];
-    }
 }
+
+template <typename T, int MODE>
+__device__ __forceinline__ void generate_group(const VolDesc &d, int64_t grp, int lane, GenLds &L)
+{
+    const Geom &g = d.g;
+    const int64_t gw = grp * kGenWords + lane;
+    const bool live = lane < kGenWords && gw < g.R * g.W;
+    // ---- phase 1: one lane per word
+    int32_t r = 0, w = 0, j = 0, k = 0;
+    if (live) {
+        r = (int32_t)((uint32_t)gw / (uint32_t)g.W);
+        w = (int32_t)((uint32_t)gw - (uint32_t)r * (uint32_t)g.W);
+        j = (int32_t)((uint32_t)r % (uint32_t)g.CN);
+        k = (int32_t)((uint32_t)r / (uint32_t)g.CN);
+    }
+    PlaneWords p{};
+    uint64_t nm[5] = {0, 0, 0, 0, 0};
+    int32_t nb[5] = {0, 0, 0, 0, 0};
+    int32_t own_p = 0, own_q = 0, own_s = 0;
+    if (live) {
+        p = plane_words(glb(d.planes), g.N * g.O * g.WS, g.WS, j + g.N * (int64_t)k, g.N, w);
+        const bool ex[5] = {j >= 1, j + 1 <= g.CN - 1, k >= 1, k + 1 <= g.CO - 1, j >= 1 && k >= 1};
+        const int64_t dr[5] = {-1, 1, -g.CN, g.CN, -g.CN - 1};
+#pragma unroll
+        for (int n = 0; n < 5; ++n)
+            if (ex[n]) {
+                const int64_t nw = gw + dr[n] * g.W;
+                nm[n] = glb(d.pmask)[nw];
+                nb[n] = glb(d.wbP)[nw];
+            }
+        if (lane == 0) own_p = glb(d.wbP)[gw], own_q = glb(d.wbQ)[gw], own_s = glb(d.wbS)[gw];
+    }
+    const WordMasks m = word_masks(p, w, j, k, g);  // all zero for lanes without a word
+    const int32_t np = __popcll(m.pt);
+    const int32_t npi = wave_incl_scan_dpp(np, lane);
+    const int32_t start = npi - np;
+    const int32_t npg = __builtin_amdgcn_readlane(npi, 63);
+    const int32_t pbase = __builtin_amdgcn_readlane(own_p, 0);
+    const int32_t qbase = __builtin_amdgcn_readlane(own_q, 0);
+    const int32_t sbase = __builtin_amdgcn_readlane(own_s, 0);
+    if (npg == 0) return;
+    if (lane < kGenWords) {
+        GenWord &W = L.word[lane];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            GenHalf &H = W.h[h];
+#pragma unroll
+            for (int f = 0; f < 6; ++f) H.f[f] = (uint32_t)(m.f[f] >> (32 * h));
+            H.q[0] = (uint32_t)(m.qx >> (32 * h));
+            H.q[1] = (uint32_t)(m.qy >> (32 * h));
+            H.q[2] = (uint32_t)(m.qz >> (32 * h));
+#pragma unroll
+            for (int n = 0; n < 5; ++n) {
+                H.nm[n] = (uint32_t)(nm[n] >> (32 * h));
+                H.nb[n] = nb[n] + (h ? __popc((uint32_t)nm[n]) : 0);
+            }
+        }
+        W.soff = g.M * ((int64_t)j + g.N * (int64_t)k);
+        W.ci0 = 64 * w;
+        W.cell0 = (uint32_t)(64 * w) + (uint32_t)g.CM * (uint32_t)r;
+        W.py = (float)(d.origin[1] + d.spacing[1] * ((double)j + 0.5));
+        W.pz = (float)(d.origin[2] + d.spacing[2] * ((double)k + 0.5));
+    }
+    {
+        uint64_t mm = m.pt;
+        int32_t pos = start;
+        while (mm) {
+            L.list[pos++] = (uint16_t)((lane << 6) | (int)__builtin_ctzll(mm));
+            mm &= mm - 1;
+        }
+    }
+    wave_lds_sync();
+    // ---- phase 2: one lane per point, 64 list entries per step; the LDS
+    // reads and label loads of step t+1 are issued before the stores of step t
+    const int64_t sy = g.M, sz = g.M * g.N;
+    int32_t scarry = 0, qcarry = 0;
+    GenStep<T> A, B;  // two steps in flight, alternating
+    generate_front<T>(d, L, npg, pbase, 0, lane, sy, sz, A);
+    for (int32_t base = 0; base < npg; base += 128) {
+        const bool more = base + 64 < npg;
+        if (more) generate_front<T>(d, L, npg, pbase, base + 64, lane, sy, sz, B);
+        generate_back<T, MODE>(d, L, A, sbase, qbase, scarry, qcarry, lane);
+        if (!more) break;
+        if (base + 128 < npg) generate_front<T>(d, L, npg, pbase, base + 128, lane, sy, sz, A);
+        generate_back<T, MODE>(d, L, B, sbase, qbase, scarry, qcarry, lane);
+    }
+    wave_lds_sync();
+}
+
+template <typename T, int MODE>
+__global__ __launch_bounds__(kBlock) void k_generate(const VolDesc *__restrict__ descs,
+                                                     const int64_t *__restrict__ prefix,
+                                                     int32_t nvol, int64_t tile_base, int32_t gpw)
+{
+    __shared__ GenLds lds[kWavesPerBlock];
+    const int64_t t = tile_base + blockIdx.x;
+    int v;
+    int64_t first;
+    const VolDesc &d = vol_of(ManyVols{descs, prefix, nvol}, t, v, first);
+    const int64_t ngroups = (d.g.R * d.g.W + kGenWords - 1) / kGenWords;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (threadIdx.x == 0 && t == first) glb(d.st_off)[d.P] = (int32_t)d.S;
+    const int64_t g0 = (t - first) * (kWavesPerBlock * gpw) + (int64_t)wave * gpw;
+    for (int q = 0; q < gpw && g0 + q < ngroups; ++q) generate_group<T, MODE>(d, g0 + q, lane, lds[wave]);
+}
+
+// ---------------------------------------------------------------------------
+// k_emit: points = origin + spacing * (cell centre + offset)
+// ---------------------------------------------------------------------------
 
 __device__ __forceinline__ uint64_t readlane64(uint64_t x, int l)
 {
@@ -712,219 +913,6 @@ __device__ __forceinline__ uint64_t readlane64(uint64_t x, int l)
     const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), l);
     return ((uint64_t)hi << 32) | lo;
 }
-
-// Label rows for the label pairs: samples 64(w0+u) + lane of rows (j,k),
-// (j+1,k), (j,k+1), plus (lane 63) the sample just after the batch in row (j,k).
-template <typename T>
-struct PairLoads {
-    T a[kU], b[kU], c[kU];
-    T e;
-};
-
-template <typename T>
-__device__ __forceinline__ void issue_pair_loads(const T *vol_, const Geom &g, const BatchPos &bp,
-                                                 int lane, PairLoads<T> &L)
-{
-    const SN_GLOBAL T *ra = glb(vol_) + g.M * ((int64_t)bp.j + g.N * (int64_t)bp.k);
-    const SN_GLOBAL T *rb = ra + g.M, *rc = ra + g.M * g.N;
-    const int32_t M1 = (int32_t)(g.M - 1);
-#pragma unroll
-    for (int u = 0; u < kU; ++u) {
-        const int32_t i = 64 * (bp.w0 + u) + lane;
-        const uint32_t ic = (uint32_t)(i < M1 ? i : M1);
-        L.a[u] = ra[ic], L.b[u] = rb[ic], L.c[u] = rc[ic];
-    }
-    L.e = 0;
-    if (lane == 63) L.e = ra[(uint32_t)(64 * (bp.w0 + kU) < M1 ? 64 * (bp.w0 + kU) : M1)];
-}
-
-template <typename T, int MODE, int U>
-__device__ __forceinline__ void generate_word(const VolDesc &d, const BatchPos &bp, const GenAux &A,
-                                              const PairLoads<T> &L, Stage &st, int lane)
-{
-    const int32_t w = bp.w0 + U;
-    const uint64_t own = readlane64(A.pmn, U);
-    if (own == 0) return;  // no point: no quad and no stencil face either
-    PlaneWords p;
-    p.x00 = readlane64(A.pw, 0 * 4 + U), p.x10 = readlane64(A.pw, 1 * 4 + U);
-    p.x01 = readlane64(A.pw, 2 * 4 + U), p.x11 = readlane64(A.pw, 3 * 4 + U);
-    p.y00 = readlane64(A.pw, 4 * 4 + U), p.y00n = readlane64(A.pw, 5 * 4 + U);
-    p.y01 = readlane64(A.pw, 6 * 4 + U), p.y01n = readlane64(A.pw, 7 * 4 + U);
-    p.z00 = readlane64(A.pw, 8 * 4 + U), p.z00n = readlane64(A.pw, 9 * 4 + U);
-    p.z10 = readlane64(A.pw, 10 * 4 + U), p.z10n = readlane64(A.pw, 11 * 4 + U);
-    const WordMasks m = word_masks(p, w, bp.j, bp.k, d.g);
-    const uint64_t mym = readlane64(A.pmn, 4 + U), myp = readlane64(A.pmn, 8 + U);
-    const uint64_t mzm = readlane64(A.pmn, 12 + U), mzp = readlane64(A.pmn, 16 + U);
-    const uint64_t mmm = readlane64(A.pmn, 20 + U);
-    const int32_t b0 = __builtin_amdgcn_readlane(A.wbp, U);
-    const int32_t bq = __builtin_amdgcn_readlane(A.wbq, U);
-    const int32_t bs = __builtin_amdgcn_readlane(A.wbs, U);
-    const int32_t r0 = (int32_t)rank_below(m.pt);
-    const int32_t R0 = b0 + r0;
-    const int32_t Rym = __builtin_amdgcn_readlane(A.wbp, 4 + U) + (int32_t)rank_below(mym);
-    const int32_t Ryp = __builtin_amdgcn_readlane(A.wbp, 8 + U) + (int32_t)rank_below(myp);
-    const int32_t Rzm = __builtin_amdgcn_readlane(A.wbp, 12 + U) + (int32_t)rank_below(mzm);
-    const int32_t Rzp = __builtin_amdgcn_readlane(A.wbp, 16 + U) + (int32_t)rank_below(mzp);
-    const int32_t Rmm = __builtin_amdgcn_readlane(A.wbp, 20 + U) + (int32_t)rank_below(mmm);
-    uint32_t fm = 0;
-    int32_t sp = 0, ns = 0;
-#pragma unroll
-    for (int f = 0; f < 6; ++f) {
-        fm |= lane_bit(m.f[f], lane) << f;
-        sp += (int32_t)rank_below(m.f[f]);
-        ns += __popcll(m.f[f]);
-    }
-    const int32_t np = __popcll(m.pt);
-    // --- stage in LDS, in output order
-    if (lane_bit(m.pt, lane)) {
-        const int32_t i = 64 * w + lane;
-        st.pts[3 * r0 + 0] = (float)(d.origin[0] + d.spacing[0] * ((double)i + 0.5));
-        st.pts[3 * r0 + 1] = (float)(d.origin[1] + d.spacing[1] * ((double)bp.j + 0.5));
-        st.pts[3 * r0 + 2] = (float)(d.origin[2] + d.spacing[2] * ((double)bp.k + 0.5));
-        st.faces[r0] = (uint8_t)fm;
-        st.cell[r0] = (uint32_t)i + (uint32_t)d.g.CM * (uint32_t)bp.r;
-        st.off[r0] = bs + sp;
-        int32_t e = sp;
-        if (fm & 1u) st.ids[e++] = R0 - 1;
-        if (fm & 2u) st.ids[e++] = R0 + 1;
-        if (fm & 4u) st.ids[e++] = Rym;
-        if (fm & 8u) st.ids[e++] = Ryp;
-        if (fm & 16u) st.ids[e++] = Rzm;
-        if (fm & 32u) st.ids[e++] = Rzp;
-    }
-    const uint64_t anyq = m.qx | m.qy | m.qz;
-    int32_t nq = 0;
-    if (anyq) {
-        nq = __popcll(m.qx) + __popcll(m.qy) + __popcll(m.qz);
-        using P = typename Pair<T>::type;
-        const uint32_t ca = classify<MODE>((uint32_t)L.a[U], d.cs);
-        uint32_t cn = __shfl_down(ca, 1u);
-        // computed in every lane: readlane must read a value lane 0 has produced
-        const uint32_t cnext = classify<MODE>((uint32_t)L.a[(U + 1) % kU], d.cs);
-        const uint32_t after = (U + 1 < kU) ? (uint32_t)__builtin_amdgcn_readlane((int)cnext, 0)
-                                            : classify<MODE>((uint32_t)L.e, d.cs);
-        if (lane == 63) cn = after;
-        const uint32_t cb = classify<MODE>((uint32_t)L.b[U], d.cs);
-        const uint32_t cc = classify<MODE>((uint32_t)L.c[U], d.cs);
-        int32_t q = (int32_t)(rank_below(m.qx) + rank_below(m.qy) + rank_below(m.qz));
-        P *pairs = reinterpret_cast<P *>(st.pairs);
-        auto pack = [](uint32_t f, uint32_t bk) { return (P)(T)f | ((P)(T)bk << Pair<T>::sh); };
-        if (lane_bit(m.qx, lane)) {
-            st.quads[q] = v4i{Rmm, Rym, R0, Rzm};
-            pairs[q] = pack(ca, cn);
-            ++q;
-        }
-        if (lane_bit(m.qy, lane)) {
-            st.quads[q] = v4i{Rzm - 1, Rzm, R0, R0 - 1};
-            pairs[q] = pack(ca, cb);
-            ++q;
-        }
-        if (lane_bit(m.qz, lane)) {
-            st.quads[q] = v4i{Rym - 1, R0 - 1, R0, Rym};
-            pairs[q] = pack(ca, cc);
-        }
-    }
-    // LDS operations of one wave complete in order; this only stops the
-    // compiler from moving the copies above the staging writes.
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    // --- consecutive-address copies to the output arrays
-    {
-        SN_GLOBAL float *gp = glb(d.points) + 3 * (int64_t)b0;
-        for (int32_t e = lane; e < 3 * np; e += 64) gp[e] = st.pts[e];
-        SN_GLOBAL int32_t *go = glb(d.st_off) + b0;
-        SN_GLOBAL uint8_t *gf = glb(d.faces) + b0;
-        if (lane < np) go[lane] = st.off[lane], gf[lane] = st.faces[lane];
-        if (d.pcell && lane < np) glb(d.pcell)[b0 + lane] = st.cell[lane];
-        SN_GLOBAL int32_t *gi = glb(d.st_ids) + bs;
-        for (int32_t e = lane; e < ns; e += 64) gi[e] = st.ids[e];
-    }
-    if (nq) {
-        using P = typename Pair<T>::type;
-        SN_GLOBAL v4i *gq = glb(reinterpret_cast<v4i *>(d.quads)) + bq;
-        SN_GLOBAL P *gpp = glb(static_cast<P *>(d.pairs)) + bq;
-        const P *pairs = reinterpret_cast<const P *>(st.pairs);
-        for (int32_t e = lane; e < nq; e += 64) gq[e] = st.quads[e], gpp[e] = pairs[e];
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-template <typename T, int MODE>
-__device__ __forceinline__ void generate_process(const VolDesc &d, const BatchPos &bp,
-                                                 const GenAux &A, const PairLoads<T> &L, Stage &st,
-                                                 int lane)
-{
-    static_assert(kU == 4, "generate_process unrolls four words");
-    __builtin_amdgcn_sched_barrier(0);
-    generate_word<T, MODE, 0>(d, bp, A, L, st, lane);
-    if (bp.nw > 1) {
-        __builtin_amdgcn_sched_barrier(0);
-        generate_word<T, MODE, 1>(d, bp, A, L, st, lane);
-    }
-    if (bp.nw > 2) {
-        __builtin_amdgcn_sched_barrier(0);
-        generate_word<T, MODE, 2>(d, bp, A, L, st, lane);
-    }
-    if (bp.nw > 3) {
-        __builtin_amdgcn_sched_barrier(0);
-        generate_word<T, MODE, 3>(d, bp, A, L, st, lane);
-    }
-}
-
-// nb consecutive batches from b0, two in flight.
-template <typename T, int MODE>
-__device__ __forceinline__ void generate_stream(const VolDesc &d, int64_t b0, int nb, int lane, Stage &st)
-{
-    const T *vol = static_cast<const T *>(d.labels);
-    PairLoads<T> L0, L1;
-    GenAux A0, A1;
-    BatchPos P0 = batch_pos(d.g, b0), P1;
-    issue_gen_aux(d, P0, lane, A0);
-    issue_pair_loads<T>(vol, d.g, P0, lane, L0);
-    for (int q = 0; q < nb; q += 2) {
-        if (q + 1 < nb) {
-            P1 = P0;
-            batch_next(d.g, P1);
-            issue_gen_aux(d, P1, lane, A1);
-            issue_pair_loads<T>(vol, d.g, P1, lane, L1);
-        }
-        generate_process<T, MODE>(d, P0, A0, L0, st, lane);
-        if (q + 1 >= nb) break;
-        if (q + 2 < nb) {
-            P0 = P1;
-            batch_next(d.g, P0);
-            issue_gen_aux(d, P0, lane, A0);
-            issue_pair_loads<T>(vol, d.g, P0, lane, L0);
-        }
-        generate_process<T, MODE>(d, P1, A1, L1, st, lane);
-    }
-}
-
-template <typename T, int MODE>
-__global__ __launch_bounds__(kBlock) void k_generate(const VolDesc *__restrict__ descs,
-                                                     const int64_t *__restrict__ prefix,
-                                                     int32_t nvol, int64_t tile_base, int32_t bpw)
-{
-    __shared__ Stage stage[kWavesPerBlock];
-    const int64_t t = tile_base + blockIdx.x;
-    int v;
-    int64_t first;
-    const VolDesc &d = vol_of(ManyVols{descs, prefix, nvol}, t, v, first);
-    const int64_t nbv = d.g.R * d.g.NB;
-    const int64_t bt0 = (t - first) * (kWavesPerBlock * bpw);
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
-    if (threadIdx.x == 0 && t == first) glb(d.st_off)[d.P] = (int32_t)d.S;
-    const int64_t b0 = bt0 + (int64_t)wave * bpw;
-    const int64_t nb = nbv - b0 < bpw ? nbv - b0 : bpw;
-    if (nb > 0) generate_stream<T, MODE>(d, b0, (int)nb, lane, stage[wave]);
-}
-
-// ---------------------------------------------------------------------------
-// k_emit: points = origin + spacing * (cell centre + offset)
-// ---------------------------------------------------------------------------
 
 // Own-word data of one batch in lanes u < kU: point bits and first point id.
 struct EmitAux {

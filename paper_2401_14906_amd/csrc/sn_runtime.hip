@@ -770,8 +770,9 @@ sn_status sn::extract_many(sn_ctx *c, const sn_volume *vols, int32_t n, hipStrea
         const int64_t nbatch = d.g.R * d.g.NB;
         // every volume has at least one generation tile: its first tile writes
         // st_off[P] = S (st_off[0] = 0 for an empty mesh)
-        m->ntiles = std::max<int64_t>(1, (nbatch + TB - 1) / TB);
-        tile_prefix[k + 1] = tile_prefix[k] + m->ntiles;
+        m->ntiles = std::max<int64_t>(1, (nbatch + TB - 1) / TB);  // k_emit
+        const int64_t ngroups = (words + kGenWords - 1) / kGenWords;
+        tile_prefix[k + 1] = tile_prefix[k] + std::max<int64_t>(1, (ngroups + TB - 1) / TB);
         const int64_t nseg = d.g.N * d.g.O * d.g.NSEG;
         etile_prefix[k + 1] = etile_prefix[k] + (nseg + kSegmentsPerTile - 1) / kSegmentsPerTile;
         ctile_prefix[k + 1] = words;  // words for now; tiles below
