@@ -372,9 +372,10 @@ def pmc_summary(pmc_dir, out_path, workload):
                 key = name.split("(")[0].split("<")[0].replace("void ", "").replace("sn::", "")
                 key = key.strip()
                 # one entry per kernel as the library's timing names it: the
-                # single-volume forms (_one), the first sweep (k_jacobi_first)
-                # and the row-width forms of k_edges count with their kernel
-                for suf in ("_one", "_wide", "_narrow"):
+                # single-volume forms (_one), the first sweep (k_jacobi_first),
+                # the row-width forms of k_edges and the store forms of
+                # k_generate count with their kernel
+                for suf in ("_one", "_wide", "_narrow", "_staged"):
                     key = key.replace(suf, "")
                 if key.startswith("k_jacobi"):
                     key = "k_jacobi"

@@ -39,6 +39,7 @@ constexpr int kSegmentsPerTile = 16;  // k_edges: 4 waves x 4 segments of 256 sa
 // k_generate: a wave takes groups of kGenWords consecutive words (any rows),
 // bpw groups per wave
 constexpr int kGenWords = 32;
+constexpr int64_t kGenStagedPointsPerWord = 8;
 // k_count: 1024 threads per workgroup, one or kCountWideV words per thread
 // (the wide form for launches of at least kCountWideWords words: fewer scan
 // tiles, and fewer of the ordered tile tickets every workgroup takes)
@@ -163,7 +164,9 @@ hipError_t launch_edges(int32_t dtype, int32_t mode, bool wide, const VolDesc *d
 hipError_t launch_count(const VolDesc *d_descs, const int64_t *d_tile_prefix, int32_t nvol,
                         int64_t ntiles, int32_t words_per_thread, uint64_t *d_status,
                         uint32_t *d_ticket, int64_t *d_totals, hipStream_t s);
-hipError_t launch_generate(int32_t dtype, int32_t mode, const VolDesc *d_descs,
+// staged: stencil ids, quads and pairs go through LDS (for meshes with at
+// least kGenStagedPointsPerWord points per word on average)
+hipError_t launch_generate(int32_t dtype, int32_t mode, bool staged, const VolDesc *d_descs,
                            const int64_t *d_tile_prefix, int32_t nvol, int64_t tile_base,
                            int64_t ntiles, int32_t bpw, hipStream_t s);
 // k_emit: d_sds[v] (iterations, ping-pong buffers) names volume v's final offsets

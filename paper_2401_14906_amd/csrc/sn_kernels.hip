@@ -686,9 +686,17 @@ struct GenWord {
     float py, pz;   // world y and z of the row's cell centres
 };
 constexpr int kGenList = 64 * kGenWords;  // every cell of a group may hold a point
-struct GenLds {
+struct GenLdsBase {
     GenWord word[kGenWords];
     uint16_t list[kGenList];  // (word << 6) | bit, in point-id order
+};
+template <bool STAGE>
+struct GenLds : GenLdsBase {};
+// The staged form: one step's stencil ids (<= 6 per point), then its quads
+// (<= 3 per point, 16 bytes), then its label pairs, in output order.
+template <>
+struct GenLds<true> : GenLdsBase {
+    alignas(16) uint32_t stage[64 * 3 * 4];
 };
 
 __device__ __forceinline__ void wave_lds_sync()
@@ -713,7 +721,7 @@ struct GenStep {
 };
 
 template <typename T>
-__device__ __forceinline__ void generate_front(const VolDesc &d, const GenLds &L, int32_t npg,
+__device__ __forceinline__ void generate_front(const VolDesc &d, const GenLdsBase &L, int32_t npg,
                                                int32_t pbase, int32_t base, int lane, int64_t sy,
                                                int64_t sz, GenStep<T> &x)
 {
@@ -743,8 +751,31 @@ __device__ __forceinline__ void generate_front(const VolDesc &d, const GenLds &L
     x.R0 = pbase + e;
 }
 
-template <typename T, int MODE>
-__device__ __forceinline__ void generate_back(const VolDesc &d, const GenLds &L, const GenStep<T> &x,
+// Copy n staged 4*V-byte elements to consecutive output addresses.
+template <int V>
+__device__ __forceinline__ void copy_staged(SN_GLOBAL uint32_t *out, const uint32_t *st, int32_t n,
+                                            int lane)
+{
+    for (int32_t t = lane; t < n; t += 64) {
+        if constexpr (V == 1) {
+            out[t] = st[t];
+        } else if constexpr (V == 2) {
+            reinterpret_cast<SN_GLOBAL v2u *>(out)[t] = reinterpret_cast<const v2u *>(st)[t];
+        } else {
+            reinterpret_cast<SN_GLOBAL v4u *>(out)[t] = reinterpret_cast<const v4u *>(st)[t];
+        }
+    }
+}
+
+// Stores of one step.  Stencil ids, quads and label pairs are several per
+// lane, so each store instruction for them covers the step's output range
+// sparsely.  The staged form places them in LDS in output order first and
+// copies them out with consecutive-address stores: one memory request per
+// touched 64-byte line instead of one per instruction and line, which is what
+// bounds meshes with many points per word.  The direct form saves the LDS
+// round trip where steps are few.
+template <typename T, int MODE, bool STAGE>
+__device__ __forceinline__ void generate_back(const VolDesc &d, GenLds<STAGE> &L, const GenStep<T> &x,
                                               int32_t sbase, int32_t qbase, int32_t &scarry,
                                               int32_t &qcarry, int lane)
 {
@@ -753,53 +784,82 @@ __device__ __forceinline__ void generate_back(const VolDesc &d, const GenLds &L,
     const int32_t inc = wave_incl_scan_dpp((ns << 16) | nq, lane);
     const int32_t tot = __builtin_amdgcn_readlane(inc, 63);
     const int32_t ex = inc - ((ns << 16) | nq);
-    const int32_t so = sbase + scarry + (ex >> 16);
-    int32_t q = qbase + qcarry + (ex & 0xffff);
-    scarry += tot >> 16;
-    qcarry += tot & 0xffff;
+    const int32_t so0 = sbase + scarry, qo0 = qbase + qcarry;  // first entry / quad of the step
+    const int32_t nst = tot >> 16, nqt = tot & 0xffff;
+    scarry += nst;
+    qcarry += nqt;
     // the bounds hold by construction; checked so that no store can leave
     // the mesh's arrays
-    if (!x.act || x.R0 >= d.P || so + ns > d.S || q + nq > d.Q) return;
-    const int u = (int)(x.ent >> 6), i = (int)(x.ent & 63u);
-    const GenWord &W = L.word[u];
-    const int32_t R0 = x.R0;
-    store_point(glb(d.points), R0, (float)(d.origin[0] + d.spacing[0] * ((double)(W.ci0 + i) + 0.5)),
-                W.py, W.pz);
-    glb(d.faces)[R0] = (uint8_t)x.fm;
-    glb(d.st_off)[R0] = so;
-    if (d.pcell) glb(d.pcell)[R0] = W.cell0 + (uint32_t)i;
-    SN_GLOBAL int32_t *ids = glb(d.st_ids) + so;
-    int32_t s = 0;
-    if (x.fm & 1u) ids[s++] = R0 - 1;
-    if (x.fm & 2u) ids[s++] = R0 + 1;
-    if (x.fm & 4u) ids[s++] = x.R[0];
-    if (x.fm & 8u) ids[s++] = x.R[1];
-    if (x.fm & 16u) ids[s++] = x.R[2];
-    if (x.fm & 32u) ids[s++] = x.R[3];
-    if (x.qa) {
-        SN_GLOBAL v4i *gq = glb(reinterpret_cast<v4i *>(d.quads));
-        SN_GLOBAL P *gp = glb(static_cast<P *>(d.pairs));
+    const bool fits = so0 + nst <= d.S && qo0 + nqt <= d.Q;
+    const bool act = x.act && x.R0 < d.P && fits;
+    const int32_t R0 = x.R0, sr = ex >> 16, qr = ex & 0xffff;  // positions within the step
+    const auto pack = [](uint32_t f, uint32_t bk) { return (P)(T)f | ((P)(T)bk << Pair<T>::sh); };
+    if (act) {
+        const int u = (int)(x.ent >> 6), i = (int)(x.ent & 63u);
+        const GenWord &W = L.word[u];
+        store_point(glb(d.points), R0,
+                    (float)(d.origin[0] + d.spacing[0] * ((double)(W.ci0 + i) + 0.5)), W.py, W.pz);
+        glb(d.faces)[R0] = (uint8_t)x.fm;
+        glb(d.st_off)[R0] = so0 + sr;
+        if (d.pcell) glb(d.pcell)[R0] = W.cell0 + (uint32_t)i;
+    }
+    // ids in face order -x, +x, -y, +y, -z, +z; a point's quads along x, y, z
+    auto put_ids = [&](auto *ids) {
+        int32_t s = 0;
+        if (x.fm & 1u) ids[s++] = R0 - 1;
+        if (x.fm & 2u) ids[s++] = R0 + 1;
+        if (x.fm & 4u) ids[s++] = x.R[0];
+        if (x.fm & 8u) ids[s++] = x.R[1];
+        if (x.fm & 16u) ids[s++] = x.R[2];
+        if (x.fm & 32u) ids[s++] = x.R[3];
+    };
+    auto put_quads = [&](auto *qs) {
+        int32_t k = 0;
+        if (x.qa & 1u) qs[k++] = v4i{x.R[4], x.R[0], R0, x.R[2]};
+        if (x.qa & 2u) qs[k++] = v4i{x.R[2] - 1, x.R[2], R0, R0 - 1};
+        if (x.qa & 4u) qs[k] = v4i{x.R[0] - 1, R0 - 1, R0, x.R[0]};
+    };
+    auto put_pairs = [&](auto *ps) {
         const uint32_t ca = classify<MODE>(x.la, d.cs);
-        auto pack = [](uint32_t f, uint32_t bk) { return (P)(T)f | ((P)(T)bk << Pair<T>::sh); };
-        if (x.qa & 1u) {
-            gq[q] = v4i{x.R[4], x.R[0], R0, x.R[2]};
-            gp[q] = pack(ca, classify<MODE>(x.lx, d.cs));
-            ++q;
+        int32_t k = 0;
+        if (x.qa & 1u) ps[k++] = pack(ca, classify<MODE>(x.lx, d.cs));
+        if (x.qa & 2u) ps[k++] = pack(ca, classify<MODE>(x.ly, d.cs));
+        if (x.qa & 4u) ps[k] = pack(ca, classify<MODE>(x.lz, d.cs));
+    };
+    if constexpr (!STAGE) {
+        if (act) {
+            put_ids(glb(d.st_ids) + so0 + sr);
+            if (x.qa) {
+                put_quads(glb(reinterpret_cast<v4i *>(d.quads)) + qo0 + qr);
+                put_pairs(glb(static_cast<P *>(d.pairs)) + qo0 + qr);
+            }
         }
-        if (x.qa & 2u) {
-            gq[q] = v4i{x.R[2] - 1, x.R[2], R0, R0 - 1};
-            gp[q] = pack(ca, classify<MODE>(x.ly, d.cs));
-            ++q;
+    } else {
+        if (act) put_ids(reinterpret_cast<int32_t *>(L.stage) + sr);
+        wave_lds_sync();
+        if (fits)
+            copy_staged<1>(reinterpret_cast<SN_GLOBAL uint32_t *>(glb(d.st_ids) + so0), L.stage, nst, lane);
+        wave_lds_sync();
+        if (nqt == 0) return;
+        if (act && x.qa) put_quads(reinterpret_cast<v4i *>(L.stage) + qr);
+        wave_lds_sync();
+        if (fits)
+            copy_staged<4>(reinterpret_cast<SN_GLOBAL uint32_t *>(glb(d.quads) + 4 * (int64_t)qo0),
+                           L.stage, nqt, lane);
+        wave_lds_sync();
+        if (act && x.qa) put_pairs(reinterpret_cast<P *>(L.stage) + qr);
+        wave_lds_sync();
+        if (fits) {
+            SN_GLOBAL P *gp = glb(static_cast<P *>(d.pairs)) + qo0;
+            const P *sp = reinterpret_cast<const P *>(L.stage);
+            for (int32_t t = lane; t < nqt; t += 64) gp[t] = sp[t];
         }
-        if (x.qa & 4u) {
-            gq[q] = v4i{x.R[0] - 1, R0 - 1, R0, x.R[0]};
-            gp[q] = pack(ca, classify<MODE>(x.lz, d.cs));
-        }
+        wave_lds_sync();
     }
 }
 
-template <typename T, int MODE>
-__device__ __forceinline__ void generate_group(const VolDesc &d, int64_t grp, int lane, GenLds &L)
+template <typename T, int MODE, bool STAGE>
+__device__ __forceinline__ void generate_group(const VolDesc &d, int64_t grp, int lane, GenLds<STAGE> &L)
 {
     const Geom &g = d.g;
     const int64_t gw = grp * kGenWords + lane;
@@ -878,20 +938,19 @@ __device__ __forceinline__ void generate_group(const VolDesc &d, int64_t grp, in
     for (int32_t base = 0; base < npg; base += 128) {
         const bool more = base + 64 < npg;
         if (more) generate_front<T>(d, L, npg, pbase, base + 64, lane, sy, sz, B);
-        generate_back<T, MODE>(d, L, A, sbase, qbase, scarry, qcarry, lane);
+        generate_back<T, MODE, STAGE>(d, L, A, sbase, qbase, scarry, qcarry, lane);
         if (!more) break;
         if (base + 128 < npg) generate_front<T>(d, L, npg, pbase, base + 128, lane, sy, sz, A);
-        generate_back<T, MODE>(d, L, B, sbase, qbase, scarry, qcarry, lane);
+        generate_back<T, MODE, STAGE>(d, L, B, sbase, qbase, scarry, qcarry, lane);
     }
     wave_lds_sync();
 }
 
-template <typename T, int MODE>
-__global__ __launch_bounds__(kBlock) void k_generate(const VolDesc *__restrict__ descs,
-                                                     const int64_t *__restrict__ prefix,
-                                                     int32_t nvol, int64_t tile_base, int32_t gpw)
+template <typename T, int MODE, bool STAGE>
+__device__ __forceinline__ void generate_body(const VolDesc *descs, const int64_t *prefix, int32_t nvol,
+                                              int64_t tile_base, int32_t gpw)
 {
-    __shared__ GenLds lds[kWavesPerBlock];
+    __shared__ GenLds<STAGE> lds[kWavesPerBlock];
     const int64_t t = tile_base + blockIdx.x;
     int v;
     int64_t first;
@@ -900,7 +959,25 @@ __global__ __launch_bounds__(kBlock) void k_generate(const VolDesc *__restrict__
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     if (threadIdx.x == 0 && t == first) glb(d.st_off)[d.P] = (int32_t)d.S;
     const int64_t g0 = (t - first) * (kWavesPerBlock * gpw) + (int64_t)wave * gpw;
-    for (int q = 0; q < gpw && g0 + q < ngroups; ++q) generate_group<T, MODE>(d, g0 + q, lane, lds[wave]);
+    for (int q = 0; q < gpw && g0 + q < ngroups; ++q)
+        generate_group<T, MODE, STAGE>(d, g0 + q, lane, lds[wave]);
+}
+
+template <typename T, int MODE>
+__global__ __launch_bounds__(kBlock) void k_generate(const VolDesc *__restrict__ descs,
+                                                     const int64_t *__restrict__ prefix,
+                                                     int32_t nvol, int64_t tile_base, int32_t gpw)
+{
+    generate_body<T, MODE, false>(descs, prefix, nvol, tile_base, gpw);
+}
+
+template <typename T, int MODE>
+__global__ __launch_bounds__(kBlock) void k_generate_staged(const VolDesc *__restrict__ descs,
+                                                            const int64_t *__restrict__ prefix,
+                                                            int32_t nvol, int64_t tile_base,
+                                                            int32_t gpw)
+{
+    generate_body<T, MODE, true>(descs, prefix, nvol, tile_base, gpw);
 }
 
 // ---------------------------------------------------------------------------
@@ -1404,13 +1481,18 @@ hipError_t launch_count_one(const VolDesc &d, int64_t ntiles, int32_t words_per_
     return hipGetLastError();
 }
 
-hipError_t launch_generate(int32_t dtype, int32_t mode, const VolDesc *d_descs,
+hipError_t launch_generate(int32_t dtype, int32_t mode, bool staged, const VolDesc *d_descs,
                            const int64_t *d_tile_prefix, int32_t nvol, int64_t tile_base,
                            int64_t ntiles, int32_t bpw, hipStream_t s)
 {
     if (ntiles <= 0) return hipSuccess;
-    SN_KEY_SWITCH(k_generate, dim3((uint32_t)ntiles), dim3(kBlock), 0, s, d_descs, d_tile_prefix,
-                  nvol, tile_base, bpw)
+    if (staged) {
+        SN_KEY_SWITCH(k_generate_staged, dim3((uint32_t)ntiles), dim3(kBlock), 0, s, d_descs,
+                      d_tile_prefix, nvol, tile_base, bpw)
+    } else {
+        SN_KEY_SWITCH(k_generate, dim3((uint32_t)ntiles), dim3(kBlock), 0, s, d_descs, d_tile_prefix,
+                      nvol, tile_base, bpw)
+    }
     return hipGetLastError();
 }
 

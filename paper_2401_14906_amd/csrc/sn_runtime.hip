@@ -889,7 +889,8 @@ sn_status sn::extract_many(sn_ctx *c, const sn_volume *vols, int32_t n, hipStrea
         HIP_TRY(hipMemcpyAsync(d_b, h_b, sizeof(VolDesc) + sizeof tp1, hipMemcpyHostToDevice, s));
         {
             ProfScope ps(c, "k_generate", s);
-            HIP_TRY(launch_generate(hd[0].dtype, hd[0].cs.mode, reinterpret_cast<VolDesc *>(d_b),
+            const bool staged = hd[0].P >= kGenStagedPointsPerWord * hd[0].g.R * hd[0].g.W;
+            HIP_TRY(launch_generate(hd[0].dtype, hd[0].cs.mode, staged, reinterpret_cast<VolDesc *>(d_b),
                                     reinterpret_cast<int64_t *>(d_b + sizeof(VolDesc)), 1, 0,
                                     tile_prefix[1], bpw, s));
         }
@@ -918,7 +919,10 @@ sn_status sn::extract_many(sn_ctx *c, const sn_volume *vols, int32_t n, hipStrea
             ProfScope ps(c, "k_generate", s);
             for (int32_t gi = 0; gi < ngroups; ++gi) {
                 const int32_t k0 = gbeg[gi], k1 = gbeg[gi + 1];
-                HIP_TRY(launch_generate(hd[k0].dtype, hd[k0].cs.mode, d_desc2 + k0, d_tp + k0, k1 - k0,
+                int64_t gp = 0, gw = 0;
+                for (int32_t k = k0; k < k1; ++k) gp += hd[k].P, gw += hd[k].g.R * hd[k].g.W;
+                const bool staged = gp >= kGenStagedPointsPerWord * gw;
+                HIP_TRY(launch_generate(hd[k0].dtype, hd[k0].cs.mode, staged, d_desc2 + k0, d_tp + k0, k1 - k0,
                                         tile_prefix[k0], tile_prefix[k1] - tile_prefix[k0], bpw, s));
             }
         }
