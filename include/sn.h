@@ -223,11 +223,12 @@ sn_status sn_autotune(sn_ctx *ctx, const sn_volume *vol, void *stream, int32_t *
 sn_status sn_set_batches_per_wave(sn_ctx *ctx, int32_t batches_per_wave);
 
 /* Per-kernel timing: with on = 1 every library kernel launch is bracketed by
- * HIP events on the stream it runs on, and a replay of the sweep
- * graph is bracketed as a whole (counted as `iterations` launches of
- * k_jacobi); with on = 2 the sweeps are launched one by one instead, each with
- * its own events.  on = 0 turns timing off.  sn_profile_read synchronises,
- * folds the events into per-kernel totals and fills up to `cap` records. */
+ * HIP events on the stream it runs on, and the sweeps of one smoothing call
+ * (a mesh's run of launches, or a batch's sweep graph) are bracketed as a
+ * whole (counted as `iterations` launches of k_jacobi); with on = 2 every
+ * sweep is launched with its own events.  on = 0 turns timing off.
+ * sn_profile_read synchronises, folds the events into per-kernel totals and
+ * fills up to `cap` records. */
 typedef struct sn_kernel_stat {
     char name[48];
     int64_t launches;

@@ -191,11 +191,6 @@ hipError_t launch_count_one(const VolDesc &d, int64_t ntiles, int32_t words_per_
 hipError_t launch_emit_one(const VolDesc &d, const SmoothDesc &sd, int64_t ntiles, int32_t bpw,
                            hipStream_t s);
 hipError_t launch_jacobi_one(const SmoothDesc &sd, int64_t nblocks, int32_t it, int K, hipStream_t s);
-hipError_t add_jacobi_nodes_one(hipGraph_t graph, const SmoothDesc &sd, int64_t nblocks,
-                                int32_t iters, int K, std::vector<hipGraphNode_t> *nodes);
-// new descriptor for the nodes of an instantiated graph made by add_jacobi_nodes_one
-hipError_t set_jacobi_nodes_one(hipGraphExec_t exec, const std::vector<hipGraphNode_t> &nodes,
-                                const SmoothDesc &sd, int64_t nblocks, int K);
 hipError_t launch_triangulate_one(const VolDesc &d, hipStream_t s);
 // quad blocks (256 quads per block) of the volumes with prim 3
 hipError_t launch_triangulate(const VolDesc *d_descs, const int64_t *d_block_prefix, int32_t nvol,

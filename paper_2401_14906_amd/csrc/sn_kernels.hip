@@ -1586,60 +1586,6 @@ hipError_t add_jacobi_nodes(hipGraph_t graph, const SmoothDesc *d_sd,
     return hipSuccess;
 }
 
-// Node parameters of sweep `it` of one mesh; `arg` and `itv` must outlive the
-// API call that consumes the parameters.
-static void sweep_params_one(OneSmooth &arg, int32_t &itv, void **args, int64_t nblocks, int K,
-                             hipKernelNodeParams &kp)
-{
-    args[0] = &arg;
-    args[1] = &itv;
-    kp = hipKernelNodeParams{};
-    kp.func = itv == 0 ? (K == 1 ? reinterpret_cast<void *>(&k_jacobi_first_one<1>)
-                                 : reinterpret_cast<void *>(&k_jacobi_first_one<2>))
-                       : (K == 1 ? reinterpret_cast<void *>(&k_jacobi_one<1>)
-                                 : reinterpret_cast<void *>(&k_jacobi_one<2>));
-    kp.gridDim = dim3((uint32_t)nblocks);
-    kp.blockDim = dim3(256);
-    kp.sharedMemBytes = 0;
-    kp.kernelParams = args;
-    kp.extra = nullptr;
-}
-
-hipError_t add_jacobi_nodes_one(hipGraph_t graph, const SmoothDesc &sd, int64_t nblocks,
-                                int32_t iters, int K, std::vector<hipGraphNode_t> *nodes)
-{
-    OneSmooth arg{sd};
-    hipGraphNode_t prev = nullptr;
-    nodes->clear();
-    for (int32_t it = 0; it < iters && nblocks > 0; ++it) {
-        void *args[2];
-        hipKernelNodeParams kp;
-        int32_t itv = it;
-        sweep_params_one(arg, itv, args, nblocks, K, kp);
-        hipGraphNode_t node;
-        const hipError_t e =
-            hipGraphAddKernelNode(&node, graph, prev ? &prev : nullptr, prev ? 1 : 0, &kp);
-        if (e != hipSuccess) return e;
-        nodes->push_back(node);
-        prev = node;
-    }
-    return hipSuccess;
-}
-
-hipError_t set_jacobi_nodes_one(hipGraphExec_t exec, const std::vector<hipGraphNode_t> &nodes,
-                                const SmoothDesc &sd, int64_t nblocks, int K)
-{
-    OneSmooth arg{sd};
-    for (size_t it = 0; it < nodes.size(); ++it) {
-        void *args[2];
-        hipKernelNodeParams kp;
-        int32_t itv = (int32_t)it;
-        sweep_params_one(arg, itv, args, nblocks, K, kp);
-        const hipError_t e = hipGraphExecKernelNodeSetParams(exec, nodes[it], &kp);
-        if (e != hipSuccess) return e;
-    }
-    return hipSuccess;
-}
 
 hipError_t launch_triangulate(const VolDesc *d_descs, const int64_t *d_block_prefix, int32_t nvol,
                               int64_t nblocks, hipStream_t s)

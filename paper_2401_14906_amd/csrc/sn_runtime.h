@@ -82,24 +82,10 @@ struct sn_ctx {
     // Freed meshes: the retire stream waits for each mesh's completion event
     // and their pool blocks are released behind an event recorded on it.
     hipStream_t retire_stream = nullptr;
-    // Sweep graphs of single meshes by (iterations, bucketed block count,
-    // chunks per wave).
-    // The smoothing descriptor is a kernel-node argument; a new mesh of a
-    // similar size reuses an instantiated graph by rewriting those arguments
-    // once the graph's previous launch has completed.
-    struct SweepGraph {
-        hipGraph_t graph = nullptr;
-        hipGraphExec_t exec = nullptr;
-        std::vector<hipGraphNode_t> nodes;
-        sn::SmoothDesc args{};
-        hipEvent_t last = nullptr;  // after the last launch of the graph
-    };
-    std::mutex sweep_mu;
-    std::map<std::tuple<int32_t, int64_t, int>, SweepGraph> sweep_graphs;  // (iters, blocks, K)
     sn::EventCache timing_events{hipEventDefault};
     // profiling
     bool profiling = false;
-    bool profile_eager = false;  // sweeps launched one by one instead of a graph
+    bool profile_eager = false;  // every sweep bracketed by its own events
     struct ProfEv {
         std::string name;
         hipEvent_t a, b;

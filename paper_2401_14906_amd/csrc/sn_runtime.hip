@@ -271,13 +271,6 @@ void sn::ctx_release(sn_ctx *c)
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->copy_stream);
     (void)hipStreamSynchronize(c->retire_stream);
-    for (auto &kv : c->sweep_graphs) {
-        (void)hipEventSynchronize(kv.second.last);
-        (void)hipEventDestroy(kv.second.last);
-        (void)hipGraphExecDestroy(kv.second.exec);
-        (void)hipGraphDestroy(kv.second.graph);
-    }
-    c->sweep_graphs.clear();
     (void)hipStreamDestroy(c->copy_stream);
     (void)hipStreamDestroy(c->retire_stream);
     delete c;
@@ -1020,16 +1013,9 @@ sn_status sn::run_sweeps(sn_ctx *c, const SmoothDesc *d_sd, const int64_t *d_bp,
     return SN_OK;
 }
 
-// Launch-grid size of a cached sweep graph: the block count rounded up to
-// three significant bits (at most 1/8 of the blocks find no points and exit).
-static int64_t sweep_bucket(int64_t n)
-{
-    if (n <= 8) return n;
-    const int sh = 63 - __builtin_clzll((uint64_t)n) - 2;
-    return ((n + (int64_t(1) << sh) - 1) >> sh) << sh;
-}
-
-// n sweeps of one mesh from the context's cache of sweep graphs
+// n sweeps of one mesh, launched one by one: a single mesh's sweeps are
+// launched from the calling thread (a graph launch holds that thread until
+// the replay has nearly finished, so the next call's work would start late)
 sn_status sn::run_sweeps_one(sn_ctx *c, const SmoothDesc &sd, int64_t nblocks, int K, hipStream_t s)
 {
     const int32_t iters = sd.iters;
@@ -1041,49 +1027,9 @@ sn_status sn::run_sweeps_one(sn_ctx *c, const SmoothDesc &sd, int64_t nblocks, i
         }
         return SN_OK;
     }
-    const int64_t nb = sweep_bucket(nblocks);
-    std::lock_guard<std::mutex> g(c->sweep_mu);
-    auto key = std::make_tuple(iters, nb, K);
-    auto it = c->sweep_graphs.find(key);
-    if (it == c->sweep_graphs.end()) {
-        if (c->sweep_graphs.size() >= 32) {
-            // drop one cached graph once its last launch has completed
-            auto victim = c->sweep_graphs.begin();
-            (void)hipEventSynchronize(victim->second.last);
-            (void)hipEventDestroy(victim->second.last);
-            (void)hipGraphExecDestroy(victim->second.exec);
-            (void)hipGraphDestroy(victim->second.graph);
-            c->sweep_graphs.erase(victim);
-        }
-        sn_ctx::SweepGraph sg;
-        hipError_t e = hipGraphCreate(&sg.graph, 0);
-        if (e == hipSuccess) e = add_jacobi_nodes_one(sg.graph, sd, nb, iters, K, &sg.nodes);
-        if (e == hipSuccess) e = hipGraphInstantiate(&sg.exec, sg.graph, nullptr, nullptr, 0);
-        if (e == hipSuccess) e = hipEventCreateWithFlags(&sg.last, hipEventDisableTiming);
-        if (e != hipSuccess) {
-            if (sg.exec) (void)hipGraphExecDestroy(sg.exec);
-            if (sg.graph) (void)hipGraphDestroy(sg.graph);
-            return fail(SN_EDEVICE, std::string("smooth: sweep graph: ") + hipGetErrorString(e));
-        }
-        sg.args = sd;
-        it = c->sweep_graphs.emplace(key, std::move(sg)).first;
-    }
-    sn_ctx::SweepGraph &sg = it->second;
-    if (std::memcmp(&sg.args, &sd, sizeof(SmoothDesc)) != 0) {
-        // arguments of a launch still pending must not change under it
-        hipError_t e = hipEventSynchronize(sg.last);
-        if (e == hipSuccess) e = set_jacobi_nodes_one(sg.exec, sg.nodes, sd, nb, K);
-        if (e != hipSuccess) return fail(SN_EDEVICE, std::string("smooth: graph update: ") + hipGetErrorString(e));
-        sg.args = sd;
-    }
-    hipError_t e;
-    {
-        // one event pair around the whole graph replay: `iters` launches
-        ProfScope ps(c, "k_jacobi", s, iters);
-        e = hipGraphLaunch(sg.exec, s);
-    }
-    if (e == hipSuccess) e = hipEventRecord(sg.last, s);
-    if (e != hipSuccess) return fail(SN_EDEVICE, std::string("smooth: graph launch: ") + hipGetErrorString(e));
+    // one event pair around the `iters` launches
+    ProfScope ps(c, "k_jacobi", s, iters);
+    for (int32_t it = 0; it < iters; ++it) HIP_TRY(launch_jacobi_one(sd, nblocks, it, K, s));
     return SN_OK;
 }
 

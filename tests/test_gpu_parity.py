@@ -201,27 +201,35 @@ def test_resmooth_restarts_from_cache(ctx, sn, torch):
 
 
 def test_graph_replays_match_eager(ctx, sn, torch):
-    """The sweep graph, replayed many times with other device work and
-    synchronisations in between, gives the eager (profiled, one launch per sweep) result
-    every time."""
+    """Batches smooth through a HIP graph of sweep kernels; repeated with other
+    device work and synchronisations in between, every batch gives the result
+    of the single-mesh path with one profiled launch per sweep."""
     rng = np.random.default_rng(9)
-    vol = synth.blocky_tiny(rng, (70, 50, 30), 7, np.uint16)
-    t = sn.to_device(vol)
-    m = ctx.extract(t)
-    ctx.profile(2)  # eager sweeps, no graph
-    ctx.smooth(m, iterations=17, relaxation=0.5, constraint=0.7)
-    ref = m.to_host()
+    vols = [synth.blocky_tiny(rng, (70, 50, 30), 7, np.uint16),
+            synth.blocky_tiny(rng, (40, 66, 21), 5, np.uint16),
+            synth.random_tiny(rng, (33, 20, 17), 4, np.uint16)]
+    params = [(17, 0.5, 0.7), (9, 0.25, 1.0), (23, 1.0, 0.4)]
+    ts = [sn.to_device(v) for v in vols]
+    ctx.profile(2)  # every sweep its own launch and events
+    ref = []
+    for t, (it, lam, d) in zip(ts, params):
+        m = ctx.extract(t)
+        ctx.smooth(m, iterations=it, relaxation=lam, constraint=d)
+        ref.append(m.to_host())
+        m.free()
     ctx.profile(False)
     ctx.profile_reset()
     junk = torch.zeros(1 << 20, device="cuda")
     for rep in range(6):
         junk.add_(1.0)
         torch.cuda.synchronize()
-        ctx.smooth(m, iterations=17, relaxation=0.5, constraint=0.7)
-        g = m.to_host()
-        assert np.array_equal(g.offsets, ref.offsets), f"replay {rep}"
-        assert np.array_equal(g.points, ref.points), f"replay {rep}"
-    m.free()
+        announce(f"batch graph replay {rep}")
+        ms = ctx.batch_submit([dict(labels=t) for t in ts], params)
+        for k, m in enumerate(ms):
+            g = m.to_host()
+            assert np.array_equal(g.offsets, ref[k].offsets), f"replay {rep} volume {k}"
+            assert np.array_equal(g.points, ref[k].points), f"replay {rep} volume {k}"
+            m.free()
 
 
 def test_determinism(ctx, sn):
