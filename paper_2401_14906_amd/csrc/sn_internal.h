@@ -188,6 +188,7 @@ hipError_t launch_edges_one(const VolDesc &d, bool wide, int64_t ntiles, uint64_
                             int64_t nzero, hipStream_t s);
 hipError_t launch_count_one(const VolDesc &d, int64_t ntiles, int32_t words_per_thread,
                             uint64_t *d_status, uint32_t *d_ticket, int64_t *d_totals, hipStream_t s);
+hipError_t launch_generate_one(const VolDesc &d, bool staged, int64_t ntiles, int32_t bpw, hipStream_t s);
 hipError_t launch_emit_one(const VolDesc &d, const SmoothDesc &sd, int64_t ntiles, int32_t bpw,
                            hipStream_t s);
 hipError_t launch_jacobi_one(const SmoothDesc &sd, int64_t nblocks, int32_t it, int K, hipStream_t s);

@@ -946,15 +946,14 @@ __device__ __forceinline__ void generate_group(const VolDesc &d, int64_t grp, in
     wave_lds_sync();
 }
 
-template <typename T, int MODE, bool STAGE>
-__device__ __forceinline__ void generate_body(const VolDesc *descs, const int64_t *prefix, int32_t nvol,
-                                              int64_t tile_base, int32_t gpw)
+template <typename T, int MODE, bool STAGE, class Src>
+__device__ __forceinline__ void generate_body(const Src &a, int64_t tile_base, int32_t gpw)
 {
     __shared__ GenLds<STAGE> lds[kWavesPerBlock];
     const int64_t t = tile_base + blockIdx.x;
     int v;
     int64_t first;
-    const VolDesc &d = vol_of(ManyVols{descs, prefix, nvol}, t, v, first);
+    const VolDesc &d = vol_of(a, t, v, first);
     const int64_t ngroups = (d.g.R * d.g.W + kGenWords - 1) / kGenWords;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     if (threadIdx.x == 0 && t == first) glb(d.st_off)[d.P] = (int32_t)d.S;
@@ -968,7 +967,7 @@ __global__ __launch_bounds__(kBlock) void k_generate(const VolDesc *__restrict__
                                                      const int64_t *__restrict__ prefix,
                                                      int32_t nvol, int64_t tile_base, int32_t gpw)
 {
-    generate_body<T, MODE, false>(descs, prefix, nvol, tile_base, gpw);
+    generate_body<T, MODE, false>(ManyVols{descs, prefix, nvol}, tile_base, gpw);
 }
 
 template <typename T, int MODE>
@@ -977,7 +976,19 @@ __global__ __launch_bounds__(kBlock) void k_generate_staged(const VolDesc *__res
                                                             int32_t nvol, int64_t tile_base,
                                                             int32_t gpw)
 {
-    generate_body<T, MODE, true>(descs, prefix, nvol, tile_base, gpw);
+    generate_body<T, MODE, true>(ManyVols{descs, prefix, nvol}, tile_base, gpw);
+}
+
+template <typename T, int MODE>
+__global__ __launch_bounds__(kBlock) void k_generate_one(OneVol a, int32_t gpw)
+{
+    generate_body<T, MODE, false>(a, 0, gpw);
+}
+
+template <typename T, int MODE>
+__global__ __launch_bounds__(kBlock) void k_generate_staged_one(OneVol a, int32_t gpw)
+{
+    generate_body<T, MODE, true>(a, 0, gpw);
 }
 
 // ---------------------------------------------------------------------------
@@ -1492,6 +1503,18 @@ hipError_t launch_generate(int32_t dtype, int32_t mode, bool staged, const VolDe
     } else {
         SN_KEY_SWITCH(k_generate, dim3((uint32_t)ntiles), dim3(kBlock), 0, s, d_descs, d_tile_prefix,
                       nvol, tile_base, bpw)
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_generate_one(const VolDesc &d, bool staged, int64_t ntiles, int32_t bpw, hipStream_t s)
+{
+    if (ntiles <= 0) return hipSuccess;
+    const int32_t dtype = d.dtype, mode = d.cs.mode;
+    if (staged) {
+        SN_KEY_SWITCH(k_generate_staged_one, dim3((uint32_t)ntiles), dim3(kBlock), 0, s, OneVol{d}, bpw)
+    } else {
+        SN_KEY_SWITCH(k_generate_one, dim3((uint32_t)ntiles), dim3(kBlock), 0, s, OneVol{d}, bpw)
     }
     return hipGetLastError();
 }

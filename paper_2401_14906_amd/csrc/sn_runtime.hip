@@ -156,14 +156,16 @@ void *Pool::alloc(size_t bytes)
         return p;
     }
     void *p = nullptr;
-    hipError_t e = pinned_ ? hipHostMalloc(&p, n, hipHostMallocDefault) : hipMalloc(&p, n);
+    // pinned host blocks are coherent: kernels may write results into them
+    // (the count totals) that the host reads after the stream's completion
+    hipError_t e = pinned_ ? hipHostMalloc(&p, n, hipHostMallocCoherent) : hipMalloc(&p, n);
     if (e != hipSuccess) {
         (void)hipGetLastError();
         // drop every cached block (waiting for deferred ones) and retry once
         reclaim_locked(true);
         for (auto &kv : free_) raw_free(kv.second), sizes_.erase(kv.second);
         free_.clear();
-        e = pinned_ ? hipHostMalloc(&p, n, hipHostMallocDefault) : hipMalloc(&p, n);
+        e = pinned_ ? hipHostMalloc(&p, n, hipHostMallocCoherent) : hipMalloc(&p, n);
         if (e != hipSuccess) {
             (void)hipGetLastError();
             return nullptr;
@@ -786,8 +788,12 @@ sn_status sn::extract_many(sn_ctx *c, const sn_volume *vols, int32_t n, hipStrea
     const int32_t ngroups = (int32_t)gbeg.size() - 1;
 
     const int64_t nctiles = ctile_prefix[n];
+    // k_count writes the per-volume totals straight into coherent pinned host
+    // memory: no copy between the count pass and the host's read of them
     int64_t *h_tot = static_cast<int64_t *>(scr.h(sizeof(int64_t) * 3 * n));
-    int64_t *d_tot = static_cast<int64_t *>(scr.d(sizeof(int64_t) * 3 * n));
+    int64_t *d_tot = nullptr;
+    if (h_tot && hipHostGetDevicePointer(reinterpret_cast<void **>(&d_tot), h_tot, 0) != hipSuccess)
+        return cleanup(fail(SN_EDEVICE, "extract: totals buffer"));
     const size_t status_bytes = sizeof(uint64_t) * 3 * (size_t)std::max<int64_t>(nctiles, 1);
     uint8_t *d_status = static_cast<uint8_t *>(scr.d(status_bytes + 256));
     if (!h_tot || !d_tot || !d_status) return cleanup(fail(SN_ENOMEM, "extract: scratch"));
@@ -827,7 +833,6 @@ sn_status sn::extract_many(sn_ctx *c, const sn_volume *vols, int32_t n, hipStrea
         else
             HIP_TRY(launch_count(d_desc, d_tp + 2 * (n + 1), n, nctiles, cv, status, ticket, d_tot, s));
     }
-    HIP_TRY(hipMemcpyAsync(h_tot, d_tot, sizeof(int64_t) * 3 * n, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
 
     // exact allocation of every output (Sec. 2.3: no incremental allocation)
@@ -870,22 +875,10 @@ sn_status sn::extract_many(sn_ctx *c, const sn_volume *vols, int32_t n, hipStrea
         hd[k] = d;
     }
     if (one) {
-        // k_generate reads its descriptor from device memory even for one
-        // volume: as a kernel argument it would be held in scalar registers,
-        // which this kernel needs for its word masks
-        uint8_t *h_b = static_cast<uint8_t *>(scr.h(sizeof(VolDesc) + 2 * sizeof(int64_t)));
-        uint8_t *d_b = static_cast<uint8_t *>(scr.d(sizeof(VolDesc) + 2 * sizeof(int64_t)));
-        if (!h_b || !d_b) return cleanup(fail(SN_ENOMEM, "extract: descriptor staging"));
-        std::memcpy(h_b, &hd[0], sizeof(VolDesc));
-        const int64_t tp1[2] = {0, tile_prefix[1]};
-        std::memcpy(h_b + sizeof(VolDesc), tp1, sizeof tp1);
-        HIP_TRY(hipMemcpyAsync(d_b, h_b, sizeof(VolDesc) + sizeof tp1, hipMemcpyHostToDevice, s));
         {
             ProfScope ps(c, "k_generate", s);
             const bool staged = hd[0].P >= kGenStagedPointsPerWord * hd[0].g.R * hd[0].g.W;
-            HIP_TRY(launch_generate(hd[0].dtype, hd[0].cs.mode, staged, reinterpret_cast<VolDesc *>(d_b),
-                                    reinterpret_cast<int64_t *>(d_b + sizeof(VolDesc)), 1, 0,
-                                    tile_prefix[1], bpw, s));
+            HIP_TRY(launch_generate_one(hd[0], staged, tile_prefix[1], bpw, s));
         }
         if (qblocks > 0) {
             ProfScope ps(c, "k_tri", s);
