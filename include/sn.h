@@ -212,12 +212,13 @@ sn_status sn_serve_stop(sn_server *srv);
 
 /* ---- schedule tuning and profiling ----------------------------------------- */
 
-/* Time the candidate schedules (batches of 4 cell words per wavefront in the
- * extraction kernels) for the volume's size class on this device and remember
- * the fastest for it (also written to SN_AUTOTUNE_CACHE if set).  Returns the
- * chosen batches-per-wave. */
+/* Time the candidate schedules (work items per wavefront in the generation
+ * kernels: groups of 32 cell words in k_generate, batches of 4 words in k_emit)
+ * for the volume's size class on this device and remember the fastest for it
+ * (also written to SN_AUTOTUNE_CACHE if set).  Untuned classes use 1.  Returns
+ * the chosen count (called batches-per-wave in this interface). */
 sn_status sn_autotune(sn_ctx *ctx, const sn_volume *vol, void *stream, int32_t *chosen);
-/* Force the batches-per-wave schedule of the extraction kernels (1..16) for
+/* Force the batches-per-wave schedule of the generation kernels (1..16) for
  * every later launch on this context; 0 returns to the tuned/default choice.
  * Results do not depend on the schedule. */
 sn_status sn_set_batches_per_wave(sn_ctx *ctx, int32_t batches_per_wave);

@@ -1242,14 +1242,17 @@ __global__ __launch_bounds__(256) void k_jacobi_first_one(OneSmooth a)
     jacobi_first_body<K>(a);
 }
 
+// Whole-wave DPP shifts by one lane (no LDS traffic): lane l receives lane
+// l - 1 (wave_shr:1) or lane l + 1 (wave_shl:1); the end lane that has no
+// source is overwritten by the caller.
 __device__ __forceinline__ float shfl_up1(float x)
 {
-    return __shfl_up(x, 1u);
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0x138, 0xf, 0xf, false));
 }
 
 __device__ __forceinline__ float shfl_down1(float x)
 {
-    return __shfl_down(x, 1u);
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0x130, 0xf, 0xf, false));
 }
 
 __device__ __forceinline__ float readlane_f(float x, int l)

@@ -100,7 +100,7 @@ struct sn_ctx {
     std::string tune_path;
     int32_t forced_bpw = 0;
     int64_t count_wide_words = sn::kCountWideWords;  // SN_TEST_COUNT_WIDE_WORDS overrides
-    int32_t batches_per_wave(const std::string &cls, int64_t nbatch) const;
+    int32_t batches_per_wave(const std::string &cls) const;
     void load_tune_cache();
     void save_tune_cache() const;
 };

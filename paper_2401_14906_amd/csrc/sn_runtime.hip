@@ -383,16 +383,16 @@ std::string sn::size_class(const sn_volume &v)
     return os.str();
 }
 
-int32_t sn_ctx::batches_per_wave(const std::string &cls, int64_t nbatch) const
+int32_t sn_ctx::batches_per_wave(const std::string &cls) const
 {
     std::lock_guard<std::mutex> g(tune_mu);
     if (forced_bpw > 0) return forced_bpw;
     auto it = tune.find(cls);
     if (it != tune.end()) return it->second;
-    // untuned: one batch per wave while that still gives few workgroups per
-    // CU (more waves in flight), three for large volumes (fewer launches of
-    // waves and the next batch's loads in flight behind the current one)
-    return nbatch < (int64_t(1) << 18) ? 1 : 3;
+    // untuned: one work item per wave, the fastest k_generate schedule at
+    // every size measured (torso 31 us against 43-80 us, connectome 3.23 ms
+    // against 3.46-3.60 ms for 2 to 8 groups per wave)
+    return 1;
 }
 
 void sn_ctx::load_tune_cache()
@@ -681,9 +681,8 @@ sn_status sn::extract_many(sn_ctx *c, const sn_volume *vols, int32_t n, hipStrea
         const int64_t vox = vols[v].dims[0] * vols[v].dims[1] * vols[v].dims[2];
         if (vox > big) big = vox, vb = v;
     }
-    const Geom gb = make_geom(vols[vb]);
     const int32_t bpw =
-        bpw_override > 0 ? bpw_override : c->batches_per_wave(size_class(vols[vb]), gb.R * gb.NB);
+        bpw_override > 0 ? bpw_override : c->batches_per_wave(size_class(vols[vb]));
     const int TB = kWavesPerBlock * bpw;
 
     // Volumes are processed grouped by (label type, classification mode): one
