@@ -11,9 +11,11 @@ spacing 1x1x2.5, 25 sweeps, relaxation 0.5, constraint 1.0).
 
 One JSON line is printed on stdout; progress goes to stderr.  `value` is
 whole-step throughput in Gvoxels/s (voxels / wall time of a full step).
-Per-kernel durations come from HIP events recorded by the library on the
-stream each kernel runs on, during the timed steps; the roofline object uses
-the kernel with the largest total time.  Extra objects report the
+Kernel durations come from HIP events recorded by the library on the stream
+each kernel runs on.  In the timed steps only the sweeps (the kernel with the
+largest total time, which the roofline object uses) are bracketed; the
+extraction kernels are timed with events around every launch in a second,
+untimed run of the same number of steps.  Extra objects report the
 connectome-like volume, the batched path against sequential plain calls and
 the served path against a plain FIFO loop, and the oracle timed on one host
 core.
@@ -104,20 +106,29 @@ def measure_workload(ctx, sn, torch, vol, steps, warmup):
     bpw = ctx.autotune(t, spacing=vol.spacing)
     log(f"[bench] {vol.name}: autotuned batches per wave {bpw}; warmup {warmup}")
     run_plain_steps(ctx, sn, torch, t, vol, warmup)
-    ctx.profile(True)
+    # timed steps: HIP events bracket the sweeps (the dominant kernel, whose
+    # launch time the roofline uses) and nothing else
+    ctx.profile(3)
     ctx.profile_reset()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     P, Q, S = run_plain_steps(ctx, sn, torch, t, vol, steps)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    timed = ctx.profile_read()
+    # the same number of steps again, untimed, with events around every launch:
+    # the per-kernel breakdown of the extraction
+    ctx.profile(True)
+    ctx.profile_reset()
+    run_plain_steps(ctx, sn, torch, t, vol, steps)
     prof = ctx.profile_read()
     ctx.profile(False)
+    prof.update(timed)
     n = vol.iterations
     per = {}
     for name, (launches, ms) in prof.items():
         per[name] = {"launches": launches, "avg_us": 1e3 * ms / max(launches, 1),
-                     "total_ms": ms}
+                     "total_ms": ms, "events": "timed steps" if name in timed else "profiled steps"}
     alg = alg_bytes(vol.dims, b, P, Q, S, n)
     for name, d in per.items():
         if name in alg:

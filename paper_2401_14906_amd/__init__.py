@@ -314,7 +314,8 @@ class Context:
         _check(_lib.sn_set_batches_per_wave(self._h, int(bpw)))
 
     def profile(self, on=True):
-        """on: False/0 off, True/1 events per launch (a smoothing call's sweeps as a whole), 2 events per sweep."""
+        """on: False/0 off, True/1 events per launch (a smoothing call's sweeps as a
+        whole), 2 events per sweep, 3 the sweeps only (as with 1)."""
         _check(_lib.sn_profile_enable(self._h, int(on)))
 
     def profile_reset(self):

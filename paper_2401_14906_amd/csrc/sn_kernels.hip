@@ -1141,6 +1141,9 @@ __device__ __forceinline__ uint32_t udiv(uint32_t n, const UDiv &u)
 // Clamp to the box, store the offset, and in the mesh's last sweep also the
 // world point origin + spacing * (cell centre + stored offset), from the
 // point's cell index (the world-coordinate output, fused into the sweep).
+// NT: streaming (non-temporal) stores, for meshes whose sweep data does not
+// stay in the caches between sweeps anyway.
+template <bool NT = false>
 __device__ __forceinline__ void store_offset(const SmoothDesc &s, SN_GLOBAL float *dout, int64_t p,
                                              double x, double y, double z, bool last, uint32_t cell)
 {
@@ -1148,9 +1151,15 @@ __device__ __forceinline__ void store_offset(const SmoothDesc &s, SN_GLOBAL floa
     const float fx = (float)fmin(fmax(x, -c), c);
     const float fy = (float)fmin(fmax(y, -c), c);
     const float fz = (float)fmin(fmax(z, -c), c);
-    dout[3 * p] = fx;
-    dout[3 * p + 1] = fy;
-    dout[3 * p + 2] = fz;
+    if constexpr (NT) {
+        __builtin_nontemporal_store(fx, dout + 3 * p);
+        __builtin_nontemporal_store(fy, dout + 3 * p + 1);
+        __builtin_nontemporal_store(fz, dout + 3 * p + 2);
+    } else {
+        dout[3 * p] = fx;
+        dout[3 * p + 1] = fy;
+        dout[3 * p + 2] = fz;
+    }
     if (last) {
         const uint32_t r = udiv(cell, s.CM), i = cell - r * s.CM.d;
         const uint32_t k = udiv(r, s.CN), j = r - k * s.CN.d;
@@ -1292,8 +1301,13 @@ __device__ __forceinline__ void jacobi_body(const Src &a, int32_t it)
         const int64_t p = p0 + 64 * c + lane;
         f[c] = 0, cell[c] = 0, nb[c] = v4i{-1, -1, -1, -1}, ox[c] = oy[c] = oz[c] = 0.f;
         if (p < P) {
-            f[c] = glb(s.faces)[p];
-            nb[c] = nbr[p];
+            if constexpr (K > 1) {  // large meshes: read-once streams
+                f[c] = __builtin_nontemporal_load(glb(s.faces) + p);
+                nb[c] = __builtin_nontemporal_load(nbr + p);
+            } else {
+                f[c] = glb(s.faces)[p];
+                nb[c] = nbr[p];
+            }
             ox[c] = din[3 * p], oy[c] = din[3 * p + 1], oz[c] = din[3 * p + 2];
             if (last) cell[c] = glb(s.pcell)[p];
         }
@@ -1362,7 +1376,7 @@ __device__ __forceinline__ void jacobi_body(const Src &a, int32_t it)
             y = y + s.lam * (sy * inv);
             z = z + s.lam * (sz * inv);
         }
-        store_offset(s, dout, p, x, y, z, last, cell[c]);
+        store_offset<(K > 1)>(s, dout, p, x, y, z, last, cell[c]);
     }
 }
 

@@ -85,7 +85,8 @@ struct sn_ctx {
     sn::EventCache timing_events{hipEventDefault};
     // profiling
     bool profiling = false;
-    bool profile_eager = false;  // every sweep bracketed by its own events
+    bool profile_eager = false;        // every sweep bracketed by its own events
+    bool profile_sweeps_only = false;  // only the sweeps are bracketed
     struct ProfEv {
         std::string name;
         hipEvent_t a, b;

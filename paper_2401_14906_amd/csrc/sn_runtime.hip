@@ -299,6 +299,7 @@ ProfScope::ProfScope(sn_ctx *c, const char *name, hipStream_t s, int64_t launche
     : c_(c), name_(name), s_(s), launches_(launches)
 {
     if (!c_ || !c_->profiling) return;
+    if (c_->profile_sweeps_only && name_ != "k_jacobi") return;
     a_ = c_->timing_events.get();
     b_ = c_->timing_events.get();
     if (!a_ || !b_) {
@@ -320,9 +321,10 @@ ProfScope::~ProfScope()
 
 extern "C" sn_status sn_profile_enable(sn_ctx *c, int on)
 {
-    if (!c || on < 0 || on > 2) return fail(SN_EINVAL, "sn_profile_enable: bad arguments");
+    if (!c || on < 0 || on > 3) return fail(SN_EINVAL, "sn_profile_enable: bad arguments");
     c->profiling = on != 0;
     c->profile_eager = on == 2;
+    c->profile_sweeps_only = on == 3;
     return SN_OK;
 }
 
