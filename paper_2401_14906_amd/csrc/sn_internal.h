@@ -161,9 +161,17 @@ constexpr uint64_t kValMask = (1ull << 62) - 1;
 hipError_t launch_edges(int32_t dtype, int32_t mode, bool wide, const VolDesc *d_descs,
                         const int64_t *d_tile_prefix, int32_t nvol, int64_t tile_base,
                         int64_t ntiles, uint64_t *d_zero, int64_t nzero, hipStream_t s);
+// Where k_count leaves each volume's totals (P, Q, S) for the host: the last
+// tile of volume v writes totals[3v..3v+2] and then, after a system-scope
+// fence, stamps[v] = seq (host-visible memory; seq differs between calls).
+struct CountOut {
+    int64_t *totals;
+    int64_t *stamps;
+    int64_t seq;
+};
 hipError_t launch_count(const VolDesc *d_descs, const int64_t *d_tile_prefix, int32_t nvol,
                         int64_t ntiles, int32_t words_per_thread, uint64_t *d_status,
-                        uint32_t *d_ticket, int64_t *d_totals, hipStream_t s);
+                        uint32_t *d_ticket, const CountOut &out, hipStream_t s);
 // staged: stencil ids, quads and pairs go through LDS (for meshes with at
 // least kGenStagedPointsPerWord points per word on average)
 hipError_t launch_generate(int32_t dtype, int32_t mode, bool staged, const VolDesc *d_descs,
@@ -187,7 +195,7 @@ hipError_t add_jacobi_nodes(hipGraph_t graph, const SmoothDesc *d_sd,
 hipError_t launch_edges_one(const VolDesc &d, bool wide, int64_t ntiles, uint64_t *d_zero,
                             int64_t nzero, hipStream_t s);
 hipError_t launch_count_one(const VolDesc &d, int64_t ntiles, int32_t words_per_thread,
-                            uint64_t *d_status, uint32_t *d_ticket, int64_t *d_totals, hipStream_t s);
+                            uint64_t *d_status, uint32_t *d_ticket, const CountOut &out, hipStream_t s);
 hipError_t launch_generate_one(const VolDesc &d, bool staged, int64_t ntiles, int32_t bpw, hipStream_t s);
 hipError_t launch_emit_one(const VolDesc &d, const SmoothDesc &sd, int64_t ntiles, int32_t bpw,
                            hipStream_t s);

@@ -537,7 +537,7 @@ __device__ __forceinline__ int64_t last_tile(const OneVol &, int)
 
 template <int V, class Src>
 __device__ __forceinline__ void count_body(const Src &a, uint64_t *status, uint32_t *ticket,
-                                           int64_t *totals)
+                                           CountOut out)
 {
     // a tile is V * kCountBlock words; word (v, thread) of the tile is
     // v * kCountBlock + thread, so each v is one coalesced pass
@@ -607,7 +607,13 @@ __device__ __forceinline__ void count_body(const Src &a, uint64_t *status, uint3
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 s_excl[c] = excl[c];
-                if (t == last_tile(a, vol)) totals[3 * vol + c] = excl[c] + agg[c];
+                if (t == last_tile(a, vol)) out.totals[3 * vol + c] = excl[c] + agg[c];
+            }
+            if (t == last_tile(a, vol)) {
+                // the host may read the totals as soon as it sees the stamp
+                __threadfence_system();
+                __hip_atomic_store(out.stamps + vol, out.seq, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_SYSTEM);
             }
         }
     }
@@ -636,16 +642,16 @@ template <int V>
 __global__ __launch_bounds__(kCountBlock) void k_count(const VolDesc *__restrict__ descs,
                                                        const int64_t *__restrict__ prefix,
                                                        int32_t nvol, uint64_t *status,
-                                                       uint32_t *ticket, int64_t *totals)
+                                                       uint32_t *ticket, CountOut out)
 {
-    count_body<V>(ManyVols{descs, prefix, nvol}, status, ticket, totals);
+    count_body<V>(ManyVols{descs, prefix, nvol}, status, ticket, out);
 }
 
 template <int V>
 __global__ __launch_bounds__(kCountBlock) void k_count_one(OneVol a, uint64_t *status,
-                                                           uint32_t *ticket, int64_t *totals)
+                                                           uint32_t *ticket, CountOut out)
 {
-    count_body<V>(a, status, ticket, totals);
+    count_body<V>(a, status, ticket, out);
 }
 
 // ---------------------------------------------------------------------------
@@ -1484,28 +1490,28 @@ hipError_t launch_edges_one(const VolDesc &d, bool wide, int64_t ntiles, uint64_
 
 hipError_t launch_count(const VolDesc *d_descs, const int64_t *d_tile_prefix, int32_t nvol,
                         int64_t ntiles, int32_t words_per_thread, uint64_t *d_status,
-                        uint32_t *d_ticket, int64_t *d_totals, hipStream_t s)
+                        uint32_t *d_ticket, const CountOut &out, hipStream_t s)
 {
     if (ntiles <= 0) return hipSuccess;
     if (words_per_thread == kCountWideV)
         hipLaunchKernelGGL(k_count<kCountWideV>, dim3((uint32_t)ntiles), dim3(kCountBlock), 0, s,
-                           d_descs, d_tile_prefix, nvol, d_status, d_ticket, d_totals);
+                           d_descs, d_tile_prefix, nvol, d_status, d_ticket, out);
     else
         hipLaunchKernelGGL(k_count<1>, dim3((uint32_t)ntiles), dim3(kCountBlock), 0, s, d_descs,
-                           d_tile_prefix, nvol, d_status, d_ticket, d_totals);
+                           d_tile_prefix, nvol, d_status, d_ticket, out);
     return hipGetLastError();
 }
 
 hipError_t launch_count_one(const VolDesc &d, int64_t ntiles, int32_t words_per_thread,
-                            uint64_t *d_status, uint32_t *d_ticket, int64_t *d_totals, hipStream_t s)
+                            uint64_t *d_status, uint32_t *d_ticket, const CountOut &out, hipStream_t s)
 {
     if (ntiles <= 0) return hipSuccess;
     if (words_per_thread == kCountWideV)
         hipLaunchKernelGGL(k_count_one<kCountWideV>, dim3((uint32_t)ntiles), dim3(kCountBlock), 0, s,
-                           OneVol{d}, d_status, d_ticket, d_totals);
+                           OneVol{d}, d_status, d_ticket, out);
     else
         hipLaunchKernelGGL(k_count_one<1>, dim3((uint32_t)ntiles), dim3(kCountBlock), 0, s, OneVol{d},
-                           d_status, d_ticket, d_totals);
+                           d_status, d_ticket, out);
     return hipGetLastError();
 }
 

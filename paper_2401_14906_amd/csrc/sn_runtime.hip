@@ -654,6 +654,34 @@ T *dalloc(sn_mesh *m, int64_t count)
 
 }  // namespace
 
+// Host spin on the count stamps before blocking on the stream (longer than the
+// edge and count passes of the largest single volumes measured, 0.75 ms).
+constexpr int64_t kTotalsSpinUs = 3000;
+
+// Wait until k_count has stamped the totals of every counted volume: spin on
+// the host-visible stamps for a while (the count pass usually ends within
+// that), then block on the stream.
+static sn_status wait_totals(const int64_t *stamps, const std::vector<char> &counted, int64_t seq,
+                             hipStream_t s)
+{
+    auto stamped = [&] {
+        for (size_t k = 0; k < counted.size(); ++k)
+            if (counted[k] && __atomic_load_n(stamps + k, __ATOMIC_ACQUIRE) != seq) return false;
+        return true;
+    };
+    const auto t0 = std::chrono::steady_clock::now();
+    for (uint32_t spin = 1;; ++spin) {
+        if (stamped()) return SN_OK;
+        if ((spin & 255u) == 0 &&
+            std::chrono::steady_clock::now() - t0 > std::chrono::microseconds(kTotalsSpinUs))
+            break;
+        __builtin_ia32_pause();
+    }
+    HIP_TRY(hipStreamSynchronize(s));
+    if (!stamped()) return fail(SN_EDEVICE, "extract: the count pass left no totals");
+    return SN_OK;
+}
+
 sn_status sn::extract_many(sn_ctx *c, const sn_volume *vols, int32_t n, hipStream_t s,
                            int32_t bpw_override, sn_mesh **out)
 {
@@ -789,9 +817,11 @@ sn_status sn::extract_many(sn_ctx *c, const sn_volume *vols, int32_t n, hipStrea
     const int32_t ngroups = (int32_t)gbeg.size() - 1;
 
     const int64_t nctiles = ctile_prefix[n];
-    // k_count writes the per-volume totals straight into coherent pinned host
-    // memory: no copy between the count pass and the host's read of them
-    int64_t *h_tot = static_cast<int64_t *>(scr.h(sizeof(int64_t) * 3 * n));
+    // k_count writes the per-volume totals, then a stamp, straight into
+    // coherent pinned host memory: no copy between the count pass and the
+    // host's read of them, and the host sees them without waiting for the
+    // whole pass to retire
+    int64_t *h_tot = static_cast<int64_t *>(scr.h(sizeof(int64_t) * 4 * n));
     int64_t *d_tot = nullptr;
     if (h_tot && hipHostGetDevicePointer(reinterpret_cast<void **>(&d_tot), h_tot, 0) != hipSuccess)
         return cleanup(fail(SN_EDEVICE, "extract: totals buffer"));
@@ -827,14 +857,21 @@ sn_status sn::extract_many(sn_ctx *c, const sn_volume *vols, int32_t n, hipStrea
             }
         }
     }
+    const int64_t seq = c->count_seq.fetch_add(1, std::memory_order_relaxed) + 1;
+    const CountOut cout{d_tot, d_tot + 3 * n, seq};
     {
         ProfScope ps(c, "k_count", s);
         if (one)
-            HIP_TRY(launch_count_one(hd[0], nctiles, cv, status, ticket, d_tot, s));
+            HIP_TRY(launch_count_one(hd[0], nctiles, cv, status, ticket, cout, s));
         else
-            HIP_TRY(launch_count(d_desc, d_tp + 2 * (n + 1), n, nctiles, cv, status, ticket, d_tot, s));
+            HIP_TRY(launch_count(d_desc, d_tp + 2 * (n + 1), n, nctiles, cv, status, ticket, cout, s));
     }
-    HIP_TRY(hipStreamSynchronize(s));
+    {
+        std::vector<char> counted(n);
+        for (int32_t k = 0; k < n; ++k) counted[k] = ctile_prefix[k + 1] > ctile_prefix[k];
+        sn_status st = wait_totals(h_tot + 3 * n, counted, seq, s);
+        if (st != SN_OK) return cleanup(st);
+    }
 
     // exact allocation of every output (Sec. 2.3: no incremental allocation)
     int64_t qblocks = 0;
