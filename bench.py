@@ -190,6 +190,12 @@ def cpu_baseline(vol, min_seconds=10.0):
                       f"{t_all:.1f} s on 1 core"}
 
 
+def mesh_alg_bytes(V, b, P, Q, S, n):
+    """Algorithmic bytes of one volume's extraction and n smoothing sweeps
+    (the extraction and per-sweep figures of alg_bytes())."""
+    return bytes_extract(V, b, P, Q, S) + n * (P * (12 + 12 + 4) + 4 * S)
+
+
 def bench_batched(ctx, sn, torch, count=64, reps=3):
     import synth
 
@@ -211,6 +217,13 @@ def bench_batched(ctx, sn, torch, count=64, reps=3):
         for m in ms:
             m.free()
 
+    # mesh sizes (untimed) for the algorithmic bytes of the whole batch
+    alg = 0
+    for m, v in zip(ctx.batch_submit(specs, params), vols):
+        mv = m.view()
+        alg += mesh_alg_bytes(int(v.labels.size), v.labels.dtype.itemsize, int(mv.n_points),
+                              int(mv.n_quads), int(mv.n_stencil), v.iterations)
+        m.free()
     out = {}
     for name, fn in (("plain", plain), ("batched", batched)):
         fn()
@@ -227,7 +240,12 @@ def bench_batched(ctx, sn, torch, count=64, reps=3):
             "plain_ms": round(out["plain"] * 1e3, 2), "batched_ms": round(out["batched"] * 1e3, 2),
             "plain_gvox_per_s": round(V / out["plain"] / 1e9, 3),
             "batched_gvox_per_s": round(V / out["batched"] / 1e9, 3),
-            "speedup": round(out["plain"] / out["batched"], 3)}
+            "speedup": round(out["plain"] / out["batched"], 3),
+            "alg_bytes": int(alg),
+            "plain_alg_GBs": round(alg / out["plain"] / 1e9, 1),
+            "batched_alg_GBs": round(alg / out["batched"] / 1e9, 1),
+            "plain_frac_hbm": round(alg / out["plain"] / 1e9 / HBM_PEAK_GBS, 4),
+            "batched_frac_hbm": round(alg / out["batched"] / 1e9 / HBM_PEAK_GBS, 4)}
 
 
 def bench_served(ctx, sn, torch, n_requests=240, pool=16, seed=5):
@@ -255,6 +273,14 @@ def bench_served(ctx, sn, torch, n_requests=240, pool=16, seed=5):
             torch.cuda.current_stream().synchronize()
 
     vox = [int(vols[k].labels.size) for k, _, _ in reqs]
+    # algorithmic bytes of every request (untimed plain runs for the mesh sizes)
+    alg = 0
+    for k, sel, it in reqs:
+        m = ctx.extract(ts[k], selected=sel)
+        mv = m.view()
+        alg += mesh_alg_bytes(int(vols[k].labels.size), vols[k].labels.dtype.itemsize,
+                              int(mv.n_points), int(mv.n_quads), int(mv.n_stencil), it)
+        m.free()
 
     # saturation: every request at once; the plain path runs them one by one
     for r in reqs[:8]:
@@ -276,7 +302,10 @@ def bench_served(ctx, sn, torch, n_requests=240, pool=16, seed=5):
     srv.stop()
     saturation = {"plain_gvox_per_s": round(sum(vox) / sat_plain / 1e9, 3),
                   "served_gvox_per_s": round(sum(vox) / sat_served / 1e9, 3),
-                  "speedup": round(sat_plain / sat_served, 3), "served_batches": sat_batches}
+                  "speedup": round(sat_plain / sat_served, 3), "served_batches": sat_batches,
+                  "alg_bytes": int(alg),
+                  "plain_frac_hbm": round(alg / sat_plain / 1e9 / HBM_PEAK_GBS, 4),
+                  "served_frac_hbm": round(alg / sat_served / 1e9 / HBM_PEAK_GBS, 4)}
     log(f"[bench] served: saturation plain {sat_plain * 1e3:.1f} ms, served {sat_served * 1e3:.1f} ms")
 
     # latency: a Poisson stream at 80 % of the plain path's capacity
@@ -337,6 +366,35 @@ def bench_served(ctx, sn, torch, n_requests=240, pool=16, seed=5):
     return {"requests": n_requests, "pool_volumes": pool, "saturation": saturation,
             "poisson_qps": round(qps, 2), "plain_fifo": plain, "served": served,
             "p99_speedup": round(plain["p99_ms"] / max(served["p99_ms"], 1e-9), 3)}
+
+
+def bench_triangulate(ctx, sn, torch, vol, reps=10):
+    """The final triangulation (Sec. 2.5) of the smoothed mesh of `vol` under
+    each diagonal rule, timed with HIP events around the library's launches.
+    Algorithmic bytes per launch: quads (16 B) and label pairs (2b B) read,
+    points (12 B) read once, triangles (24 B) and their pairs (4b B) written."""
+    t = sn.to_device(vol.labels)
+    m = ctx.extract(t, spacing=vol.spacing)
+    ctx.smooth(m, iterations=vol.iterations, relaxation=vol.relaxation, constraint=vol.constraint)
+    v = m.view()
+    P, Q, b = int(v.n_points), int(v.n_quads), int(v.dtype)
+    alg = Q * (16 + 2 * b + 24 + 4 * b) + 12 * P
+    out = {"quads": Q, "alg_bytes_per_launch": alg}
+    for rule in ("fixed", "shortest", "min_area", "planar"):
+        ctx.triangulate(m, rule)
+        torch.cuda.synchronize()
+        ctx.profile(True)
+        ctx.profile_reset()
+        for _ in range(reps):
+            ctx.triangulate(m, rule)
+        prof = ctx.profile_read()
+        ctx.profile(False)
+        n, ms = prof["k_tri_rule"]
+        us = 1e3 * ms / n
+        out[rule] = {"avg_us": round(us, 2), "alg_GBs": round(alg / (us * 1e-6) / 1e9, 1),
+                     "frac_hbm": round(alg / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)}
+    m.free()
+    return out
 
 
 COPY_PROBE_BYTES = 256 << 20
@@ -487,6 +545,7 @@ def main():
             del cvol
         extra["batched"] = bench_batched(ctx, sn, torch)
         extra["served"] = bench_served(ctx, sn, torch)
+        extra["triangulate"] = bench_triangulate(ctx, sn, torch, vol)
 
     cpu = None if args.no_cpu else cpu_baseline(vol)
     line = {

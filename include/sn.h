@@ -137,7 +137,8 @@ const char *sn_version(void);
 /* ---- plain path ----------------------------------------------------------- */
 
 /* Extract the SurfaceNets mesh of one volume (Sec. 2.3).  The call blocks until
- * the output sizes are known (one device-to-host read of three totals), then
+ * the output sizes are known (the count pass writes three totals per volume
+ * into host memory), then
  * enqueues generation on `stream` and returns; the mesh is complete once
  * `stream` reaches that point.  Points are cell centres; offsets are NULL. */
 sn_status sn_extract(sn_ctx *ctx, const sn_volume *vol, void *stream, sn_mesh **out);
@@ -145,9 +146,34 @@ sn_status sn_extract(sn_ctx *ctx, const sn_volume *vol, void *stream, sn_mesh **
 /* Smooth a mesh (Eq. (1), Sec. 2.4).  Always restarts from the unsmoothed
  * centres kept with the mesh (the smoothing cache of Sec. 3.7), so repeated
  * calls with different parameters are independent.  Enqueued on `stream`
- * (the sweeps are replayed from a cached HIP graph).  iterations == 0
- * restores the centres. */
+ * (one launch per sweep).  iterations == 0 restores the centres. */
 sn_status sn_smooth(sn_ctx *ctx, sn_mesh *mesh, const sn_smooth_params *p, void *stream);
+
+/* Choice of the tessellating diagonal of a quad (Sec. 2.5 lists shortest
+ * diagonal, minimum area and most co-planar without defining the measures). */
+typedef enum sn_diag_rule {
+    SN_DIAG_FIXED = 0,    /* always A-C: the split SN_TRIS makes at extraction     */
+    SN_DIAG_SHORTEST = 1, /* A-C iff |C - A| <= |D - B|                            */
+    SN_DIAG_MIN_AREA = 2, /* A-C iff area(ABC) + area(ACD) <= area(ABD) + area(BCD) */
+    SN_DIAG_PLANAR = 3    /* A-C iff its two triangle normals are at least as
+                             parallel (cosine) as those of the B-D split; a split
+                             with a degenerate triangle has cosine -2            */
+} sn_diag_rule;
+
+/* Triangulate a mesh's quads from its current world points (Sec. 2.5: the
+ * final step, after smoothing).  For quad (A,B,C,D) the A-C split gives
+ * triangles (A,B,C), (A,C,D) and the B-D split (A,B,D), (B,C,D): both keep
+ * the quad's orientation.  Measures are computed in FP64 from the FP32 world
+ * points, in the order written above; ties go to A-C.  Triangles 2q and 2q+1
+ * come from quad q.
+ *   tris:       DEVICE [2*n_quads][3] int32, owned by the caller;
+ *   tri_labels: DEVICE [2*n_quads][2] of the label type (the quad's label
+ *               pair, repeated), owned by the caller, or NULL.
+ * Works for meshes of either primitive (the quads are kept).  Enqueued on
+ * `stream`, which must be ordered after the mesh's smoothing.  SN_EINVAL for
+ * a NULL context or mesh, an unknown rule, or tris == NULL with n_quads > 0. */
+sn_status sn_triangulate(sn_ctx *ctx, sn_mesh *mesh, sn_diag_rule rule, int32_t *tris,
+                         void *tri_labels, void *stream);
 
 sn_status sn_mesh_view_get(const sn_mesh *mesh, sn_mesh_view *out);
 

@@ -25,7 +25,8 @@ def build() -> str:
 
     src = os.path.join(_HERE, "sn_oracle.c")
     tmp = _LIB_PATH + ".tmp"
-    subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", "-ffp-contract=off", "-o", tmp, src])
+    subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", "-ffp-contract=off", "-o", tmp, src,
+                           "-lm"])
     os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
 
@@ -55,6 +56,10 @@ def _load():
         lib.orc_world.restype = None
         lib.orc_triangulate.argtypes = [P, P, P]
         lib.orc_triangulate.restype = None
+        lib.orc_split_ac.argtypes = [P, P, P, P, ctypes.c_int]
+        lib.orc_split_ac.restype = ctypes.c_int
+        lib.orc_triangulate_rule.argtypes = [I64, P, P, ctypes.c_int, P]
+        lib.orc_triangulate_rule.restype = None
         _lib = lib
     return _lib
 
@@ -148,3 +153,24 @@ def world(idx_pos: np.ndarray, origin, spacing) -> np.ndarray:
     out = np.empty_like(idx_pos)
     lib.orc_world(idx_pos.shape[0], _p(idx_pos), _p(o), _p(h), _p(out))
     return out
+
+
+# Diagonal rules of Sec. 2.5 (readings in sn_oracle.c): 0 fixed (A-C),
+# 1 shortest diagonal, 2 minimum area, 3 most planar.
+DIAG_RULES = {"fixed": 0, "shortest": 1, "min_area": 2, "planar": 3}
+
+
+def split_ac(a, b, c, d, rule: int) -> bool:
+    """True if quad (a, b, c, d) (world points) is split along A-C under `rule`."""
+    pts = [np.ascontiguousarray(x, dtype=np.float64) for x in (a, b, c, d)]
+    return bool(_load().orc_split_ac(*(_p(x) for x in pts), int(rule)))
+
+
+def triangulate_rule(quads: np.ndarray, points: np.ndarray, rule: int) -> np.ndarray:
+    """Triangles [2Q, 3] of quads [Q, 4] over world points [P, 3] (FP64) under
+    a diagonal rule: (A,B,C), (A,C,D) for the A-C split, (A,B,D), (B,C,D) for B-D."""
+    q = np.ascontiguousarray(quads, dtype=np.int32)
+    pts = np.ascontiguousarray(points, dtype=np.float64)
+    tris = np.empty((2 * q.shape[0], 3), dtype=np.int32)
+    _load().orc_triangulate_rule(q.shape[0], _p(q), _p(pts), int(rule), _p(tris))
+    return tris

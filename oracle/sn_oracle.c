@@ -42,8 +42,11 @@
  *   - Eq. (1) is the mean over the N stencil neighbours; N = 0 means no motion;
  *   - the constraint is a box of half-width d (voxel units) per axis around
  *     the cell centre, applied after every sweep;
- *   - the triangles of quad (A,B,C,D) are (A,B,C) and (A,C,D).
+ *   - the triangles of quad (A,B,C,D) are (A,B,C) and (A,C,D);
+ *   - the other tessellating diagonals Sec. 2.5 lists are read in
+ *     orc_triangulate_rule below.
  */
+#include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -376,6 +379,96 @@ void orc_triangulate(const orc_mesh *m, int32_t *tris, uint32_t *tri_pairs)
             tri_pairs[4 * q + 1] = m->pairs[2 * q + 1];
             tri_pairs[4 * q + 2] = m->pairs[2 * q + 0];
             tri_pairs[4 * q + 3] = m->pairs[2 * q + 1];
+        }
+    }
+}
+
+/*
+ * Sec. 2.5 lists ways to choose the tessellating diagonal of a (non-planar,
+ * smoothed) quad without defining them; the readings, for quad (A,B,C,D) with
+ * world points a, b, c, d:
+ *   split AC: triangles (A,B,C), (A,C,D);  split BD: (A,B,D), (B,C,D)
+ *   (both keep the quad's orientation);
+ *   rule 0 fixed:        always AC;
+ *   rule 1 shortest:     AC iff |c - a| <= |d - b|;
+ *   rule 2 minimum area: AC iff area(ABC) + area(ACD) <= area(ABD) + area(BCD);
+ *   rule 3 most planar:  AC iff the cosine of the angle between the normals of
+ *                        its two triangles is >= that of the BD split (a split
+ *                        with a degenerate triangle has cosine -2, never
+ *                        preferred unless both are degenerate).
+ * Ties go to AC.  pts: world points [P*3] (FP64); tris: [2Q*3].
+ */
+static void vsub(const double *x, const double *y, double *r)
+{
+    r[0] = x[0] - y[0], r[1] = x[1] - y[1], r[2] = x[2] - y[2];
+}
+
+static void vcross(const double *x, const double *y, double *r)
+{
+    r[0] = x[1] * y[2] - x[2] * y[1];
+    r[1] = x[2] * y[0] - x[0] * y[2];
+    r[2] = x[0] * y[1] - x[1] * y[0];
+}
+
+static double vdot(const double *x, const double *y) { return x[0] * y[0] + x[1] * y[1] + x[2] * y[2]; }
+
+/* normal (y - x) x (z - x) of triangle (x, y, z) */
+static void tri_normal(const double *x, const double *y, const double *z, double *n)
+{
+    double u[3], v[3];
+    vsub(y, x, u);
+    vsub(z, x, v);
+    vcross(u, v, n);
+}
+
+static double tri_area(const double *x, const double *y, const double *z)
+{
+    double n[3];
+    tri_normal(x, y, z, n);
+    return 0.5 * sqrt(vdot(n, n));
+}
+
+static double normals_cos(const double *n1, const double *n2)
+{
+    const double l = sqrt(vdot(n1, n1) * vdot(n2, n2));
+    return l > 0.0 ? vdot(n1, n2) / l : -2.0;
+}
+
+/* 1 if quad (a,b,c,d) is split along AC under `rule`, 0 for BD */
+int orc_split_ac(const double *a, const double *b, const double *c, const double *d, int rule)
+{
+    if (rule == 1) {
+        double ac[3], bd[3];
+        vsub(c, a, ac);
+        vsub(d, b, bd);
+        return vdot(ac, ac) <= vdot(bd, bd);
+    }
+    if (rule == 2)
+        return tri_area(a, b, c) + tri_area(a, c, d) <= tri_area(a, b, d) + tri_area(b, c, d);
+    if (rule == 3) {
+        double n1[3], n2[3], n3[3], n4[3];
+        tri_normal(a, b, c, n1);
+        tri_normal(a, c, d, n2);
+        tri_normal(a, b, d, n3);
+        tri_normal(b, c, d, n4);
+        return normals_cos(n1, n2) >= normals_cos(n3, n4);
+    }
+    return 1;
+}
+
+void orc_triangulate_rule(int64_t Q, const int32_t *quads, const double *pts, int rule, int32_t *tris)
+{
+    for (int64_t q = 0; q < Q; ++q) {
+        const int32_t *v = quads + 4 * q;
+        const double *a = pts + 3 * (int64_t)v[0], *b = pts + 3 * (int64_t)v[1];
+        const double *c = pts + 3 * (int64_t)v[2], *d = pts + 3 * (int64_t)v[3];
+        int32_t *t0 = tris + 6 * q, *t1 = tris + 6 * q + 3;
+        if (orc_split_ac(a, b, c, d, rule)) {
+            t0[0] = v[0], t0[1] = v[1], t0[2] = v[2];
+            t1[0] = v[0], t1[1] = v[2], t1[2] = v[3];
+        } else {
+            t0[0] = v[0], t0[1] = v[1], t0[2] = v[3];
+            t1[0] = v[1], t1[1] = v[2], t1[2] = v[3];
         }
     }
 }

@@ -30,6 +30,8 @@ SN_OK, SN_EINVAL, SN_ENOMEM, SN_EDEVICE, SN_ETOOBIG = 0, -1, -2, -3, -4
 SN_EAGAIN, SN_ENOTFOUND, SN_ESHUTDOWN, SN_ETIMEDOUT = -5, -6, -7, -8
 SN_TRIS, SN_QUADS = 3, 4
 _NP_DT = {1: np.uint8, 2: np.uint16, 4: np.uint32}
+# tessellating-diagonal rules of sn_triangulate
+DIAG_RULES = {"fixed": 0, "shortest": 1, "min_area": 2, "planar": 3}
 
 
 class SNError(RuntimeError):
@@ -92,6 +94,7 @@ _API = [
     ("sn_version", ctypes.c_char_p, []),
     ("sn_extract", _S, [_P, ctypes.POINTER(sn_volume), _P, ctypes.POINTER(_P)]),
     ("sn_smooth", _S, [_P, _P, ctypes.POINTER(sn_smooth_params), _P]),
+    ("sn_triangulate", _S, [_P, _P, ctypes.c_int, _P, _P, _P]),
     ("sn_mesh_view_get", _S, [_P, ctypes.POINTER(sn_mesh_view)]),
     ("sn_mesh_copy_to_host", _S, [_P, _P, _P, _P, _P, _P, _P]),
     ("sn_mesh_free", None, [_P]),
@@ -283,6 +286,25 @@ class Context:
     def smooth(self, mesh: Mesh, iterations=25, relaxation=0.5, constraint=1.0, stream=None):
         p = smooth_params(iterations, relaxation, constraint)
         _check(_lib.sn_smooth(self._h, mesh.handle, ctypes.byref(p), _stream_handle(stream)))
+
+    def triangulate(self, mesh: Mesh, rule="fixed", labels=True, stream=None):
+        """Triangles of the mesh's quads under a diagonal rule ("fixed",
+        "shortest", "min_area", "planar"), from its current world points:
+        device tensors (tris [2Q, 3] int32, labels [2Q, 2] or None)."""
+        import torch
+
+        r = DIAG_RULES[rule] if isinstance(rule, str) else int(rule)
+        v = mesh.view()
+        nq, b = int(v.n_quads), int(v.dtype)
+        tris = torch.empty((2 * nq, 3), dtype=torch.int32, device="cuda")
+        lab = None
+        if labels:
+            lab = torch.empty((2 * nq, 2), dtype={1: torch.uint8, 2: torch.int16, 4: torch.int32}[b],
+                              device="cuda")
+        _check(_lib.sn_triangulate(self._h, mesh.handle, r, ctypes.c_void_p(tris.data_ptr()),
+                                   ctypes.c_void_p(lab.data_ptr()) if lab is not None else None,
+                                   _stream_handle(stream)))
+        return tris, lab
 
     def batch_submit(self, volumes: Sequence[dict], params: Optional[Sequence] = None,
                      stream=None) -> list:

@@ -201,6 +201,10 @@ hipError_t launch_emit_one(const VolDesc &d, const SmoothDesc &sd, int64_t ntile
                            hipStream_t s);
 hipError_t launch_jacobi_one(const SmoothDesc &sd, int64_t nblocks, int32_t it, int K, hipStream_t s);
 hipError_t launch_triangulate_one(const VolDesc &d, hipStream_t s);
+// quads [Q][4] over world points -> tris [2Q][3] under diagonal rule 0..3;
+// tri_pairs [2Q][2] of the label type (dtype bytes) when not null
+hipError_t launch_tri_rule(int32_t rule, int32_t dtype, const int32_t *quads, const float *pts,
+                           const void *pairs, int64_t Q, int32_t *tris, void *tri_pairs, hipStream_t s);
 // quad blocks (256 quads per block) of the volumes with prim 3
 hipError_t launch_triangulate(const VolDesc *d_descs, const int64_t *d_block_prefix, int32_t nvol,
                               int64_t nblocks, hipStream_t s);

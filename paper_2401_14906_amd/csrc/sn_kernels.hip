@@ -24,6 +24,7 @@
 //                (Sec. 2.2, 2.4), on cell-relative offsets.
 //   k_emit     : world coordinates of the points from the offsets.
 //   k_tri      : two triangles per quad (Sec. 2.5).
+//   k_tri_rule : two triangles per quad with a geometric diagonal choice.
 #include "sn_internal.h"
 
 #define SN_GLOBAL __attribute__((address_space(1)))
@@ -1439,6 +1440,125 @@ __global__ __launch_bounds__(256) void k_tri(const VolDesc *__restrict__ descs,
 __global__ __launch_bounds__(256) void k_tri_one(OneVol a)
 {
     tri_body(a);
+}
+
+// ---------------------------------------------------------------------------
+// k_tri_rule: quads -> triangles with a geometric choice of diagonal (Sec. 2.5)
+// ---------------------------------------------------------------------------
+// Split AC gives (A,B,C), (A,C,D); split BD gives (A,B,D), (B,C,D); both keep
+// the quad's orientation.  Measures, in FP64 on the mesh's FP32 world points,
+// evaluated in the order written (no contraction), ties to AC:
+//   shortest diagonal: |c - a|^2 <= |d - b|^2;
+//   minimum area:      area(ABC) + area(ACD) <= area(ABD) + area(BCD);
+//   most planar:       cos(normals of ABC, ACD) >= cos(normals of ABD, BCD),
+//                      -2 for a split with a degenerate triangle.
+
+struct D3 {
+    double x, y, z;
+};
+
+__device__ __forceinline__ D3 load_point(const float *pts, int32_t id)
+{
+    const SN_GLOBAL float *p = glb(pts) + 3 * (int64_t)id;
+    return D3{(double)p[0], (double)p[1], (double)p[2]};
+}
+
+#pragma clang fp contract(off)
+__device__ __forceinline__ D3 d3_sub(const D3 &u, const D3 &v) { return D3{u.x - v.x, u.y - v.y, u.z - v.z}; }
+__device__ __forceinline__ double d3_dot(const D3 &u, const D3 &v) { return u.x * v.x + u.y * v.y + u.z * v.z; }
+__device__ __forceinline__ D3 d3_cross(const D3 &u, const D3 &v)
+{
+    return D3{u.y * v.z - u.z * v.y, u.z * v.x - u.x * v.z, u.x * v.y - u.y * v.x};
+}
+__device__ __forceinline__ D3 tri_normal3(const D3 &a, const D3 &b, const D3 &c)
+{
+    return d3_cross(d3_sub(b, a), d3_sub(c, a));
+}
+__device__ __forceinline__ double tri_area3(const D3 &a, const D3 &b, const D3 &c)
+{
+    const D3 n = tri_normal3(a, b, c);
+    return 0.5 * sqrt(d3_dot(n, n));
+}
+__device__ __forceinline__ double normals_cos3(const D3 &n1, const D3 &n2)
+{
+    const double l = sqrt(d3_dot(n1, n1) * d3_dot(n2, n2));
+    return l > 0.0 ? d3_dot(n1, n2) / l : -2.0;
+}
+
+template <int RULE>
+__device__ __forceinline__ bool split_ac(const D3 &a, const D3 &b, const D3 &c, const D3 &d)
+{
+    if constexpr (RULE == 1) {
+        const D3 ac = d3_sub(c, a), bd = d3_sub(d, b);
+        return d3_dot(ac, ac) <= d3_dot(bd, bd);
+    } else if constexpr (RULE == 2) {
+        return tri_area3(a, b, c) + tri_area3(a, c, d) <= tri_area3(a, b, d) + tri_area3(b, c, d);
+    } else {
+        return normals_cos3(tri_normal3(a, b, c), tri_normal3(a, c, d)) >=
+               normals_cos3(tri_normal3(a, b, d), tri_normal3(b, c, d));
+    }
+}
+#pragma clang fp contract(on)
+
+template <typename T, int RULE>
+__global__ __launch_bounds__(256) void k_tri_rule(const int32_t *__restrict__ quads,
+                                                  const float *__restrict__ pts,
+                                                  const T *__restrict__ pairs, int64_t Q,
+                                                  int32_t *__restrict__ tris,
+                                                  T *__restrict__ tri_pairs)
+{
+    const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (q >= Q) return;
+    const v4i v = glb(reinterpret_cast<const v4i *>(quads))[q];
+    bool ac = true;
+    if constexpr (RULE != 0)
+        ac = split_ac<RULE>(load_point(pts, v.x), load_point(pts, v.y), load_point(pts, v.z),
+                            load_point(pts, v.w));
+    SN_GLOBAL int32_t *o = glb(tris) + 6 * q;
+    if (ac) {
+        o[0] = v.x, o[1] = v.y, o[2] = v.z, o[3] = v.x, o[4] = v.z, o[5] = v.w;
+    } else {
+        o[0] = v.x, o[1] = v.y, o[2] = v.w, o[3] = v.y, o[4] = v.z, o[5] = v.w;
+    }
+    if (tri_pairs) {
+        const T f = glb(pairs)[2 * q], bk = glb(pairs)[2 * q + 1];
+        SN_GLOBAL T *tp = glb(tri_pairs) + 4 * q;
+        tp[0] = f, tp[1] = bk, tp[2] = f, tp[3] = bk;
+    }
+}
+
+hipError_t launch_tri_rule(int32_t rule, int32_t dtype, const int32_t *quads, const float *pts,
+                           const void *pairs, int64_t Q, int32_t *tris, void *tri_pairs, hipStream_t s)
+{
+    if (Q <= 0) return hipSuccess;
+    const dim3 grid((uint32_t)((Q + 255) / 256)), block(256);
+#define SN_TRI_RULE(T)                                                                                \
+    switch (rule) {                                                                                   \
+    case 0: hipLaunchKernelGGL((k_tri_rule<T, 0>), grid, block, 0, s, quads, pts,                    \
+                               static_cast<const T *>(pairs), Q, tris, static_cast<T *>(tri_pairs)); \
+        break;                                                                                        \
+    case 1: hipLaunchKernelGGL((k_tri_rule<T, 1>), grid, block, 0, s, quads, pts,                    \
+                               static_cast<const T *>(pairs), Q, tris, static_cast<T *>(tri_pairs)); \
+        break;                                                                                        \
+    case 2: hipLaunchKernelGGL((k_tri_rule<T, 2>), grid, block, 0, s, quads, pts,                    \
+                               static_cast<const T *>(pairs), Q, tris, static_cast<T *>(tri_pairs)); \
+        break;                                                                                        \
+    case 3: hipLaunchKernelGGL((k_tri_rule<T, 3>), grid, block, 0, s, quads, pts,                    \
+                               static_cast<const T *>(pairs), Q, tris, static_cast<T *>(tri_pairs)); \
+        break;                                                                                        \
+    default: return hipErrorInvalidValue;                                                             \
+    }
+    if (dtype == 1) {
+        SN_TRI_RULE(uint8_t)
+    } else if (dtype == 2) {
+        SN_TRI_RULE(uint16_t)
+    } else if (dtype == 4) {
+        SN_TRI_RULE(uint32_t)
+    } else {
+        return hipErrorInvalidValue;
+    }
+#undef SN_TRI_RULE
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------

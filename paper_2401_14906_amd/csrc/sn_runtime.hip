@@ -1064,6 +1064,23 @@ sn_status sn::run_sweeps_one(sn_ctx *c, const SmoothDesc &sd, int64_t nblocks, i
     return SN_OK;
 }
 
+extern "C" sn_status sn_triangulate(sn_ctx *c, sn_mesh *m, sn_diag_rule rule, int32_t *tris,
+                                    void *tri_labels, void *stream)
+{
+    if (!c || !m) return fail(SN_EINVAL, "sn_triangulate: NULL argument");
+    if (rule < SN_DIAG_FIXED || rule > SN_DIAG_PLANAR) return fail(SN_EINVAL, "sn_triangulate: unknown rule");
+    if (m->Q > 0 && !tris) return fail(SN_EINVAL, "sn_triangulate: NULL triangle buffer");
+    if (m->Q == 0) return SN_OK;
+    HIP_TRY(hipSetDevice(c->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    {
+        ProfScope ps(c, "k_tri_rule", s);
+        HIP_TRY(launch_tri_rule((int32_t)rule, m->d.dtype, m->d.quads, m->d.points, m->d.pairs, m->Q,
+                                tris, tri_labels, s));
+    }
+    return mesh_mark(m, s);
+}
+
 extern "C" sn_status sn_smooth(sn_ctx *c, sn_mesh *m, const sn_smooth_params *p, void *stream)
 {
     if (!c || !m) return fail(SN_EINVAL, "sn_smooth: NULL argument");

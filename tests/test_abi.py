@@ -63,6 +63,7 @@ def test_null_arguments_are_rejected_without_gpu(lib):
     assert lib.sn_smooth(None, None, None, None) == sn.SN_EINVAL
     assert lib.sn_mesh_view_get(None, None) == sn.SN_EINVAL
     assert lib.sn_serve_stop(None) == sn.SN_EINVAL
+    assert lib.sn_triangulate(None, None, 0, None, None, None) == sn.SN_EINVAL
     assert b"NULL" in lib.sn_last_error() or lib.sn_last_error() != b""
 
 
