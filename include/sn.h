@@ -96,11 +96,20 @@ typedef struct sn_volume {
     int32_t prim;              /* sn_prim                                                 */
 } sn_volume;
 
-/* Eq. (1) parameters: sweeps >= 0, 0 <= relaxation <= 1, constraint >= 0 (voxels). */
+/* Region a smoothed point is held in, around its cell centre, in voxel units
+ * (Sec. 2.2 names a fraction of the voxel cell, or a sphere). */
+typedef enum sn_constraint_shape {
+    SN_BOX = 0,    /* |delta_a| <= constraint on each axis (clamped per axis)    */
+    SN_SPHERE = 1  /* |delta| <= constraint (scaled back onto the sphere)        */
+} sn_constraint_shape;
+
+/* Eq. (1) parameters: sweeps >= 0, 0 <= relaxation <= 1, constraint >= 0 (voxels),
+ * shape an sn_constraint_shape (0 = box). */
 typedef struct sn_smooth_params {
     int32_t iterations;
     float relaxation;
     float constraint;
+    int32_t shape;
 } sn_smooth_params;
 
 /* Borrowed device pointers, valid until sn_mesh_free. */

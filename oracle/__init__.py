@@ -50,6 +50,9 @@ def _load():
         lib.orc_mesh_copy.restype = None
         lib.orc_smooth.argtypes = [P, ctypes.c_int32, ctypes.c_double, ctypes.c_double, P]
         lib.orc_smooth.restype = ctypes.c_int
+        lib.orc_smooth_shape.argtypes = [P, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+                                         ctypes.c_int, P]
+        lib.orc_smooth_shape.restype = ctypes.c_int
         lib.orc_centres.argtypes = [P, P]
         lib.orc_centres.restype = None
         lib.orc_world.argtypes = [I64, P, P, P, P]
@@ -100,11 +103,14 @@ class OracleMesh:
         _load().orc_centres(self._handle, _p(out))
         return out
 
-    def smooth(self, iterations: int, relaxation: float, constraint: float) -> np.ndarray:
-        """Index-space positions after `iterations` Jacobi sweeps (FP64)."""
+    def smooth(self, iterations: int, relaxation: float, constraint: float,
+               shape: str = "box") -> np.ndarray:
+        """Index-space positions after `iterations` Jacobi sweeps (FP64), each
+        point held in the box of half-width `constraint` per axis or the sphere
+        of that radius around its cell centre."""
         out = np.empty((self.n_points, 3), dtype=np.float64)
-        rc = _load().orc_smooth(self._handle, int(iterations), float(relaxation),
-                                float(constraint), _p(out))
+        rc = _load().orc_smooth_shape(self._handle, int(iterations), float(relaxation),
+                                      float(constraint), {"box": 0, "sphere": 1}[shape], _p(out))
         if rc != 0:
             raise MemoryError("oracle smoothing allocation failed")
         return out

@@ -41,7 +41,7 @@
  *   - stencil entries in face order -x, +x, -y, +y, -z, +z;
  *   - Eq. (1) is the mean over the N stencil neighbours; N = 0 means no motion;
  *   - the constraint is a box of half-width d (voxel units) per axis around
- *     the cell centre, applied after every sweep;
+ *     the cell centre, or a sphere of radius d, applied after every sweep;
  *   - the triangles of quad (A,B,C,D) are (A,B,C) and (A,C,D);
  *   - the other tessellating diagonals Sec. 2.5 lists are read in
  *     orc_triangulate_rule below.
@@ -305,12 +305,16 @@ static void cell_centre(const orc_mesh *m, int64_t p, double *x)
 /*
  * Constrained Laplacian smoothing in index (voxel) space, FP64.
  * Eq. (1): p_i <- p_i + lambda * (1/N) * sum_j (p_j - p_i) over the N stencil
- * neighbours of p_i; the moved point is then held inside the box of half-width
- * d around its cell centre (the constraint of Sec. 2.2).  All points are
+ * neighbours of p_i; the moved point is then held inside its constraint
+ * region around its cell centre (Sec. 2.2, which names a fraction of the
+ * voxel cell or a sphere): shape 0, the box of half-width d per axis
+ * (clamped axis by axis); shape 1, the sphere of radius d (a point outside is
+ * moved back along the ray from the centre onto the sphere).  All points are
  * updated from the previous sweep's positions (double buffering, Sec. 2.4).
  * out: [P*3] positions after `iterations` sweeps.  Returns 0 on success.
  */
-int orc_smooth(const orc_mesh *m, int32_t iterations, double lambda, double d, double *out)
+int orc_smooth_shape(const orc_mesh *m, int32_t iterations, double lambda, double d, int shape,
+                     double *out)
 {
     const int64_t P = m->P;
     double *centre = (double *)malloc(sizeof(double) * 3 * (size_t)(P > 0 ? P : 1));
@@ -327,19 +331,32 @@ int orc_smooth(const orc_mesh *m, int32_t iterations, double lambda, double d, d
     for (int32_t it = 0; it < iterations; ++it) {
         for (int64_t p = 0; p < P; ++p) {
             const int64_t n = m->st_off[p + 1] - m->st_off[p];
+            double q[3];
             for (int ax = 0; ax < 3; ++ax) {
-                double q = a[3 * p + ax];
+                q[ax] = a[3 * p + ax];
                 if (n > 0) {
                     double sum = 0.0;
                     for (int64_t e = m->st_off[p]; e < m->st_off[p + 1]; ++e)
                         sum += a[3 * (int64_t)m->st_ids[e] + ax] - a[3 * p + ax];
-                    q = a[3 * p + ax] + lambda * (sum / (double)n);
+                    q[ax] = a[3 * p + ax] + lambda * (sum / (double)n);
                 }
-                double lo = centre[3 * p + ax] - d, hi = centre[3 * p + ax] + d;
-                if (q < lo) q = lo;
-                if (q > hi) q = hi;
-                b[3 * p + ax] = q;
             }
+            const double *c = centre + 3 * p;
+            if (shape == 1) {
+                const double dx = q[0] - c[0], dy = q[1] - c[1], dz = q[2] - c[2];
+                const double len = sqrt(dx * dx + dy * dy + dz * dz);
+                if (len > d) {
+                    q[0] = c[0] + dx * (d / len);
+                    q[1] = c[1] + dy * (d / len);
+                    q[2] = c[2] + dz * (d / len);
+                }
+            } else {
+                for (int ax = 0; ax < 3; ++ax) {
+                    if (q[ax] < c[ax] - d) q[ax] = c[ax] - d;
+                    if (q[ax] > c[ax] + d) q[ax] = c[ax] + d;
+                }
+            }
+            memcpy(b + 3 * p, q, sizeof q);
         }
         double *t = a;
         a = b;
@@ -348,6 +365,12 @@ int orc_smooth(const orc_mesh *m, int32_t iterations, double lambda, double d, d
     memcpy(out, a, sizeof(double) * 3 * (size_t)P);
     free(centre), free(a), free(b);
     return 0;
+}
+
+/* The box constraint (shape 0). */
+int orc_smooth(const orc_mesh *m, int32_t iterations, double lambda, double d, double *out)
+{
+    return orc_smooth_shape(m, iterations, lambda, d, 0, out);
 }
 
 /* Index-space centres of all points (the unsmoothed positions). */

@@ -50,7 +50,7 @@ class sn_volume(ctypes.Structure):
 
 class sn_smooth_params(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int32), ("relaxation", ctypes.c_float),
-                ("constraint", ctypes.c_float)]
+                ("constraint", ctypes.c_float), ("shape", ctypes.c_int32)]
 
 
 class sn_mesh_view(ctypes.Structure):
@@ -251,9 +251,14 @@ def make_volume(labels, spacing=(1.0, 1.0, 1.0), origin=(0.0, 0.0, 0.0), selecte
     return v, (labels, sel)
 
 
-def smooth_params(iterations, relaxation, constraint) -> sn_smooth_params:
+# constraint regions of the smoothing (sn_constraint_shape)
+SHAPES = {"box": 0, "sphere": 1}
+
+
+def smooth_params(iterations, relaxation, constraint, shape="box") -> sn_smooth_params:
     p = sn_smooth_params()
     p.iterations, p.relaxation, p.constraint = int(iterations), float(relaxation), float(constraint)
+    p.shape = SHAPES[shape] if isinstance(shape, str) else int(shape)
     return p
 
 
@@ -283,8 +288,9 @@ class Context:
         _check(_lib.sn_extract(self._h, ctypes.byref(v), _stream_handle(stream), ctypes.byref(out)))
         return Mesh(out.value, keep)
 
-    def smooth(self, mesh: Mesh, iterations=25, relaxation=0.5, constraint=1.0, stream=None):
-        p = smooth_params(iterations, relaxation, constraint)
+    def smooth(self, mesh: Mesh, iterations=25, relaxation=0.5, constraint=1.0, shape="box",
+               stream=None):
+        p = smooth_params(iterations, relaxation, constraint, shape)
         _check(_lib.sn_smooth(self._h, mesh.handle, ctypes.byref(p), _stream_handle(stream)))
 
     def triangulate(self, mesh: Mesh, rule="fixed", labels=True, stream=None):
@@ -308,7 +314,8 @@ class Context:
 
     def batch_submit(self, volumes: Sequence[dict], params: Optional[Sequence] = None,
                      stream=None) -> list:
-        """volumes: dicts of make_volume keyword arguments; params: (iters, relax, constr)."""
+        """volumes: dicts of make_volume keyword arguments; params: (iters, relax, constr[,
+        shape])."""
         n = len(volumes)
         arr = (sn_volume * n)()
         keep = []
@@ -367,9 +374,10 @@ class Server:
         self._ctx = ctx
         self._keep = {}
 
-    def submit(self, labels, iterations=20, relaxation=0.5, constraint=1.0, **vol_kw) -> int:
+    def submit(self, labels, iterations=20, relaxation=0.5, constraint=1.0, shape="box",
+               **vol_kw) -> int:
         v, keep = make_volume(labels, **vol_kw)
-        p = smooth_params(iterations, relaxation, constraint)
+        p = smooth_params(iterations, relaxation, constraint, shape)
         t = ctypes.c_uint64()
         _check(_lib.sn_serve_submit(self._h, ctypes.byref(v), ctypes.byref(p), ctypes.byref(t)))
         self._keep[int(t.value)] = keep

@@ -120,6 +120,7 @@ struct SmoothDesc {
     float *da;
     float *db;
     int32_t iters;
+    int32_t sphere;  // constraint: 0 box of half-width dist, 1 sphere of radius dist
     double lam;
     double dist;
     // the last sweep also writes world points when pcell is set:

@@ -1145,7 +1145,8 @@ __device__ __forceinline__ uint32_t udiv(uint32_t n, const UDiv &u)
     return (t + ((n - t) >> u.s1)) >> u.s2;
 }
 
-// Clamp to the box, store the offset, and in the mesh's last sweep also the
+// Hold the offset in the constraint region (a box of half-width d per axis, or
+// a sphere of radius d), store it, and in the mesh's last sweep also the
 // world point origin + spacing * (cell centre + stored offset), from the
 // point's cell index (the world-coordinate output, fused into the sweep).
 // NT: streaming (non-temporal) stores, for meshes whose sweep data does not
@@ -1155,9 +1156,19 @@ __device__ __forceinline__ void store_offset(const SmoothDesc &s, SN_GLOBAL floa
                                              double x, double y, double z, bool last, uint32_t cell)
 {
     const double c = s.dist;
-    const float fx = (float)fmin(fmax(x, -c), c);
-    const float fy = (float)fmin(fmax(y, -c), c);
-    const float fz = (float)fmin(fmax(z, -c), c);
+    if (s.sphere) {
+        // back onto the sphere of radius c around the cell centre
+        const double l2 = x * x + y * y + z * z;
+        if (l2 > c * c) {
+            const double f = c / sqrt(l2);
+            x *= f, y *= f, z *= f;
+        }
+    } else {
+        x = fmin(fmax(x, -c), c);
+        y = fmin(fmax(y, -c), c);
+        z = fmin(fmax(z, -c), c);
+    }
+    const float fx = (float)x, fy = (float)y, fz = (float)z;
     if constexpr (NT) {
         __builtin_nontemporal_store(fx, dout + 3 * p);
         __builtin_nontemporal_store(fy, dout + 3 * p + 1);

@@ -983,6 +983,8 @@ sn_status sn::validate_smooth(const sn_smooth_params *p)
         return fail(SN_EINVAL, "relaxation must be in [0, 1]");
     if (!(p->constraint >= 0.f) || !std::isfinite(p->constraint))
         return fail(SN_EINVAL, "constraint must be >= 0 and finite");
+    if (p->shape != SN_BOX && p->shape != SN_SPHERE)
+        return fail(SN_EINVAL, "constraint shape must be SN_BOX or SN_SPHERE");
     return SN_OK;
 }
 
@@ -1006,6 +1008,7 @@ static void fill_smooth_desc(const sn_mesh *m, const sn_smooth_params &p, Smooth
     sd->P = m->P, sd->faces = m->d.faces, sd->off = m->d.st_off, sd->ids = m->d.st_ids;
     sd->nbr = m->nbr, sd->da = m->da, sd->db = m->db, sd->iters = p.iterations;
     sd->lam = (double)p.relaxation, sd->dist = (double)p.constraint;
+    sd->sphere = p.shape == SN_SPHERE ? 1 : 0;
     sd->pcell = m->d.pcell, sd->points = m->d.points;
     sd->CM = make_udiv((uint32_t)std::max<int64_t>(m->d.g.CM, 1));
     sd->CN = make_udiv((uint32_t)std::max<int64_t>(m->d.g.CN, 1));

@@ -72,7 +72,7 @@ def test_struct_layouts_match_header():
 
     # sizes implied by the C declarations (x86-64 SysV alignment)
     assert ctypes.sizeof(sn.sn_volume) == 8 + 4 + 4 + 24 + 24 + 24 + 8 + 4 + 4 + 4 + 4
-    assert ctypes.sizeof(sn.sn_smooth_params) == 12
+    assert ctypes.sizeof(sn.sn_smooth_params) == 16
     assert ctypes.sizeof(sn.sn_mesh_view) == 4 * 8 + 2 * 4 + 7 * 8
     assert ctypes.sizeof(sn.sn_serve_config) == 8 + 4 * 4
     assert ctypes.sizeof(sn.sn_serve_stats) == 6 * 8 + 4 * 8 + 8

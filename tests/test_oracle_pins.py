@@ -249,6 +249,52 @@ def test_smoothing_cube_closed_form(orc, lam, d, n):
     np.testing.assert_allclose(np.abs(p - 1.0), s, rtol=0, atol=1e-14)
 
 
+@pytest.mark.parametrize("lam,d,n", [(0.5, 1.0, 16), (0.5, 0.2, 16), (1.0, 1.0, 7), (0.3, 0.45, 40),
+                                     (1.5, 1.0, 5)])
+def test_smoothing_cube_closed_form_sphere(orc, lam, d, n):
+    """Single voxel, sphere constraint: the points move along the cube's
+    diagonals, so a displacement of u per axis has length sqrt(3) u and the
+    sphere of radius d binds at u = d / sqrt(3):
+    s_{t+1} = max(1/2 - d / sqrt(3), s_t (1 - 2 lambda / 3))."""
+    v = np.zeros((3, 3, 3), np.uint8)
+    v[1, 1, 1] = 1
+    m = orc.extract(v)
+    p = m.smooth(n, lam, d, shape="sphere")
+    s = max(0.5 - d / np.sqrt(3.0), 0.5 * (1 - 2 * lam / 3) ** n)
+    np.testing.assert_allclose(np.abs(p - 1.0), s, rtol=0, atol=1e-14)
+
+
+def test_smoothing_sphere_off_diagonal(orc):
+    """Two labelled samples (1,1,1), (2,1,1): one sweep with lambda = 1 from
+    the centres.  The middle cell (1,0,0) has neighbours -x, +x, +y, +z, so
+    it moves by (0, 1/4, 1/4) (length 0.354); the corner cell (0,0,0) has
+    +x, +y, +z and moves by (1/3, 1/3, 1/3) (length 0.577).  The sphere of
+    radius 0.3 scales both back to length 0.3 along the same directions; the
+    box of half-width 0.3 leaves the first and clamps the second per axis."""
+    v = np.zeros((3, 3, 4), np.uint16)  # [O][N][M]
+    v[1, 1, 1] = v[1, 1, 2] = 5
+    m = orc.extract(v)
+    c = m.centres()
+    mid = int(np.flatnonzero(np.all(c == (1.5, 0.5, 0.5), axis=1))[0])
+    cor = int(np.flatnonzero(np.all(c == (0.5, 0.5, 0.5), axis=1))[0])
+    ps = m.smooth(1, 1.0, 0.3, shape="sphere") - c
+    pb = m.smooth(1, 1.0, 0.3) - c
+    r = 0.3 / np.sqrt(2.0)
+    np.testing.assert_allclose(ps[mid], (0.0, r, r), atol=1e-15)
+    np.testing.assert_allclose(ps[cor], (0.3 / np.sqrt(3.0),) * 3, atol=1e-15)
+    np.testing.assert_allclose(pb[mid], (0.0, 0.25, 0.25), atol=1e-15)
+    np.testing.assert_allclose(pb[cor], (0.3, 0.3, 0.3), atol=1e-15)
+
+
+@pytest.mark.parametrize("lam,d", [(0.5, 1.0), (1.0, 0.3), (0.9, 0.05)])
+def test_smoothing_constraint_sphere(orc, lam, d):
+    m = _sample_mesh(orc, seed=12)
+    p = m.smooth(30, lam, d, shape="sphere")
+    assert np.max(np.linalg.norm(p - m.centres(), axis=1)) <= d + 1e-12
+    # a radius no point reaches constrains nothing: the same as a box that large
+    np.testing.assert_array_equal(m.smooth(9, lam, 50.0, shape="sphere"), m.smooth(9, lam, 50.0))
+
+
 def test_smoothing_linear_part_scipy(orc):
     """With an inactive constraint the n sweeps are the linear map
     (I - lambda (I - D^-1 A))^n applied to the centres; A is built here from
