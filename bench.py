@@ -397,6 +397,53 @@ def bench_triangulate(ctx, sn, torch, vol, reps=10):
     return out
 
 
+def bench_label_sweep(ctx, sn, torch, counts=(1, 2, 4, 8, 16, 32, 64, 128), steps=3):
+    """Extraction + 25 sweeps of the paper-scale synthetic volume (512^3 u16,
+    128 spheres) with the first k labels selected, k = 1 .. 128: the effect of
+    the number of extracted objects on the run time.  Kernel times from HIP
+    events around every launch; whole steps from the wall clock."""
+    import synth
+
+    vol = synth.synthetic_spheres()
+    t = sn.to_device(vol.labels)
+    V = int(vol.labels.size)
+    rows = []
+    for k in counts:
+        sel = tuple(range(1, k + 1))
+
+        def step():
+            m = ctx.extract(t, selected=sel)
+            ctx.smooth(m, iterations=vol.iterations, relaxation=vol.relaxation,
+                       constraint=vol.constraint)
+            v = m.view()
+            n = (int(v.n_points), int(v.n_quads))
+            m.free()
+            return n
+
+        step()
+        torch.cuda.synchronize()
+        ctx.profile(True)
+        ctx.profile_reset()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            P, Q = step()
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / steps
+        prof = ctx.profile_read()
+        ctx.profile(False)
+        ext = sum(prof.get(n_, (0, 0.0))[1] for n_ in ("k_edges", "k_count", "k_generate")) / steps
+        smo = prof.get("k_jacobi", (0, 0.0))[1] / steps
+        rows.append({"labels": k, "points": P, "quads": Q, "ms_per_step": round(1e3 * wall, 3),
+                     "extract_kernel_ms": round(ext, 3), "smooth_kernel_ms": round(smo, 3),
+                     "extract_gvox_per_s": round(V / (ext * 1e-3) / 1e9, 2) if ext > 0 else None})
+        log(f"[bench] label sweep: {k} labels, {1e3 * wall:.2f} ms/step, P {P}")
+    base = rows[0]["ms_per_step"]
+    for r in rows:
+        r["relative_time"] = round(r["ms_per_step"] / base, 3)
+    del t
+    return {"volume": vol.name, "steps": steps, "rows": rows}
+
+
 COPY_PROBE_BYTES = 256 << 20
 
 
@@ -546,6 +593,7 @@ def main():
         extra["batched"] = bench_batched(ctx, sn, torch)
         extra["served"] = bench_served(ctx, sn, torch)
         extra["triangulate"] = bench_triangulate(ctx, sn, torch, vol)
+        extra["label_sweep"] = bench_label_sweep(ctx, sn, torch)
 
     cpu = None if args.no_cpu else cpu_baseline(vol)
     line = {

@@ -165,6 +165,20 @@ def spheres_small(seed: int = 1) -> Volume:
                   meta={"seed": seed})
 
 
+def synthetic_spheres(seed: int = 6, n: int = 512, count: int = 128) -> Volume:
+    """n^3 uint16 with `count` overlapping balls labelled 1..count (a later
+    label overwrites an earlier one), background 0: the shape of the paper's
+    Synthetic dataset (512^3, 128 spheres, 129 labels with the background).
+    Radii ~ U[n/32, n/8], centres uniform inside the volume.  25 iterations,
+    relaxation 0.5, constraint 1.0."""
+    rng = np.random.default_rng(seed)
+    r = rng.uniform(n / 32, n / 8, size=count)
+    c = rng.uniform(0, n, size=(count, 3))
+    lab = spheres((n, n, n), 2, c, r, np.arange(1, count + 1))
+    return Volume(lab, iterations=25, relaxation=0.5, constraint=1.0,
+                  name=f"synthetic_spheres_{n}^3_u16_{count}", meta={"seed": seed})
+
+
 def torso_like(seed: int = 2, n: int = 256) -> Volume:
     """n^3 uint16, spacing (1, 1, 2.5); 100 Voronoi cells (seeds uniform over
     the world box, label = nearest seed + 1, ties to the lower index) clipped

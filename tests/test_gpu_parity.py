@@ -333,3 +333,13 @@ def test_sphere_constraint(ctx, sn, torch):
             g = m.to_host()
             m.free()
         assert np.array_equal(h_.offsets, g.offsets) and np.array_equal(h_.points, g.points), k
+
+
+def test_label_subsets_of_many_spheres(ctx, sn, torch):
+    """The label-count workload at reduced size (96^3 u16, 32 overlapping
+    spheres): the first k labels selected, k = 1, 5, 32, against the oracle
+    (topology bit-exact, smoothed offsets and world points to the bar)."""
+    vol = synth.synthetic_spheres(seed=7, n=96, count=32)
+    for k in (1, 5, 32):
+        announce(f"label subset: first {k} of 32 spheres")
+        run_case(ctx, sn, vol.labels, selected=tuple(range(1, k + 1)), iters=25, lam=0.5, d=1.0)
