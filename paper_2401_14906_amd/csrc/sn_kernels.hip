@@ -879,11 +879,20 @@ __device__ __forceinline__ void generate_group(const VolDesc &d, int64_t grp, in
         j = (int32_t)((uint32_t)r % (uint32_t)g.CN);
         k = (int32_t)((uint32_t)r / (uint32_t)g.CN);
     }
+    bool need = live;
+    if constexpr (!STAGE) {
+        // sparse meshes: a word without points (the point bits k_count left)
+        // has no outputs, so its plane words and neighbour rows are not read,
+        // and a group without points ends here
+        if (live) need = glb(d.pmask)[gw] != 0;
+        if (__builtin_amdgcn_ballot_w64(need) == 0) return;
+    }
     PlaneWords p{};
     uint64_t nm[5] = {0, 0, 0, 0, 0};
     int32_t nb[5] = {0, 0, 0, 0, 0};
     int32_t own_p = 0, own_q = 0, own_s = 0;
-    if (live) {
+    if (live && lane == 0) own_p = glb(d.wbP)[gw], own_q = glb(d.wbQ)[gw], own_s = glb(d.wbS)[gw];
+    if (need) {
         p = plane_words(glb(d.planes), g.N * g.O * g.WS, g.WS, j + g.N * (int64_t)k, g.N, w);
         const bool ex[5] = {j >= 1, j + 1 <= g.CN - 1, k >= 1, k + 1 <= g.CO - 1, j >= 1 && k >= 1};
         const int64_t dr[5] = {-1, 1, -g.CN, g.CN, -g.CN - 1};
@@ -894,7 +903,6 @@ __device__ __forceinline__ void generate_group(const VolDesc &d, int64_t grp, in
                 nm[n] = glb(d.pmask)[nw];
                 nb[n] = glb(d.wbP)[nw];
             }
-        if (lane == 0) own_p = glb(d.wbP)[gw], own_q = glb(d.wbQ)[gw], own_s = glb(d.wbS)[gw];
     }
     const WordMasks m = word_masks(p, w, j, k, g);  // all zero for lanes without a word
     const int32_t np = __popcll(m.pt);
