@@ -46,7 +46,9 @@ constexpr int64_t kGenStagedPointsPerWord = 8;
 constexpr int kCountWaves = 16;
 constexpr int kCountBlock = 64 * kCountWaves;
 constexpr int kCountWideV = 4;
-constexpr int64_t kCountWideWords = int64_t(1) << 22;
+// (measured: 2.1 M words count in 48 us wide against 68 us narrow; 260 K
+// words in 15.5 us narrow against 21 us wide)
+constexpr int64_t kCountWideWords = int64_t(1) << 18;
 
 // Sample lattice M x N x O; cell grid CM x CN x CO = (M-1)(N-1)(O-1).
 // Cut-edge planes (k_edges) hold one bit per sample, WS words per sample row,
