@@ -682,6 +682,15 @@ static sn_status wait_totals(const int64_t *stamps, const std::vector<char> &cou
     return SN_OK;
 }
 
+// As HIP_TRY, releasing the meshes of a failed extraction (the `cleanup`
+// of extract_many) before returning.
+#define HIP_TRY_CLEANUP(expr)                                                                      \
+    do {                                                                                           \
+        hipError_t _e = (expr);                                                                    \
+        if (_e != hipSuccess)                                                                      \
+            return cleanup(fail(SN_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(_e)));   \
+    } while (0)
+
 sn_status sn::extract_many(sn_ctx *c, const sn_volume *vols, int32_t n, hipStream_t s,
                            int32_t bpw_override, sn_mesh **out)
 {
@@ -838,19 +847,19 @@ sn_status sn::extract_many(sn_ctx *c, const sn_volume *vols, int32_t n, hipStrea
         std::memcpy(h_tp + (n + 1), etile_prefix.data(), sizeof(int64_t) * (n + 1));
         std::memcpy(h_tp + 2 * (n + 1), ctile_prefix.data(), sizeof(int64_t) * (n + 1));
     }
-    if (up_a > 0) HIP_TRY(hipMemcpyAsync(d_up, h_up, up_a, hipMemcpyHostToDevice, s));
+    if (up_a > 0) HIP_TRY_CLEANUP(hipMemcpyAsync(d_up, h_up, up_a, hipMemcpyHostToDevice, s));
     // the first edges launch clears the count pass's status words and ticket
     const int64_t nzero = (int64_t)((status_bytes + 256) / 8);
     {
         ProfScope ps(c, "k_edges", s);
         if (one) {
-            HIP_TRY(launch_edges_one(hd[0], wide(order[0]), etile_prefix[1], status, nzero, s));
+            HIP_TRY_CLEANUP(launch_edges_one(hd[0], wide(order[0]), etile_prefix[1], status, nzero, s));
         } else {
             bool zeroed = false;
             for (int32_t gi = 0; gi < ngroups; ++gi) {
                 const int32_t k0 = gbeg[gi], k1 = gbeg[gi + 1];
                 const int64_t nt = etile_prefix[k1] - etile_prefix[k0];
-                HIP_TRY(launch_edges(hd[k0].dtype, hd[k0].cs.mode, wide(order[k0]), d_desc + k0,
+                HIP_TRY_CLEANUP(launch_edges(hd[k0].dtype, hd[k0].cs.mode, wide(order[k0]), d_desc + k0,
                                      d_tp + (n + 1) + k0, k1 - k0, etile_prefix[k0], nt, status,
                                      (nt > 0 && !zeroed) ? nzero : 0, s));
                 zeroed = zeroed || nt > 0;
@@ -862,9 +871,9 @@ sn_status sn::extract_many(sn_ctx *c, const sn_volume *vols, int32_t n, hipStrea
     {
         ProfScope ps(c, "k_count", s);
         if (one)
-            HIP_TRY(launch_count_one(hd[0], nctiles, cv, status, ticket, cout, s));
+            HIP_TRY_CLEANUP(launch_count_one(hd[0], nctiles, cv, status, ticket, cout, s));
         else
-            HIP_TRY(launch_count(d_desc, d_tp + 2 * (n + 1), n, nctiles, cv, status, ticket, cout, s));
+            HIP_TRY_CLEANUP(launch_count(d_desc, d_tp + 2 * (n + 1), n, nctiles, cv, status, ticket, cout, s));
     }
     {
         std::vector<char> counted(n);
@@ -916,11 +925,11 @@ sn_status sn::extract_many(sn_ctx *c, const sn_volume *vols, int32_t n, hipStrea
         {
             ProfScope ps(c, "k_generate", s);
             const bool staged = hd[0].P >= kGenStagedPointsPerWord * hd[0].g.R * hd[0].g.W;
-            HIP_TRY(launch_generate_one(hd[0], staged, tile_prefix[1], bpw, s));
+            HIP_TRY_CLEANUP(launch_generate_one(hd[0], staged, tile_prefix[1], bpw, s));
         }
         if (qblocks > 0) {
             ProfScope ps(c, "k_tri", s);
-            HIP_TRY(launch_triangulate_one(hd[0], s));
+            HIP_TRY_CLEANUP(launch_triangulate_one(hd[0], s));
         }
     } else {
         // second upload: descriptors with the output arrays, and the triangle
@@ -937,7 +946,7 @@ sn_status sn::extract_many(sn_ctx *c, const sn_volume *vols, int32_t n, hipStrea
             if (hd[k].prim == SN_TRIS) acc += (hd[k].Q + 255) / 256;
         }
         h_qp[n] = acc;
-        HIP_TRY(hipMemcpyAsync(d_b, h_b, up_b, hipMemcpyHostToDevice, s));
+        HIP_TRY_CLEANUP(hipMemcpyAsync(d_b, h_b, up_b, hipMemcpyHostToDevice, s));
         VolDesc *d_desc2 = reinterpret_cast<VolDesc *>(d_b);
         {
             ProfScope ps(c, "k_generate", s);
@@ -946,13 +955,13 @@ sn_status sn::extract_many(sn_ctx *c, const sn_volume *vols, int32_t n, hipStrea
                 int64_t gp = 0, gw = 0;
                 for (int32_t k = k0; k < k1; ++k) gp += hd[k].P, gw += hd[k].g.R * hd[k].g.W;
                 const bool staged = gp >= kGenStagedPointsPerWord * gw;
-                HIP_TRY(launch_generate(hd[k0].dtype, hd[k0].cs.mode, staged, d_desc2 + k0, d_tp + k0, k1 - k0,
+                HIP_TRY_CLEANUP(launch_generate(hd[k0].dtype, hd[k0].cs.mode, staged, d_desc2 + k0, d_tp + k0, k1 - k0,
                                         tile_prefix[k0], tile_prefix[k1] - tile_prefix[k0], bpw, s));
             }
         }
         if (qblocks > 0) {
             ProfScope ps(c, "k_tri", s);
-            HIP_TRY(launch_triangulate(d_desc2, reinterpret_cast<int64_t *>(d_b + sizeof(VolDesc) * n),
+            HIP_TRY_CLEANUP(launch_triangulate(d_desc2, reinterpret_cast<int64_t *>(d_b + sizeof(VolDesc) * n),
                                        n, acc, s));
         }
     }
@@ -964,6 +973,8 @@ sn_status sn::extract_many(sn_ctx *c, const sn_volume *vols, int32_t n, hipStrea
     for (int32_t v = 0; v < n; ++v) out[v] = meshes[v];
     return SN_OK;
 }
+
+#undef HIP_TRY_CLEANUP
 
 extern "C" sn_status sn_extract(sn_ctx *c, const sn_volume *vol, void *stream, sn_mesh **out)
 {
