@@ -343,3 +343,29 @@ def test_label_subsets_of_many_spheres(ctx, sn, torch):
     for k in (1, 5, 32):
         announce(f"label subset: first {k} of 32 spheres")
         run_case(ctx, sn, vol.labels, selected=tuple(range(1, k + 1)), iters=25, lam=0.5, d=1.0)
+
+
+def test_extreme_aspect_ratios(ctx, sn, torch):
+    """Rows far longer than a group (100 000 samples: 1 563 words per row, the
+    x-neighbour distances of the sweeps and the row division of the world
+    points at their widest), columns of one-cell rows (a group spans 32 rows),
+    and a thin slab, each against the oracle, smoothed with both constraints."""
+    rng = np.random.default_rng(51)
+    cases = [((100_000, 3, 3), np.uint16, 7), ((3, 4, 70_000), np.uint8, 4),
+             ((4, 40_000, 3), np.uint32, 9), ((700, 500, 3), np.uint16, 6)]
+    for dims, dt, nv in cases:
+        M, N, O = dims
+        vol = synth.blocky_tiny(rng, dims, nv, dt)
+        announce(f"extreme aspect {dims} {np.dtype(dt).name}")
+        run_case(ctx, sn, vol, iters=6, lam=0.7, d=0.8, spacing=(0.5, 1.0, 3.0))
+        t = sn.to_device(vol)
+        m = ctx.extract(t)
+        ctx.smooth(m, iterations=6, relaxation=0.7, constraint=0.8, shape="sphere")
+        g = m.to_host()
+        m.free()
+        import oracle
+
+        o = oracle.extract(vol)
+        if o.n_points:
+            ref = o.smooth(6, 0.7, 0.8, shape="sphere") - o.centres()
+            assert np.max(np.abs(g.offsets.astype(np.float64) - ref)) <= TOL
