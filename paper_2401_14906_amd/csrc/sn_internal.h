@@ -133,16 +133,17 @@ struct SmoothDesc {
     double origin[3], spacing[3];
 };
 
-// A smoothing block covers kBlock * K consecutive points: each wave holds K
+// A smoothing block covers kSweepBlock * K consecutive points: each wave holds K
 // chunks of 64 points.  Meshes of up to kSweepSmallPoints points (their sweep
 // data fits the last-level cache; latency decides) run with K = 1, more and
 // shorter waves, and XCD-contiguous blocks; larger ones (bandwidth decides)
 // with K = 2 and the hardware's round-robin block order.
 constexpr int64_t kSweepSmallPoints = int64_t(1) << 22;
 inline int sweep_chunks(int64_t points) { return points <= kSweepSmallPoints ? 1 : 2; }
+constexpr int kSweepBlock = 256;  // threads per smoothing workgroup
 inline int64_t sweep_blocks_for(int64_t points, int K)
 {
-    return (points + (int64_t)kBlock * K - 1) / ((int64_t)kBlock * K);
+    return (points + (int64_t)kSweepBlock * K - 1) / ((int64_t)kSweepBlock * K);
 }
 
 // Scan tile status word: [63:62] flag, [61:0] value.
@@ -183,7 +184,7 @@ hipError_t launch_generate(int32_t dtype, int32_t mode, bool staged, const VolDe
 // k_emit: d_sds[v] (iterations, ping-pong buffers) names volume v's final offsets
 hipError_t launch_emit(const VolDesc *d_descs, const SmoothDesc *d_sds, const int64_t *d_tile_prefix,
                        int32_t nvol, int64_t ntiles, int32_t bpw, hipStream_t s);
-// block_prefix[v] = first block of volume v (kBlock * K points per block, K
+// block_prefix[v] = first block of volume v (kSweepBlock * K points per block, K
 // from sweep_chunks of the launch's points); it = 0 runs the first sweep
 // (zero input offsets, builds nbr)
 hipError_t launch_jacobi(const SmoothDesc *d_sd, const int64_t *d_block_prefix, int32_t nvol,

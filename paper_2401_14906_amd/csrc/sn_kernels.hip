@@ -1206,7 +1206,7 @@ __device__ __forceinline__ uint32_t sweep_blocks(const ManySmooth &) { return gr
 template <int K>
 __device__ __forceinline__ uint32_t sweep_blocks(const OneSmooth &a)
 {
-    return (uint32_t)((a.s.P + kBlock * K - 1) / (kBlock * K));
+    return (uint32_t)((a.s.P + kSweepBlock * K - 1) / (kSweepBlock * K));
 }
 
 // Logical block of a sweep.  Small meshes (K = 1), whose sweep data fits the
@@ -1231,7 +1231,7 @@ __device__ __forceinline__ void jacobi_first_body(const Src &a)
     SN_GLOBAL float *dout = glb(s.db);
 #pragma unroll
     for (int c = 0; c < K; ++c) {
-        const int64_t p = (b - first) * (kBlock * K) + c * kBlock + threadIdx.x;
+        const int64_t p = (b - first) * (kSweepBlock * K) + c * kSweepBlock + threadIdx.x;
         if (p >= s.P) break;
         const uint32_t f = glb(s.faces)[p];
         const int n = __popc(f);
@@ -1264,7 +1264,7 @@ __device__ __forceinline__ void jacobi_first_body(const Src &a)
 }
 
 template <int K>
-__global__ __launch_bounds__(256) void k_jacobi_first(const SmoothDesc *__restrict__ sds,
+__global__ __launch_bounds__(kSweepBlock) void k_jacobi_first(const SmoothDesc *__restrict__ sds,
                                                       const int64_t *__restrict__ prefix,
                                                       int32_t nvol)
 {
@@ -1272,7 +1272,7 @@ __global__ __launch_bounds__(256) void k_jacobi_first(const SmoothDesc *__restri
 }
 
 template <int K>
-__global__ __launch_bounds__(256) void k_jacobi_first_one(OneSmooth a)
+__global__ __launch_bounds__(kSweepBlock) void k_jacobi_first_one(OneSmooth a)
 {
     jacobi_first_body<K>(a);
 }
@@ -1310,7 +1310,7 @@ __device__ __forceinline__ void jacobi_body(const Src &a, int32_t it)
     const SmoothDesc &s = smooth_of(a, b, first);
     if (it >= s.iters) return;  // this mesh has finished its sweeps
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
-    const int64_t p0 = (b - first) * (kBlock * K) + (int64_t)wave * (64 * K);
+    const int64_t p0 = (b - first) * (kSweepBlock * K) + (int64_t)wave * (64 * K);
     const int64_t P = s.P;
     if (p0 >= P) return;
     const SN_GLOBAL float *din = glb((it & 1) ? s.db : s.da);
@@ -1407,7 +1407,7 @@ __device__ __forceinline__ void jacobi_body(const Src &a, int32_t it)
 }
 
 template <int K>
-__global__ __launch_bounds__(256) void k_jacobi(const SmoothDesc *__restrict__ sds,
+__global__ __launch_bounds__(kSweepBlock) void k_jacobi(const SmoothDesc *__restrict__ sds,
                                                 const int64_t *__restrict__ prefix, int32_t nvol,
                                                 int32_t it)
 {
@@ -1415,7 +1415,7 @@ __global__ __launch_bounds__(256) void k_jacobi(const SmoothDesc *__restrict__ s
 }
 
 template <int K>
-__global__ __launch_bounds__(256) void k_jacobi_one(OneSmooth a, int32_t it)
+__global__ __launch_bounds__(kSweepBlock) void k_jacobi_one(OneSmooth a, int32_t it)
 {
     jacobi_body<K>(a, it);
 }
@@ -1703,10 +1703,10 @@ static void jacobi_k(const SmoothDesc *d_sd, const int64_t *d_block_prefix, int3
                      int64_t nblocks, int32_t it, hipStream_t s)
 {
     if (it == 0)
-        hipLaunchKernelGGL(k_jacobi_first<K>, dim3((uint32_t)nblocks), dim3(256), 0, s, d_sd,
+        hipLaunchKernelGGL(k_jacobi_first<K>, dim3((uint32_t)nblocks), dim3(kSweepBlock), 0, s, d_sd,
                            d_block_prefix, nvol);
     else
-        hipLaunchKernelGGL(k_jacobi<K>, dim3((uint32_t)nblocks), dim3(256), 0, s, d_sd,
+        hipLaunchKernelGGL(k_jacobi<K>, dim3((uint32_t)nblocks), dim3(kSweepBlock), 0, s, d_sd,
                            d_block_prefix, nvol, it);
 }
 
@@ -1714,10 +1714,10 @@ template <int K>
 static void jacobi_one_k(const SmoothDesc &sd, int64_t nblocks, int32_t it, hipStream_t s)
 {
     if (it == 0)
-        hipLaunchKernelGGL(k_jacobi_first_one<K>, dim3((uint32_t)nblocks), dim3(256), 0, s,
+        hipLaunchKernelGGL(k_jacobi_first_one<K>, dim3((uint32_t)nblocks), dim3(kSweepBlock), 0, s,
                            OneSmooth{sd});
     else
-        hipLaunchKernelGGL(k_jacobi_one<K>, dim3((uint32_t)nblocks), dim3(256), 0, s, OneSmooth{sd},
+        hipLaunchKernelGGL(k_jacobi_one<K>, dim3((uint32_t)nblocks), dim3(kSweepBlock), 0, s, OneSmooth{sd},
                            it);
 }
 
@@ -1758,7 +1758,7 @@ hipError_t add_jacobi_nodes(hipGraph_t graph, const SmoothDesc *d_sd,
                           : (K == 1 ? reinterpret_cast<void *>(&k_jacobi<1>)
                                     : reinterpret_cast<void *>(&k_jacobi<2>));
         kp.gridDim = dim3((uint32_t)nblocks);
-        kp.blockDim = dim3(256);
+        kp.blockDim = dim3(kSweepBlock);
         kp.sharedMemBytes = 0;
         kp.kernelParams = it == 0 ? args_first : args;
         kp.extra = nullptr;
