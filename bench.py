@@ -565,13 +565,14 @@ def main():
     log(f"[bench] {vol.name}: {res['ms_per_step']:.3f} ms/step, {res['gvox_per_s']:.2f} Gvox/s")
 
     probe = copy_probe(torch) if args.copy_probe else None
-    traffic = None
-    dom = roofline_of(res)["kernel"]
-    if os.path.exists(args.traffic_json):
-        tj = json.load(open(args.traffic_json)).get(args.workload, {})
-        if dom in tj:
-            traffic = tj[dom]["bytes"]
-    roof = roofline_of(res, traffic)
+    tj_all = json.load(open(args.traffic_json)) if os.path.exists(args.traffic_json) else {}
+
+    def traffic_for(workload, r):
+        """Counter-measured HBM bytes per launch of r's dominant kernel, if recorded."""
+        entry = tj_all.get(workload, {}).get(roofline_of(r)["kernel"])
+        return entry["bytes"] if entry else None
+
+    roof = roofline_of(res, traffic_for(args.workload, res))
 
     extra = {}
     if not args.no_extra:
@@ -586,7 +587,7 @@ def main():
                 "extract_frac_hbm": round(r3["extract_frac_hbm"], 4),
                 "smooth_gptit_per_s": round(r3["smooth_gptit_per_s"], 3),
                 "points": r3["points"], "quads": r3["quads"],
-                "roofline": roofline_of(r3),
+                "roofline": roofline_of(r3, traffic_for("connectome", r3)),
                 "kernels": {k: {kk: (round(vv, 3) if isinstance(vv, float) else vv)
                                 for kk, vv in d.items()} for k, d in r3["kernels"].items()}}
             del cvol
