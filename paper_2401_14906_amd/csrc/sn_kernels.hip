@@ -1199,8 +1199,8 @@ __device__ __forceinline__ void store_offset(const SmoothDesc &s, SN_GLOBAL floa
 // Sweep 0: every input offset is zero, so p_q - p_p is the face step alone.
 // Reads the CSR stencil once and writes the y/z neighbour table.
 // Blocks of a sweep launch that carry points: a launch over many meshes has
-// exactly those; a single mesh may run on a larger cached grid whose extra
-// blocks leave at once (and must not take part in the XCD remap).
+// exactly those; for a single mesh they follow from its point count, so any
+// blocks of a larger grid leave at once (and take no part in the XCD remap).
 template <int K>
 __device__ __forceinline__ uint32_t sweep_blocks(const ManySmooth &) { return gridDim.x; }
 template <int K>

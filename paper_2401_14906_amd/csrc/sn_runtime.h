@@ -142,7 +142,7 @@ sn_status extract_many(sn_ctx *c, const sn_volume *vols, int32_t n, hipStream_t 
                        int32_t bpw_override, sn_mesh **out);
 sn_status smooth_many(sn_ctx *c, sn_mesh **ms, const sn_smooth_params *pv, int32_t n,
                       hipStream_t s);
-// the plain path of one mesh (cached sweep graph, descriptors by value)
+// the plain path of one mesh (sweeps launched one by one, descriptor by value)
 sn_status smooth_one(sn_ctx *c, sn_mesh *m, const sn_smooth_params *p, hipStream_t s);
 sn_status ensure_smooth_buffers(sn_mesh *m);
 // sweep `it` of grid.size() sweeps launches grid[it] blocks

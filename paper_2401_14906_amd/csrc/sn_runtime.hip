@@ -460,9 +460,11 @@ sn_status sn::validate_volume(const sn_volume *v)
     const bool empty = v->dims[0] < 2 || v->dims[1] < 2 || v->dims[2] < 2;
     if (!v->labels && !empty) return fail(SN_EINVAL, "labels is NULL");
     {
-        // the kernels index rows, words and batches of one volume with int32
+        // the kernels index rows, words and batches of one volume with int32;
+        // the factors are bounded first, so that no product overflows int64
         const Geom g = make_geom(*v);
-        if (g.R * g.W >= INT32_MAX || g.R * g.NB >= INT32_MAX || g.N * g.O * g.NSEG >= INT32_MAX)
+        if (g.R >= INT32_MAX || g.N * g.O >= INT32_MAX || g.R * g.W >= INT32_MAX ||
+            g.R * g.NB >= INT32_MAX || g.N * g.O * g.NSEG >= INT32_MAX)
             return fail(SN_ETOOBIG, "volume has more than 2^31 cell words or sample segments");
     }
     return SN_OK;
@@ -1196,7 +1198,14 @@ sn_status sn::smooth_many(sn_ctx *c, sn_mesh **ms, const sn_smooth_params *pv, i
     }
     std::memcpy(h_p, bp.data(), sizeof(int64_t) * (n + 1));
     std::memcpy(h_p + n + 1, tp.data(), sizeof(int64_t) * (n + 1));
-    HIP_TRY(hipMemcpyAsync(d_up, h_up, up, hipMemcpyHostToDevice, s));
+    // the scratch blocks go back to the pool behind the stream's work, also on failure
+    auto device_fail = [&](hipError_t e, const char *what) {
+        (void)hipGetLastError();
+        scr.retire(s);
+        return fail(SN_EDEVICE, std::string("batch smooth: ") + what + ": " + hipGetErrorString(e));
+    };
+    if (hipError_t e = hipMemcpyAsync(d_up, h_up, up, hipMemcpyHostToDevice, s); e != hipSuccess)
+        return device_fail(e, "descriptor upload");
     sn_status st = run_sweeps(c, d_sd, d_p, n, grid, K, s);
     if (st != SN_OK) {
         scr.retire(s);
@@ -1207,11 +1216,14 @@ sn_status sn::smooth_many(sn_ctx *c, sn_mesh **ms, const sn_smooth_params *pv, i
     if (need_emit) {  // meshes whose last sweep wrote the points skip inside k_emit
         ProfScope ps(c, "k_emit", s);
         if (same_bpw) {
-            HIP_TRY(launch_emit(d_vd, d_sd, d_p + n + 1, n, tp[n], ms[0]->bpw, s));
+            if (hipError_t e = launch_emit(d_vd, d_sd, d_p + n + 1, n, tp[n], ms[0]->bpw, s); e != hipSuccess)
+                return device_fail(e, "k_emit");
         } else {
             for (int32_t k = 0; k < n; ++k)
-                HIP_TRY(launch_emit(d_vd + k, d_sd + k, d_p + 2 * (n + 1) + 2 * k, 1,
-                                    ms[ord[k]]->ntiles, ms[ord[k]]->bpw, s));
+                if (hipError_t e = launch_emit(d_vd + k, d_sd + k, d_p + 2 * (n + 1) + 2 * k, 1,
+                                               ms[ord[k]]->ntiles, ms[ord[k]]->bpw, s);
+                    e != hipSuccess)
+                    return device_fail(e, "k_emit");
         }
     }
     scr.retire(s);
@@ -1261,7 +1273,12 @@ extern "C" sn_status sn_autotune(sn_ctx *c, const sn_volume *vol, void *stream, 
     const int32_t cands[] = {1, 2, 3, 4, 8};
     double best = 1e30;
     int32_t arg = 2;
-    const bool was = c->profiling;
+    // the timed runs record no profiling events; the setting is restored on every return
+    struct ProfilingOff {
+        sn_ctx *c;
+        bool was;
+        ~ProfilingOff() { c->profiling = was; }
+    } off{c, c->profiling};
     c->profiling = false;
     for (int32_t bpw : cands) {
         double tbest = 1e30;
@@ -1270,18 +1287,15 @@ extern "C" sn_status sn_autotune(sn_ctx *c, const sn_volume *vol, void *stream, 
             auto t0 = std::chrono::steady_clock::now();
             sn_mesh *m = nullptr;
             st = extract_many(c, vol, 1, s, bpw, &m);
-            if (st != SN_OK) {
-                c->profiling = was;
-                return st;
-            }
-            HIP_TRY(hipStreamSynchronize(s));
+            if (st != SN_OK) return st;
+            const hipError_t e = hipStreamSynchronize(s);
             auto t1 = std::chrono::steady_clock::now();
             mesh_release(m);
+            if (e != hipSuccess) return fail(SN_EDEVICE, std::string("sn_autotune: ") + hipGetErrorString(e));
             if (rep > 0) tbest = std::min(tbest, std::chrono::duration<double>(t1 - t0).count());
         }
         if (tbest < best) best = tbest, arg = bpw;
     }
-    c->profiling = was;
     {
         std::lock_guard<std::mutex> g(c->tune_mu);
         c->tune[size_class(*vol)] = arg;

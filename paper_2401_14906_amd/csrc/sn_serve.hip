@@ -107,7 +107,7 @@ sn_status sn_server::run_fused(const sn_volume *vols, const sn_smooth_params *ps
     std::fill(ms, ms + n, nullptr);
     sn_status st = extract_many(ctx, vols, n, s, 0, ms);
     if (st == SN_OK) {
-        // a batch of one takes the plain path (its sweep graph is cached)
+        // a batch of one takes the plain path (no descriptor upload, no graph build)
         st = n == 1 ? smooth_one(ctx, ms[0], ps, s) : smooth_many(ctx, ms, ps, n, s);
         if (st == SN_OK && wait_stream(s) != hipSuccess) st = SN_EDEVICE;
         if (st != SN_OK) {
@@ -150,11 +150,11 @@ void sn_server::worker(int w)
                 ++inflight;
                 batch.push_back(h);
             }
+            if (batch.empty()) continue;
             peak_reserved = std::max(peak_reserved, reserved);
             if (busy_count++ == 0) busy_since = Clock::now();
             ++n_batches;
         }
-        if (batch.empty()) continue;
         const int32_t n = (int32_t)batch.size();
         std::vector<sn_volume> vols(n);
         std::vector<sn_smooth_params> ps(n);

@@ -255,6 +255,15 @@ def test_invalid_arguments(ctx, sn, torch):
         ctx.extract(t, selected=(0,), background=0)  # background selected
     with pytest.raises(sn.SNError):
         ctx.extract(t, background=70000)  # does not fit u16
+    # sizes whose int32 indexing bound would overflow int64 if multiplied
+    # unchecked: refused before any device work
+    import ctypes
+    for dims in [(1 << 30, 1 << 30, 1 << 30), (1 << 30, 1 << 16, 1 << 16), (64, 1 << 30, 1 << 30)]:
+        v, keep = sn.make_volume(t)
+        v.dims[:] = dims
+        out = ctypes.c_void_p()
+        st = sn._lib.sn_extract(ctx._h, ctypes.byref(v), None, ctypes.byref(out))
+        assert st == sn.SN_ETOOBIG and not out.value, (dims, st)
     m = ctx.extract(t)
     with pytest.raises(sn.SNError):
         ctx.smooth(m, iterations=-1)
