@@ -167,7 +167,9 @@ def roofline_of(res, traffic=None):
     return {"kernel": dom, "bound": "hbm", "achieved": round(d["achieved_GBs"], 1),
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(d["frac_hbm"], 4),
             "traffic": traffic, "avg_us": round(d["avg_us"], 2),
-            "alg_bytes_per_launch": int(d["alg_bytes"])}
+            "alg_bytes_per_launch": int(d["alg_bytes"]),
+            # counted L2-miss bytes per algorithmic byte: above 1 means re-reads
+            "traffic_over_alg": round(traffic / d["alg_bytes"], 3) if traffic else None}
 
 
 def cpu_baseline(vol, min_seconds=10.0):
