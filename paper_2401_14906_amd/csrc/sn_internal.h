@@ -130,6 +130,7 @@ struct SmoothDesc {
     const uint32_t *pcell;
     float *points;
     UDiv CM, CN;  // cells per row, rows per slice
+    int32_t chunk;  // single mesh, K = 2: blocks an XCD takes in turn (about 1/16 of a slab)
     double origin[3], spacing[3];
 };
 
@@ -137,7 +138,8 @@ struct SmoothDesc {
 // chunks of 64 points.  Meshes of up to kSweepSmallPoints points (their sweep
 // data fits the last-level cache; latency decides) run with K = 1, more and
 // shorter waves, and XCD-contiguous blocks; larger ones (bandwidth decides)
-// with K = 2 and the hardware's round-robin block order.
+// with K = 2, in slab-chunked block order for a single mesh and the hardware's
+// round-robin order for a launch over many.
 constexpr int64_t kSweepSmallPoints = int64_t(1) << 22;
 inline int sweep_chunks(int64_t points) { return points <= kSweepSmallPoints ? 1 : 2; }
 constexpr int kSweepBlock = 256;  // threads per smoothing workgroup
@@ -158,10 +160,11 @@ constexpr uint64_t kValMask = (1ull << 62) - 1;
 //   k_edges   : a tile is 4*4 segments of 256 samples; every volume of a launch has
 //               the given label type (bytes), classification mode and `wide`
 //               (rows 16-byte aligned and M % 4 == 0: one wide load per lane).
-//   k_count   : a tile is kCountBlock or kCountWideV * kCountBlock cell words.
-//   k_generate: a tile is 4*bpw batches; label type and mode as for k_edges.
 //               The launch also zeroes d_zero[0 .. nzero) (the count pass's scan
 //               status), so the extraction needs no separate memset.
+//   k_count   : a tile is kCountBlock or kCountWideV * kCountBlock cell words.
+//   k_generate: a tile is 4*bpw groups of kGenWords words; label type and mode
+//               as for k_edges.
 hipError_t launch_edges(int32_t dtype, int32_t mode, bool wide, const VolDesc *d_descs,
                         const int64_t *d_tile_prefix, int32_t nvol, int64_t tile_base,
                         int64_t ntiles, uint64_t *d_zero, int64_t nzero, hipStream_t s);

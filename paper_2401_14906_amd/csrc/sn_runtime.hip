@@ -1026,6 +1026,11 @@ static void fill_smooth_desc(const sn_mesh *m, const sn_smooth_params &p, Smooth
     sd->CM = make_udiv((uint32_t)std::max<int64_t>(m->d.g.CM, 1));
     sd->CN = make_udiv((uint32_t)std::max<int64_t>(m->d.g.CN, 1));
     for (int a = 0; a < 3; ++a) sd->origin[a] = m->d.origin[a], sd->spacing[a] = m->d.spacing[a];
+    // block order of a large single mesh: each XCD takes runs of about a
+    // sixteenth of a slab's blocks in turn
+    const int K = sweep_chunks(m->P);
+    const int64_t per_slab = sweep_blocks_for(m->P, K) / std::max<int64_t>(1, m->d.g.CO);
+    sd->chunk = (int32_t)std::max<int64_t>(1, (per_slab + 8) / 16);
 }
 
 // Sweeps over `nvol` meshes (descriptor array), replayed from a HIP graph of
