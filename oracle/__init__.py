@@ -15,7 +15,9 @@ from dataclasses import dataclass
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(_HERE, "libsn_oracle.so")
+# SN_ORACLE_LIB names another build of sn_oracle.c (the mutation test loads
+# builds with planted mistakes this way)
+_LIB_PATH = os.environ.get("SN_ORACLE_LIB") or os.path.join(_HERE, "libsn_oracle.so")
 _lib = None
 
 

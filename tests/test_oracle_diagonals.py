@@ -68,6 +68,19 @@ def test_area_and_planarity_disagree():
     assert not oracle.split_ac(a, b, c, d, SHORTEST)
 
 
+def test_area_sums_use_the_split_triangles():
+    # a=(0,0,0) b=(1,0,0) c=(0,1,-1) d=(0,0,1)
+    #   A-C: ABC normal (0,1,1) area sqrt2/2, ACD normal (1,0,0) area 1/2, sum 1.207
+    #   B-D: ABD normal (0,-1,0) area 1/2, BCD normal (1,2,1) area sqrt6/2, sum 1.725
+    #   -> minimum area A-C; a sum that took ACD in place of BCD (1/2 + 1/2 = 1)
+    #   would pick B-D.  Shortest: |AC|^2 = |BD|^2 = 2, a tie -> A-C.  Most
+    #   planar: cosine 0 for A-C against -2/sqrt6 for B-D -> A-C
+    a, b, c, d = P(0, 0, 0), P(1, 0, 0), P(0, 1, -1), P(0, 0, 1)
+    assert oracle.split_ac(a, b, c, d, MIN_AREA)
+    assert oracle.split_ac(a, b, c, d, SHORTEST)
+    assert oracle.split_ac(a, b, c, d, PLANAR)
+
+
 def test_degenerate_split_is_not_preferred_by_planarity():
     # b = c: the A-C split has the degenerate triangle ABC (cosine -2), the B-D
     # split has ABD (0,0,1) and BCD degenerate too (b = c): both -2, tie -> A-C;
