@@ -9,7 +9,7 @@
  *     cells around it, a region-label pair per quad and a smoothing stencil
  *     linking face-neighbour cells;
  *   - smoothing (Eq. (1), Sec. 2.2, 2.4): double-buffered Laplacian relaxation
- *     of the points, each held inside a box around its cell centre;
+ *     of the points, each held inside a box or a sphere around its cell centre;
  *   - triangulation (Sec. 2.5): two triangles per quad.
  *
  * Conventions (all counts are int64; ids inside meshes are int32):
@@ -39,7 +39,9 @@
  *     cell-relative offsets ("offsets"), zero before smoothing.
  *   - Smoothing, per sweep: d <- clamp(d + lambda * mean_n(e_n + d_n - d),
  *     -c, c) per axis, where e_n is the unit step to neighbour n and c is the
- *     constraint distance in voxel units; no neighbours -> no motion.
+ *     constraint distance in voxel units; no neighbours -> no motion.  With
+ *     the sphere constraint the moved d is instead scaled back to length c
+ *     when it is longer.
  *   - Triangles (SN_TRIS): quad (A,B,C,D) -> (A,B,C), (A,C,D); triangle 2q
  *     and 2q+1 come from quad q and repeat its label pair.
  *
@@ -52,8 +54,9 @@
  * Errors: every call returns an sn_status; out-parameters are written only on
  * SN_OK; nothing throws across the ABI.  sn_strerror() names a status.
  *
- * Threads: an sn_ctx is used by one host thread at a time; the sn_serve_*
- * calls are thread-safe.
+ * Threads: the plain, batched, tuning and profiling calls on one sn_ctx come
+ * from one host thread at a time; a server's worker threads share its
+ * context safely with that thread, and the sn_serve_* calls are thread-safe.
  */
 #ifndef SN_H
 #define SN_H
