@@ -44,6 +44,8 @@ def _load():
         lib.orc_extract.restype = P
         lib.orc_extract.argtypes = [P, ctypes.c_int, I64, I64, I64, P, ctypes.c_int32,
                                     ctypes.c_uint32]
+        lib.orc_extract2d.restype = P
+        lib.orc_extract2d.argtypes = [P, ctypes.c_int, I64, I64, P, ctypes.c_int32, ctypes.c_uint32]
         lib.orc_mesh_free.argtypes = [P]
         lib.orc_mesh_free.restype = None
         lib.orc_mesh_sizes.argtypes = [P, P]
@@ -77,7 +79,7 @@ def _p(a):
 class OracleMesh:
     dims: tuple            # (M, N, O)
     cell_of: np.ndarray    # int64 [P] linear cell index i + (M-1)(j + (N-1)k)
-    quads: np.ndarray      # int32 [Q, 4]
+    quads: np.ndarray      # int32 [Q, 4], or [Q, 2] segments for an image
     pairs: np.ndarray      # uint32 [Q, 2] (front, back)
     st_off: np.ndarray     # int64 [P+1]
     st_ids: np.ndarray     # int32 [S]
@@ -151,6 +153,31 @@ def extract(labels: np.ndarray, selected=(), background: int = 0) -> OracleMesh:
     st_ids = np.empty(S, dtype=np.int32)
     lib.orc_mesh_copy(h, _p(cell_of), _p(quads), _p(pairs), _p(st_off), _p(st_ids))
     return OracleMesh((M, N, O), cell_of, quads, pairs, st_off, st_ids, h)
+
+
+def extract2d(labels: np.ndarray, selected=(), background: int = 0) -> OracleMesh:
+    """Extract the 2D SurfaceNets contour of a label image of shape (N, M):
+    points, segments [Q, 2], label pairs and the stencil; dims are (M, N, 1)."""
+    lib = _load()
+    labels = np.ascontiguousarray(labels)
+    if labels.dtype not in (np.uint8, np.uint16, np.uint32):
+        raise TypeError("labels must be uint8, uint16 or uint32")
+    N, M = labels.shape
+    sel = np.ascontiguousarray(np.asarray(selected, dtype=np.uint32).reshape(-1))
+    h = lib.orc_extract2d(_p(labels), labels.dtype.itemsize, M, N,
+                          _p(sel) if sel.size else None, int(sel.size), int(background))
+    if not h:
+        raise MemoryError("oracle extraction failed")
+    sizes = np.zeros(4, dtype=np.int64)
+    lib.orc_mesh_sizes(h, _p(sizes))
+    P, Q, S = (int(x) for x in sizes[:3])
+    cell_of = np.empty(P, dtype=np.int64)
+    segs = np.empty((Q, 2), dtype=np.int32)
+    pairs = np.empty((Q, 2), dtype=np.uint32)
+    st_off = np.empty(P + 1, dtype=np.int64)
+    st_ids = np.empty(S, dtype=np.int32)
+    lib.orc_mesh_copy(h, _p(cell_of), _p(segs), _p(pairs), _p(st_off), _p(st_ids))
+    return OracleMesh((M, N, 1), cell_of, segs, pairs, st_off, st_ids, h)
 
 
 def world(idx_pos: np.ndarray, origin, spacing) -> np.ndarray:

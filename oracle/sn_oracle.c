@@ -29,6 +29,8 @@
  *   smoothing         Eq. (1), Sec. 2.2, with the per-cell box constraint and
  *                     the double-buffered (Jacobi) update of Sec. 2.4.
  *   triangulation     Sec. 2.5: every quad becomes two triangles.
+ *   2D                Sec. 5 (the method exists in 2D and 3D): the same
+ *                     definitions on an image; see orc_extract2d.
  *
  * Readings of points the paper leaves open (all restated in the design notes):
  *   - point ids follow the cell linear index i + (M-1)(j + (N-1)k);
@@ -52,10 +54,11 @@
 #include <string.h>
 
 typedef struct {
-    int64_t M, N, O;      /* lattice (sample) dimensions                         */
-    int64_t P, Q, S;      /* points, quads, directed stencil entries             */
+    int64_t M, N, O;      /* lattice (sample) dimensions (O = 1: an image)       */
+    int64_t P, Q, S;      /* points, quads (segments in 2D), directed stencil    */
+    int32_t nv;           /* point ids per quad: 4, or 2 for the segments of 2D   */
     int64_t *cell_of;     /* [P]   linear cell index of each point               */
-    int32_t *quads;       /* [Q*4] point ids                                      */
+    int32_t *quads;       /* [Q*nv] point ids                                     */
     uint32_t *pairs;      /* [Q*2] (front, back) classified labels               */
     int64_t *st_off;      /* [P+1] CSR offsets                                    */
     int32_t *st_ids;      /* [S]   neighbour point ids                            */
@@ -171,6 +174,7 @@ orc_mesh *orc_extract(const void *labels, int b, int64_t M, int64_t N, int64_t O
     if (!m)
         return NULL;
     m->M = M, m->N = N, m->O = O;
+    m->nv = 4;
     const int64_t V = M * N * O;
     uint32_t *sel = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(n_sel > 0 ? n_sel : 1));
     uint32_t *cv = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)V);
@@ -286,10 +290,130 @@ void orc_mesh_copy(const orc_mesh *m, int64_t *cell_of, int32_t *quads, uint32_t
                    int64_t *st_off, int32_t *st_ids)
 {
     if (cell_of) memcpy(cell_of, m->cell_of, sizeof(int64_t) * (size_t)m->P);
-    if (quads) memcpy(quads, m->quads, sizeof(int32_t) * 4 * (size_t)m->Q);
+    if (quads) memcpy(quads, m->quads, sizeof(int32_t) * (size_t)m->nv * (size_t)m->Q);
     if (pairs) memcpy(pairs, m->pairs, sizeof(uint32_t) * 2 * (size_t)m->Q);
     if (st_off) memcpy(st_off, m->st_off, sizeof(int64_t) * (size_t)(m->P + 1));
     if (st_ids) memcpy(st_ids, m->st_ids, sizeof(int32_t) * (size_t)m->S);
+}
+
+/*
+ * 2D.  An image of M x N samples, x fastest; cell (i,j), 0 <= i <= M-2,
+ * 0 <= j <= N-2, spans samples (i..i+1, j..j+1).  The 3D definitions restated
+ * in the plane:
+ *   point    a cell gets one point, at its centre, iff any of its four edges
+ *            (x-edges from (i,j) and (i,j+1), y-edges from (i,j) and (i+1,j))
+ *            is cut;
+ *   segment  one per cut edge, joining the points of the two cells that
+ *            share it; an edge on the boundary of the cell grid emits none.
+ *            Order: lattice linear index i + M j of the edge origin s0, then
+ *            axis x, y.  Vertex order, with the right-hand normal facing s0 as
+ *            for the quads: x-edge at (i,j): (i,j) (i,j-1); y-edge at (i,j):
+ *            (i-1,j) (i,j).  Label pair (front, back) = (C(s0), C(s1));
+ *   stencil  a point is linked to the point of an edge-neighbour cell iff
+ *            their shared edge is cut; order -x, +x, -y, +y.
+ * Points are cell centres as in 3D with k = 0; smoothing (orc_smooth_shape)
+ * is unchanged and leaves the z coordinate alone (no point has a z neighbour).
+ */
+static int cell2_exists(int64_t M, int64_t N, int64_t i, int64_t j)
+{
+    return i >= 0 && j >= 0 && i <= M - 2 && j <= N - 2;
+}
+
+orc_mesh *orc_extract2d(const void *labels, int b, int64_t M, int64_t N, const uint32_t *selected,
+                        int32_t n_sel, uint32_t background)
+{
+    if (M < 1 || N < 1 || (b != 1 && b != 2 && b != 4) || n_sel < 0)
+        return NULL;
+    orc_mesh *m = (orc_mesh *)calloc(1, sizeof(orc_mesh));
+    if (!m)
+        return NULL;
+    m->M = M, m->N = N, m->O = 1;
+    m->nv = 2;
+    const int64_t V = M * N;
+    uint32_t *sel = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(n_sel > 0 ? n_sel : 1));
+    uint32_t *cv = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)V);
+    if (!sel || !cv) {
+        free(sel), free(cv), free(m);
+        return NULL;
+    }
+    if (n_sel > 0)
+        memcpy(sel, selected, sizeof(uint32_t) * (size_t)n_sel);
+    qsort(sel, (size_t)n_sel, sizeof(uint32_t), cmp_u32);
+    for (int64_t t = 0; t < V; ++t)
+        cv[t] = classify(raw_label(labels, b, t), sel, n_sel, background);
+    free(sel);
+    cvol v = {cv, M, N, 1};
+
+    const int64_t CM = M - 1, CN = N - 1;
+    const int64_t ncell = (CM > 0 && CN > 0) ? CM * CN : 0;
+    int64_t *pid = (int64_t *)malloc(sizeof(int64_t) * (size_t)(ncell > 0 ? ncell : 1));
+    int64_t P = 0;
+    for (int64_t j = 0; j < CN; ++j)
+        for (int64_t i = 0; i < CM; ++i) {
+            const int pt = cut(&v, i, j, 0, 0) || cut(&v, i, j + 1, 0, 0) || cut(&v, i, j, 0, 1) ||
+                           cut(&v, i + 1, j, 0, 1);
+            pid[i + CM * j] = pt ? P++ : -1;
+        }
+    m->P = P;
+    m->cell_of = (int64_t *)malloc(sizeof(int64_t) * (size_t)(P > 0 ? P : 1));
+    for (int64_t c = 0; c < ncell; ++c)
+        if (pid[c] >= 0)
+            m->cell_of[pid[c]] = c;
+
+    int64_t Q = 0, cap = 16;
+    int32_t *sg = (int32_t *)malloc(sizeof(int32_t) * 2 * (size_t)cap);
+    uint32_t *pr = (uint32_t *)malloc(sizeof(uint32_t) * 2 * (size_t)cap);
+    for (int64_t j = 0; j < N; ++j)
+        for (int64_t i = 0; i < M; ++i)
+            for (int a = 0; a < 2; ++a) {
+                if (!cut(&v, i, j, 0, a))
+                    continue;
+                /* the two cells sharing the edge, in vertex order */
+                const int64_t ai = a == 0 ? i : i - 1, aj = a == 0 ? j : j;
+                const int64_t bi = a == 0 ? i : i, bj = a == 0 ? j - 1 : j;
+                if (!cell2_exists(M, N, ai, aj) || !cell2_exists(M, N, bi, bj))
+                    continue;
+                if (Q == cap) {
+                    cap *= 2;
+                    sg = (int32_t *)realloc(sg, sizeof(int32_t) * 2 * (size_t)cap);
+                    pr = (uint32_t *)realloc(pr, sizeof(uint32_t) * 2 * (size_t)cap);
+                }
+                sg[2 * Q + 0] = (int32_t)pid[ai + CM * aj];
+                sg[2 * Q + 1] = (int32_t)pid[bi + CM * bj];
+                pr[2 * Q + 0] = C(&v, i, j, 0);
+                pr[2 * Q + 1] = C(&v, i + (a == 0), j + (a == 1), 0);
+                ++Q;
+            }
+    m->Q = Q;
+    m->quads = sg;
+    m->pairs = pr;
+
+    m->st_off = (int64_t *)malloc(sizeof(int64_t) * (size_t)(P + 1));
+    int64_t S = 0, scap = 16;
+    int32_t *ids = (int32_t *)malloc(sizeof(int32_t) * (size_t)scap);
+    for (int64_t p = 0; p < P; ++p) {
+        m->st_off[p] = S;
+        const int64_t c = m->cell_of[p], i = c % CM, j = c / CM;
+        /* neighbour cell and the edge the two cells share, per face */
+        const int64_t ni[4] = {i - 1, i + 1, i, i}, nj[4] = {j, j, j - 1, j + 1};
+        const int shared[4] = {cut(&v, i, j, 0, 1), cut(&v, i + 1, j, 0, 1), cut(&v, i, j, 0, 0),
+                               cut(&v, i, j + 1, 0, 0)};
+        for (int f = 0; f < 4; ++f) {
+            if (!cell2_exists(M, N, ni[f], nj[f]) || !shared[f])
+                continue;
+            if (S == scap) {
+                scap *= 2;
+                ids = (int32_t *)realloc(ids, sizeof(int32_t) * (size_t)scap);
+            }
+            ids[S++] = (int32_t)pid[ni[f] + CM * nj[f]];
+        }
+    }
+    m->st_off[P] = S;
+    m->S = S;
+    m->st_ids = ids;
+    free(pid);
+    free(cv);
+    return m;
 }
 
 /* Sec. 2.2: the generated point sits at the centre of its cell. */

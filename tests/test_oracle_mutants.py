@@ -3,7 +3,7 @@
 Each mutant below is one plausible slip in ``oracle/sn_oracle.c``: a dropped
 term, a wrong sign or index, a transposed operand, a swapped order.  The test
 builds every mutant into a temporary library and runs the oracle's pin tests
-(``test_oracle_pins.py``, ``test_oracle_diagonals.py``) against it through
+(``test_oracle_pins.py``, ``test_oracle_pins2d.py``, ``test_oracle_diagonals.py``) against it through
 ``SN_ORACLE_LIB``; each mutant must make at least one pin fail.  A mutant that
 passes every pin would be a mistake the pins cannot see.  Mistakes are planted
 only in temporary copies of the oracle, on the CPU.
@@ -30,6 +30,7 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "sn_oracle.c")
 PINS = [os.path.join(ROOT, "tests", "test_oracle_pins.py"),
+        os.path.join(ROOT, "tests", "test_oracle_pins2d.py"),
         os.path.join(ROOT, "tests", "test_oracle_diagonals.py")]
 
 # (name, original text, mutated text); the original occurs exactly once
@@ -90,6 +91,17 @@ MUTANTS = [
      "if (len > d) {", "if (len > 2 * d) {"),
     ("sphere projection transposed",
      "q[1] = c[1] + dy * (d / len);", "q[1] = c[1] + dx * (d / len);"),
+    # the method in the plane
+    ("2D point test without its y-edges",
+     "|| cut(&v, i, j, 0, 1) ||\n                           cut(&v, i + 1, j, 0, 1);", ";"),
+    ("2D y-segment on the wrong side",
+     "const int64_t ai = a == 0 ? i : i - 1,", "const int64_t ai = a == 0 ? i : i + 1,"),
+    ("2D +y face checks the wrong edge",
+     "cut(&v, i, j, 0, 0),\n                               cut(&v, i, j + 1, 0, 0)};",
+     "cut(&v, i, j, 0, 0),\n                               cut(&v, i, j, 0, 0)};"),
+    ("2D back label on the wrong axis",
+     "pr[2 * Q + 1] = C(&v, i + (a == 0), j + (a == 1), 0);",
+     "pr[2 * Q + 1] = C(&v, i + (a == 1), j + (a == 0), 0);"),
     # world coordinates and triangles (Sec. 2.5)
     ("world origin scaled",
      "out[3 * p + ax] = origin[ax] + spacing[ax] * idx_pos[3 * p + ax];",
