@@ -44,6 +44,16 @@
  *     when it is longer.
  *   - Triangles (SN_TRIS): quad (A,B,C,D) -> (A,B,C), (A,C,D); triangle 2q
  *     and 2q+1 come from quad q and repeat its label pair.
+ *   - Images (SN_LINES, dims[2] == 1): the same definitions in the plane.
+ *     Cell (i,j) spans samples (i..i+1, j..j+1) and has a point iff any of
+ *     its four edges is intersected; one segment per intersected edge joins
+ *     the points of the two cells sharing it (none on the cell-grid
+ *     boundary), ordered by the sample linear index of s0, then axis x, y,
+ *     with vertex order x: (i,j) (i,j-1), y: (i-1,j) (i,j) (right-hand
+ *     normal facing s0) and label pair (class(s0), class(s1)).  The stencil
+ *     links edge neighbours across an intersected edge (faces -x, +x, -y,
+ *     +y).  Points are xyz with z = origin[2] and stay in that plane under
+ *     smoothing (spacing[2] is not used).
  *
  * Memory: `labels` is a DEVICE pointer owned by the caller; every sn_mesh and
  * everything it points to is device memory owned by the library until
@@ -80,7 +90,9 @@ typedef enum sn_status {
 } sn_status;
 
 typedef enum sn_dtype { SN_U8 = 1, SN_U16 = 2, SN_U32 = 4 } sn_dtype;
-typedef enum sn_prim { SN_TRIS = 3, SN_QUADS = 4 } sn_prim;
+/* SN_LINES: the 2D method (Sec. 5: SurfaceNets exists in 2D and 3D) on an
+ * image, dims = {M, N, 1}: contour segments instead of quads; see below. */
+typedef enum sn_prim { SN_LINES = 2, SN_TRIS = 3, SN_QUADS = 4 } sn_prim;
 
 typedef struct sn_ctx sn_ctx;
 typedef struct sn_mesh sn_mesh;
@@ -90,7 +102,8 @@ typedef struct sn_server sn_server;
 typedef struct sn_volume {
     const void *labels;        /* device, dims[0]*dims[1]*dims[2] values, x fastest       */
     int32_t dtype;             /* sn_dtype: bytes per label                               */
-    int64_t dims[3];           /* M, N, O >= 1; a dim below 2 gives an empty mesh          */
+    int64_t dims[3];           /* M, N, O >= 1; a dim below 2 gives an empty mesh (O = 1
+                                  for SN_LINES)                                            */
     double spacing[3];         /* > 0 and finite                                          */
     double origin[3];          /* world position of sample (0,0,0)                        */
     const uint32_t *selected;  /* host; duplicates allowed                                */
@@ -125,7 +138,8 @@ typedef struct sn_mesh_view {
     const void *label_pairs;    /* [n_polys*2] (front, back), dtype bytes each            */
     const int32_t *stencil_off; /* [n_points+1]                                           */
     const int32_t *stencil_ids; /* [n_stencil]                                            */
-    const int32_t *quads;       /* [n_quads*4] (same as polys for SN_QUADS)               */
+    const int32_t *quads;       /* [n_quads*4] (same as polys for SN_QUADS; NULL for
+                                   SN_LINES, whose polys are the segments [n_quads*2])   */
 } sn_mesh_view;
 
 /* ---- context -------------------------------------------------------------- */
@@ -183,7 +197,8 @@ typedef enum sn_diag_rule {
  *               pair, repeated), owned by the caller, or NULL.
  * Works for meshes of either primitive (the quads are kept).  Enqueued on
  * `stream`, which must be ordered after the mesh's smoothing.  SN_EINVAL for
- * a NULL context or mesh, an unknown rule, or tris == NULL with n_quads > 0. */
+ * a NULL context or mesh, an unknown rule, an SN_LINES mesh (no quads), or
+ * tris == NULL with n_quads > 0. */
 sn_status sn_triangulate(sn_ctx *ctx, sn_mesh *mesh, sn_diag_rule rule, int32_t *tris,
                          void *tri_labels, void *stream);
 

@@ -28,7 +28,7 @@ LIB_PATH = os.path.join(_HERE, "libsn.so")
 
 SN_OK, SN_EINVAL, SN_ENOMEM, SN_EDEVICE, SN_ETOOBIG = 0, -1, -2, -3, -4
 SN_EAGAIN, SN_ENOTFOUND, SN_ESHUTDOWN, SN_ETIMEDOUT = -5, -6, -7, -8
-SN_TRIS, SN_QUADS = 3, 4
+SN_LINES, SN_TRIS, SN_QUADS = 2, 3, 4
 _NP_DT = {1: np.uint8, 2: np.uint16, 4: np.uint32}
 # tessellating-diagonal rules of sn_triangulate
 DIAG_RULES = {"fixed": 0, "shortest": 1, "min_area": 2, "planar": 3}
@@ -226,17 +226,22 @@ def to_device(a: np.ndarray, device="cuda"):
 
 def make_volume(labels, spacing=(1.0, 1.0, 1.0), origin=(0.0, 0.0, 0.0), selected=(),
                 background=0, prim=SN_QUADS):
-    """Build an sn_volume for a CUDA tensor of shape (O, N, M); returns (vol, keepalive)."""
+    """Build an sn_volume for a CUDA tensor of shape (O, N, M), or for an image
+    of shape (N, M) (2D contours: SN_LINES, dims (M, N, 1)); returns (vol, keepalive)."""
     import torch
 
     if not isinstance(labels, torch.Tensor) or not labels.is_cuda:
         raise TypeError("labels must be a CUDA (HIP) torch tensor")
-    if labels.dim() != 3 or not labels.is_contiguous():
-        raise ValueError("labels must be a contiguous 3-D tensor (O, N, M)")
+    if labels.dim() not in (2, 3) or not labels.is_contiguous():
+        raise ValueError("labels must be a contiguous 3-D tensor (O, N, M) or image (N, M)")
+    if labels.dim() == 2:
+        if prim not in (SN_QUADS, SN_LINES):
+            raise ValueError("an image is contoured with segments (SN_LINES)")
+        prim = SN_LINES
     b = labels.element_size()
     if b not in (1, 2, 4) or labels.is_floating_point():
         raise TypeError("labels must hold 8-, 16- or 32-bit integers")
-    O, N, M = labels.shape
+    O, N, M = (1, *labels.shape) if labels.dim() == 2 else labels.shape
     v = sn_volume()
     v.labels = labels.data_ptr()
     v.dtype = b

@@ -32,6 +32,8 @@ struct ClassSpec {
 // one wavefront; a tile is 4*bpw consecutive batches, the work item of one
 // workgroup and the unit of the device-wide scan.
 constexpr int kU = 4;
+// prim of an image (SN_LINES): 2D contours, one sample slice, segments [Q][2]
+constexpr int32_t kPrimLines = 2;
 constexpr int kWavesPerBlock = 4;
 constexpr int kBlock = 64 * kWavesPerBlock;
 constexpr int kMaxBatchesPerWave = 16;
@@ -67,7 +69,7 @@ struct Geom {
 struct VolDesc {
     const void *labels;
     int32_t dtype;  // 1, 2, 4
-    int32_t prim;   // 3 or 4
+    int32_t prim;   // 3 or 4, or kPrimLines (an image)
     Geom g;
     ClassSpec cs;
     // cut-edge planes X, Y, Z: [3][O*N][WS]
@@ -181,7 +183,7 @@ hipError_t launch_count(const VolDesc *d_descs, const int64_t *d_tile_prefix, in
                         uint32_t *d_ticket, const CountOut &out, hipStream_t s);
 // staged: stencil ids, quads and pairs go through LDS (for meshes with at
 // least kGenStagedPointsPerWord points per word on average)
-hipError_t launch_generate(int32_t dtype, int32_t mode, bool staged, const VolDesc *d_descs,
+hipError_t launch_generate(int32_t dtype, int32_t mode, bool staged, bool two_d, const VolDesc *d_descs,
                            const int64_t *d_tile_prefix, int32_t nvol, int64_t tile_base,
                            int64_t ntiles, int32_t bpw, hipStream_t s);
 // k_emit: d_sds[v] (iterations, ping-pong buffers) names volume v's final offsets

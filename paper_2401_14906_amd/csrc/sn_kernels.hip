@@ -192,6 +192,7 @@ __device__ __forceinline__ void batch_next(const Geom &g, BatchPos &p)
 }
 
 typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v2i __attribute__((ext_vector_type(2)));
 
 // One point's world coordinates (three consecutive floats).
 __device__ __forceinline__ void store_point(SN_GLOBAL float *points, int32_t id, float x, float y,
@@ -239,8 +240,28 @@ __device__ __forceinline__ PlaneWords plane_words(const P *planes, int64_t plane
     return p;
 }
 
+// An image (one sample slice, the method in the plane): X of sample rows j
+// and j+1 and Y of row j (with the following word); there are no z planes and
+// no k+1 rows, and those words read as zero.
+template <typename P>
+__device__ __forceinline__ PlaneWords plane_words2d(const P *planes, int64_t plane_stride, int64_t WS,
+                                                    int64_t s00, int32_t w)
+{
+    const P *X = planes, *Y = planes + plane_stride;
+    PlaneWords p{};
+    p.x00 = X[s00 * WS + w], p.x10 = X[(s00 + 1) * WS + w];
+    p.y00 = Y[s00 * WS + w];
+    p.y00n = w + 1 < WS ? Y[s00 * WS + w + 1] : 0ull;
+    return p;
+}
+
 __device__ __forceinline__ uint64_t next_bit(uint64_t a, uint64_t an) { return (a >> 1) | (an << 63); }
 
+// TWO_D: the same algebra on an image's words (z inputs zero, k = 0, one cell
+// slice): a point where any of the cell's four edges is cut, faces -x, +x,
+// -y, +y, and a segment per cut x- or y-edge owned by the cell (qx, qy) whose
+// two cells exist.
+template <bool TWO_D = false>
 __device__ __forceinline__ WordMasks word_masks(const PlaneWords &p, int32_t w, int32_t j, int32_t k,
                                                 const Geom &g)
 {
@@ -262,8 +283,9 @@ __device__ __forceinline__ WordMasks word_masks(const PlaneWords &p, int32_t w, 
     m.f[3] = (x1 | x3 | z2 | z3) & valid & yp;
     m.f[4] = (x0 | x1 | y0 | y1) & valid & zm;
     m.f[5] = (x2 | x3 | y2 | y3) & valid & zp;
-    m.qx = x0 & valid & ym & zm;
-    m.qy = y0 & valid & hasprev & zm;
+    const uint64_t zq = TWO_D ? ~0ull : zm;  // an image's segments have no z neighbour cells
+    m.qx = x0 & valid & ym & zq;
+    m.qy = y0 & valid & hasprev & zq;
     m.qz = z0 & valid & hasprev & ym;
     return m;
 }
@@ -565,8 +587,14 @@ __device__ __forceinline__ void count_body(const Src &a, uint64_t *status, uint3
             const int32_t w = (int32_t)((uint32_t)gw - r * (uint32_t)g.W);
             const int32_t j = (int32_t)(r % (uint32_t)g.CN), k = (int32_t)(r / (uint32_t)g.CN);
             const int64_t ps = g.N * g.O * g.WS;
-            const PlaneWords p = plane_words(glb(d.planes), ps, g.WS, j + g.N * (int64_t)k, g.N, w);
-            const WordMasks m = word_masks(p, w, j, k, g);
+            WordMasks m;
+            if (d.prim == kPrimLines) {  // an image: contour segments
+                const PlaneWords p = plane_words2d(glb(d.planes), ps, g.WS, (int64_t)j, w);
+                m = word_masks<true>(p, w, j, k, g);
+            } else {
+                const PlaneWords p = plane_words(glb(d.planes), ps, g.WS, j + g.N * (int64_t)k, g.N, w);
+                m = word_masks(p, w, j, k, g);
+            }
             glb(d.pmask)[gw] = m.pt;
             cnt[0] = __popcll(m.pt);
             cnt[1] = __popcll(m.qx) + __popcll(m.qy) + __popcll(m.qz);
@@ -727,7 +755,7 @@ struct GenStep {
     uint32_t la, lx, ly, lz;  // labels at the sample and at +x, +y, +z
 };
 
-template <typename T>
+template <typename T, bool TWO_D>
 __device__ __forceinline__ void generate_front(const VolDesc &d, const GenLdsBase &L, int32_t npg,
                                                int32_t pbase, int32_t base, int lane, int64_t sy,
                                                int64_t sz, GenStep<T> &x)
@@ -751,7 +779,8 @@ __device__ __forceinline__ void generate_front(const VolDesc &d, const GenLdsBas
     // without a point is the first cell of the group's first word, whose +x,
     // +y and +z samples exist
     const SN_GLOBAL T *s0 = glb(static_cast<const T *>(d.labels)) + W.soff + (W.ci0 + i);
-    x.la = s0[0], x.lx = s0[1], x.ly = s0[sy], x.lz = s0[sz];
+    x.la = s0[0], x.lx = s0[1], x.ly = s0[sy];
+    x.lz = TWO_D ? 0u : (uint32_t)s0[sz];  // an image has no +z sample
     const uint32_t below = (1u << ib) - 1u;
 #pragma unroll
     for (int n = 0; n < 5; ++n) x.R[n] = H.nb[n] + __popc(H.nm[n] & below);
@@ -781,7 +810,7 @@ __device__ __forceinline__ void copy_staged(SN_GLOBAL uint32_t *out, const uint3
 // touched 64-byte line instead of one per instruction and line, which is what
 // bounds meshes with many points per word.  The direct form saves the LDS
 // round trip where steps are few.
-template <typename T, int MODE, bool STAGE>
+template <typename T, int MODE, bool STAGE, bool TWO_D>
 __device__ __forceinline__ void generate_back(const VolDesc &d, GenLds<STAGE> &L, const GenStep<T> &x,
                                               int32_t sbase, int32_t qbase, int32_t &scarry,
                                               int32_t &qcarry, int lane)
@@ -826,6 +855,13 @@ __device__ __forceinline__ void generate_back(const VolDesc &d, GenLds<STAGE> &L
         if (x.qa & 2u) qs[k++] = v4i{x.R[2] - 1, x.R[2], R0, R0 - 1};
         if (x.qa & 4u) qs[k] = v4i{x.R[0] - 1, R0 - 1, R0, x.R[0]};
     };
+    // an image's segments: x-edge (i,j) joins cells (i,j), (i,j-1); y-edge
+    // (i,j) joins (i-1,j), (i,j) (right-hand normal facing the edge origin)
+    auto put_segs = [&](auto *qs) {
+        int32_t k = 0;
+        if (x.qa & 1u) qs[k++] = v2i{R0, x.R[0]};
+        if (x.qa & 2u) qs[k] = v2i{R0 - 1, R0};
+    };
     auto put_pairs = [&](auto *ps) {
         const uint32_t ca = classify<MODE>(x.la, d.cs);
         int32_t k = 0;
@@ -837,7 +873,10 @@ __device__ __forceinline__ void generate_back(const VolDesc &d, GenLds<STAGE> &L
         if (act) {
             put_ids(glb(d.st_ids) + so0 + sr);
             if (x.qa) {
-                put_quads(glb(reinterpret_cast<v4i *>(d.quads)) + qo0 + qr);
+                if constexpr (TWO_D)
+                    put_segs(glb(reinterpret_cast<v2i *>(d.quads)) + qo0 + qr);
+                else
+                    put_quads(glb(reinterpret_cast<v4i *>(d.quads)) + qo0 + qr);
                 put_pairs(glb(static_cast<P *>(d.pairs)) + qo0 + qr);
             }
         }
@@ -848,11 +887,20 @@ __device__ __forceinline__ void generate_back(const VolDesc &d, GenLds<STAGE> &L
             copy_staged<1>(reinterpret_cast<SN_GLOBAL uint32_t *>(glb(d.st_ids) + so0), L.stage, nst, lane);
         wave_lds_sync();
         if (nqt == 0) return;
-        if (act && x.qa) put_quads(reinterpret_cast<v4i *>(L.stage) + qr);
+        if constexpr (TWO_D) {
+            if (act && x.qa) put_segs(reinterpret_cast<v2i *>(L.stage) + qr);
+        } else {
+            if (act && x.qa) put_quads(reinterpret_cast<v4i *>(L.stage) + qr);
+        }
         wave_lds_sync();
-        if (fits)
-            copy_staged<4>(reinterpret_cast<SN_GLOBAL uint32_t *>(glb(d.quads) + 4 * (int64_t)qo0),
-                           L.stage, nqt, lane);
+        if (fits) {
+            if constexpr (TWO_D)
+                copy_staged<2>(reinterpret_cast<SN_GLOBAL uint32_t *>(glb(d.quads) + 2 * (int64_t)qo0),
+                               L.stage, nqt, lane);
+            else
+                copy_staged<4>(reinterpret_cast<SN_GLOBAL uint32_t *>(glb(d.quads) + 4 * (int64_t)qo0),
+                               L.stage, nqt, lane);
+        }
         wave_lds_sync();
         if (act && x.qa) put_pairs(reinterpret_cast<P *>(L.stage) + qr);
         wave_lds_sync();
@@ -865,7 +913,7 @@ __device__ __forceinline__ void generate_back(const VolDesc &d, GenLds<STAGE> &L
     }
 }
 
-template <typename T, int MODE, bool STAGE>
+template <typename T, int MODE, bool STAGE, bool TWO_D>
 __device__ __forceinline__ void generate_group(const VolDesc &d, int64_t grp, int lane, GenLds<STAGE> &L)
 {
     const Geom &g = d.g;
@@ -893,7 +941,10 @@ __device__ __forceinline__ void generate_group(const VolDesc &d, int64_t grp, in
     int32_t own_p = 0, own_q = 0, own_s = 0;
     if (live && lane == 0) own_p = glb(d.wbP)[gw], own_q = glb(d.wbQ)[gw], own_s = glb(d.wbS)[gw];
     if (need) {
-        p = plane_words(glb(d.planes), g.N * g.O * g.WS, g.WS, j + g.N * (int64_t)k, g.N, w);
+        if constexpr (TWO_D)
+            p = plane_words2d(glb(d.planes), g.N * g.O * g.WS, g.WS, (int64_t)j, w);
+        else
+            p = plane_words(glb(d.planes), g.N * g.O * g.WS, g.WS, j + g.N * (int64_t)k, g.N, w);
         const bool ex[5] = {j >= 1, j + 1 <= g.CN - 1, k >= 1, k + 1 <= g.CO - 1, j >= 1 && k >= 1};
         const int64_t dr[5] = {-1, 1, -g.CN, g.CN, -g.CN - 1};
 #pragma unroll
@@ -904,7 +955,7 @@ __device__ __forceinline__ void generate_group(const VolDesc &d, int64_t grp, in
                 nb[n] = glb(d.wbP)[nw];
             }
     }
-    const WordMasks m = word_masks(p, w, j, k, g);  // all zero for lanes without a word
+    const WordMasks m = word_masks<TWO_D>(p, w, j, k, g);  // all zero for lanes without a word
     const int32_t np = __popcll(m.pt);
     const int32_t npi = wave_incl_scan_dpp(np, lane);
     const int32_t start = npi - np;
@@ -949,19 +1000,19 @@ __device__ __forceinline__ void generate_group(const VolDesc &d, int64_t grp, in
     const int64_t sy = g.M, sz = g.M * g.N;
     int32_t scarry = 0, qcarry = 0;
     GenStep<T> A, B;  // two steps in flight, alternating
-    generate_front<T>(d, L, npg, pbase, 0, lane, sy, sz, A);
+    generate_front<T, TWO_D>(d, L, npg, pbase, 0, lane, sy, sz, A);
     for (int32_t base = 0; base < npg; base += 128) {
         const bool more = base + 64 < npg;
-        if (more) generate_front<T>(d, L, npg, pbase, base + 64, lane, sy, sz, B);
-        generate_back<T, MODE, STAGE>(d, L, A, sbase, qbase, scarry, qcarry, lane);
+        if (more) generate_front<T, TWO_D>(d, L, npg, pbase, base + 64, lane, sy, sz, B);
+        generate_back<T, MODE, STAGE, TWO_D>(d, L, A, sbase, qbase, scarry, qcarry, lane);
         if (!more) break;
-        if (base + 128 < npg) generate_front<T>(d, L, npg, pbase, base + 128, lane, sy, sz, A);
-        generate_back<T, MODE, STAGE>(d, L, B, sbase, qbase, scarry, qcarry, lane);
+        if (base + 128 < npg) generate_front<T, TWO_D>(d, L, npg, pbase, base + 128, lane, sy, sz, A);
+        generate_back<T, MODE, STAGE, TWO_D>(d, L, B, sbase, qbase, scarry, qcarry, lane);
     }
     wave_lds_sync();
 }
 
-template <typename T, int MODE, bool STAGE, class Src>
+template <typename T, int MODE, bool STAGE, bool TWO_D, class Src>
 __device__ __forceinline__ void generate_body(const Src &a, int64_t tile_base, int32_t gpw)
 {
     __shared__ GenLds<STAGE> lds[kWavesPerBlock];
@@ -974,7 +1025,7 @@ __device__ __forceinline__ void generate_body(const Src &a, int64_t tile_base, i
     if (threadIdx.x == 0 && t == first) glb(d.st_off)[d.P] = (int32_t)d.S;
     const int64_t g0 = (t - first) * (kWavesPerBlock * gpw) + (int64_t)wave * gpw;
     for (int q = 0; q < gpw && g0 + q < ngroups; ++q)
-        generate_group<T, MODE, STAGE>(d, g0 + q, lane, lds[wave]);
+        generate_group<T, MODE, STAGE, TWO_D>(d, g0 + q, lane, lds[wave]);
 }
 
 template <typename T, int MODE>
@@ -982,7 +1033,7 @@ __global__ __launch_bounds__(kBlock) void k_generate(const VolDesc *__restrict__
                                                      const int64_t *__restrict__ prefix,
                                                      int32_t nvol, int64_t tile_base, int32_t gpw)
 {
-    generate_body<T, MODE, false>(ManyVols{descs, prefix, nvol}, tile_base, gpw);
+    generate_body<T, MODE, false, false>(ManyVols{descs, prefix, nvol}, tile_base, gpw);
 }
 
 template <typename T, int MODE>
@@ -991,19 +1042,49 @@ __global__ __launch_bounds__(kBlock) void k_generate_staged(const VolDesc *__res
                                                             int32_t nvol, int64_t tile_base,
                                                             int32_t gpw)
 {
-    generate_body<T, MODE, true>(ManyVols{descs, prefix, nvol}, tile_base, gpw);
+    generate_body<T, MODE, true, false>(ManyVols{descs, prefix, nvol}, tile_base, gpw);
 }
 
 template <typename T, int MODE>
 __global__ __launch_bounds__(kBlock) void k_generate_one(OneVol a, int32_t gpw)
 {
-    generate_body<T, MODE, false>(a, 0, gpw);
+    generate_body<T, MODE, false, false>(a, 0, gpw);
 }
 
 template <typename T, int MODE>
 __global__ __launch_bounds__(kBlock) void k_generate_staged_one(OneVol a, int32_t gpw)
 {
-    generate_body<T, MODE, true>(a, 0, gpw);
+    generate_body<T, MODE, true, false>(a, 0, gpw);
+}
+
+// The same passes on images (contour segments in the plane).
+template <typename T, int MODE>
+__global__ __launch_bounds__(kBlock) void k_generate2d(const VolDesc *__restrict__ descs,
+                                                       const int64_t *__restrict__ prefix,
+                                                       int32_t nvol, int64_t tile_base, int32_t gpw)
+{
+    generate_body<T, MODE, false, true>(ManyVols{descs, prefix, nvol}, tile_base, gpw);
+}
+
+template <typename T, int MODE>
+__global__ __launch_bounds__(kBlock) void k_generate2d_staged(const VolDesc *__restrict__ descs,
+                                                              const int64_t *__restrict__ prefix,
+                                                              int32_t nvol, int64_t tile_base,
+                                                              int32_t gpw)
+{
+    generate_body<T, MODE, true, true>(ManyVols{descs, prefix, nvol}, tile_base, gpw);
+}
+
+template <typename T, int MODE>
+__global__ __launch_bounds__(kBlock) void k_generate2d_one(OneVol a, int32_t gpw)
+{
+    generate_body<T, MODE, false, true>(a, 0, gpw);
+}
+
+template <typename T, int MODE>
+__global__ __launch_bounds__(kBlock) void k_generate2d_staged_one(OneVol a, int32_t gpw)
+{
+    generate_body<T, MODE, true, true>(a, 0, gpw);
 }
 
 // ---------------------------------------------------------------------------
@@ -1674,12 +1755,18 @@ hipError_t launch_count_one(const VolDesc &d, int64_t ntiles, int32_t words_per_
     return hipGetLastError();
 }
 
-hipError_t launch_generate(int32_t dtype, int32_t mode, bool staged, const VolDesc *d_descs,
+hipError_t launch_generate(int32_t dtype, int32_t mode, bool staged, bool two_d, const VolDesc *d_descs,
                            const int64_t *d_tile_prefix, int32_t nvol, int64_t tile_base,
                            int64_t ntiles, int32_t bpw, hipStream_t s)
 {
     if (ntiles <= 0) return hipSuccess;
-    if (staged) {
+    if (two_d && staged) {
+        SN_KEY_SWITCH(k_generate2d_staged, dim3((uint32_t)ntiles), dim3(kBlock), 0, s, d_descs,
+                      d_tile_prefix, nvol, tile_base, bpw)
+    } else if (two_d) {
+        SN_KEY_SWITCH(k_generate2d, dim3((uint32_t)ntiles), dim3(kBlock), 0, s, d_descs, d_tile_prefix,
+                      nvol, tile_base, bpw)
+    } else if (staged) {
         SN_KEY_SWITCH(k_generate_staged, dim3((uint32_t)ntiles), dim3(kBlock), 0, s, d_descs,
                       d_tile_prefix, nvol, tile_base, bpw)
     } else {
@@ -1693,7 +1780,11 @@ hipError_t launch_generate_one(const VolDesc &d, bool staged, int64_t ntiles, in
 {
     if (ntiles <= 0) return hipSuccess;
     const int32_t dtype = d.dtype, mode = d.cs.mode;
-    if (staged) {
+    if (d.prim == kPrimLines && staged) {
+        SN_KEY_SWITCH(k_generate2d_staged_one, dim3((uint32_t)ntiles), dim3(kBlock), 0, s, OneVol{d}, bpw)
+    } else if (d.prim == kPrimLines) {
+        SN_KEY_SWITCH(k_generate2d_one, dim3((uint32_t)ntiles), dim3(kBlock), 0, s, OneVol{d}, bpw)
+    } else if (staged) {
         SN_KEY_SWITCH(k_generate_staged_one, dim3((uint32_t)ntiles), dim3(kBlock), 0, s, OneVol{d}, bpw)
     } else {
         SN_KEY_SWITCH(k_generate_one, dim3((uint32_t)ntiles), dim3(kBlock), 0, s, OneVol{d}, bpw)

@@ -447,7 +447,10 @@ sn_status sn::validate_volume(const sn_volume *v)
     if (v->dims[0] > (int64_t(1) << 30) || v->dims[1] > (int64_t(1) << 30) ||
         v->dims[2] > (int64_t(1) << 30))
         return fail(SN_ETOOBIG, "a dimension exceeds 2^30");
-    if (v->prim != SN_QUADS && v->prim != SN_TRIS) return fail(SN_EINVAL, "prim must be SN_QUADS or SN_TRIS");
+    if (v->prim != SN_QUADS && v->prim != SN_TRIS && v->prim != SN_LINES)
+        return fail(SN_EINVAL, "prim must be SN_QUADS, SN_TRIS or SN_LINES");
+    if (v->prim == SN_LINES && v->dims[2] != 1)
+        return fail(SN_EINVAL, "SN_LINES contours an image: dims[2] must be 1");
     const uint64_t vmax = v->dtype == 4 ? 0xFFFFFFFFull : ((1ull << (8 * v->dtype)) - 1);
     if (v->background > vmax) return fail(SN_EINVAL, "background does not fit the dtype");
     if (v->n_selected < 0 || (v->n_selected > 0 && !v->selected))
@@ -457,7 +460,7 @@ sn_status sn::validate_volume(const sn_volume *v)
         if (v->selected[s] == v->background)
             return fail(SN_EINVAL, "the background value cannot be selected");
     }
-    const bool empty = v->dims[0] < 2 || v->dims[1] < 2 || v->dims[2] < 2;
+    const bool empty = v->dims[0] < 2 || v->dims[1] < 2 || (v->prim != SN_LINES && v->dims[2] < 2);
     if (!v->labels && !empty) return fail(SN_EINVAL, "labels is NULL");
     {
         // the kernels index rows, words and batches of one volume with int32;
@@ -474,10 +477,12 @@ Geom sn::make_geom(const sn_volume &v)
 {
     Geom g;
     g.M = v.dims[0], g.N = v.dims[1], g.O = v.dims[2];
-    const bool empty = g.M < 2 || g.N < 2 || g.O < 2;
+    // an image (SN_LINES, O = 1) has one slice of cells
+    const bool image = v.prim == SN_LINES;
+    const bool empty = g.M < 2 || g.N < 2 || (!image && g.O < 2);
     g.CM = empty ? 0 : g.M - 1;
     g.CN = empty ? 0 : g.N - 1;
-    g.CO = empty ? 0 : g.O - 1;
+    g.CO = empty ? 0 : (image ? 1 : g.O - 1);
     g.R = g.CN * g.CO;
     g.W = (int32_t)((g.CM + 63) / 64);
     g.NB = (g.W + kU - 1) / kU;
@@ -561,6 +566,11 @@ extern "C" sn_status sn_mesh_view_get(const sn_mesh *m, sn_mesh_view *out)
         v.n_polys = 2 * m->Q;
         v.polys = m->d.tris;
         v.label_pairs = m->d.tri_pairs;
+    } else if (m->d.prim == SN_LINES) {  // an image's contour segments
+        v.n_polys = m->Q;
+        v.polys = m->d.quads;
+        v.label_pairs = m->d.pairs;
+        v.quads = nullptr;
     } else {
         v.n_polys = m->Q;
         v.polys = m->d.quads;
@@ -739,7 +749,9 @@ sn_status sn::extract_many(sn_ctx *c, const sn_volume *vols, int32_t n, hipStrea
     auto wide = [&](int32_t v) {
         return vols[v].dims[0] % 4 == 0 && (reinterpret_cast<uintptr_t>(vols[v].labels) & 15) == 0;
     };
-    auto key = [&](int32_t v) { return vols[v].dtype * 8 + mode[v] * 2 + (wide(v) ? 1 : 0); };
+    auto key = [&](int32_t v) {
+        return (vols[v].prim == SN_LINES ? 64 : 0) + vols[v].dtype * 8 + mode[v] * 2 + (wide(v) ? 1 : 0);
+    };
     std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return key(a) < key(b); });
 
     std::vector<int64_t> tile_prefix(n + 1, 0), etile_prefix(n + 1, 0), ctile_prefix(n + 1, 0);
@@ -779,6 +791,9 @@ sn_status sn::extract_many(sn_ctx *c, const sn_volume *vols, int32_t n, hipStrea
         d.prim = vol.prim;
         d.g = make_geom(vol);
         for (int a = 0; a < 3; ++a) d.origin[a] = vol.origin[a], d.spacing[a] = vol.spacing[a];
+        // an image's points lie in the plane z = origin[2]: with a zero z
+        // spacing every kernel that writes world points puts them there
+        if (vol.prim == SN_LINES) d.spacing[2] = 0.0;
         d.cs.mode = mode[v];
         d.cs.bg = vol.background;
         d.cs.n = (int32_t)tabs[v].size();
@@ -900,7 +915,8 @@ sn_status sn::extract_many(sn_ctx *c, const sn_volume *vols, int32_t n, hipStrea
         // every output of the mesh in one block, sized exactly
         Carve cv;
         const size_t o_pts = cv.add(12 * m->P), o_fc = cv.add(m->P), o_off = cv.add(4 * (m->P + 1));
-        const size_t o_ids = cv.add(4 * m->S), o_q = cv.add(16 * m->Q), o_pr = cv.add(2 * m->Q * d.dtype);
+        const int64_t quad_bytes = d.prim == SN_LINES ? 8 : 16;  // segments [Q][2] or quads [Q][4]
+        const size_t o_ids = cv.add(4 * m->S), o_q = cv.add(quad_bytes * m->Q), o_pr = cv.add(2 * m->Q * d.dtype);
         const bool tris = d.prim == SN_TRIS;
         const size_t o_t = tris ? cv.add(24 * m->Q) : 0, o_tp = tris ? cv.add(4 * m->Q * d.dtype) : 0;
         // cell index per point (for world points written by the last sweep),
@@ -957,8 +973,9 @@ sn_status sn::extract_many(sn_ctx *c, const sn_volume *vols, int32_t n, hipStrea
                 int64_t gp = 0, gw = 0;
                 for (int32_t k = k0; k < k1; ++k) gp += hd[k].P, gw += hd[k].g.R * hd[k].g.W;
                 const bool staged = gp >= kGenStagedPointsPerWord * gw;
-                HIP_TRY_CLEANUP(launch_generate(hd[k0].dtype, hd[k0].cs.mode, staged, d_desc2 + k0, d_tp + k0, k1 - k0,
-                                        tile_prefix[k0], tile_prefix[k1] - tile_prefix[k0], bpw, s));
+                HIP_TRY_CLEANUP(launch_generate(hd[k0].dtype, hd[k0].cs.mode, staged, hd[k0].prim == SN_LINES,
+                                                d_desc2 + k0, d_tp + k0, k1 - k0, tile_prefix[k0],
+                                                tile_prefix[k1] - tile_prefix[k0], bpw, s));
             }
         }
         if (qblocks > 0) {
@@ -1090,6 +1107,7 @@ extern "C" sn_status sn_triangulate(sn_ctx *c, sn_mesh *m, sn_diag_rule rule, in
 {
     if (!c || !m) return fail(SN_EINVAL, "sn_triangulate: NULL argument");
     if (rule < SN_DIAG_FIXED || rule > SN_DIAG_PLANAR) return fail(SN_EINVAL, "sn_triangulate: unknown rule");
+    if (m->d.prim == SN_LINES) return fail(SN_EINVAL, "sn_triangulate: an image's contour has no quads");
     if (m->Q > 0 && !tris) return fail(SN_EINVAL, "sn_triangulate: NULL triangle buffer");
     if (m->Q == 0) return SN_OK;
     HIP_TRY(hipSetDevice(c->device));

@@ -98,6 +98,9 @@ class Volume:
 
     @property
     def dims(self):
+        if self.labels.ndim == 2:  # an image (N, M)
+            N, M = self.labels.shape
+            return (M, N, 1)
         O, N, M = self.labels.shape
         return (M, N, O)
 
@@ -211,6 +214,24 @@ def connectome_like(seed: int = 3, dims=(1024, 1024, 512), n_cells: int = 50_000
     lab = stretched(dims, 4, seeds, d, np.arange(1, n_cells + 1), alpha, radius, membrane)
     return Volume(lab, iterations=20, relaxation=0.5, constraint=0.8,
                   name=f"connectome_like_{M}x{N}x{O}_u32", meta={"seed": seed})
+
+
+def section_like(seed: int = 7, n: int = 8192, n_cells: int = 40_000, alpha: float = 4.0,
+                 radius: float = 64.0, membrane: float = 0.02) -> Volume:
+    """An n x n uint32 image shaped like one section of the connectome-like
+    volume (the 2D method, SN_LINES): n_cells seeds uniform in the plane, each
+    with a random in-plane direction, cells stretched alpha-fold along it,
+    and the `membrane` fraction of pixels with the smallest gap between the two
+    best distances set to 0.  20 iterations, relaxation 0.5, constraint 0.8."""
+    rng = np.random.default_rng(seed)
+    seeds = np.zeros((n_cells, 3))
+    seeds[:, :2] = rng.uniform(0, 1, size=(n_cells, 2)) * (n - 1)
+    d = np.zeros((n_cells, 3))
+    ang = rng.uniform(0, 2 * np.pi, size=n_cells)
+    d[:, 0], d[:, 1] = np.cos(ang), np.sin(ang)
+    lab = stretched((n, n, 1), 4, seeds, d, np.arange(1, n_cells + 1), alpha, radius, membrane)
+    return Volume(lab.reshape(n, n), iterations=20, relaxation=0.5, constraint=0.8,
+                  name=f"section_like_{n}^2_u32", meta={"seed": seed})
 
 
 def mixed_volume(rng: np.random.Generator, dims, b: int, n_labels: int) -> np.ndarray:
