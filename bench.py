@@ -51,23 +51,24 @@ def log(*a):
 
 def words_of(dims):
     M, N, O = dims
-    R = max(N - 1, 0) * max(O - 1, 0)
+    # an image (O = 1) has one slice of cell rows
+    R = max(N - 1, 0) * (1 if O == 1 else max(O - 1, 0))
     W = (max(M - 1, 0) + 63) // 64
     WS = (M + 63) // 64
     return R * W, 3 * N * O * WS * 8  # cell words, plane bytes
 
 
-def bytes_extract(V, b, P, Q, S):
+def bytes_extract(V, b, P, Q, S, qb=16):
     """Whole extraction: read the labels once; write points (12 B) and CSR
-    offsets (4 B) per point, quads (16 B) and label pairs (2b B) per quad,
-    4 B per stencil id."""
-    return V * b + 16 * P + 4 + Q * (16 + 2 * b) + 4 * S
+    offsets (4 B) per point, quads (qb = 16 B; an image's segments 8 B) and
+    label pairs (2b B) per quad, 4 B per stencil id."""
+    return V * b + 16 * P + 4 + Q * (qb + 2 * b) + 4 * S
 
 
-def alg_bytes(dims, b, P, Q, S, n):
+def alg_bytes(dims, b, P, Q, S, n, qb=16):
     V = dims[0] * dims[1] * dims[2]
     words, planes = words_of(dims)
-    out_gen = 16 * P + 4 + Q * (16 + 2 * b) + 4 * S
+    out_gen = 16 * P + 4 + Q * (qb + 2 * b) + 4 * S
     return {
         # kernel: (algorithmic, design)
         "k_edges": (V * b, V * b + planes),
@@ -129,7 +130,8 @@ def measure_workload(ctx, sn, torch, vol, steps, warmup):
     for name, (launches, ms) in prof.items():
         per[name] = {"launches": launches, "avg_us": 1e3 * ms / max(launches, 1),
                      "total_ms": ms, "events": "timed steps" if name in timed else "profiled steps"}
-    alg = alg_bytes(vol.dims, b, P, Q, S, n)
+    qb = 8 if vol.labels.ndim == 2 else 16  # an image's segments: two ids
+    alg = alg_bytes(vol.dims, b, P, Q, S, n, qb)
     for name, d in per.items():
         if name in alg:
             a, dsg = alg[name]
@@ -141,7 +143,7 @@ def measure_workload(ctx, sn, torch, vol, steps, warmup):
     ext_ms = sum(per.get(k, {}).get("total_ms", 0.0)
                  for k in ("k_edges", "k_count", "k_generate")) / steps
     smo_ms = sum(per.get(k, {}).get("total_ms", 0.0) for k in ("k_jacobi", "k_emit")) / steps
-    bx = bytes_extract(V, b, P, Q, S)
+    bx = bytes_extract(V, b, P, Q, S, qb)
     res = {
         "voxels": V, "points": P, "quads": Q, "stencil": S, "iterations": n,
         "batches_per_wave": bpw,
@@ -492,8 +494,8 @@ def pmc_summary(pmc_dir, out_path, workload):
                 # one entry per kernel as the library's timing names it: the
                 # single-volume forms (_one), the first sweep (k_jacobi_first),
                 # the row-width forms of k_edges and the store forms of
-                # k_generate count with their kernel
-                for suf in ("_one", "_wide", "_narrow", "_staged"):
+                # k_generate (and its image form) count with their kernel
+                for suf in ("_one", "_wide", "_narrow", "_staged", "2d"):
                     key = key.replace(suf, "")
                 if key.startswith("k_jacobi"):
                     key = "k_jacobi"
@@ -531,7 +533,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="torso", choices=["torso", "connectome", "spheres"])
+    ap.add_argument("--workload", default="torso",
+                    choices=["torso", "connectome", "spheres", "section"])
     ap.add_argument("--no-extra", action="store_true", help="skip connectome/batched/served")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"),
@@ -561,6 +564,7 @@ def main():
     ctx = sn.Context(0)
     log(f"[bench] device {torch.cuda.get_device_name(0)}; workload {args.workload}")
     gen = {"torso": synth.torso_like, "connectome": synth.connectome_like,
+           "section": synth.section_like,
            "spheres": synth.spheres_small}[args.workload]
     vol = gen()
     res = measure_workload(ctx, sn, torch, vol, args.steps, args.warmup)
@@ -593,6 +597,22 @@ def main():
                 "kernels": {k: {kk: (round(vv, 3) if isinstance(vv, float) else vv)
                                 for kk, vv in d.items()} for k, d in r3["kernels"].items()}}
             del cvol
+        if args.workload != "section":
+            # the 2D method on an image (SN_LINES)
+            svol = synth.section_like()
+            r2 = measure_workload(ctx, sn, torch, svol, max(3, args.steps // 4), 1)
+            extra["section_like_2d"] = {
+                "name": svol.name, "ms_per_step": round(r2["ms_per_step"], 3),
+                "gpix_per_s": round(r2["gvox_per_s"], 3),
+                "extract_gpix_per_s": round(r2["extract_gvox_per_s"], 3),
+                "extract_alg_GBs": round(r2["extract_alg_GBs"], 1),
+                "extract_frac_hbm": round(r2["extract_frac_hbm"], 4),
+                "smooth_gptit_per_s": round(r2["smooth_gptit_per_s"], 3),
+                "points": r2["points"], "segments": r2["quads"],
+                "roofline": roofline_of(r2, traffic_for("section", r2)),
+                "kernels": {k: {kk: (round(vv, 3) if isinstance(vv, float) else vv)
+                                for kk, vv in d.items()} for k, d in r2["kernels"].items()}}
+            del svol
         extra["batched"] = bench_batched(ctx, sn, torch)
         extra["served"] = bench_served(ctx, sn, torch)
         extra["triangulate"] = bench_triangulate(ctx, sn, torch, vol)
@@ -606,10 +626,11 @@ def main():
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(res["ms_per_step"], 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "u16 labels; f64 math / f32 storage for smoothing",
+        "dtype": f"{'u' + str(8 * vol.labels.dtype.itemsize)} labels; f64 math / f32 storage for smoothing",
         "data": "synthetic (seeded generator, resident in HBM)",
         "config": {"workload": vol.name, "dims": list(vol.dims), "spacing": list(vol.spacing),
-                   "labels": "all", "prim": "quads", "iterations": vol.iterations,
+                   "labels": "all", "prim": "lines" if vol.labels.ndim == 2 else "quads",
+                   "iterations": vol.iterations,
                    "relaxation": vol.relaxation, "constraint": vol.constraint,
                    "batches_per_wave": res["batches_per_wave"]},
         "extract_gvox_per_s": round(res["extract_gvox_per_s"], 3),

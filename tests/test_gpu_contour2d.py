@@ -136,6 +136,14 @@ def test_section_image(ctx, sn):
     run_image(ctx, sn, v.labels, selected=(17, 1000), iters=5, d=0.5, shape="sphere")
 
 
+def test_section_bench_size(ctx, sn):
+    """The benchmark's 2D configuration in full: the 8192^2 section-like u32
+    image, extraction and 20 sweeps, every output against the oracle."""
+    v = synth.section_like()
+    announce(f"2D {v.name}, {v.iterations} sweeps")
+    run_image(ctx, sn, v.labels, iters=v.iterations, lam=v.relaxation, d=v.constraint)
+
+
 def test_batch_of_images_and_volumes(ctx, sn, torch):
     """Images and volumes in one batch: every mesh equals its plain extraction."""
     rng = np.random.default_rng(5)
