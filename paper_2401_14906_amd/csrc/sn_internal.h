@@ -209,6 +209,9 @@ hipError_t launch_generate_one(const VolDesc &d, bool staged, int64_t ntiles, in
 hipError_t launch_emit_one(const VolDesc &d, const SmoothDesc &sd, int64_t ntiles, int32_t bpw,
                            hipStream_t s);
 hipError_t launch_jacobi_one(const SmoothDesc &sd, int64_t nblocks, int32_t it, int K, hipStream_t s);
+// sweeps 0 and 1 of one mesh (iterations >= 2) in one launch, equal to two
+// launch_jacobi_one calls bit for bit
+hipError_t launch_jacobi_first2_one(const SmoothDesc &sd, int64_t nblocks, int K, hipStream_t s);
 hipError_t launch_triangulate_one(const VolDesc &d, hipStream_t s);
 // quads [Q][4] over world points -> tris [2Q][3] under diagonal rule 0..3;
 // tri_pairs [2Q][2] of the label type (dtype bytes) when not null

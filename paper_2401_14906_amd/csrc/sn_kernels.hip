@@ -1228,6 +1228,33 @@ __device__ __forceinline__ double face_term(int face, int axis, double n, double
     return (face >> 1) == axis ? step + n - own : n - own;
 }
 
+// Eq. (1) for one point with face mask fc: its offset (x, y, z) moves by
+// lambda times the mean over its faces of (unit step + neighbour offset - own
+// offset); nx, ny, nz hold the neighbour offsets in face order.  The first
+// sweep and its table (first_offset) use this form; the later sweeps write the
+// same arithmetic inline, which keeps their neighbour values out of arrays
+// (40 registers instead of 60).
+__device__ __forceinline__ void sweep_update(const SmoothDesc &s, uint32_t fc, const float (&nx)[6],
+                                             const float (&ny)[6], const float (&nz)[6], double &x,
+                                             double &y, double &z)
+{
+    const int n = __popc(fc);
+    if (n == 0) return;
+    double sx = 0.0, sy = 0.0, sz = 0.0;
+#pragma unroll
+    for (int face = 0; face < 6; ++face) {
+        if (!((fc >> face) & 1u)) continue;
+        sx += face_term(face, 0, (double)nx[face], x);
+        sy += face_term(face, 1, (double)ny[face], y);
+        sz += face_term(face, 2, (double)nz[face], z);
+    }
+    const double inv = 1.0 / (double)n;
+    x = x + s.lam * (sx * inv);
+    y = y + s.lam * (sy * inv);
+    z = z + s.lam * (sz * inv);
+}
+
+
 __device__ __forceinline__ uint32_t udiv(uint32_t n, const UDiv &u)
 {
     const uint32_t t = __umulhi(n, u.m);
@@ -1240,9 +1267,7 @@ __device__ __forceinline__ uint32_t udiv(uint32_t n, const UDiv &u)
 // point's cell index (the world-coordinate output, fused into the sweep).
 // NT: streaming (non-temporal) stores, for meshes whose sweep data does not
 // stay in the caches between sweeps anyway.
-template <bool NT = false>
-__device__ __forceinline__ void store_offset(const SmoothDesc &s, SN_GLOBAL float *dout, int64_t p,
-                                             double x, double y, double z, bool last, uint32_t cell)
+__device__ __forceinline__ void constrain(const SmoothDesc &s, double &x, double &y, double &z)
 {
     const double c = s.dist;
     if (s.sphere) {
@@ -1257,6 +1282,13 @@ __device__ __forceinline__ void store_offset(const SmoothDesc &s, SN_GLOBAL floa
         y = fmin(fmax(y, -c), c);
         z = fmin(fmax(z, -c), c);
     }
+}
+
+template <bool NT = false>
+__device__ __forceinline__ void store_offset(const SmoothDesc &s, SN_GLOBAL float *dout, int64_t p,
+                                             double x, double y, double z, bool last, uint32_t cell)
+{
+    constrain(s, x, y, z);
     const float fx = (float)x, fy = (float)y, fz = (float)z;
     if constexpr (NT) {
         __builtin_nontemporal_store(fx, dout + 3 * p);
@@ -1275,6 +1307,36 @@ __device__ __forceinline__ void store_offset(const SmoothDesc &s, SN_GLOBAL floa
         o[1] = (float)(s.origin[1] + s.spacing[1] * ((double)j + 0.5 + (double)fy));
         o[2] = (float)(s.origin[2] + s.spacing[2] * ((double)k + 0.5 + (double)fz));
     }
+}
+
+// The offset the first sweep gives a point with face mask f, as that sweep
+// stores it: every input offset is zero, so it depends on f alone.
+__device__ __forceinline__ void first_offset(const SmoothDesc &s, uint32_t f, float &fx, float &fy,
+                                             float &fz)
+{
+    const float zero[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    double x = 0.0, y = 0.0, z = 0.0;
+    sweep_update(s, f, zero, zero, zero, x, y, z);
+    constrain(s, x, y, z);
+    fx = (float)x, fy = (float)y, fz = (float)z;
+}
+
+// The y/z stencil neighbours of point p (face mask f) from the CSR stencil:
+// ids of -y, +y, -z, +z, -1 where absent.
+__device__ __forceinline__ v4i stencil_yz(const SmoothDesc &s, uint32_t f, int64_t p)
+{
+    int64_t e = glb(s.off)[p];
+    v4i q = {-1, -1, -1, -1};
+#pragma unroll
+    for (int face = 0; face < 6; ++face) {
+        if (!((f >> face) & 1u)) continue;
+        const int32_t id = glb(s.ids)[e++];
+        if (face == 2) q.x = id;
+        if (face == 3) q.y = id;
+        if (face == 4) q.z = id;
+        if (face == 5) q.w = id;
+    }
+    return q;
 }
 
 // Sweep 0: every input offset is zero, so p_q - p_p is the face step alone.
@@ -1335,30 +1397,10 @@ __device__ __forceinline__ void jacobi_first_body(const Src &a)
         const int64_t p = (b - first) * (kSweepBlock * K) + c * kSweepBlock + threadIdx.x;
         if (p >= s.P) break;
         const uint32_t f = glb(s.faces)[p];
-        const int n = __popc(f);
-        int64_t e = glb(s.off)[p];
-        v4i q = {-1, -1, -1, -1};
-        double sx = 0.0, sy = 0.0, sz = 0.0;
-#pragma unroll
-        for (int face = 0; face < 6; ++face) {
-            if (!((f >> face) & 1u)) continue;
-            const int32_t id = glb(s.ids)[e++];
-            if (face == 2) q.x = id;
-            if (face == 3) q.y = id;
-            if (face == 4) q.z = id;
-            if (face == 5) q.w = id;
-            sx += face_term(face, 0, 0.0, 0.0);
-            sy += face_term(face, 1, 0.0, 0.0);
-            sz += face_term(face, 2, 0.0, 0.0);
-        }
-        glb(reinterpret_cast<v4i *>(s.nbr))[p] = q;
+        glb(reinterpret_cast<v4i *>(s.nbr))[p] = stencil_yz(s, f, p);
+        const float zero[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
         double x = 0.0, y = 0.0, z = 0.0;
-        if (n > 0) {
-            const double inv = 1.0 / (double)n;
-            x = x + s.lam * (sx * inv);
-            y = y + s.lam * (sy * inv);
-            z = z + s.lam * (sz * inv);
-        }
+        sweep_update(s, f, zero, zero, zero, x, y, z);
         const bool last = s.iters == 1 && s.pcell;
         store_offset(s, dout, p, x, y, z, last, last ? glb(s.pcell)[p] : 0u);
     }
@@ -1401,7 +1443,15 @@ __device__ __forceinline__ float readlane_f(float x, int l)
 // before any use.  The -x / +x neighbours of point p are points p - 1 / p + 1
 // (consecutive cells of a row get consecutive ids), read from the adjacent
 // lane; only the first and the last point of the wave load them.
-template <int K, class Src>
+//
+// FUSED: sweeps 0 and 1 in one launch (it = 1).  The first sweep's offset of a
+// point depends on its face mask alone (every input offset is zero), so the
+// block tabulates it for all 64 masks in LDS, exactly as k_jacobi_first stores
+// it, and sweep 1 reads its own and its neighbours' first-sweep offsets from
+// the table through their face bytes instead of from an offset buffer; it
+// also builds the neighbour table from the CSR stencil.  The result equals
+// the two separate sweeps bit for bit.
+template <int K, bool FUSED, class Src>
 __device__ __forceinline__ void jacobi_body(const Src &a, int32_t it)
 {
     const uint32_t nbl = sweep_blocks<K>(a);
@@ -1410,6 +1460,15 @@ __device__ __forceinline__ void jacobi_body(const Src &a, int32_t it)
     int64_t first;
     const SmoothDesc &s = smooth_of(a, b, first);
     if (it >= s.iters) return;  // this mesh has finished its sweeps
+    __shared__ float s_first[FUSED ? 64 * 3 : 1];
+    if constexpr (FUSED) {
+        // every wave of the block reaches this barrier (no exit before it
+        // depends on the wave)
+        if (threadIdx.x < 64)
+            first_offset(s, threadIdx.x, s_first[3 * threadIdx.x], s_first[3 * threadIdx.x + 1],
+                         s_first[3 * threadIdx.x + 2]);
+        __syncthreads();
+    }
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int64_t p0 = (b - first) * (kSweepBlock * K) + (int64_t)wave * (64 * K);
     const int64_t P = s.P;
@@ -1428,25 +1487,42 @@ __device__ __forceinline__ void jacobi_body(const Src &a, int32_t it)
         const int64_t p = p0 + 64 * c + lane;
         f[c] = 0, cell[c] = 0, nb[c] = v4i{-1, -1, -1, -1}, ox[c] = oy[c] = oz[c] = 0.f;
         if (p < P) {
-            if constexpr (K > 1) {  // large meshes: read-once streams
-                f[c] = __builtin_nontemporal_load(glb(s.faces) + p);
-                nb[c] = __builtin_nontemporal_load(nbr + p);
-            } else {
+            if constexpr (FUSED) {
                 f[c] = glb(s.faces)[p];
-                nb[c] = nbr[p];
+                nb[c] = stencil_yz(s, f[c], p);
+                glb(reinterpret_cast<v4i *>(s.nbr))[p] = nb[c];
+                ox[c] = s_first[3 * f[c]], oy[c] = s_first[3 * f[c] + 1], oz[c] = s_first[3 * f[c] + 2];
+            } else {
+                if constexpr (K > 1) {  // large meshes: read-once streams
+                    f[c] = __builtin_nontemporal_load(glb(s.faces) + p);
+                    nb[c] = __builtin_nontemporal_load(nbr + p);
+                } else {
+                    f[c] = glb(s.faces)[p];
+                    nb[c] = nbr[p];
+                }
+                ox[c] = din[3 * p], oy[c] = din[3 * p + 1], oz[c] = din[3 * p + 2];
             }
-            ox[c] = din[3 * p], oy[c] = din[3 * p + 1], oz[c] = din[3 * p + 2];
             if (last) cell[c] = glb(s.pcell)[p];
         }
     }
     // wave halo: -x of the first point, +x of the last one (p0 + 64K - 1)
     float hmx = 0.f, hmy = 0.f, hmz = 0.f, hpx = 0.f, hpy = 0.f, hpz = 0.f;
     if (lane == 0 && (f[0] & 1u)) {
-        hmx = din[3 * (p0 - 1)], hmy = din[3 * (p0 - 1) + 1], hmz = din[3 * (p0 - 1) + 2];
+        if constexpr (FUSED) {
+            const uint32_t fq = glb(s.faces)[p0 - 1];
+            hmx = s_first[3 * fq], hmy = s_first[3 * fq + 1], hmz = s_first[3 * fq + 2];
+        } else {
+            hmx = din[3 * (p0 - 1)], hmy = din[3 * (p0 - 1) + 1], hmz = din[3 * (p0 - 1) + 2];
+        }
     }
     if (lane == 63 && (f[K - 1] & 2u)) {
         const int64_t q = p0 + 64 * K;
-        hpx = din[3 * q], hpy = din[3 * q + 1], hpz = din[3 * q + 2];
+        if constexpr (FUSED) {
+            const uint32_t fq = glb(s.faces)[q];
+            hpx = s_first[3 * fq], hpy = s_first[3 * fq + 1], hpz = s_first[3 * fq + 2];
+        } else {
+            hpx = din[3 * q], hpy = din[3 * q + 1], hpz = din[3 * q + 2];
+        }
     }
     // y / z neighbours
     float gx[K][4], gy[K][4], gz[K][4];
@@ -1458,7 +1534,12 @@ __device__ __forceinline__ void jacobi_body(const Src &a, int32_t it)
             gx[c][e] = gy[c][e] = gz[c][e] = 0.f;
             if (id[e] >= 0) {
                 const int64_t q = id[e];
-                gx[c][e] = din[3 * q], gy[c][e] = din[3 * q + 1], gz[c][e] = din[3 * q + 2];
+                if constexpr (FUSED) {
+                    const uint32_t fq = glb(s.faces)[q];
+                    gx[c][e] = s_first[3 * fq], gy[c][e] = s_first[3 * fq + 1], gz[c][e] = s_first[3 * fq + 2];
+                } else {
+                    gx[c][e] = din[3 * q], gy[c][e] = din[3 * q + 1], gz[c][e] = din[3 * q + 2];
+                }
             }
         }
     }
@@ -1512,13 +1593,20 @@ __global__ __launch_bounds__(kSweepBlock) void k_jacobi(const SmoothDesc *__rest
                                                 const int64_t *__restrict__ prefix, int32_t nvol,
                                                 int32_t it)
 {
-    jacobi_body<K>(ManySmooth{sds, prefix, nvol}, it);
+    jacobi_body<K, false>(ManySmooth{sds, prefix, nvol}, it);
 }
 
 template <int K>
 __global__ __launch_bounds__(kSweepBlock) void k_jacobi_one(OneSmooth a, int32_t it)
 {
-    jacobi_body<K>(a, it);
+    jacobi_body<K, false>(a, it);
+}
+
+// Sweeps 0 and 1 of one mesh in one launch (meshes of at least two sweeps).
+template <int K>
+__global__ __launch_bounds__(kSweepBlock) void k_jacobi_first2_one(OneSmooth a)
+{
+    jacobi_body<K, true>(a, 1);
 }
 
 // ---------------------------------------------------------------------------
@@ -1840,6 +1928,18 @@ hipError_t launch_jacobi(const SmoothDesc *d_sd, const int64_t *d_block_prefix, 
         jacobi_k<1>(d_sd, d_block_prefix, nvol, nblocks, it, s);
     else
         jacobi_k<2>(d_sd, d_block_prefix, nvol, nblocks, it, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_jacobi_first2_one(const SmoothDesc &sd, int64_t nblocks, int K, hipStream_t s)
+{
+    if (nblocks <= 0) return hipSuccess;
+    if (K == 1)
+        hipLaunchKernelGGL(k_jacobi_first2_one<1>, dim3((uint32_t)nblocks), dim3(kSweepBlock), 0, s,
+                           OneSmooth{sd});
+    else
+        hipLaunchKernelGGL(k_jacobi_first2_one<2>, dim3((uint32_t)nblocks), dim3(kSweepBlock), 0, s,
+                           OneSmooth{sd});
     return hipGetLastError();
 }
 

@@ -1082,23 +1082,30 @@ sn_status sn::run_sweeps(sn_ctx *c, const SmoothDesc *d_sd, const int64_t *d_bp,
     return SN_OK;
 }
 
-// n sweeps of one mesh, launched one by one: a single mesh's sweeps are
+// n sweeps of one mesh, launched one by one (the first two fused): a single mesh's sweeps are
 // launched from the calling thread (a graph launch holds that thread until
 // the replay has nearly finished, so the next call's work would start late)
 sn_status sn::run_sweeps_one(sn_ctx *c, const SmoothDesc &sd, int64_t nblocks, int K, hipStream_t s)
 {
     const int32_t iters = sd.iters;
     if (iters <= 0 || nblocks <= 0) return SN_OK;
+    // sweeps 0 and 1 go in one launch when there are two or more
+    const int32_t it0 = iters >= 2 ? 2 : 0;
     if (c->profile_eager) {
-        for (int32_t it = 0; it < iters; ++it) {
+        if (it0 == 2) {
+            ProfScope ps(c, "k_jacobi", s, 2);
+            HIP_TRY(launch_jacobi_first2_one(sd, nblocks, K, s));
+        }
+        for (int32_t it = it0; it < iters; ++it) {
             ProfScope ps(c, "k_jacobi", s);
             HIP_TRY(launch_jacobi_one(sd, nblocks, it, K, s));
         }
         return SN_OK;
     }
-    // one event pair around the `iters` launches
+    // one event pair around the launches of the `iters` sweeps
     ProfScope ps(c, "k_jacobi", s, iters);
-    for (int32_t it = 0; it < iters; ++it) HIP_TRY(launch_jacobi_one(sd, nblocks, it, K, s));
+    if (it0 == 2) HIP_TRY(launch_jacobi_first2_one(sd, nblocks, K, s));
+    for (int32_t it = it0; it < iters; ++it) HIP_TRY(launch_jacobi_one(sd, nblocks, it, K, s));
     return SN_OK;
 }
 
