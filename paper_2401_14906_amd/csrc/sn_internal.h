@@ -194,8 +194,12 @@ hipError_t launch_emit(const VolDesc *d_descs, const SmoothDesc *d_sds, const in
 // (zero input offsets, builds nbr)
 hipError_t launch_jacobi(const SmoothDesc *d_sd, const int64_t *d_block_prefix, int32_t nvol,
                          int64_t nblocks, int32_t it, int K, hipStream_t s);
+// sweeps 0 and 1 over many meshes: fused over the leading grid1 blocks (the
+// meshes of at least two sweeps), sweep 0 alone over blocks grid1 .. grid0
+hipError_t launch_jacobi_first2(const SmoothDesc *d_sd, const int64_t *d_block_prefix, int32_t nvol,
+                                int64_t grid0, int64_t grid1, int K, hipStream_t s);
 // the same n sweeps as kernel nodes of `graph`, each depending on the one before
-// (sweep `it` launches grid[it] blocks)
+// (sweep `it` launches grid[it] blocks; sweeps 0 and 1 as launch_jacobi_first2)
 hipError_t add_jacobi_nodes(hipGraph_t graph, const SmoothDesc *d_sd,
                             const int64_t *d_block_prefix, int32_t nvol, const int64_t *grid,
                             int32_t iters, int K);

@@ -1382,12 +1382,14 @@ __device__ __forceinline__ int64_t sweep_block(const OneSmooth &a, uint32_t b, u
     return K == 1 ? xcd_block(b, nb) : (int64_t)slab_chunk_block(b, nb, (uint32_t)a.s.chunk);
 }
 
+// block0: the launch covers logical blocks block0 .. (a launch over many
+// meshes that runs the first sweep of its one-sweep meshes only)
 template <int K, class Src>
-__device__ __forceinline__ void jacobi_first_body(const Src &a)
+__device__ __forceinline__ void jacobi_first_body(const Src &a, int64_t block0)
 {
     const uint32_t nb = sweep_blocks<K>(a);
     if (blockIdx.x >= nb) return;
-    const int64_t b = sweep_block<K>(a, blockIdx.x, nb);
+    const int64_t b = block0 + sweep_block<K>(a, blockIdx.x, nb);
     int64_t first;
     const SmoothDesc &s = smooth_of(a, b, first);
     if (s.iters < 1) return;
@@ -1409,15 +1411,15 @@ __device__ __forceinline__ void jacobi_first_body(const Src &a)
 template <int K>
 __global__ __launch_bounds__(kSweepBlock) void k_jacobi_first(const SmoothDesc *__restrict__ sds,
                                                       const int64_t *__restrict__ prefix,
-                                                      int32_t nvol)
+                                                      int32_t nvol, int64_t block0)
 {
-    jacobi_first_body<K>(ManySmooth{sds, prefix, nvol});
+    jacobi_first_body<K>(ManySmooth{sds, prefix, nvol}, block0);
 }
 
 template <int K>
 __global__ __launch_bounds__(kSweepBlock) void k_jacobi_first_one(OneSmooth a)
 {
-    jacobi_first_body<K>(a);
+    jacobi_first_body<K>(a, 0);
 }
 
 // Whole-wave DPP shifts by one lane (no LDS traffic): lane l receives lane
@@ -1602,11 +1604,21 @@ __global__ __launch_bounds__(kSweepBlock) void k_jacobi_one(OneSmooth a, int32_t
     jacobi_body<K, false>(a, it);
 }
 
-// Sweeps 0 and 1 of one mesh in one launch (meshes of at least two sweeps).
+// Sweeps 0 and 1 in one launch (meshes of at least two sweeps; in a launch
+// over many meshes these are the leading blocks, meshes being ordered by
+// descending sweep count).
 template <int K>
 __global__ __launch_bounds__(kSweepBlock) void k_jacobi_first2_one(OneSmooth a)
 {
     jacobi_body<K, true>(a, 1);
+}
+
+template <int K>
+__global__ __launch_bounds__(kSweepBlock) void k_jacobi_first2(const SmoothDesc *__restrict__ sds,
+                                                       const int64_t *__restrict__ prefix,
+                                                       int32_t nvol)
+{
+    jacobi_body<K, true>(ManySmooth{sds, prefix, nvol}, 1);
 }
 
 // ---------------------------------------------------------------------------
@@ -1903,7 +1915,7 @@ static void jacobi_k(const SmoothDesc *d_sd, const int64_t *d_block_prefix, int3
 {
     if (it == 0)
         hipLaunchKernelGGL(k_jacobi_first<K>, dim3((uint32_t)nblocks), dim3(kSweepBlock), 0, s, d_sd,
-                           d_block_prefix, nvol);
+                           d_block_prefix, nvol, int64_t(0));
     else
         hipLaunchKernelGGL(k_jacobi<K>, dim3((uint32_t)nblocks), dim3(kSweepBlock), 0, s, d_sd,
                            d_block_prefix, nvol, it);
@@ -1953,31 +1965,77 @@ hipError_t launch_jacobi_one(const SmoothDesc &sd, int64_t nblocks, int32_t it, 
     return hipGetLastError();
 }
 
-// Kernel nodes of n sweeps over many meshes, each depending on the one before.
+template <int K>
+static void jacobi_first2_k(const SmoothDesc *d_sd, const int64_t *d_block_prefix, int32_t nvol,
+                            int64_t grid0, int64_t grid1, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_jacobi_first2<K>, dim3((uint32_t)grid1), dim3(kSweepBlock), 0, s, d_sd,
+                       d_block_prefix, nvol);
+    if (grid0 > grid1)
+        hipLaunchKernelGGL(k_jacobi_first<K>, dim3((uint32_t)(grid0 - grid1)), dim3(kSweepBlock), 0, s,
+                           d_sd, d_block_prefix, nvol, grid1);
+}
+
+hipError_t launch_jacobi_first2(const SmoothDesc *d_sd, const int64_t *d_block_prefix, int32_t nvol,
+                                int64_t grid0, int64_t grid1, int K, hipStream_t s)
+{
+    if (grid1 <= 0) return hipErrorInvalidValue;
+    if (K == 1)
+        jacobi_first2_k<1>(d_sd, d_block_prefix, nvol, grid0, grid1, s);
+    else
+        jacobi_first2_k<2>(d_sd, d_block_prefix, nvol, grid0, grid1, s);
+    return hipGetLastError();
+}
+
+// Kernel nodes of n sweeps over many meshes, each depending on the one before:
+// sweeps 0 and 1 fused over the meshes of at least two sweeps (the leading
+// grid[1] blocks) and sweep 0 alone over the rest, then sweeps 2 ...
 hipError_t add_jacobi_nodes(hipGraph_t graph, const SmoothDesc *d_sd,
                             const int64_t *d_block_prefix, int32_t nvol, const int64_t *grid,
                             int32_t iters, int K)
 {
     hipGraphNode_t prev = nullptr;
-    for (int32_t it = 0; it < iters && grid[it] > 0; ++it) {
-        const int64_t nblocks = grid[it];
-        void *args_first[] = {&d_sd, &d_block_prefix, &nvol};
-        void *args[] = {&d_sd, &d_block_prefix, &nvol, &it};
+    auto add = [&](void *func, int64_t nblocks, void **args) -> hipError_t {
         hipKernelNodeParams kp{};
-        kp.func = it == 0 ? (K == 1 ? reinterpret_cast<void *>(&k_jacobi_first<1>)
-                                    : reinterpret_cast<void *>(&k_jacobi_first<2>))
-                          : (K == 1 ? reinterpret_cast<void *>(&k_jacobi<1>)
-                                    : reinterpret_cast<void *>(&k_jacobi<2>));
+        kp.func = func;
         kp.gridDim = dim3((uint32_t)nblocks);
         kp.blockDim = dim3(kSweepBlock);
         kp.sharedMemBytes = 0;
-        kp.kernelParams = it == 0 ? args_first : args;
+        kp.kernelParams = args;
         kp.extra = nullptr;
         hipGraphNode_t node;
         const hipError_t e =
             hipGraphAddKernelNode(&node, graph, prev ? &prev : nullptr, prev ? 1 : 0, &kp);
+        if (e == hipSuccess) prev = node;
+        return e;
+    };
+    auto first = [K]() {
+        return K == 1 ? reinterpret_cast<void *>(&k_jacobi_first<1>) : reinterpret_cast<void *>(&k_jacobi_first<2>);
+    };
+    int32_t it = 0;
+    if (iters >= 2 && grid[1] > 0) {
+        void *args_f2[] = {&d_sd, &d_block_prefix, &nvol};
+        hipError_t e = add(K == 1 ? reinterpret_cast<void *>(&k_jacobi_first2<1>)
+                                  : reinterpret_cast<void *>(&k_jacobi_first2<2>),
+                           grid[1], args_f2);
         if (e != hipSuccess) return e;
-        prev = node;
+        if (grid[0] > grid[1]) {
+            int64_t block0 = grid[1];
+            void *args_first[] = {&d_sd, &d_block_prefix, &nvol, &block0};
+            e = add(first(), grid[0] - grid[1], args_first);
+            if (e != hipSuccess) return e;
+        }
+        it = 2;
+    }
+    for (; it < iters && grid[it] > 0; ++it) {
+        int64_t block0 = 0;
+        void *args_first[] = {&d_sd, &d_block_prefix, &nvol, &block0};
+        void *args[] = {&d_sd, &d_block_prefix, &nvol, &it};
+        const hipError_t e = it == 0 ? add(first(), grid[it], args_first)
+                                     : add(K == 1 ? reinterpret_cast<void *>(&k_jacobi<1>)
+                                                  : reinterpret_cast<void *>(&k_jacobi<2>),
+                                           grid[it], args);
+        if (e != hipSuccess) return e;
     }
     return hipSuccess;
 }

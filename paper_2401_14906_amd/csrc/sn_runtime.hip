@@ -1058,8 +1058,15 @@ sn_status sn::run_sweeps(sn_ctx *c, const SmoothDesc *d_sd, const int64_t *d_bp,
     const int32_t iters = (int32_t)grid.size();
     if (iters <= 0 || grid[0] <= 0) return SN_OK;
     if (c->profile_eager) {
-        // eager launches, each sweep bracketed by its own events
-        for (int32_t it = 0; it < iters; ++it) {
+        // eager launches, each sweep bracketed by its own events (sweeps 0
+        // and 1 together, as in the graph)
+        int32_t it0 = 0;
+        if (iters >= 2 && grid[1] > 0) {
+            ProfScope ps(c, "k_jacobi", s, 2);
+            HIP_TRY(launch_jacobi_first2(d_sd, d_bp, nvol, grid[0], grid[1], K, s));
+            it0 = 2;
+        }
+        for (int32_t it = it0; it < iters && grid[it] > 0; ++it) {
             ProfScope ps(c, "k_jacobi", s);
             HIP_TRY(launch_jacobi(d_sd, d_bp, nvol, grid[it], it, K, s));
         }
