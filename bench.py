@@ -1,6 +1,6 @@
 """Benchmark: SurfaceNets extraction + constrained smoothing on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload torso|connectome|spheres]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload torso|connectome|spheres|section]
 
 A step is one pass of the whole hot path over one synthetic label volume that
 is already resident in HBM: extraction (classification, counting, scan,
@@ -16,7 +16,8 @@ each kernel runs on.  In the timed steps only the sweeps (the kernel with the
 largest total time, which the roofline object uses) are bracketed; the
 extraction kernels are timed with events around every launch in a second,
 untimed run of the same number of steps.  Extra objects report the
-connectome-like volume, the batched path against sequential plain calls and
+connectome-like volume, the 2D method on a section-like image, the batched
+path against sequential plain calls and
 the served path against a plain FIFO loop, and the oracle timed on one host
 core.
 """
@@ -548,7 +549,8 @@ def main():
         pmc_summary(args.pmc_summary, args.traffic_json, args.workload)
         return
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (the method here has no multi-GPU path); "
+        print(f"bench.py measures one GPU only: this implementation runs on a single GPU "
+              f"(how the path would shard over z-slabs is a design, not code); "
               f"--gpus {args.gpus} is not supported", file=sys.stderr)
         sys.exit(2)
 
