@@ -169,6 +169,38 @@ def test_batch_of_images_and_volumes(ctx, sn, torch):
         p.free()
 
 
+def test_served_images_equal_plain(ctx, sn, torch):
+    """Images and volumes served together (fused into batches on two streams):
+    every result equals the plain result of the same request."""
+    rng = np.random.default_rng(9)
+    items = []
+    for c in range(12):
+        if c % 3:
+            M, N = (int(x) for x in rng.integers(30, 300, size=2))
+            lab = synth.blocky_tiny(rng, (M, N, 1), 6, np.uint16).reshape(N, M)
+        else:
+            lab = synth.blocky_tiny(rng, (20, 18, 14), 6, np.uint16)
+        items.append((sn.to_device(lab), int(rng.integers(2, 12))))
+    alone = []
+    for t, it in items:
+        m = ctx.extract(t)
+        ctx.smooth(m, iterations=it, relaxation=0.5, constraint=0.8)
+        alone.append(m.to_host())
+        m.free()
+    srv = ctx.serve_start(hbm_budget_bytes=2 << 30, max_inflight=16, n_streams=2, max_batch=6)
+    try:
+        announce(f"2D/3D served: {len(items)} requests")
+        tickets = [srv.submit(t, iterations=it, relaxation=0.5, constraint=0.8) for t, it in items]
+        for tk, ref in zip(tickets, alone):
+            got = srv.wait(tk, timeout_us=60_000_000)
+            g = got.to_host()
+            for f in ("points", "offsets", "polys", "label_pairs", "stencil_off", "stencil_ids"):
+                np.testing.assert_array_equal(getattr(g, f), getattr(ref, f), err_msg=f)
+            got.free()
+    finally:
+        srv.stop()
+
+
 def test_invalid_image_arguments(ctx, sn, torch):
     t = sn.to_device(np.zeros((5, 6), np.uint16))
     m = ctx.extract(t)
