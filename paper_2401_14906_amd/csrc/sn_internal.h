@@ -132,18 +132,22 @@ struct SmoothDesc {
     const uint32_t *pcell;
     float *points;
     UDiv CM, CN;  // cells per row, rows per slice
-    int32_t chunk;  // single mesh, K = 2: blocks an XCD takes in turn (about 1/16 of a slab)
+    int32_t chunk;  // single large mesh: blocks an XCD takes in turn (about 1/16 of a slab)
     double origin[3], spacing[3];
 };
 
 // A smoothing block covers kSweepBlock * K consecutive points: each wave holds K
-// chunks of 64 points.  Meshes of up to kSweepSmallPoints points (their sweep
-// data fits the last-level cache; latency decides) run with K = 1, more and
-// shorter waves, and XCD-contiguous blocks; larger ones (bandwidth decides)
-// with K = 2, in slab-chunked block order for a single mesh and the hardware's
-// round-robin order for a launch over many.
+// chunks of 64 points.  K = 1 everywhere: two chunks per wave (K = 2, kept as a
+// tuning option) need 91 registers against 40 and measure slower on every
+// workload once large meshes take non-temporal accesses and the slab-chunked
+// block order (connectome 1.45 ms per sweep against 1.15 ms, a batch of 64
+// volumes 10.0 ms against 8.3 ms, torso 8.2 us against 7.1 us).  A mesh of more
+// than kSweepSmallPoints points (its sweep data does not stay in the
+// last-level cache) reads its read-once streams and writes its offsets with
+// non-temporal hints, and alone in a launch it takes the slab-chunked order;
+// smaller meshes take XCD-contiguous blocks.
 constexpr int64_t kSweepSmallPoints = int64_t(1) << 22;
-inline int sweep_chunks(int64_t points) { return points <= kSweepSmallPoints ? 1 : 2; }
+inline int sweep_chunks(int64_t /*points*/) { return 1; }
 constexpr int kSweepBlock = 256;  // threads per smoothing workgroup
 inline int64_t sweep_blocks_for(int64_t points, int K)
 {

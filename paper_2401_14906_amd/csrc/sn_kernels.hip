@@ -1366,11 +1366,12 @@ __device__ __forceinline__ uint32_t slab_chunk_block(uint32_t b, uint32_t nb, ui
     return (i / C) * S + x * C + (i % C);
 }
 
-// Logical block of a sweep.  Small meshes (K = 1), whose sweep data fits the
+// Logical block of a sweep.  Small meshes, whose sweep data fits the
 // last-level cache, gain from XCD-contiguous blocks (stencil neighbours in
-// the same L2).  Larger ones stream from HBM: a single mesh takes the
-// slab-chunked order (connectome 1.486 ms per sweep against 1.508 ms in
-// hardware order), a launch over many meshes the hardware's order.
+// the same L2), and so does a launch over many meshes (with one chunk per
+// wave; the hardware's order with two was 10.0 ms against 8.3 ms for a batch
+// of 64 volumes).  A single large mesh streams from HBM and takes the
+// slab-chunked order.
 template <int K>
 __device__ __forceinline__ int64_t sweep_block(const ManySmooth &, uint32_t b, uint32_t nb)
 {
@@ -1379,7 +1380,8 @@ __device__ __forceinline__ int64_t sweep_block(const ManySmooth &, uint32_t b, u
 template <int K>
 __device__ __forceinline__ int64_t sweep_block(const OneSmooth &a, uint32_t b, uint32_t nb)
 {
-    return K == 1 ? xcd_block(b, nb) : (int64_t)slab_chunk_block(b, nb, (uint32_t)a.s.chunk);
+    return a.s.P <= kSweepSmallPoints ? xcd_block(b, nb)
+                                      : (int64_t)slab_chunk_block(b, nb, (uint32_t)a.s.chunk);
 }
 
 // block0: the launch covers logical blocks block0 .. (a launch over many
@@ -1495,7 +1497,7 @@ __device__ __forceinline__ void jacobi_body(const Src &a, int32_t it)
                 glb(reinterpret_cast<v4i *>(s.nbr))[p] = nb[c];
                 ox[c] = s_first[3 * f[c]], oy[c] = s_first[3 * f[c] + 1], oz[c] = s_first[3 * f[c] + 2];
             } else {
-                if constexpr (K > 1) {  // large meshes: read-once streams
+                if (P > kSweepSmallPoints) {  // large meshes: read-once streams
                     f[c] = __builtin_nontemporal_load(glb(s.faces) + p);
                     nb[c] = __builtin_nontemporal_load(nbr + p);
                 } else {
@@ -1586,7 +1588,10 @@ __device__ __forceinline__ void jacobi_body(const Src &a, int32_t it)
             y = y + s.lam * (sy * inv);
             z = z + s.lam * (sz * inv);
         }
-        store_offset<(K > 1)>(s, dout, p, x, y, z, last, cell[c]);
+        if (P > kSweepSmallPoints)  // large meshes: streaming stores
+            store_offset<true>(s, dout, p, x, y, z, last, cell[c]);
+        else
+            store_offset<false>(s, dout, p, x, y, z, last, cell[c]);
     }
 }
 
