@@ -142,11 +142,13 @@ struct SmoothDesc {
 // workload once large meshes take non-temporal accesses and the slab-chunked
 // block order (connectome 1.45 ms per sweep against 1.15 ms, a batch of 64
 // volumes 10.0 ms against 8.3 ms, torso 8.2 us against 7.1 us).  A mesh of more
-// than kSweepSmallPoints points (its sweep data does not stay in the
+// than kSweepSmallPoints points (sweep data of about 2.5 times the 256 MB
 // last-level cache) reads its read-once streams and writes its offsets with
 // non-temporal hints, and alone in a launch it takes the slab-chunked order;
-// smaller meshes take XCD-contiguous blocks.
-constexpr int64_t kSweepSmallPoints = int64_t(1) << 22;
+// smaller meshes take XCD-contiguous blocks and ordinary accesses.  Measured:
+// 3.5 M points 27 us per sweep against 34 us the other way, 7.1 M points 54 us
+// against 61 us, and 140 M points the other way round, 1.14 ms against 1.23 ms.
+constexpr int64_t kSweepSmallPoints = int64_t(1) << 24;
 inline int sweep_chunks(int64_t /*points*/) { return 1; }
 constexpr int kSweepBlock = 256;  // threads per smoothing workgroup
 inline int64_t sweep_blocks_for(int64_t points, int K)
