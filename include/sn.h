@@ -279,9 +279,11 @@ sn_status sn_set_batches_per_wave(sn_ctx *ctx, int32_t batches_per_wave);
 /* Per-kernel timing: with on = 1 every library kernel launch is bracketed by
  * HIP events on the stream it runs on, and the sweeps of one smoothing call
  * (a mesh's run of launches, or a batch's sweep graph) are bracketed as a
- * whole (counted as `iterations` launches of k_jacobi); with on = 2 every
- * sweep is launched with its own events; with on = 3 only the sweeps are
- * timed, as with on = 1 (the least added work between kernels).  on = 0 turns
+ * whole (counted as `iterations` launches of k_jacobi: the count is of
+ * sweeps, and a mesh's first two sweeps run in one launch); with on = 2 every
+ * sweep launch has its own events (the fused first two counting as two); with
+ * on = 3 only the sweeps are timed, as with on = 1 (the least added work
+ * between kernels).  on = 0 turns
  * timing off.  sn_profile_read synchronises, folds the events into
  * per-kernel totals and fills up to `cap` records. */
 typedef struct sn_kernel_stat {
