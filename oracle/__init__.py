@@ -181,10 +181,14 @@ def extract2d(labels: np.ndarray, selected=(), background: int = 0) -> OracleMes
 
 
 def world(idx_pos: np.ndarray, origin, spacing) -> np.ndarray:
+    """World points origin + spacing * p of index-space points p [P, 3]."""
     lib = _load()
     idx_pos = np.ascontiguousarray(idx_pos, dtype=np.float64)
     o = np.ascontiguousarray(origin, dtype=np.float64)
     h = np.ascontiguousarray(spacing, dtype=np.float64)
+    # the C loop reads three coordinates per point and three of each vector
+    if idx_pos.ndim != 2 or idx_pos.shape[1] != 3 or o.shape != (3,) or h.shape != (3,):
+        raise ValueError("world() takes points [P, 3] and 3-vectors origin and spacing")
     out = np.empty_like(idx_pos)
     lib.orc_world(idx_pos.shape[0], _p(idx_pos), _p(o), _p(h), _p(out))
     return out

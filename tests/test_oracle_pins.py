@@ -361,6 +361,20 @@ def test_spacing_commutes_with_box(orc):
     np.testing.assert_allclose(w, x, rtol=0, atol=1e-11)
 
 
+def test_world_rejects_other_shapes(orc):
+    """The world map reads three coordinates per point: 2D arrays of another
+    width, or origin/spacing of another length, are refused before the call."""
+    p = np.zeros((4, 3))
+    with pytest.raises(ValueError):
+        orc.world(np.zeros((4, 2)), (0.0, 0.0, 0.0), (1.0, 1.0, 1.0))
+    with pytest.raises(ValueError):
+        orc.world(p, (0.0, 0.0), (1.0, 1.0, 1.0))
+    with pytest.raises(ValueError):
+        orc.world(p, (0.0, 0.0, 0.0), (1.0, 1.0))
+    np.testing.assert_array_equal(orc.world(p + 1.0, (1.0, 2.0, 3.0), (2.0, 2.0, 2.0)),
+                                  np.tile([3.0, 4.0, 5.0], (4, 1)))
+
+
 # --------------------------------------------------------------------------
 # P14/P15: classification
 # --------------------------------------------------------------------------
