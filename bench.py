@@ -1,6 +1,7 @@
 """Benchmark: SurfaceNets extraction + constrained smoothing on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload torso|connectome|spheres|section]
+    python bench.py --only batched|served    (that path alone, e.g. under a profiler)
 
 A step is one pass of the whole hot path over one synthetic label volume that
 is already resident in HBM: extraction (classification, counting, scan,
@@ -542,6 +543,9 @@ def main():
                     help="HBM traffic per launch from rocprofv3 counters, if measured")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain streaming kernel of known size (counter calibration)")
+    ap.add_argument("--only", choices=["batched", "served"],
+                    help="run one of the extra measurements alone and print its figures as the "
+                         "JSON line (for a profile of that path); no headline workload")
     ap.add_argument("--pmc-summary", metavar="DIR",
                     help="no GPU work: reduce rocprofv3 --pmc output in DIR into --traffic-json")
     args = ap.parse_args()
@@ -564,6 +568,12 @@ def main():
 
         _build.build()
     ctx = sn.Context(0)
+    if args.only:
+        log(f"[bench] device {torch.cuda.get_device_name(0)}; {args.only} path alone")
+        fn = {"batched": bench_batched, "served": bench_served}[args.only]
+        print(json.dumps({"only": args.only, args.only: fn(ctx, sn, torch)}), flush=True)
+        ctx.close()
+        return
     log(f"[bench] device {torch.cuda.get_device_name(0)}; workload {args.workload}")
     gen = {"torso": synth.torso_like, "connectome": synth.connectome_like,
            "section": synth.section_like,

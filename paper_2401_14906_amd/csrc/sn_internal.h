@@ -13,8 +13,9 @@ namespace sn {
 // C(v) = v if v is selected and is not the background value, else background.
 enum ClassMode : int32_t {
     CLS_IDENT = 0,   // every value selected: C is the identity
-    CLS_BITMAP = 1,  // u8/u16: bit v of `table` set <=> v selected (background bit clear)
-    CLS_SORTED = 2   // u32: `table` holds n sorted, unique selected values (no background)
+    CLS_BITMAP = 1,  // bit v of `table` (2048 words, 8 for u8) set <=> v selected (background
+                     // bit clear): u8, u16, and u32 whose selected values are all below 65536
+    CLS_SORTED = 2   // other u32: `table` holds n sorted, unique selected values (no background)
 };
 
 struct ClassSpec {

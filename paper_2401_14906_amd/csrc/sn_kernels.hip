@@ -141,7 +141,12 @@ __device__ __forceinline__ uint32_t classify(uint32_t v, const ClassSpec &cs)
     if constexpr (MODE == CLS_IDENT) {
         return v;
     } else if constexpr (MODE == CLS_BITMAP) {
-        return ((glb(cs.table)[v >> 5] >> (v & 31u)) & 1u) ? v : cs.bg;
+        // the table covers values below 65536 (the whole range of u8 and
+        // u16, for which this test folds away); larger u32 values are never
+        // selected in this mode
+        const bool in = v < 65536u;
+        const uint32_t vi = in ? v : 0u;
+        return (in && ((glb(cs.table)[vi >> 5] >> (vi & 31u)) & 1u)) ? v : cs.bg;
     } else {
         const SN_GLOBAL uint32_t *tab = glb(cs.table);
         int lo = 0, hi = cs.n;
@@ -1799,6 +1804,7 @@ hipError_t launch_tri_rule(int32_t rule, int32_t dtype, const int32_t *quads, co
     case 2 * 4 + CLS_IDENT: hipLaunchKernelGGL((KERNEL<uint16_t, CLS_IDENT>), __VA_ARGS__); break; \
     case 2 * 4 + CLS_BITMAP: hipLaunchKernelGGL((KERNEL<uint16_t, CLS_BITMAP>), __VA_ARGS__); break; \
     case 4 * 4 + CLS_IDENT: hipLaunchKernelGGL((KERNEL<uint32_t, CLS_IDENT>), __VA_ARGS__); break; \
+    case 4 * 4 + CLS_BITMAP: hipLaunchKernelGGL((KERNEL<uint32_t, CLS_BITMAP>), __VA_ARGS__); break; \
     case 4 * 4 + CLS_SORTED: hipLaunchKernelGGL((KERNEL<uint32_t, CLS_SORTED>), __VA_ARGS__); break; \
     default: return hipErrorInvalidValue;                                                   \
     }

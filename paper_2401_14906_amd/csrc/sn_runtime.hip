@@ -499,7 +499,10 @@ static void class_table(const sn_volume &v, int32_t *mode, std::vector<uint32_t>
         *mode = CLS_IDENT;
         return;
     }
-    if (v.dtype <= 2) {
+    // a bitmap over [0, 65536) serves u8 and u16, and u32 selections of small
+    // values: one table load per sample instead of a binary search
+    const uint32_t top = *std::max_element(v.selected, v.selected + v.n_selected);
+    if (v.dtype <= 2 || top < 65536u) {
         *mode = CLS_BITMAP;
         tab->assign(v.dtype == 1 ? 8 : 2048, 0u);
         for (int32_t s = 0; s < v.n_selected; ++s) {

@@ -119,6 +119,19 @@ def test_random_images(ctx, sn):
         run_image(ctx, sn, img, sel, bg, iters, lam, d, shape, spacing, origin)
 
 
+def test_u32_selection_forms_2d(ctx, sn):
+    """u32 images with a selection of small labels (bitmap classification, next
+    to values of 65536 and more that share their low bits) and of large
+    labels (sorted-list classification)."""
+    rng = np.random.default_rng(31)
+    pool = np.array([0, 1, 2, 65536 + 1, 65536 + 2, 2**32 - 1, 70_000, 70_001], dtype=np.uint64)
+    for M, N in ((37, 29), (64, 21)):
+        img = pool[rng.integers(0, len(pool), size=(N, M))].astype(np.uint32)
+        for sel in ((1,), (2, 65535), (70_000,), (65537, 2**32 - 1)):
+            announce(f"2D u32 selection {sel} {M}x{N}")
+            run_image(ctx, sn, img, selected=sel, iters=4)
+
+
 def test_degenerate_images(ctx, sn):
     for shape in [(1, 1), (1, 17), (17, 1), (2, 2), (2, 130)]:
         announce(f"2D degenerate {shape}")

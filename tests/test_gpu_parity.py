@@ -147,13 +147,32 @@ def test_dtype_edge_values(ctx, sn):
         run_case(ctx, sn, vol, selected=(1, top), background=0, iters=3)
 
 
-def test_large_selection_u32(ctx, sn):
-    """A sorted-list classification with many entries (u32)."""
+@pytest.mark.parametrize("offset", [0, 70_000])
+def test_large_selection_u32(ctx, sn, offset):
+    """A u32 selection with many entries: labels below 65536 take the bitmap,
+    larger ones the sorted list."""
     rng = np.random.default_rng(6)
-    vol = rng.integers(0, 5000, size=(20, 30, 40)).astype(np.uint32)
-    sel = tuple(int(x) for x in rng.choice(5000, size=1500, replace=False) if x != 0)
-    announce("u32 selection of 1500 labels")
+    vol = (rng.integers(0, 5000, size=(20, 30, 40)) + offset).astype(np.uint32)
+    sel = tuple(int(x) + offset for x in rng.choice(5000, size=1500, replace=False) if x != 0)
+    announce(f"u32 selection of 1500 labels from {offset}")
     run_case(ctx, sn, vol, selected=sel, iters=2)
+
+
+def test_u32_small_selection_ignores_large_values(ctx, sn):
+    """A u32 selection of small labels (bitmap classification) next to values
+    of 65536 and more, some equal to a selected label modulo 2^16 or 2^5:
+    those are never selected."""
+    rng = np.random.default_rng(8)
+    pool = np.array([0, 1, 2, 3, 65536, 65537, 65538, 65536 + 3, 2**31 + 1, 2**32 - 1,
+                     2**32 - 65536 + 2, 33, 35], dtype=np.uint64)
+    for shape in ((14, 19, 23), (9, 13, 24)):  # ragged rows, then rows of a multiple of 4
+        vol = pool[rng.integers(0, len(pool), size=shape)].astype(np.uint32)
+        for sel, bg in (((1, 3), 0), ((2,), 7), ((1, 2, 3, 33), 0), ((65535,), 0)):
+            announce(f"u32 small selection {sel} bg={bg} shape={shape}")
+            run_case(ctx, sn, vol, selected=sel, background=bg, iters=3)
+    vol2 = np.where(vol == 65536, 65535, vol).astype(np.uint32)
+    announce("u32 selection of 65535 next to 65536")
+    run_case(ctx, sn, vol2, selected=(65535,), iters=2)
 
 
 def test_degenerate_volumes(ctx, sn):
