@@ -67,7 +67,9 @@ def against_oracle(g, labels, selected, background, iters, lam, d):
 
 def mixed_volumes(seed, count):
     """Uneven sizes (ragged rows, 1..6 words per row), all three label types,
-    selections and non-zero backgrounds, per-volume smoothing parameters."""
+    selections and non-zero backgrounds, per-volume smoothing parameters.
+    Volumes 5, 29, ... (u32) have their labels above 65536 (a selection takes the
+    sorted-list classification, the other u32 selections the bitmap)."""
     rng = np.random.default_rng(seed)
     out = []
     for k in range(count):
@@ -82,6 +84,9 @@ def mixed_volumes(seed, count):
         sel = ()
         if k % 4 == 1:
             sel = tuple(sorted({int(x) for x in rng.integers(0, nv, size=3)} - {bg}))
+        if k % 24 == 5:  # u32
+            lab = (lab.astype(np.uint64) + 70_000).astype(np.uint32)
+            sel = tuple(x + 70_000 for x in sel)
         params = (int(rng.integers(0, 30)), float(rng.choice([0.25, 0.5, 1.0])),
                   float(rng.choice([0.5, 0.8, 1.0])))
         sp = tuple(float(x) for x in rng.uniform(0.5, 2.5, size=3))
