@@ -193,7 +193,26 @@ def cpu_baseline(vol, min_seconds=10.0):
     return {"value": round(V * reps / t_all / 1e9, 5), "unit": "Gvoxels/s", "cores": 1,
             "kind": "oracle",
             "sample": f"whole {vol.name} volume (extract + {vol.iterations} sweeps) x{reps}, "
-                      f"{t_all:.1f} s on 1 core"}
+                      f"{t_all:.1f} s on 1 core",
+            "host": host_cpu()}
+
+
+def host_cpu():
+    """The host's CPU model and CPU counts (the oracle's timing runs on one)."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = None
+    return {"cpu": model, "logical_cpus": os.cpu_count(), "usable_cpus": usable}
 
 
 def mesh_alg_bytes(V, b, P, Q, S, n):
