@@ -102,6 +102,15 @@ MUTANTS = [
     ("2D back label on the wrong axis",
      "pr[2 * Q + 1] = C(&v, i + (a == 0), j + (a == 1), 0);",
      "pr[2 * Q + 1] = C(&v, i + (a == 1), j + (a == 0), 0);"),
+    ("2D segment ends swapped",
+     "sg[2 * Q + 0] = (int32_t)pid[ai + CM * aj];\n                sg[2 * Q + 1] = (int32_t)pid[bi + CM * bj];",
+     "sg[2 * Q + 0] = (int32_t)pid[bi + CM * bj];\n                sg[2 * Q + 1] = (int32_t)pid[ai + CM * aj];"),
+    ("2D stencil faces in reverse order",
+     "        for (int f = 0; f < 4; ++f) {\n            if (!cell2_exists(M, N, ni[f], nj[f]) || !shared[f])",
+     "        for (int f = 3; f >= 0; --f) {\n            if (!cell2_exists(M, N, ni[f], nj[f]) || !shared[f])"),
+    ("2D -x face checks the +x edge",
+     "const int shared[4] = {cut(&v, i, j, 0, 1), cut(&v, i + 1, j, 0, 1),",
+     "const int shared[4] = {cut(&v, i + 1, j, 0, 1), cut(&v, i + 1, j, 0, 1),"),
     # world coordinates and triangles (Sec. 2.5)
     ("world origin scaled",
      "out[3 * p + ax] = origin[ax] + spacing[ax] * idx_pos[3 * p + ax];",
