@@ -64,6 +64,12 @@ MUTANTS = [
     ("x-quad winding reversed",
      "{{i, j - 1, k - 1}, {i, j - 1, k}, {i, j, k}, {i, j, k - 1}}",
      "{{i, j - 1, k - 1}, {i, j, k - 1}, {i, j, k}, {i, j - 1, k}}"),
+    ("y-quad winding reversed",
+     "{{i - 1, j, k - 1}, {i, j, k - 1}, {i, j, k}, {i - 1, j, k}}",
+     "{{i - 1, j, k - 1}, {i - 1, j, k}, {i, j, k}, {i, j, k - 1}}"),
+    ("x-quad starting at another corner",
+     "{{i, j - 1, k - 1}, {i, j - 1, k}, {i, j, k}, {i, j, k - 1}}",
+     "{{i, j - 1, k}, {i, j, k}, {i, j, k - 1}, {i, j - 1, k - 1}}"),
     ("z-quad winding reversed",
      "{{i - 1, j - 1, k}, {i - 1, j, k}, {i, j, k}, {i, j - 1, k}}",
      "{{i - 1, j - 1, k}, {i, j - 1, k}, {i, j, k}, {i - 1, j, k}}"),
