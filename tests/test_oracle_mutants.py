@@ -61,6 +61,12 @@ MUTANTS = [
     ("stencil faces in reverse order",
      "for (int f = 0; f < 6; ++f) {\n            int64_t d", "for (int f = 5; f >= 0; --f) {\n            int64_t d"),
     # quads and label pairs (Sec. 2.2-2.3)
+    ("stencil ignores the cut edges of a face",
+     "if (!cell_exists(&v, ni, nj, nk) || !face_has_cut(&v, i, j, k, f))",
+     "if (!cell_exists(&v, ni, nj, nk))"),
+    ("2D stencil ignores the shared edge",
+     "if (!cell2_exists(M, N, ni[f], nj[f]) || !shared[f])",
+     "if (!cell2_exists(M, N, ni[f], nj[f]))"),
     ("x-quad winding reversed",
      "{{i, j - 1, k - 1}, {i, j - 1, k}, {i, j, k}, {i, j, k - 1}}",
      "{{i, j - 1, k - 1}, {i, j, k - 1}, {i, j, k}, {i, j - 1, k}}"),
