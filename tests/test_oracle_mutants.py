@@ -99,6 +99,18 @@ MUTANTS = [
      "memcpy(b + 3 * p, q, sizeof q);", "memcpy(b + 3 * p, q, sizeof q);\n            memcpy(a + 3 * p, q, sizeof q);"),
     ("box clamp to the wrong side",
      "if (q[ax] < c[ax] - d) q[ax] = c[ax] - d;", "if (q[ax] < c[ax] - d) q[ax] = c[ax] + d;"),
+    ("box around the moving point, not the centre",
+     "if (q[ax] < c[ax] - d) q[ax] = c[ax] - d;",
+     "if (q[ax] < a[3 * p + ax] - d) q[ax] = a[3 * p + ax] - d;"),
+    ("sphere test on the squared length",
+     "if (len > d) {",
+     "if (len * len > d) {"),
+    ("one sweep too few",
+     "for (int32_t it = 0; it < iterations; ++it) {",
+     "for (int32_t it = 1; it < iterations; ++it) {"),
+    ("relaxation times the sum, not the mean",
+     "q[ax] = a[3 * p + ax] + lambda * (sum / (double)n);",
+     "q[ax] = a[3 * p + ax] + lambda * sum;"),
     ("sphere radius doubled",
      "if (len > d) {", "if (len > 2 * d) {"),
     ("sphere projection transposed",
