@@ -38,6 +38,10 @@ MUTANTS = [
     # classification (Sec. 2.1)
     ("selection inverted",
      "cmp_u32) ? v : bg;", "cmp_u32) ? bg : v;"),
+    ("selection ignored",
+     "cmp_u32) ? v : bg;", "cmp_u32) ? v : v;"),
+    ("unselected values become 0, not the background",
+     "cmp_u32) ? v : bg;", "cmp_u32) ? v : 0u;"),
     ("empty selection selects nothing",
      "    if (n_sel == 0)\n        return v;", "    if (n_sel == 0)\n        return bg;"),
     # cut edges and points (Sec. 2.2)
