@@ -145,11 +145,25 @@ typedef struct sn_mesh_view {
 /* ---- context -------------------------------------------------------------- */
 
 /* Bind a context to HIP device `device`.  Reads SN_AUTOTUNE_CACHE (a JSON file
- * of schedule choices) from the environment, and two test knobs:
- * SN_TEST_MEM_LIMIT (a byte cap on the library's device pool, to force
- * SN_ENOMEM) and SN_TEST_COUNT_WIDE_WORDS (the number of cell words from which
- * an extraction counts four words per thread; results do not depend on it). */
+ * of schedule choices) from the environment, and four test knobs, none of
+ * which changes results:
+ *   SN_TEST_MEM_LIMIT          a byte cap on the library's device pool, to
+ *                              force SN_ENOMEM;
+ *   SN_TEST_COUNT_WIDE_WORDS   the number of cell words from which an
+ *                              extraction counts four words per thread;
+ *   SN_TEST_SWEEP_SMALL_POINTS the number of points above which a mesh takes
+ *                              the large-mesh sweep form (non-temporal
+ *                              accesses, slab-chunked block order; 2^24 by
+ *                              default);
+ *   SN_TEST_SWEEP_CHUNK        the blocks an XCD takes in turn in that block
+ *                              order (default about a sixteenth of a slab). */
 sn_status sn_ctx_create(int device, sn_ctx **out);
+/* Device memory of the context's pool: the bytes handed out now (meshes and
+ * the scratch of calls in progress) and the most ever handed out at once, each
+ * block counted at the size asked for, rounded up to the pool's size classes
+ * (512 B steps up to 1 MiB, 2 MiB steps above).  Cached free blocks are not
+ * counted.  Either pointer may be NULL. */
+sn_status sn_ctx_memory(sn_ctx *ctx, int64_t *in_use_bytes, int64_t *peak_bytes);
 /* Release the caller's handle.  Meshes and servers made by the context hold
  * it alive: its device memory and streams go when the last of them is freed
  * (sn_mesh_free, sn_serve_stop), so meshes may be freed in any order. */
@@ -242,18 +256,38 @@ typedef struct sn_serve_stats {
     int64_t voxels_done, point_iters_done;
     double p50_us, p99_us, mean_us; /* completion - submission, finished requests     */
     double busy_s;                  /* wall time with at least one request in flight  */
-    int64_t peak_reserved_bytes;
+    int64_t peak_reserved_bytes;    /* most device bytes reserved at once (see below) */
+    int64_t n_split_batches;        /* fused batches that hit SN_ENOMEM and ran their
+                                       requests one at a time                          */
+    int64_t n_requeued;             /* requests queued again by the second admission
+                                       phase (see sn_serve_start)                      */
 } sn_serve_stats;
 
-/* Start a request loop on ctx's device.  The server admits a pending request
- * when its device-footprint estimate fits the budget next to the work in
- * flight, fuses the admitted requests of a round into one batch (continuous
- * batching: requests arriving while batches run join the next free stream),
- * and keeps result meshes device-resident until claimed. */
+/* Start a request loop on ctx's device.  The server fuses the admitted
+ * requests of a round into one batch (continuous batching: requests arriving
+ * while batches run join the next free stream) and keeps result meshes
+ * device-resident until claimed.  Admission reserves device bytes in two
+ * phases, since a mesh's size is known only after its volume is counted
+ * (Sec. 2.3):
+ *   1. a pending request is admitted when its exact extraction scratch plus
+ *      an estimate of its mesh (bytes per voxel of finished requests) fits
+ *      the budget next to the reservations in flight;
+ *   2. once the batch is counted, the exact mesh bytes (outputs, word
+ *      metadata and smoothing buffers) replace the estimate; if they do not
+ *      fit, the batch waits for reservations to be released, or, when every
+ *      other batch in flight is waiting too, goes back to the head of the
+ *      queue with its exact sizes (n_requeued).
+ * Bytes are counted as sn_ctx_memory counts them; a request that alone
+ * exceeds the budget runs when nothing else is in flight.  A fused batch that
+ * still fails with SN_ENOMEM runs its requests one at a time
+ * (n_split_batches). */
 sn_status sn_serve_start(sn_ctx *ctx, const sn_serve_config *cfg, sn_server **out);
-/* Queue a request.  `vol->labels` must stay valid until the ticket is done. */
+/* Queue a request.  The labels are read on the server's own streams after the
+ * work enqueued on `stream` (a hipStream_t; NULL = the legacy default stream)
+ * up to this call has completed, so they may still be being written there;
+ * they must stay valid until the ticket is done. */
 sn_status sn_serve_submit(sn_server *srv, const sn_volume *vol, const sn_smooth_params *p,
-                          uint64_t *ticket);
+                          void *stream, uint64_t *ticket);
 /* SN_OK and the mesh (ownership passes to the caller) once done; SN_EAGAIN
  * if not yet; the request's own error status if it failed. */
 sn_status sn_serve_poll(sn_server *srv, uint64_t ticket, sn_mesh **out);

@@ -75,7 +75,8 @@ class sn_serve_stats(ctypes.Structure):
                 ("voxels_done", ctypes.c_int64), ("point_iters_done", ctypes.c_int64),
                 ("p50_us", ctypes.c_double), ("p99_us", ctypes.c_double),
                 ("mean_us", ctypes.c_double), ("busy_s", ctypes.c_double),
-                ("peak_reserved_bytes", ctypes.c_int64)]
+                ("peak_reserved_bytes", ctypes.c_int64), ("n_split_batches", ctypes.c_int64),
+                ("n_requeued", ctypes.c_int64)]
 
 
 class sn_kernel_stat(ctypes.Structure):
@@ -89,6 +90,7 @@ _S = ctypes.c_int
 _API = [
     ("sn_ctx_create", _S, [ctypes.c_int, ctypes.POINTER(_P)]),
     ("sn_ctx_destroy", None, [_P]),
+    ("sn_ctx_memory", _S, [_P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]),
     ("sn_strerror", ctypes.c_char_p, [_S]),
     ("sn_last_error", ctypes.c_char_p, []),
     ("sn_version", ctypes.c_char_p, []),
@@ -101,7 +103,7 @@ _API = [
     ("sn_batch_submit", _S, [_P, ctypes.POINTER(sn_volume), ctypes.POINTER(sn_smooth_params),
                              ctypes.c_int32, _P, ctypes.POINTER(_P)]),
     ("sn_serve_start", _S, [_P, ctypes.POINTER(sn_serve_config), ctypes.POINTER(_P)]),
-    ("sn_serve_submit", _S, [_P, ctypes.POINTER(sn_volume), ctypes.POINTER(sn_smooth_params),
+    ("sn_serve_submit", _S, [_P, ctypes.POINTER(sn_volume), ctypes.POINTER(sn_smooth_params), _P,
                              ctypes.POINTER(ctypes.c_uint64)]),
     ("sn_serve_poll", _S, [_P, ctypes.c_uint64, ctypes.POINTER(_P)]),
     ("sn_serve_wait", _S, [_P, ctypes.c_uint64, ctypes.c_int64, ctypes.POINTER(_P)]),
@@ -344,6 +346,12 @@ class Context:
         _check(_lib.sn_autotune(self._h, ctypes.byref(v), _stream_handle(stream), ctypes.byref(ch)))
         return int(ch.value)
 
+    def memory(self) -> tuple:
+        """(bytes handed out by the context's device pool now, most at once)."""
+        a, b = ctypes.c_int64(), ctypes.c_int64()
+        _check(_lib.sn_ctx_memory(self._h, ctypes.byref(a), ctypes.byref(b)))
+        return int(a.value), int(b.value)
+
     def set_batches_per_wave(self, bpw: int):
         _check(_lib.sn_set_batches_per_wave(self._h, int(bpw)))
 
@@ -380,11 +388,14 @@ class Server:
         self._keep = {}
 
     def submit(self, labels, iterations=20, relaxation=0.5, constraint=1.0, shape="box",
-               **vol_kw) -> int:
+               stream=None, **vol_kw) -> int:
+        """Queue a request; the labels are read after the work enqueued so far on
+        `stream` (default: torch's current stream)."""
         v, keep = make_volume(labels, **vol_kw)
         p = smooth_params(iterations, relaxation, constraint, shape)
         t = ctypes.c_uint64()
-        _check(_lib.sn_serve_submit(self._h, ctypes.byref(v), ctypes.byref(p), ctypes.byref(t)))
+        _check(_lib.sn_serve_submit(self._h, ctypes.byref(v), ctypes.byref(p),
+                                    _stream_handle(stream), ctypes.byref(t)))
         self._keep[int(t.value)] = keep
         return int(t.value)
 

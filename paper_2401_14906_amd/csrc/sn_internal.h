@@ -134,6 +134,11 @@ struct SmoothDesc {
     float *points;
     UDiv CM, CN;  // cells per row, rows per slice
     int32_t chunk;  // single large mesh: blocks an XCD takes in turn (about 1/16 of a slab)
+    // 1: the mesh's sweep data is far beyond the last-level cache (more than
+    // kSweepSmallPoints points, or the context's test threshold): read-once
+    // streams and offset stores take non-temporal hints, and a single mesh
+    // takes the slab-chunked block order
+    int32_t big;
     double origin[3], spacing[3];
 };
 

@@ -1385,8 +1385,7 @@ __device__ __forceinline__ int64_t sweep_block(const ManySmooth &, uint32_t b, u
 template <int K>
 __device__ __forceinline__ int64_t sweep_block(const OneSmooth &a, uint32_t b, uint32_t nb)
 {
-    return a.s.P <= kSweepSmallPoints ? xcd_block(b, nb)
-                                      : (int64_t)slab_chunk_block(b, nb, (uint32_t)a.s.chunk);
+    return !a.s.big ? xcd_block(b, nb) : (int64_t)slab_chunk_block(b, nb, (uint32_t)a.s.chunk);
 }
 
 // block0: the launch covers logical blocks block0 .. (a launch over many
@@ -1502,7 +1501,7 @@ __device__ __forceinline__ void jacobi_body(const Src &a, int32_t it)
                 glb(reinterpret_cast<v4i *>(s.nbr))[p] = nb[c];
                 ox[c] = s_first[3 * f[c]], oy[c] = s_first[3 * f[c] + 1], oz[c] = s_first[3 * f[c] + 2];
             } else {
-                if (P > kSweepSmallPoints) {  // large meshes: read-once streams
+                if (s.big) {  // large meshes: read-once streams
                     f[c] = __builtin_nontemporal_load(glb(s.faces) + p);
                     nb[c] = __builtin_nontemporal_load(nbr + p);
                 } else {
@@ -1593,7 +1592,7 @@ __device__ __forceinline__ void jacobi_body(const Src &a, int32_t it)
             y = y + s.lam * (sy * inv);
             z = z + s.lam * (sz * inv);
         }
-        if (P > kSweepSmallPoints)  // large meshes: streaming stores
+        if (s.big)  // large meshes: streaming stores
             store_offset<true>(s, dout, p, x, y, z, last, cell[c]);
         else
             store_offset<false>(s, dout, p, x, y, z, last, cell[c]);

@@ -5,6 +5,7 @@
 
 #include <atomic>
 #include <deque>
+#include <functional>
 #include <map>
 #include <mutex>
 #include <string>
@@ -17,6 +18,9 @@
 namespace sn {
 
 sn_status fail(sn_status s, const std::string &msg);
+
+// Size class of a pool block: 512-byte steps up to 1 MiB, 2 MiB steps above.
+size_t round_size(size_t n);
 
 #define HIP_TRY(expr)                                                                   \
     do {                                                                                \
@@ -44,7 +48,11 @@ class Pool {
     static inline const hipStream_t kNoWait = reinterpret_cast<hipStream_t>(~uintptr_t(0));
     Pool(int device, bool pinned);
     ~Pool();
-    void *alloc(size_t bytes);  // nullptr on failure (or over the test limit)
+    // nullptr on failure (or over the test limit).  A cached block handed out
+    // may be larger than asked for; in_use() and peak() count what was asked
+    // for, rounded to the pool's size classes (round_size), so they do not
+    // depend on the state of the cache.
+    void *alloc(size_t bytes);
     // Return a block; with a stream, it is reused only after the stream's
     // current work has completed.
     void release(void *p, hipStream_t after);
@@ -62,7 +70,8 @@ class Pool {
     bool pinned_;
     mutable std::mutex mu_;
     std::multimap<size_t, void *> free_;
-    std::map<void *, size_t> sizes_;
+    std::map<void *, size_t> sizes_;    // block sizes
+    std::map<void *, size_t> charged_;  // live blocks: bytes counted in in_use_
     std::deque<Pending> pending_;  // in release order
     EventCache events_{hipEventDisableTiming};
     int64_t in_use_ = 0, peak_ = 0, limit_ = -1;
@@ -83,6 +92,7 @@ struct sn_ctx {
     // and their pool blocks are released behind an event recorded on it.
     hipStream_t retire_stream = nullptr;
     sn::EventCache timing_events{hipEventDefault};
+    sn::EventCache sync_events{hipEventDisableTiming};  // ordering only (served requests)
     // profiling
     bool profiling = false;
     bool profile_eager = false;        // every sweep bracketed by its own events
@@ -102,6 +112,11 @@ struct sn_ctx {
     std::string tune_path;
     int32_t forced_bpw = 0;
     int64_t count_wide_words = sn::kCountWideWords;  // SN_TEST_COUNT_WIDE_WORDS overrides
+    // meshes of more than this many points take the large-mesh sweep form
+    // (SN_TEST_SWEEP_SMALL_POINTS overrides); sweep_chunk > 0 replaces the
+    // slab-chunk size of that form's block order (SN_TEST_SWEEP_CHUNK)
+    int64_t sweep_small_points = sn::kSweepSmallPoints;
+    int32_t sweep_chunk = 0;
     int32_t batches_per_wave(const std::string &cls) const;
     void load_tune_cache();
     void save_tune_cache() const;
@@ -138,8 +153,19 @@ sn_status validate_volume(const sn_volume *v);
 sn_status validate_smooth(const sn_smooth_params *p);
 Geom make_geom(const sn_volume &v);
 std::string size_class(const sn_volume &v);
+// Called by extract_many once the totals of every volume are known and before
+// any output is allocated: totals[3v .. 3v+2] = (P, Q, S) of vols[v].  A status
+// other than SN_OK ends the extraction with that status (no mesh).
+using AdmitFn = std::function<sn_status(const int64_t *totals)>;
 sn_status extract_many(sn_ctx *c, const sn_volume *vols, int32_t n, hipStream_t s,
-                       int32_t bpw_override, sn_mesh **out);
+                       int32_t bpw_override, sn_mesh **out, const AdmitFn *admit = nullptr);
+// Device bytes, as the pool counts them (round_size per block), that an
+// extraction of v holds for the call only (cut-edge planes, quad and stencil
+// word bases, scan status, its share of the descriptor uploads), and that its
+// mesh holds (word metadata, outputs, and the smoothing buffers when smoothed)
+// for totals P, Q, S.
+int64_t extract_scratch_bytes(const sn_volume &v);
+int64_t mesh_bytes(const sn_volume &v, int64_t P, int64_t Q, int64_t S, bool smoothed);
 sn_status smooth_many(sn_ctx *c, sn_mesh **ms, const sn_smooth_params *pv, int32_t n,
                       hipStream_t s);
 // the plain path of one mesh (sweeps launched one by one, descriptor by value)

@@ -93,7 +93,7 @@ void EventCache::put(hipEvent_t e)
     free_.push_back(e);
 }
 
-static size_t round_size(size_t n)
+size_t sn::round_size(size_t n)
 {
     if (n == 0) n = 1;
     if (n <= (1u << 20)) return (n + 511) & ~size_t(511);
@@ -152,7 +152,9 @@ void *Pool::alloc(size_t bytes)
     if (it != free_.end() && it->first <= 2 * n + (size_t(4) << 20)) {
         void *p = it->second;
         free_.erase(it);
-        in_use_ += (int64_t)sizes_[p];
+        charged_[p] = n;
+        in_use_ += (int64_t)n;
+        peak_ = std::max(peak_, in_use_);
         return p;
     }
     void *p = nullptr;
@@ -163,7 +165,7 @@ void *Pool::alloc(size_t bytes)
         (void)hipGetLastError();
         // drop every cached block (waiting for deferred ones) and retry once
         reclaim_locked(true);
-        for (auto &kv : free_) raw_free(kv.second), sizes_.erase(kv.second);
+        for (auto &kv : free_) raw_free(kv.second), sizes_.erase(kv.second), charged_.erase(kv.second);
         free_.clear();
         e = pinned_ ? hipHostMalloc(&p, n, hipHostMallocCoherent) : hipMalloc(&p, n);
         if (e != hipSuccess) {
@@ -172,6 +174,7 @@ void *Pool::alloc(size_t bytes)
         }
     }
     sizes_[p] = n;
+    charged_[p] = n;
     in_use_ += (int64_t)n;
     peak_ = std::max(peak_, in_use_);
     return p;
@@ -183,7 +186,8 @@ void Pool::release(void *p, hipStream_t after)
     std::lock_guard<std::mutex> g(mu_);
     auto it = sizes_.find(p);
     if (it == sizes_.end()) return;
-    in_use_ -= (int64_t)it->second;
+    in_use_ -= (int64_t)charged_[p];
+    charged_.erase(p);
     if (after == kNoWait) {
         free_.emplace(it->second, p);
         return;
@@ -207,7 +211,8 @@ void Pool::release_all(const std::vector<void *> &ps, hipStream_t after)
         if (!p) continue;
         auto it = sizes_.find(p);
         if (it == sizes_.end()) continue;
-        in_use_ -= (int64_t)it->second;
+        in_use_ -= (int64_t)charged_[p];
+        charged_.erase(p);
         live.push_back(p);
     }
     if (live.empty()) return;
@@ -256,12 +261,25 @@ extern "C" sn_status sn_ctx_create(int device, sn_ctx **out)
     }
     if (const char *cw = std::getenv("SN_TEST_COUNT_WIDE_WORDS"); cw && *cw)
         c->count_wide_words = std::strtoll(cw, nullptr, 10);
+    if (const char *sp = std::getenv("SN_TEST_SWEEP_SMALL_POINTS"); sp && *sp)
+        c->sweep_small_points = std::max<int64_t>(0, std::strtoll(sp, nullptr, 10));
+    if (const char *sc = std::getenv("SN_TEST_SWEEP_CHUNK"); sc && *sc)
+        c->sweep_chunk = (int32_t)std::min<int64_t>(std::max<int64_t>(0, std::strtoll(sc, nullptr, 10)),
+                                                    int64_t(1) << 20);
     const char *cache = std::getenv("SN_AUTOTUNE_CACHE");
     if (cache && *cache) {
         c->tune_path = cache;
         c->load_tune_cache();
     }
     *out = c;
+    return SN_OK;
+}
+
+extern "C" sn_status sn_ctx_memory(sn_ctx *c, int64_t *in_use_bytes, int64_t *peak_bytes)
+{
+    if (!c) return fail(SN_EINVAL, "sn_ctx_memory: ctx is NULL");
+    if (in_use_bytes) *in_use_bytes = c->pool.in_use();
+    if (peak_bytes) *peak_bytes = c->pool.peak();
     return SN_OK;
 }
 
@@ -659,6 +677,59 @@ struct Carve {
     }
 };
 
+// The mesh's word metadata block: point bits, then first point ids.
+struct MetaLayout {
+    size_t o_pm, o_wb, bytes;
+};
+MetaLayout meta_layout(int64_t words)
+{
+    Carve cv;
+    MetaLayout l;
+    l.o_pm = cv.add(8 * words);
+    l.o_wb = cv.add(4 * words);
+    l.bytes = cv.bytes;
+    return l;
+}
+
+// Every output of a mesh in one block, sized exactly from the totals.
+struct OutLayout {
+    size_t o_pts, o_fc, o_off, o_ids, o_q, o_pr, o_t, o_tp, o_pc, bytes;
+    bool tris, cells32;
+};
+OutLayout out_layout(const Geom &g, int32_t prim, int32_t dtype, int64_t P, int64_t Q, int64_t S)
+{
+    Carve cv;
+    OutLayout l{};
+    l.o_pts = cv.add(12 * P), l.o_fc = cv.add(P), l.o_off = cv.add(4 * (P + 1));
+    const int64_t quad_bytes = prim == SN_LINES ? 8 : 16;  // segments [Q][2] or quads [Q][4]
+    l.o_ids = cv.add(4 * S), l.o_q = cv.add(quad_bytes * Q), l.o_pr = cv.add(2 * Q * dtype);
+    l.tris = prim == SN_TRIS;
+    if (l.tris) l.o_t = cv.add(24 * Q), l.o_tp = cv.add(4 * Q * dtype);
+    // cell index per point (for world points written by the last sweep),
+    // when every cell index fits 32 bits
+    l.cells32 = (uint64_t)g.R * (uint64_t)g.CM < (uint64_t(1) << 32);
+    if (l.cells32) l.o_pc = cv.add(4 * P);
+    l.bytes = cv.bytes;
+    return l;
+}
+
+// The smoothing block: two offset buffers and the y/z neighbour table.
+struct SmoothLayout {
+    size_t o_a, o_b, o_n, bytes;
+};
+SmoothLayout smooth_layout(int64_t P)
+{
+    Carve cv;
+    SmoothLayout l;
+    l.o_a = cv.add(12 * P), l.o_b = cv.add(12 * P), l.o_n = cv.add(16 * P);
+    l.bytes = cv.bytes;
+    return l;
+}
+
+// Extraction scratch of one volume: quad and stencil word bases, cut-edge planes.
+int64_t words_of(const Geom &g) { return g.R * g.W; }
+int64_t plane_words_of(const Geom &g) { return 3 * g.N * g.O * g.WS; }
+
 template <typename T>
 T *dalloc(sn_mesh *m, int64_t count)
 {
@@ -668,6 +739,31 @@ T *dalloc(sn_mesh *m, int64_t count)
 }
 
 }  // namespace
+
+int64_t sn::extract_scratch_bytes(const sn_volume &v)
+{
+    const Geom g = make_geom(v);
+    const int64_t words = words_of(g);
+    const int64_t w1 = std::max<int64_t>(words, 1);
+    // wbQ, wbS, planes; scan status (narrow tiles are the most) with the
+    // ticket; descriptor, tile-map and table staging of a batch (three
+    // uploads, each rounded on its own)
+    const int64_t tiles = (words + kCountBlock - 1) / kCountBlock;
+    const int64_t stage = 3 * (int64_t)sizeof(VolDesc) + (int64_t)sizeof(SmoothDesc) + 8 * 8 +
+                          8 * (v.n_selected > 0 ? (v.dtype == 1 ? 4 : 1024) + v.n_selected : 0);
+    return (int64_t)(2 * round_size(4 * w1) + round_size(8 * std::max<int64_t>(plane_words_of(g), 1)) +
+                     round_size(24 * std::max<int64_t>(tiles, 1) + 256)) +
+           stage + 3 * 512;
+}
+
+int64_t sn::mesh_bytes(const sn_volume &v, int64_t P, int64_t Q, int64_t S, bool smoothed)
+{
+    const Geom g = make_geom(v);
+    int64_t b = (int64_t)round_size(meta_layout(words_of(g)).bytes) +
+                (int64_t)round_size(out_layout(g, v.prim, v.dtype, P, Q, S).bytes);
+    if (smoothed && P > 0) b += (int64_t)round_size(smooth_layout(P).bytes);
+    return b;
+}
 
 // Host spin on the count stamps before blocking on the stream (longer than the
 // edge and count passes of the largest single volumes measured, 0.75 ms).
@@ -707,7 +803,7 @@ static sn_status wait_totals(const int64_t *stamps, const std::vector<char> &cou
     } while (0)
 
 sn_status sn::extract_many(sn_ctx *c, const sn_volume *vols, int32_t n, hipStream_t s,
-                           int32_t bpw_override, sn_mesh **out)
+                           int32_t bpw_override, sn_mesh **out, const AdmitFn *admit)
 {
     if (!c || !vols || !out || n < 1) return fail(SN_EINVAL, "extract: bad arguments");
     for (int32_t v = 0; v < n; ++v) {
@@ -805,18 +901,17 @@ sn_status sn::extract_many(sn_ctx *c, const sn_volume *vols, int32_t n, hipStrea
             d.cs.table = d_tab + tab_at;
             tab_at += 2 * ((tabs[v].size() + 1) / 2);
         }
-        const int64_t words = d.g.R * d.g.W;
+        const int64_t words = words_of(d.g);
         {
-            Carve cv;
-            const size_t o_pm = cv.add(8 * words), o_wb = cv.add(4 * words);
-            uint8_t *blk = dalloc<uint8_t>(m, (int64_t)cv.bytes);
-            d.pmask = blk ? reinterpret_cast<uint64_t *>(blk + o_pm) : nullptr;
-            d.wbP = blk ? reinterpret_cast<int32_t *>(blk + o_wb) : nullptr;
+            const MetaLayout ml = meta_layout(words);
+            uint8_t *blk = dalloc<uint8_t>(m, (int64_t)ml.bytes);
+            d.pmask = blk ? reinterpret_cast<uint64_t *>(blk + ml.o_pm) : nullptr;
+            d.wbP = blk ? reinterpret_cast<int32_t *>(blk + ml.o_wb) : nullptr;
         }
         // extraction-only metadata: cut-edge planes and quad/stencil word bases
         d.wbQ = static_cast<int32_t *>(scr.d(sizeof(int32_t) * (size_t)std::max<int64_t>(words, 1)));
         d.wbS = static_cast<int32_t *>(scr.d(sizeof(int32_t) * (size_t)std::max<int64_t>(words, 1)));
-        const int64_t pwords = 3 * d.g.N * d.g.O * d.g.WS;
+        const int64_t pwords = plane_words_of(d.g);
         d.planes = static_cast<uint64_t *>(scr.d(sizeof(uint64_t) * (size_t)std::max<int64_t>(pwords, 1)));
         if (!d.pmask || !d.wbP || !d.wbQ || !d.wbS || !d.planes)
             return cleanup(fail(SN_ENOMEM, "extract: word metadata"));
@@ -902,6 +997,15 @@ sn_status sn::extract_many(sn_ctx *c, const sn_volume *vols, int32_t n, hipStrea
         if (st != SN_OK) return cleanup(st);
     }
 
+    if (admit) {
+        // the caller sees every volume's totals before any output is allocated
+        std::vector<int64_t> tot(3 * (size_t)n, 0);
+        for (int32_t k = 0; k < n; ++k)
+            if (ctile_prefix[k + 1] > ctile_prefix[k])
+                for (int q = 0; q < 3; ++q) tot[3 * order[k] + q] = h_tot[3 * k + q];
+        sn_status st = (*admit)(tot.data());
+        if (st != SN_OK) return cleanup(st);
+    }
     // exact allocation of every output (Sec. 2.3: no incremental allocation)
     int64_t qblocks = 0;
     for (int32_t k = 0; k < n; ++k) {
@@ -916,30 +1020,21 @@ sn_status sn::extract_many(sn_ctx *c, const sn_volume *vols, int32_t n, hipStrea
             return cleanup(fail(SN_ETOOBIG, "extract: mesh indices exceed int32"));
         d.P = m->P, d.Q = m->Q, d.S = m->S;
         // every output of the mesh in one block, sized exactly
-        Carve cv;
-        const size_t o_pts = cv.add(12 * m->P), o_fc = cv.add(m->P), o_off = cv.add(4 * (m->P + 1));
-        const int64_t quad_bytes = d.prim == SN_LINES ? 8 : 16;  // segments [Q][2] or quads [Q][4]
-        const size_t o_ids = cv.add(4 * m->S), o_q = cv.add(quad_bytes * m->Q), o_pr = cv.add(2 * m->Q * d.dtype);
-        const bool tris = d.prim == SN_TRIS;
-        const size_t o_t = tris ? cv.add(24 * m->Q) : 0, o_tp = tris ? cv.add(4 * m->Q * d.dtype) : 0;
-        // cell index per point (for world points written by the last sweep),
-        // when every cell index fits 32 bits
-        const bool cells32 = (uint64_t)d.g.R * (uint64_t)d.g.CM < (uint64_t(1) << 32);
-        const size_t o_pc = cells32 ? cv.add(4 * m->P) : 0;
-        uint8_t *blk = dalloc<uint8_t>(m, (int64_t)cv.bytes);
+        const OutLayout ol = out_layout(d.g, d.prim, d.dtype, m->P, m->Q, m->S);
+        uint8_t *blk = dalloc<uint8_t>(m, (int64_t)ol.bytes);
         if (!blk) return cleanup(fail(SN_ENOMEM, "extract: outputs"));
-        d.points = reinterpret_cast<float *>(blk + o_pts);
-        d.faces = blk + o_fc;
-        d.st_off = reinterpret_cast<int32_t *>(blk + o_off);
-        d.st_ids = reinterpret_cast<int32_t *>(blk + o_ids);
-        d.quads = reinterpret_cast<int32_t *>(blk + o_q);
-        d.pairs = blk + o_pr;
-        if (tris) {
-            d.tris = reinterpret_cast<int32_t *>(blk + o_t);
-            d.tri_pairs = blk + o_tp;
+        d.points = reinterpret_cast<float *>(blk + ol.o_pts);
+        d.faces = blk + ol.o_fc;
+        d.st_off = reinterpret_cast<int32_t *>(blk + ol.o_off);
+        d.st_ids = reinterpret_cast<int32_t *>(blk + ol.o_ids);
+        d.quads = reinterpret_cast<int32_t *>(blk + ol.o_q);
+        d.pairs = blk + ol.o_pr;
+        if (ol.tris) {
+            d.tris = reinterpret_cast<int32_t *>(blk + ol.o_t);
+            d.tri_pairs = blk + ol.o_tp;
             qblocks += (m->Q + 255) / 256;
         }
-        d.pcell = cells32 ? reinterpret_cast<uint32_t *>(blk + o_pc) : nullptr;
+        d.pcell = ol.cells32 ? reinterpret_cast<uint32_t *>(blk + ol.o_pc) : nullptr;
         hd[k] = d;
     }
     if (one) {
@@ -1024,13 +1119,12 @@ sn_status sn::validate_smooth(const sn_smooth_params *p)
 sn_status sn::ensure_smooth_buffers(sn_mesh *m)
 {
     if (m->d.P == 0 || m->da) return SN_OK;
-    Carve cv;
-    const size_t o_a = cv.add(12 * m->P), o_b = cv.add(12 * m->P), o_n = cv.add(16 * m->P);
-    uint8_t *blk = dalloc<uint8_t>(m, (int64_t)cv.bytes);
+    const SmoothLayout sl = smooth_layout(m->P);
+    uint8_t *blk = dalloc<uint8_t>(m, (int64_t)sl.bytes);
     if (!blk) return fail(SN_ENOMEM, "smooth: offset buffers");
-    m->da = reinterpret_cast<float *>(blk + o_a);
-    m->db = reinterpret_cast<float *>(blk + o_b);
-    m->nbr = reinterpret_cast<int32_t *>(blk + o_n);
+    m->da = reinterpret_cast<float *>(blk + sl.o_a);
+    m->db = reinterpret_cast<float *>(blk + sl.o_b);
+    m->nbr = reinterpret_cast<int32_t *>(blk + sl.o_n);
     return SN_OK;
 }
 
@@ -1051,6 +1145,8 @@ static void fill_smooth_desc(const sn_mesh *m, const sn_smooth_params &p, Smooth
     const int K = sweep_chunks(m->P);
     const int64_t per_slab = sweep_blocks_for(m->P, K) / std::max<int64_t>(1, m->d.g.CO);
     sd->chunk = (int32_t)std::max<int64_t>(1, (per_slab + 8) / 16);
+    if (m->ctx->sweep_chunk > 0) sd->chunk = m->ctx->sweep_chunk;
+    sd->big = m->P > m->ctx->sweep_small_points ? 1 : 0;
 }
 
 // Sweeps over `nvol` meshes (descriptor array), replayed from a HIP graph of

@@ -2,13 +2,26 @@
 //
 // Submitted requests wait in a FIFO queue.  Each of n_streams worker threads
 // owns one HIP stream; when a worker is free it admits queued requests in
-// order while (a) the sum of device-footprint estimates of everything in
-// flight stays within the budget and (b) fewer than max_inflight requests are
-// in flight, fuses the admitted requests into one batch (one counting launch,
-// one generation launch, one HIP-graph replay of the sweeps for the whole
-// batch) and runs it on its stream.  Requests arriving meanwhile join the next
-// batch of whichever worker frees first, so device work of different batches
+// order while (a) the device bytes reserved for everything in flight stay
+// within the budget and (b) fewer than max_inflight requests are in flight,
+// fuses the admitted requests into one batch (one counting launch, one
+// generation launch, one HIP-graph replay of the sweeps for the whole batch)
+// and runs it on its stream.  Requests arriving meanwhile join the next batch
+// of whichever worker frees first, so device work of different batches
 // overlaps.  Finished meshes stay device-resident until claimed.
+//
+// Admission is in two phases, because a mesh's size is known only once its
+// volume is counted (Sec. 2.3: the prefix sum sizes the outputs exactly).
+//   1. A request is admitted with its exact extraction scratch plus an
+//      estimate of its mesh (a running bytes-per-voxel figure of finished
+//      requests, or the exact figure if it was counted before).
+//   2. Between the count pass and the allocation of the outputs the batch's
+//      exact mesh bytes replace the estimate.  If they do not fit the budget
+//      next to what else is in flight, the batch waits for memory to be
+//      released; if every other batch in flight is waiting the same way, the
+//      batch steps back instead: its requests go back to the head of the
+//      queue with their exact sizes and its reservation is released.
+// A request that alone exceeds the budget runs when nothing else is in flight.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -37,22 +50,17 @@ struct Request {
     sn_volume vol{};
     std::vector<uint32_t> selected;
     sn_smooth_params p{};
-    int64_t footprint = 0;
+    int64_t scratch = 0;      // extraction scratch bytes (exact)
+    int64_t mesh_exact = -1;  // exact mesh bytes once counted (kept if queued again)
+    int64_t footprint = 0;    // bytes reserved while in flight
+    hipEvent_t ready = nullptr;  // recorded on the submitter's stream: the labels are written
     Clock::time_point t_submit, t_done;
     bool done = false;
     sn_status status = SN_OK;
     sn_mesh *mesh = nullptr;
 };
 
-// Device bytes a request may hold while in flight: row metadata exactly,
-// outputs estimated from the mesh density seen so far (bytes per voxel).
-int64_t footprint_of(const sn_volume &v, double out_bytes_per_voxel)
-{
-    const Geom g = make_geom(v);
-    const int64_t meta = g.R * g.W * 8 + 3 * 8 * (g.R + 1) + 4096;
-    const double vox = (double)v.dims[0] * (double)v.dims[1] * (double)v.dims[2];
-    return meta + (int64_t)(out_bytes_per_voxel * vox);
-}
+int64_t voxels_of(const sn_volume &v) { return v.dims[0] * v.dims[1] * v.dims[2]; }
 
 // Worker threads spin this long for new work before sleeping, and poll their
 // stream for this long before blocking on it.
@@ -75,37 +83,89 @@ struct sn_server {
     sn_ctx *ctx = nullptr;
     sn_serve_config cfg{};
     std::mutex mu;
-    std::condition_variable cv_work, cv_done;
+    std::condition_variable cv_work, cv_done, cv_mem;
     std::deque<Request *> queue;
     std::unordered_map<uint64_t, Request *> reqs;
     uint64_t next_ticket = 1;
     int64_t reserved = 0, peak_reserved = 0;
-    int32_t inflight = 0;
+    int32_t inflight = 0;          // requests admitted and not finished
+    int32_t batches_inflight = 0;  // their batches
+    int32_t mem_waiting = 0;       // batches waiting in phase 2 for memory
     bool stopping = false;
     std::vector<std::thread> workers;
     std::vector<hipStream_t> streams;
     // statistics
     int64_t n_submitted = 0, n_done = 0, n_rejected = 0, n_batches = 0;
+    int64_t n_split = 0, n_requeued = 0;
     int64_t voxels_done = 0, point_iters_done = 0;
     std::vector<double> lat_us;
-    double out_bpv = 4.0;  // running estimate of output bytes per voxel
+    double mesh_bpv = 16.0;  // running estimate of mesh bytes per voxel
     Clock::time_point busy_since;
     double busy_s = 0.0;
     int32_t busy_count = 0;
 
     std::atomic<int64_t> queued{0};  // queue length, read without the lock by spinning workers
+
+    // phase-1 reservation of a queued request
+    int64_t phase1_locked(const Request *r) const
+    {
+        const int64_t mesh = r->mesh_exact >= 0 ? r->mesh_exact
+                                                : (int64_t)(mesh_bpv * (double)voxels_of(r->vol));
+        return r->scratch + mesh;
+    }
+    // phase 2 for the requests b[0..n): exact mesh bytes from the totals;
+    // SN_OK to go on, SN_EAGAIN when the batch steps back
+    sn_status phase2(Request *const *b, int32_t n, const int64_t *totals);
     void worker(int w);
     // extract + smooth n requests as one fused batch on stream s and wait for
     // it; on failure every ms[k] is null
-    sn_status run_fused(const sn_volume *vols, const sn_smooth_params *ps, int32_t n,
-                        hipStream_t s, sn_mesh **ms);
+    sn_status run_fused(Request *const *b, const sn_volume *vols, const sn_smooth_params *ps,
+                        int32_t n, hipStream_t s, sn_mesh **ms);
+    void finish_locked(Request *r, sn_status st, sn_mesh *m, Clock::time_point now);
 };
 
-sn_status sn_server::run_fused(const sn_volume *vols, const sn_smooth_params *ps, int32_t n,
-                               hipStream_t s, sn_mesh **ms)
+sn_status sn_server::phase2(Request *const *b, int32_t n, const int64_t *totals)
+{
+    std::vector<int64_t> exact(n);
+    int64_t delta = 0;
+    for (int32_t k = 0; k < n; ++k) {
+        const Request *r = b[k];
+        exact[k] = mesh_bytes(r->vol, totals[3 * k], totals[3 * k + 1], totals[3 * k + 2],
+                              r->p.iterations > 0);
+        delta += r->scratch + exact[k] - r->footprint;
+    }
+    std::unique_lock<std::mutex> lk(mu);
+    while (true) {
+        // nothing else in flight: the batch runs, whatever its size
+        const bool alone = batches_inflight == 1;
+        if (delta <= 0 || reserved + delta <= cfg.hbm_budget_bytes || alone) {
+            reserved += delta;
+            peak_reserved = std::max(peak_reserved, reserved);
+            for (int32_t k = 0; k < n; ++k) {
+                b[k]->mesh_exact = exact[k];
+                b[k]->footprint = b[k]->scratch + exact[k];
+            }
+            if (delta < 0) cv_mem.notify_all(), cv_work.notify_all();
+            return SN_OK;
+        }
+        if (mem_waiting + 1 >= batches_inflight) {
+            // every other batch in flight waits here as well: nothing will be
+            // released, so this one steps back
+            for (int32_t k = 0; k < n; ++k) b[k]->mesh_exact = exact[k];
+            return SN_EAGAIN;
+        }
+        ++mem_waiting;
+        cv_mem.wait(lk);
+        --mem_waiting;
+    }
+}
+
+sn_status sn_server::run_fused(Request *const *b, const sn_volume *vols, const sn_smooth_params *ps,
+                               int32_t n, hipStream_t s, sn_mesh **ms)
 {
     std::fill(ms, ms + n, nullptr);
-    sn_status st = extract_many(ctx, vols, n, s, 0, ms);
+    const AdmitFn admit = [&](const int64_t *totals) { return phase2(b, n, totals); };
+    sn_status st = extract_many(ctx, vols, n, s, 0, ms, &admit);
     if (st == SN_OK) {
         // a batch of one takes the plain path (no descriptor upload, no graph build)
         st = n == 1 ? smooth_one(ctx, ms[0], ps, s) : smooth_many(ctx, ms, ps, n, s);
@@ -116,6 +176,31 @@ sn_status sn_server::run_fused(const sn_volume *vols, const sn_smooth_params *ps
         }
     }
     return st;
+}
+
+void sn_server::finish_locked(Request *r, sn_status st, sn_mesh *m, Clock::time_point now)
+{
+    r->done = true;
+    r->status = st;
+    r->mesh = m;
+    r->t_done = now;
+    if (r->ready) {
+        // the worker's stream waited for it and has completed since
+        (void)hipEventSynchronize(r->ready);
+        ctx->sync_events.put(r->ready);
+        r->ready = nullptr;
+    }
+    if (st == SN_OK) {
+        ++n_done;
+        const int64_t vox = voxels_of(r->vol);
+        voxels_done += vox;
+        point_iters_done += m->P * (int64_t)r->p.iterations;
+        lat_us.push_back(std::chrono::duration<double, std::micro>(now - r->t_submit).count());
+        const int64_t mb = mesh_bytes(r->vol, m->P, m->Q, m->S, r->p.iterations > 0);
+        mesh_bpv = 0.9 * mesh_bpv + 0.1 * std::max(1.0, (double)mb / (double)std::max<int64_t>(vox, 1));
+    } else {
+        ++n_rejected;
+    }
 }
 
 void sn_server::worker(int w)
@@ -135,18 +220,19 @@ void sn_server::worker(int w)
                 if (stopping && queue.empty()) return true;
                 if (queue.empty() || inflight >= cfg.max_inflight) return false;
                 // the head must fit next to what is in flight (or run alone)
-                Request *h = queue.front();
-                return reserved + h->footprint <= cfg.hbm_budget_bytes || inflight == 0;
+                return reserved + phase1_locked(queue.front()) <= cfg.hbm_budget_bytes || inflight == 0;
             });
             if (queue.empty() && stopping) return;
             while (!queue.empty() && (int32_t)batch.size() < cfg.max_batch &&
                    inflight < cfg.max_inflight) {
                 Request *h = queue.front();
-                const bool fits = reserved + h->footprint <= cfg.hbm_budget_bytes;
+                const int64_t fp = phase1_locked(h);
+                const bool fits = reserved + fp <= cfg.hbm_budget_bytes;
                 if (!fits && !(batch.empty() && inflight == 0)) break;
                 queue.pop_front();
                 queued.fetch_sub(1, std::memory_order_release);
-                reserved += h->footprint;
+                h->footprint = fp;
+                reserved += fp;
                 ++inflight;
                 batch.push_back(h);
             }
@@ -154,6 +240,7 @@ void sn_server::worker(int w)
             peak_reserved = std::max(peak_reserved, reserved);
             if (busy_count++ == 0) busy_since = Clock::now();
             ++n_batches;
+            ++batches_inflight;
         }
         const int32_t n = (int32_t)batch.size();
         std::vector<sn_volume> vols(n);
@@ -162,47 +249,51 @@ void sn_server::worker(int w)
             vols[k] = batch[k]->vol;
             vols[k].selected = batch[k]->selected.empty() ? nullptr : batch[k]->selected.data();
             ps[k] = batch[k]->p;
+            // the labels are read only after the submitter's work on them
+            if (batch[k]->ready && hipStreamWaitEvent(s, batch[k]->ready, 0) != hipSuccess) {
+                (void)hipGetLastError();
+                (void)hipEventSynchronize(batch[k]->ready);
+            }
         }
         std::vector<sn_mesh *> ms(n, nullptr);
         std::vector<sn_status> sts(n, SN_OK);
-        const sn_status st = run_fused(vols.data(), ps.data(), n, s, ms.data());
+        const sn_status st = run_fused(batch.data(), vols.data(), ps.data(), n, s, ms.data());
+        bool split = false;
         if (st == SN_ENOMEM && n > 1) {
-            // the fused batch did not fit next to what the other streams hold:
-            // run its requests one at a time instead of failing all of them
-            for (int32_t k = 0; k < n; ++k) sts[k] = run_fused(&vols[k], &ps[k], 1, s, &ms[k]);
+            // the fused batch did not fit in device memory next to what the
+            // other streams hold: run its requests one at a time instead of
+            // failing all of them
+            split = true;
+            for (int32_t k = 0; k < n; ++k)
+                sts[k] = run_fused(&batch[k], &vols[k], &ps[k], 1, s, &ms[k]);
         } else {
             std::fill(sts.begin(), sts.end(), st);
         }
         const auto now = Clock::now();
         {
             std::lock_guard<std::mutex> lk(mu);
+            n_split += split ? 1 : 0;
+            std::vector<Request *> back;  // stepped back in phase 2: queued again
             for (int32_t k = 0; k < n; ++k) {
                 Request *r = batch[k];
-                const sn_status st = sts[k];
-                r->done = true;
-                r->status = st;
-                r->mesh = ms[k];
-                r->t_done = now;
                 reserved -= r->footprint;
+                r->footprint = 0;
                 --inflight;
-                if (st == SN_OK) {
-                    ++n_done;
-                    const int64_t vox = r->vol.dims[0] * r->vol.dims[1] * r->vol.dims[2];
-                    voxels_done += vox;
-                    point_iters_done += ms[k]->P * (int64_t)r->p.iterations;
-                    lat_us.push_back(
-                        std::chrono::duration<double, std::micro>(now - r->t_submit).count());
-                    const double bytes = 44.0 * ms[k]->P + 24.0 * ms[k]->Q + 4.0 * ms[k]->S;
-                    out_bpv = 0.9 * out_bpv + 0.1 * std::max(0.5, bytes / std::max<int64_t>(vox, 1));
-                } else {
-                    ++n_rejected;
-                }
+                if (sts[k] == SN_EAGAIN)
+                    back.push_back(r);
+                else
+                    finish_locked(r, sts[k], ms[k], now);
             }
+            for (auto it = back.rbegin(); it != back.rend(); ++it) queue.push_front(*it);
+            queued.fetch_add((int64_t)back.size(), std::memory_order_release);
+            n_requeued += (int64_t)back.size();
+            --batches_inflight;
             if (--busy_count == 0)
                 busy_s += std::chrono::duration<double>(now - busy_since).count();
         }
         cv_done.notify_all();
         cv_work.notify_all();
+        cv_mem.notify_all();
     }
 }
 
@@ -233,30 +324,40 @@ extern "C" sn_status sn_serve_start(sn_ctx *ctx, const sn_serve_config *cfg, sn_
 }
 
 extern "C" sn_status sn_serve_submit(sn_server *srv, const sn_volume *vol, const sn_smooth_params *p,
-                                     uint64_t *ticket)
+                                     void *stream, uint64_t *ticket)
 {
     if (!srv || !vol || !p || !ticket) return fail(SN_EINVAL, "sn_serve_submit: NULL argument");
     sn_status st = validate_volume(vol);
     if (st != SN_OK) return st;
     st = validate_smooth(p);
     if (st != SN_OK) return st;
+    HIP_TRY(hipSetDevice(srv->ctx->device));
     Request *r = new Request();
     r->vol = *vol;
     if (vol->n_selected > 0) r->selected.assign(vol->selected, vol->selected + vol->n_selected);
     r->vol.selected = nullptr;
     r->p = *p;
+    r->scratch = extract_scratch_bytes(r->vol);
+    // the worker's stream waits for what the submitter's stream has enqueued
+    // so far (the labels may still be being written there)
+    r->ready = srv->ctx->sync_events.get();
+    if (!r->ready || hipEventRecord(r->ready, static_cast<hipStream_t>(stream)) != hipSuccess) {
+        (void)hipGetLastError();
+        srv->ctx->sync_events.put(r->ready);
+        delete r;
+        return fail(SN_EDEVICE, "sn_serve_submit: cannot record the submitter's stream");
+    }
     r->t_submit = Clock::now();
     {
         std::lock_guard<std::mutex> lk(srv->mu);
-        if (srv->stopping) {
+        if (srv->stopping || (int32_t)srv->queue.size() >= srv->cfg.queue_capacity) {
+            const bool stop = srv->stopping;
+            (void)hipEventSynchronize(r->ready);
+            srv->ctx->sync_events.put(r->ready);
             delete r;
-            return fail(SN_ESHUTDOWN, "sn_serve_submit: server stopping");
+            return stop ? fail(SN_ESHUTDOWN, "sn_serve_submit: server stopping")
+                        : fail(SN_EAGAIN, "sn_serve_submit: queue full");
         }
-        if ((int32_t)srv->queue.size() >= srv->cfg.queue_capacity) {
-            delete r;
-            return fail(SN_EAGAIN, "sn_serve_submit: queue full");
-        }
-        r->footprint = footprint_of(r->vol, srv->out_bpv);
         r->ticket = srv->next_ticket++;
         srv->reqs[r->ticket] = r;
         srv->queue.push_back(r);
@@ -341,6 +442,8 @@ extern "C" sn_status sn_serve_stats_get(sn_server *srv, sn_serve_stats *out)
                                   ? std::chrono::duration<double>(Clock::now() - srv->busy_since).count()
                                   : 0.0);
     s.peak_reserved_bytes = srv->peak_reserved;
+    s.n_split_batches = srv->n_split;
+    s.n_requeued = srv->n_requeued;
     *out = s;
     return SN_OK;
 }
@@ -358,11 +461,17 @@ extern "C" sn_status sn_serve_stop(sn_server *srv)
             srv->queued.fetch_sub(1, std::memory_order_release);
             r->done = true;
             r->status = SN_ESHUTDOWN;
+            if (r->ready) {
+                (void)hipEventSynchronize(r->ready);
+                srv->ctx->sync_events.put(r->ready);
+                r->ready = nullptr;
+            }
             ++srv->n_rejected;
         }
     }
     srv->cv_work.notify_all();
     srv->cv_done.notify_all();
+    srv->cv_mem.notify_all();
     for (auto &t : srv->workers) t.join();
     (void)hipSetDevice(srv->ctx->device);
     for (auto s : srv->streams) {

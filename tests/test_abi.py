@@ -67,12 +67,29 @@ def test_null_arguments_are_rejected_without_gpu(lib):
     assert b"NULL" in lib.sn_last_error() or lib.sn_last_error() != b""
 
 
-def test_struct_layouts_match_header():
+def test_struct_layouts_match_header(tmp_path):
+    """Every ctypes structure of the binding has the size and field offsets
+    that the C compiler gives the header's struct of the same name."""
+    import subprocess
+
     import paper_2401_14906_amd as sn
 
-    # sizes implied by the C declarations (x86-64 SysV alignment)
-    assert ctypes.sizeof(sn.sn_volume) == 8 + 4 + 4 + 24 + 24 + 24 + 8 + 4 + 4 + 4 + 4
-    assert ctypes.sizeof(sn.sn_smooth_params) == 16
-    assert ctypes.sizeof(sn.sn_mesh_view) == 4 * 8 + 2 * 4 + 7 * 8
-    assert ctypes.sizeof(sn.sn_serve_config) == 8 + 4 * 4
-    assert ctypes.sizeof(sn.sn_serve_stats) == 6 * 8 + 4 * 8 + 8
+    structs = [sn.sn_volume, sn.sn_smooth_params, sn.sn_mesh_view, sn.sn_serve_config,
+               sn.sn_serve_stats, sn.sn_kernel_stat]
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "sn.h"', "int main(void) {"]
+    for st in structs:
+        name = st.__name__
+        lines.append(f'printf("{name} %zu\\n", sizeof({name}));')
+        for f, _ in st._fields_:
+            lines.append(f'printf("{name}.{f} %zu\\n", offsetof({name}, {f}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)])
+    got = dict(l.split() for l in subprocess.check_output([str(exe)]).decode().splitlines())
+    for st in structs:
+        name = st.__name__
+        assert int(got[name]) == ctypes.sizeof(st), name
+        for f, _ in st._fields_:
+            assert int(got[f"{name}.{f}"]) == getattr(st, f).offset, f"{name}.{f}"

@@ -138,3 +138,31 @@ def test_fixed_rule_equals_extraction_split(ctx, sn, torch):
     tris2, none = ctx.triangulate(m, "planar", labels=False)
     assert none is None and tris2.shape == tris.shape
     m.free()
+
+
+@pytest.mark.parametrize("rule", RULES)
+def test_triangulate_on_gpu_points_exact(ctx, sn, torch, rule):
+    """The oracle's rule run on the GPU's own FP32 world points (widened to
+    FP64, as the kernel does) splits every quad exactly as the kernel does: no
+    near-tie allowance.  Both evaluate the measures in FP64 in the order
+    written, without contraction, so even exact ties (symmetric quads) break
+    the same way.  The torso mesh adds 659 K quads with anisotropic spacing."""
+    import oracle
+
+    r = sn.DIAG_RULES[rule]
+    tv = synth.torso_like()
+    extra = [("torso 256^3 u16", tv.labels, (), 0, tv.spacing,
+              (tv.iterations, tv.relaxation, tv.constraint))]
+    for name, lab, sel, bg, spacing, (it, lam, dd) in list(cases()) + extra:
+        announce(f"triangulate {rule} on GPU points: {name}")
+        t = sn.to_device(lab)
+        m = ctx.extract(t, spacing=spacing, selected=sel, background=bg)
+        ctx.smooth(m, iterations=it, relaxation=lam, constraint=dd)
+        tris, _ = ctx.triangulate(m, rule, labels=False)
+        g = m.to_host()
+        gt = tris.cpu().numpy()
+        m.free()
+        ot = oracle.triangulate_rule(g.polys, g.points.astype(np.float64), r)
+        bad = np.flatnonzero(np.any((gt != ot).reshape(-1, 6), 1))
+        assert bad.size == 0, f"{name}: {bad.size} of {g.polys.shape[0]} quads split differently " \
+                              f"(first {bad[:5].tolist()})"
