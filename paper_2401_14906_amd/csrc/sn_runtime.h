@@ -97,7 +97,6 @@ struct sn_ctx {
     bool profiling = false;
     bool profile_eager = false;        // every sweep bracketed by its own events
     bool profile_sweeps_only = false;  // only the sweeps are bracketed
-    std::atomic<int64_t> count_seq{0};  // stamps of the count pass's totals
     struct ProfEv {
         std::string name;
         hipEvent_t a, b;

@@ -981,7 +981,14 @@ sn_status sn::extract_many(sn_ctx *c, const sn_volume *vols, int32_t n, hipStrea
             }
         }
     }
-    const int64_t seq = c->count_seq.fetch_add(1, std::memory_order_relaxed) + 1;
+    // Stamps: a value no earlier call in this process used (pinned blocks are
+    // recycled, also between contexts), and the slots cleared by the host
+    // before the count pass is enqueued, so a stale stamp in a recycled block
+    // can never pass for this call's totals.
+    static std::atomic<int64_t> g_count_seq{0};
+    const int64_t seq = g_count_seq.fetch_add(1, std::memory_order_relaxed) + 1;
+    for (int32_t k = 0; k < n; ++k) __atomic_store_n(h_tot + 3 * n + k, int64_t(0), __ATOMIC_RELAXED);
+    std::atomic_thread_fence(std::memory_order_seq_cst);
     const CountOut cout{d_tot, d_tot + 3 * n, seq};
     {
         ProfScope ps(c, "k_count", s);

@@ -18,10 +18,12 @@
 //   2. Between the count pass and the allocation of the outputs the batch's
 //      exact mesh bytes replace the estimate.  If they do not fit the budget
 //      next to what else is in flight, the batch waits for memory to be
-//      released; if every other batch in flight is waiting the same way, the
-//      batch steps back instead: its requests go back to the head of the
-//      queue with their exact sizes and its reservation is released.
-// A request that alone exceeds the budget runs when nothing else is in flight.
+//      released; if every other batch in flight is waiting the same way, or
+//      there is no other, the batch steps back instead: its requests go back
+//      to the head of the queue with their exact sizes and its reservation
+//      is released, so that phase 1 admits again only what fits.
+// A single request that alone exceeds the budget runs when nothing else is in
+// flight; reservations otherwise never exceed the budget.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -57,6 +59,7 @@ struct Request {
     Clock::time_point t_submit, t_done;
     bool done = false;
     sn_status status = SN_OK;
+    std::string err;  // the worker's message when the request failed
     sn_mesh *mesh = nullptr;
 };
 
@@ -136,8 +139,10 @@ sn_status sn_server::phase2(Request *const *b, int32_t n, const int64_t *totals)
     }
     std::unique_lock<std::mutex> lk(mu);
     while (true) {
-        // nothing else in flight: the batch runs, whatever its size
-        const bool alone = batches_inflight == 1;
+        // nothing else in flight: a single request runs whatever its size;
+        // a batch of several that does not fit steps back (below) and is
+        // admitted again on its exact sizes, as a prefix that fits
+        const bool alone = batches_inflight == 1 && n == 1;
         if (delta <= 0 || reserved + delta <= cfg.hbm_budget_bytes || alone) {
             reserved += delta;
             peak_reserved = std::max(peak_reserved, reserved);
@@ -149,8 +154,8 @@ sn_status sn_server::phase2(Request *const *b, int32_t n, const int64_t *totals)
             return SN_OK;
         }
         if (mem_waiting + 1 >= batches_inflight) {
-            // every other batch in flight waits here as well: nothing will be
-            // released, so this one steps back
+            // every other batch in flight waits here as well (or there is no
+            // other): nothing will be released, so this one steps back
             for (int32_t k = 0; k < n; ++k) b[k]->mesh_exact = exact[k];
             return SN_EAGAIN;
         }
@@ -257,6 +262,7 @@ void sn_server::worker(int w)
         }
         std::vector<sn_mesh *> ms(n, nullptr);
         std::vector<sn_status> sts(n, SN_OK);
+        std::vector<std::string> errs(n);
         const sn_status st = run_fused(batch.data(), vols.data(), ps.data(), n, s, ms.data());
         bool split = false;
         if (st == SN_ENOMEM && n > 1) {
@@ -264,10 +270,13 @@ void sn_server::worker(int w)
             // other streams hold: run its requests one at a time instead of
             // failing all of them
             split = true;
-            for (int32_t k = 0; k < n; ++k)
+            for (int32_t k = 0; k < n; ++k) {
                 sts[k] = run_fused(&batch[k], &vols[k], &ps[k], 1, s, &ms[k]);
+                if (sts[k] != SN_OK && sts[k] != SN_EAGAIN) errs[k] = sn_last_error();
+            }
         } else {
             std::fill(sts.begin(), sts.end(), st);
+            if (st != SN_OK && st != SN_EAGAIN) std::fill(errs.begin(), errs.end(), sn_last_error());
         }
         const auto now = Clock::now();
         {
@@ -279,10 +288,12 @@ void sn_server::worker(int w)
                 reserved -= r->footprint;
                 r->footprint = 0;
                 --inflight;
-                if (sts[k] == SN_EAGAIN)
+                if (sts[k] == SN_EAGAIN) {
                     back.push_back(r);
-                else
+                } else {
+                    r->err = std::move(errs[k]);
                     finish_locked(r, sts[k], ms[k], now);
+                }
             }
             for (auto it = back.rbegin(); it != back.rend(); ++it) queue.push_front(*it);
             queued.fetch_add((int64_t)back.size(), std::memory_order_release);
@@ -380,9 +391,10 @@ static sn_status claim_locked(sn_server *srv, std::unordered_map<uint64_t, Reque
         else
             mesh_release(r->mesh);
     }
+    const std::string err = std::move(r->err);
     srv->reqs.erase(it);
     delete r;
-    return st == SN_OK ? SN_OK : fail(st, "serve: request failed");
+    return st == SN_OK ? SN_OK : fail(st, "serve: request failed: " + err);
 }
 
 extern "C" sn_status sn_serve_poll(sn_server *srv, uint64_t ticket, sn_mesh **out)

@@ -85,16 +85,17 @@ def plain(ctx, t, it):
 
 
 def test_extract_and_batch_enomem(sn, torch, monkeypatch):
-    """A 1 MiB cap: the torso volume (and a batch holding it) fails with
-    SN_ENOMEM; no memory stays handed out; a small volume then extracts and
-    smooths to the oracle's result, alone and in a batch."""
-    c = limited_context(sn, monkeypatch, 1 << 20)
+    """A 4 MiB cap: the torso volume (its cut-edge planes alone take 6 MiB)
+    and a batch holding it fail with SN_ENOMEM; no memory stays handed out; a
+    small volume (about 0.9 MB of mesh and smoothing buffers) then extracts and
+    smooths to the oracle's result, alone and twice in a batch."""
+    c = limited_context(sn, monkeypatch, 4 << 20)
     try:
         big = sn.to_device(synth.torso_like().labels)
         rng = np.random.default_rng(61)
         small = synth.blocky_tiny(rng, (30, 20, 16), 5, np.uint16)
         ts = sn.to_device(small)
-        announce("ENOMEM: torso under a 1 MiB cap")
+        announce("ENOMEM: torso under a 4 MiB cap")
         with pytest.raises(sn.SNError) as e:
             c.extract(big)
         assert e.value.status == sn.SN_ENOMEM
@@ -153,6 +154,17 @@ def served_requests(rng, n):
     return [synth.blocky_tiny(rng, (70 + 6 * k, 50, 40), 6, np.uint16) for k in range(n)]
 
 
+def sparse_requests(n):
+    """Volumes whose extraction scratch (cut-edge planes, word bases: about
+    0.6 bytes per voxel) dwarfs their mesh: one small sphere each."""
+    out = []
+    for k in range(n):
+        dims = (256 + 16 * k, 192, 160)
+        c = np.array([[dims[0] / 2, dims[1] / 2, dims[2] / 2]])
+        out.append(synth.spheres(dims, 2, c, [6.0 + k], [k + 1]))
+    return out
+
+
 def gate(torch, cycles=20_000_000):
     """A torch stream held busy by a bounded sleep kernel."""
     s = torch.cuda.Stream()
@@ -163,11 +175,11 @@ def gate(torch, cycles=20_000_000):
 
 def test_served_enomem_splits_the_batch(sn, torch, monkeypatch):
     """A fused batch that exceeds the pool cap runs its requests one at a
-    time, with the plain results.  The cap is the pool peak of the same
-    sequence run one request at a time (results held), which is below the
-    peak of the fused form."""
-    rng = np.random.default_rng(63)
-    labs = served_requests(rng, 5)
+    time, with the plain results.  The requests hold small meshes but large
+    extraction scratch, which a fused batch needs for all of them at once: the
+    cap is the pool peak of the same sequence run one request at a time
+    (results held) plus 4 MiB, far below the fused form's peak."""
+    labs = sparse_requests(5)
     blocker = synth.torso_like().labels
     its = [4 + k for k in range(len(labs))]
     ts = [sn.to_device(x) for x in labs]
@@ -193,18 +205,24 @@ def test_served_enomem_splits_the_batch(sn, torch, monkeypatch):
     for m in ms + [mb]:
         m.free()
     b.close()
-    assert fused_peak > seq_peak, (fused_peak, seq_peak)
-    c = limited_context(sn, monkeypatch, seq_peak)
+    cap = seq_peak + (4 << 20)
+    assert fused_peak > cap + (8 << 20), (fused_peak, seq_peak)
+    c = limited_context(sn, monkeypatch, cap)
     srv = c.serve_start(hbm_budget_bytes=64 << 30, max_inflight=16, n_streams=1, max_batch=16)
     try:
-        announce(f"served batch over a pool cap of {seq_peak} bytes (fused needs {fused_peak})")
+        announce(f"served batch over a pool cap of {cap} bytes (one at a time {seq_peak}, "
+                 f"fused {fused_peak})")
         # the blocker's labels wait behind a sleep on its stream, so the other
         # requests queue up meanwhile and the worker takes them as one batch
         s = gate(torch)
         tk_b = srv.submit(tb, iterations=3, stream=s)
         tks = [srv.submit(t, iterations=it) for t, it in zip(ts, its)]
         for k, tk in enumerate(tks):
-            m = srv.wait(tk, timeout_us=60_000_000)
+            try:
+                m = srv.wait(tk, timeout_us=60_000_000)
+            except sn.SNError:
+                announce(f"request {k} failed; pool {c.memory()}, stats {srv.stats()}")
+                raise
             same_mesh(m.to_host(), ref[k], f"split request {k}")
             m.free()
         srv.wait(tk_b, timeout_us=60_000_000).free()
@@ -216,6 +234,34 @@ def test_served_enomem_splits_the_batch(sn, torch, monkeypatch):
         c.close()
     for k in (0, len(labs) - 1):
         against_oracle(ref[k], labs[k], its[k])
+
+
+def test_totals_of_recycled_host_blocks(sn, torch):
+    """Contexts made and closed one after another run the same number of
+    extractions on different volumes: the count totals a call reads are its
+    own, never a stamp an earlier context left in a recycled pinned block."""
+    import oracle
+
+    rng = np.random.default_rng(65)
+    vols = [synth.blocky_tiny(rng, (40 + 7 * k, 30 + 3 * k, 20 + 2 * k), 4 + k, np.uint16)
+            for k in range(4)]
+    want = []
+    for lab in vols:
+        o = oracle.extract(lab)
+        want.append((o.n_points, o.n_quads, o.n_stencil))
+    ts = [sn.to_device(x) for x in vols]
+    for rot in range(len(vols)):
+        announce(f"context {rot}: volumes rotated by {rot}")
+        ctx = sn.Context(0)
+        try:
+            for k in range(len(vols)):
+                v = (k + rot) % len(vols)
+                m = ctx.extract(ts[v])
+                got = (m.n_points, m.n_quads, m.n_stencil)
+                m.free()
+                assert got == want[v], f"context {rot}, call {k}: {got} against {want[v]}"
+        finally:
+            ctx.close()
 
 
 def test_served_phase2_steps_back(sn, torch):
