@@ -21,8 +21,14 @@ _LIB_PATH = os.environ.get("SN_ORACLE_LIB") or os.path.join(_HERE, "libsn_oracle
 _lib = None
 
 
+_PAR_PATH = os.path.join(_HERE, "libsn_oracle_par.so")
+_par = None
+
+
 def build() -> str:
-    """Compile libsn_oracle.so with gcc (serial, no fast-math)."""
+    """Compile libsn_oracle.so with gcc (serial, no fast-math), and
+    libsn_oracle_par.so, the same loops over z-slices with OpenMP (the
+    benchmark's all-cores CPU baseline)."""
     import subprocess
 
     src = os.path.join(_HERE, "sn_oracle.c")
@@ -30,7 +36,43 @@ def build() -> str:
     subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", "-ffp-contract=off", "-o", tmp, src,
                            "-lm"])
     os.replace(tmp, _LIB_PATH)
+    src = os.path.join(_HERE, "sn_oracle_par.c")
+    tmp = _PAR_PATH + ".tmp"
+    subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", "-ffp-contract=off", "-fopenmp",
+                           "-o", tmp, src, "-lm"])
+    os.replace(tmp, _PAR_PATH)
     return _LIB_PATH
+
+
+def _load_par():
+    global _par
+    if _par is None:
+        if not os.path.exists(_PAR_PATH):
+            build()
+        lib = ctypes.CDLL(_PAR_PATH)
+        P = ctypes.c_void_p
+        I64 = ctypes.c_int64
+        lib.orc_extract_par.restype = P
+        lib.orc_extract_par.argtypes = [P, ctypes.c_int, I64, I64, I64, P, ctypes.c_int32,
+                                        ctypes.c_uint32, ctypes.c_int32]
+        lib.orc_smooth_par.argtypes = [P, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+                                       ctypes.c_int, ctypes.c_int32, P]
+        lib.orc_smooth_par.restype = ctypes.c_int
+        lib.orc_mesh_free.argtypes = [P]
+        lib.orc_mesh_free.restype = None
+        lib.orc_mesh_sizes.argtypes = [P, P]
+        lib.orc_mesh_sizes.restype = None
+        lib.orc_mesh_copy.argtypes = [P, P, P, P, P, P]
+        lib.orc_mesh_copy.restype = None
+        lib.orc_par_max_threads.argtypes = []
+        lib.orc_par_max_threads.restype = ctypes.c_int32
+        _par = lib
+    return _par
+
+
+def par_threads() -> int:
+    """Threads the all-cores oracle uses by default (OpenMP's default)."""
+    return int(_load_par().orc_par_max_threads())
 
 
 def _load():
@@ -84,6 +126,7 @@ class OracleMesh:
     st_off: np.ndarray     # int64 [P+1]
     st_ids: np.ndarray     # int32 [S]
     _handle: int = 0
+    _par: bool = False     # made by the all-cores library (freed by it)
 
     @property
     def n_points(self):
@@ -119,6 +162,18 @@ class OracleMesh:
             raise MemoryError("oracle smoothing allocation failed")
         return out
 
+    def smooth_par(self, iterations: int, relaxation: float, constraint: float,
+                   shape: str = "box", threads: int = 0) -> np.ndarray:
+        """smooth() with the points of each sweep spread over `threads` host
+        threads (0: all); equal to smooth() bit for bit."""
+        out = np.empty((self.n_points, 3), dtype=np.float64)
+        rc = _load_par().orc_smooth_par(self._handle, int(iterations), float(relaxation),
+                                        float(constraint), {"box": 0, "sphere": 1}[shape],
+                                        int(threads), _p(out))
+        if rc != 0:
+            raise MemoryError("oracle smoothing allocation failed")
+        return out
+
     def triangulate(self):
         tris = np.empty((2 * self.n_quads, 3), dtype=np.int32)
         tp = np.empty((2 * self.n_quads, 2), dtype=np.uint32)
@@ -126,8 +181,9 @@ class OracleMesh:
         return tris, tp
 
     def __del__(self):
-        if self._handle and _lib is not None:
-            _lib.orc_mesh_free(self._handle)
+        lib = _par if self._par else _lib
+        if self._handle and lib is not None:
+            lib.orc_mesh_free(self._handle)
             self._handle = 0
 
 
@@ -153,6 +209,36 @@ def extract(labels: np.ndarray, selected=(), background: int = 0) -> OracleMesh:
     st_ids = np.empty(S, dtype=np.int32)
     lib.orc_mesh_copy(h, _p(cell_of), _p(quads), _p(pairs), _p(st_off), _p(st_ids))
     return OracleMesh((M, N, O), cell_of, quads, pairs, st_off, st_ids, h)
+
+
+def extract_par(labels: np.ndarray, selected=(), background: int = 0,
+                threads: int = 0) -> OracleMesh:
+    """extract() with the oracle's loops spread over z-slices on `threads`
+    host threads (0: all); equal to extract() bit for bit."""
+    lib = _load_par()
+    labels = np.ascontiguousarray(labels)
+    if labels.dtype not in (np.uint8, np.uint16, np.uint32):
+        raise TypeError("labels must be uint8, uint16 or uint32")
+    if labels.ndim != 3:
+        raise ValueError("extract_par takes a volume (O, N, M)")
+    O, N, M = labels.shape
+    sel = np.ascontiguousarray(np.asarray(selected, dtype=np.uint32).reshape(-1))
+    h = lib.orc_extract_par(_p(labels), labels.dtype.itemsize, M, N, O,
+                            _p(sel) if sel.size else None, int(sel.size), int(background),
+                            int(threads))
+    if not h:
+        raise MemoryError("oracle extraction failed")
+    sizes = np.zeros(4, dtype=np.int64)
+    lib.orc_mesh_sizes(h, _p(sizes))
+    P, Q, S = (int(x) for x in sizes[:3])
+    cell_of = np.empty(P, dtype=np.int64)
+    quads = np.empty((Q, 4), dtype=np.int32)
+    pairs = np.empty((Q, 2), dtype=np.uint32)
+    st_off = np.empty(P + 1, dtype=np.int64)
+    st_ids = np.empty(S, dtype=np.int32)
+    lib.orc_mesh_copy(h, _p(cell_of), _p(quads), _p(pairs), _p(st_off), _p(st_ids))
+    _load()  # centres() and smooth() of the mesh use the serial library
+    return OracleMesh((M, N, O), cell_of, quads, pairs, st_off, st_ids, h, True)
 
 
 def extract2d(labels: np.ndarray, selected=(), background: int = 0) -> OracleMesh:
