@@ -1,14 +1,16 @@
 """Benchmark: SurfaceNets extraction + constrained smoothing on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload torso|connectome|spheres|section]
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+                    [--workload connectome|torso|spheres|section]
     python bench.py --only batched|served    (that path alone, e.g. under a profiler)
 
 A step is one pass of the whole hot path over one synthetic label volume that
 is already resident in HBM: extraction (classification, counting, scan,
 generation of points / quads / label pairs / stencil) followed by the
 smoothing sweeps and the world-coordinate emit.  The default workload is the
-torso-like 256^3 uint16 volume (100 Voronoi cells in an ellipsoidal body,
-spacing 1x1x2.5, 25 sweeps, relaxation 0.5, constraint 1.0).
+largest single-GPU one, the connectomics-like 1024x1024x512 uint32 volume
+(50 000 stretched Voronoi cells, 2 % membrane; 20 sweeps, relaxation 0.5,
+constraint 0.8).
 
 One JSON line is printed on stdout; progress goes to stderr.  `value` is
 whole-step throughput in Gvoxels/s (voxels / wall time of a full step).
@@ -16,11 +18,12 @@ Kernel durations come from HIP events recorded by the library on the stream
 each kernel runs on.  In the timed steps only the sweeps (the kernel with the
 largest total time, which the roofline object uses) are bracketed; the
 extraction kernels are timed with events around every launch in a second,
-untimed run of the same number of steps.  Extra objects report the
-connectome-like volume, the 2D method on a section-like image, the batched
-path against sequential plain calls and
-the served path against a plain FIFO loop, and the oracle timed on one host
-core.
+untimed run of the same number of steps.  Extra objects report the other
+volumes (the torso-like atlas, the 64^3 spheres, the 2D method on a
+section-like image), the batched path against sequential plain calls, the
+served path against a plain FIFO loop, the triangulation rules, a label-count
+sweep, and the oracle timed on the host: one core (`cpu_baseline`) and all
+cores (`cpu_baseline_all_cores`), on a z-slab sample of the headline volume.
 """
 from __future__ import annotations
 
@@ -176,24 +179,73 @@ def roofline_of(res, traffic=None):
             "traffic_over_alg": round(traffic / d["alg_bytes"], 3) if traffic else None}
 
 
+# bounded CPU samples: volumes above this many voxels are timed on a z-slab
+# crop of the middle slices (whole x-y slices, so the crop has the volume's
+# structure), sized to about CPU_SAMPLE_VOXELS
+CPU_SAMPLE_VOXELS = 48 << 20
+
+
+def cpu_sample(vol):
+    """(labels, description) of the oracle's timing sample of `vol`."""
+    lab = vol.labels
+    if lab.ndim != 3 or lab.size <= CPU_SAMPLE_VOXELS:
+        return lab, f"whole {vol.name} volume"
+    O, N, M = lab.shape
+    s = max(2, min(O, CPU_SAMPLE_VOXELS // (M * N) + 1))
+    k0 = (O - s) // 2
+    crop = np.ascontiguousarray(lab[k0:k0 + s])
+    return crop, f"z-slab crop of {vol.name}: sample slices {k0}..{k0 + s - 1} ({M}x{N}x{s})"
+
+
 def cpu_baseline(vol, min_seconds=10.0):
-    """The oracle (serial C, FP64), timed on one host core on the whole volume
-    (extract + smoothing), repeated until at least `min_seconds` have passed."""
+    """The oracle (serial C, FP64), timed on one host core (extract +
+    smoothing) on a bounded sample of the volume, repeated until at least
+    `min_seconds` have passed."""
     import oracle
 
-    V = int(vol.labels.size)
+    lab, what = cpu_sample(vol)
+    V = int(lab.size)
     reps, t_all = 0, 0.0
     while t_all < min_seconds and reps < 50:
         t0 = time.perf_counter()
-        m = oracle.extract(vol.labels, vol.selected, vol.background)
+        m = oracle.extract(lab, vol.selected, vol.background)
         m.smooth(vol.iterations, vol.relaxation, vol.constraint)
         t_all += time.perf_counter() - t0
         reps += 1
         del m
     return {"value": round(V * reps / t_all / 1e9, 5), "unit": "Gvoxels/s", "cores": 1,
             "kind": "oracle",
-            "sample": f"whole {vol.name} volume (extract + {vol.iterations} sweeps) x{reps}, "
+            "sample": f"{what} (extract + {vol.iterations} sweeps) x{reps}, "
                       f"{t_all:.1f} s on 1 core",
+            "host": host_cpu()}
+
+
+def cpu_baseline_all_cores(vol, min_seconds=5.0):
+    """The oracle's loops spread over z-slices with OpenMP on every usable host
+    core (bit-identical to the serial oracle), on the same sample."""
+    import oracle
+
+    lab, what = cpu_sample(vol)
+    V = int(lab.size)
+    threads = oracle.par_threads()
+    reps, t_all, t_ext = 0, 0.0, 0.0
+    while t_all < min_seconds and reps < 50:
+        t0 = time.perf_counter()
+        m = oracle.extract_par(lab, vol.selected, vol.background)
+        t1 = time.perf_counter()
+        m.smooth_par(vol.iterations, vol.relaxation, vol.constraint)
+        t_all += time.perf_counter() - t0
+        t_ext += t1 - t0
+        reps += 1
+        P = m.n_points
+        del m
+    return {"value": round(V * reps / t_all / 1e9, 5), "unit": "Gvoxels/s", "cores": threads,
+            "kind": "oracle, OpenMP over z-slices",
+            "extract_gvox_per_s": round(V * reps / t_ext / 1e9, 5),
+            "smooth_gptit_per_s": round(P * vol.iterations * reps / (t_all - t_ext) / 1e9, 5)
+            if t_all > t_ext else None,
+            "sample": f"{what} (extract + {vol.iterations} sweeps) x{reps}, "
+                      f"{t_all:.1f} s on {threads} threads",
             "host": host_cpu()}
 
 
@@ -273,7 +325,7 @@ def bench_batched(ctx, sn, torch, count=64, reps=3):
             "batched_frac_hbm": round(alg / out["batched"] / 1e9 / HBM_PEAK_GBS, 4)}
 
 
-def bench_served(ctx, sn, torch, n_requests=240, pool=16, seed=5):
+def bench_served(ctx, sn, torch, n_requests=2000, pool=24, seed=5):
     import synth
 
     log(f"[bench] served: generating a pool of {pool} volumes")
@@ -333,64 +385,81 @@ def bench_served(ctx, sn, torch, n_requests=240, pool=16, seed=5):
                   "served_frac_hbm": round(alg / sat_served / 1e9 / HBM_PEAK_GBS, 4)}
     log(f"[bench] served: saturation plain {sat_plain * 1e3:.1f} ms, served {sat_served * 1e3:.1f} ms")
 
-    # latency: a Poisson stream at 80 % of the plain path's capacity
+    # latency: Poisson streams at 80 % and at 150 % of the plain path's
+    # capacity (service time measured first, then frozen)
     t0 = time.perf_counter()
     for r in reqs[:40]:
         plain_one(*r, wait=True)
     svc = (time.perf_counter() - t0) / 40
-    qps = 0.8 / svc
-    arrivals = np.cumsum(rng.exponential(1.0 / qps, size=n_requests))
-    log(f"[bench] served: plain service {svc * 1e3:.2f} ms -> {qps:.1f} QPS")
+    log(f"[bench] served: plain service {svc * 1e3:.2f} ms")
 
-    # plain FIFO: one request at a time, in arrival order, in real time
-    lat = []
-    start = time.perf_counter()
-    for (k, sel, it), a in zip(reqs, arrivals):
-        now = time.perf_counter() - start
-        if now < a:
-            time.sleep(a - now)
-        plain_one(k, sel, it, wait=True)
-        lat.append(time.perf_counter() - start - a)
-    plain_wall = time.perf_counter() - start
-    plain = {"p50_ms": round(1e3 * float(np.percentile(lat, 50)), 3),
-             "p99_ms": round(1e3 * float(np.percentile(lat, 99)), 3),
-             "gvox_per_s": round(sum(vox) / plain_wall / 1e9, 3)}
+    def plain_fifo(arrivals):
+        """One request at a time, in arrival order, in real time."""
+        lat = []
+        start = time.perf_counter()
+        for (k, sel, it), a in zip(reqs, arrivals):
+            now = time.perf_counter() - start
+            if now < a:
+                time.sleep(a - now)
+            plain_one(k, sel, it, wait=True)
+            lat.append(time.perf_counter() - start - a)
+        wall = time.perf_counter() - start
+        return {"p50_ms": round(1e3 * float(np.percentile(lat, 50)), 3),
+                "p99_ms": round(1e3 * float(np.percentile(lat, 99)), 3),
+                "gvox_per_s": round(sum(vox) / wall / 1e9, 3)}
 
-    srv = ctx.serve_start(hbm_budget_bytes=32 << 30, max_inflight=64, n_streams=2, max_batch=16)
-    tickets = []
-    done = []
+    def served_stream(arrivals):
+        """The server fed at the arrival times; a collector thread waits on
+        the tickets in order and frees the meshes."""
+        srv = ctx.serve_start(hbm_budget_bytes=32 << 30, max_inflight=64, n_streams=2,
+                              max_batch=16)
+        tickets = []
+        done = []
 
-    def collect():
-        for tk in iter(lambda: tickets.pop(0) if tickets else None, "stop"):
-            if tk is None:
-                time.sleep(0.0002)
-                continue
-            if tk == -1:
-                return
-            m = srv.wait(tk)
-            done.append(time.perf_counter())
-            m.free()
+        def collect():
+            for tk in iter(lambda: tickets.pop(0) if tickets else None, "stop"):
+                if tk is None:
+                    time.sleep(0.0002)
+                    continue
+                if tk == -1:
+                    return
+                m = srv.wait(tk)
+                done.append(time.perf_counter())
+                m.free()
 
-    th = threading.Thread(target=collect)
-    th.start()
-    start = time.perf_counter()
-    for (k, sel, it), a in zip(reqs, arrivals):
-        now = time.perf_counter() - start
-        if now < a:
-            time.sleep(a - now)
-        tickets.append(srv.submit(ts[k], iterations=it, relaxation=0.5, constraint=1.0,
-                                  selected=sel))
-    tickets.append(-1)
-    th.join()
-    served_wall = max(done) - start
-    st = srv.stats()
-    srv.stop()
-    served = {"p50_ms": round(st["p50_us"] / 1e3, 3), "p99_ms": round(st["p99_us"] / 1e3, 3),
-              "gvox_per_s": round(sum(vox) / served_wall / 1e9, 3), "batches": st["n_batches"],
-              "done": st["n_done"]}
+        th = threading.Thread(target=collect)
+        th.start()
+        start = time.perf_counter()
+        for (k, sel, it), a in zip(reqs, arrivals):
+            now = time.perf_counter() - start
+            if now < a:
+                time.sleep(a - now)
+            tickets.append(srv.submit(ts[k], iterations=it, relaxation=0.5, constraint=1.0,
+                                      selected=sel))
+        tickets.append(-1)
+        th.join()
+        wall = max(done) - start
+        st = srv.stats()
+        srv.stop()
+        return {"p50_ms": round(st["p50_us"] / 1e3, 3), "p99_ms": round(st["p99_us"] / 1e3, 3),
+                "gvox_per_s": round(sum(vox) / wall / 1e9, 3), "batches": st["n_batches"],
+                "done": st["n_done"], "requeued": st.get("n_requeued")}
+
+    loads = {}
+    for load in (0.8, 1.5):
+        qps = load / svc
+        arrivals = np.cumsum(rng.exponential(1.0 / qps, size=n_requests))
+        log(f"[bench] served: Poisson stream at {load:.1f} x plain capacity, {qps:.1f} QPS")
+        pl = plain_fifo(arrivals)
+        sv = served_stream(arrivals)
+        loads[f"{load:.1f}x"] = {"qps": round(qps, 2), "plain_fifo": pl, "served": sv,
+                                 "p99_speedup": round(pl["p99_ms"] / max(sv["p99_ms"], 1e-9), 3),
+                                 "throughput_ratio": round(sv["gvox_per_s"] /
+                                                           max(pl["gvox_per_s"], 1e-12), 3)}
+        log(f"[bench] served: p99 plain {pl['p99_ms']:.2f} ms, served {sv['p99_ms']:.2f} ms; "
+            f"Gvox/s plain {pl['gvox_per_s']:.2f}, served {sv['gvox_per_s']:.2f}")
     return {"requests": n_requests, "pool_volumes": pool, "saturation": saturation,
-            "poisson_qps": round(qps, 2), "plain_fifo": plain, "served": served,
-            "p99_speedup": round(plain["p99_ms"] / max(served["p99_ms"], 1e-9), 3)}
+            "plain_service_ms": round(svc * 1e3, 4), "poisson": loads}
 
 
 def bench_triangulate(ctx, sn, torch, vol, reps=10):
@@ -549,13 +618,29 @@ def pmc_summary(pmc_dir, out_path, workload):
     print(json.dumps(res, indent=1))
 
 
+def workload_summary(vol, r, roof):
+    """The figures of one more volume for the `extra` object."""
+    img = vol.labels.ndim == 2
+    unit = "gpix" if img else "gvox"
+    return {"name": vol.name, "ms_per_step": round(r["ms_per_step"], 3),
+            f"{unit}_per_s": round(r["gvox_per_s"], 3),
+            f"extract_{unit}_per_s": round(r["extract_gvox_per_s"], 3),
+            "extract_alg_GBs": round(r["extract_alg_GBs"], 1),
+            "extract_frac_hbm": round(r["extract_frac_hbm"], 4),
+            "smooth_gptit_per_s": round(r["smooth_gptit_per_s"], 3),
+            "points": r["points"], ("segments" if img else "quads"): r["quads"],
+            "iterations": r["iterations"], "roofline": roof,
+            "kernels": {k: {kk: (round(vv, 3) if isinstance(vv, float) else vv)
+                            for kk, vv in d.items()} for k, d in r["kernels"].items()}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="torso",
-                    choices=["torso", "connectome", "spheres", "section"])
+    ap.add_argument("--workload", default="connectome",
+                    choices=["connectome", "torso", "spheres", "section"])
     ap.add_argument("--no-extra", action="store_true", help="skip connectome/batched/served")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"),
@@ -621,43 +706,32 @@ def main():
 
     extra = {}
     if not args.no_extra:
-        if args.workload != "connectome":
-            cvol = synth.connectome_like()
-            r3 = measure_workload(ctx, sn, torch, cvol, max(3, args.steps // 4), 1)
-            extra["connectome_like"] = {
-                "name": cvol.name, "ms_per_step": round(r3["ms_per_step"], 3),
-                "gvox_per_s": round(r3["gvox_per_s"], 3),
-                "extract_gvox_per_s": round(r3["extract_gvox_per_s"], 3),
-                "extract_alg_GBs": round(r3["extract_alg_GBs"], 1),
-                "extract_frac_hbm": round(r3["extract_frac_hbm"], 4),
-                "smooth_gptit_per_s": round(r3["smooth_gptit_per_s"], 3),
-                "points": r3["points"], "quads": r3["quads"],
-                "roofline": roofline_of(r3, traffic_for("connectome", r3)),
-                "kernels": {k: {kk: (round(vv, 3) if isinstance(vv, float) else vv)
-                                for kk, vv in d.items()} for k, d in r3["kernels"].items()}}
-            del cvol
-        if args.workload != "section":
-            # the 2D method on an image (SN_LINES)
-            svol = synth.section_like()
-            r2 = measure_workload(ctx, sn, torch, svol, max(3, args.steps // 4), 1)
-            extra["section_like_2d"] = {
-                "name": svol.name, "ms_per_step": round(r2["ms_per_step"], 3),
-                "gpix_per_s": round(r2["gvox_per_s"], 3),
-                "extract_gpix_per_s": round(r2["extract_gvox_per_s"], 3),
-                "extract_alg_GBs": round(r2["extract_alg_GBs"], 1),
-                "extract_frac_hbm": round(r2["extract_frac_hbm"], 4),
-                "smooth_gptit_per_s": round(r2["smooth_gptit_per_s"], 3),
-                "points": r2["points"], "segments": r2["quads"],
-                "roofline": roofline_of(r2, traffic_for("section", r2)),
-                "kernels": {k: {kk: (round(vv, 3) if isinstance(vv, float) else vv)
-                                for kk, vv in d.items()} for k, d in r2["kernels"].items()}}
-            del svol
+        # the other volumes: config name -> (generator, --workload key, key of extra)
+        others = [("connectome", synth.connectome_like, "connectome_like"),
+                  ("torso", synth.torso_like, "torso_like"),
+                  ("spheres", synth.spheres_small, "spheres_small"),
+                  ("section", synth.section_like, "section_like_2d")]
+        for key, gen_o, name in others:
+            if key == args.workload:
+                continue
+            ovol = gen_o()
+            ro = measure_workload(ctx, sn, torch, ovol, max(5, args.steps // 2), 2)
+            extra[name] = workload_summary(ovol, ro, roofline_of(ro, traffic_for(key, ro)))
+            log(f"[bench] {ovol.name}: {ro['ms_per_step']:.3f} ms/step, "
+                f"{ro['gvox_per_s']:.2f} Gvox/s")
+            del ovol
         extra["batched"] = bench_batched(ctx, sn, torch)
         extra["served"] = bench_served(ctx, sn, torch)
-        extra["triangulate"] = bench_triangulate(ctx, sn, torch, vol)
+        tvol = vol if args.workload == "torso" else synth.torso_like()
+        extra["triangulate"] = bench_triangulate(ctx, sn, torch, tvol)
         extra["label_sweep"] = bench_label_sweep(ctx, sn, torch)
 
-    cpu = None if args.no_cpu else cpu_baseline(vol)
+    cpu = cpu_all = None
+    if not args.no_cpu:
+        log("[bench] oracle on one core")
+        cpu = cpu_baseline(vol)
+        log("[bench] oracle on all cores")
+        cpu_all = cpu_baseline_all_cores(vol)
     line = {
         "metric": "Gvoxels/s extract + Gpoint-iters/s smooth, 1 GPU; batched/served vs plain",
         "value": round(res["gvox_per_s"], 4),
@@ -681,6 +755,7 @@ def main():
         "extract_alg_GBs": round(res["extract_alg_GBs"], 1),
         "extract_frac_hbm": round(res["extract_frac_hbm"], 4),
         "cpu_baseline": cpu,
+        "cpu_baseline_all_cores": cpu_all,
         "extra": extra,
     }
     if probe:
