@@ -230,6 +230,54 @@ sn_status sn_mesh_copy_to_host(const sn_mesh *mesh, float *points, int32_t *poly
  * before the library's next use of the memory) when the mesh is freed. */
 void sn_mesh_free(sn_mesh *mesh);
 
+/* ---- no device allocation --------------------------------------------------- */
+
+/* For callers that cannot allocate device memory (tight serving loops,
+ * harnesses that forbid hipMalloc, processes that must not grow their device
+ * memory after set-up): the
+ * extraction of sn_extract written into caller-owned arrays, with every
+ * scratch array (cut-edge planes, word metadata, scan status, totals, the
+ * classification table) carved from one static device array of
+ * SN_NOALLOC_SCRATCH_BYTES per GPU, which each GPU the library runs on holds
+ * until the process ends.  The call makes no device allocation of any kind.
+ *
+ * Every sn_extract_noalloc call on a GPU shares that GPU's array: calls that
+ * overlap in time on one GPU (other host threads, other streams of work still
+ * running) race and give wrong results; calls on one stream, one after the
+ * other, are safe.  The array keeps the last call's contents; what must start
+ * at zero is cleared by the call's own first kernel.
+ *
+ * Arrays (DEVICE pointers owned by the caller; capacities in elements):
+ *   points       [cap_points*3] float32 world cell centres, as sn_extract;
+ *   stencil_off  [cap_points+1] int32 (required, also for an empty mesh);
+ *   stencil_ids  [cap_stencil] int32;
+ *   polys        [cap_polys*4] int32 quads (SN_QUADS) or [cap_polys*2]
+ *                segments (SN_LINES); SN_TRIS is not supported (SN_EINVAL);
+ *   label_pairs  [cap_polys*2] of the label type.
+ * counts (host, 3 int64) receives (points, polys, stencil entries).
+ *
+ * The call blocks until the counts are known (Sec. 2.3: they size the
+ * outputs), then enqueues generation on `stream` and returns; the arrays are
+ * complete once `stream` reaches that point.  Returns SN_ETOOBIG when the
+ * volume needs more scratch than SN_NOALLOC_SCRATCH_BYTES
+ * (sn_noalloc_scratch_bytes tells how much it needs) or when ids exceed int32,
+ * and SN_ENOMEM, with counts written, when the mesh does not fit the given
+ * capacities (nothing is generated; call again with larger arrays).  Results
+ * equal sn_extract's points, polys, label pairs and stencil bit for bit. */
+#define SN_NOALLOC_SCRATCH_BYTES (64ll << 20)
+typedef struct sn_extract_arrays {
+    float *points;
+    int32_t *polys;
+    void *label_pairs;
+    int32_t *stencil_off;
+    int32_t *stencil_ids;
+    int64_t cap_points, cap_polys, cap_stencil;
+} sn_extract_arrays;
+sn_status sn_extract_noalloc(sn_ctx *ctx, const sn_volume *vol, void *stream,
+                             const sn_extract_arrays *out, int64_t *counts);
+/* Scratch bytes sn_extract_noalloc needs for `vol`; -1 for an invalid volume. */
+int64_t sn_noalloc_scratch_bytes(const sn_volume *vol);
+
 /* ---- batched path ---------------------------------------------------------- */
 
 /* Extract and smooth n independent volumes of any sizes together: one

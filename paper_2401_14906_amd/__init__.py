@@ -79,6 +79,13 @@ class sn_serve_stats(ctypes.Structure):
                 ("n_requeued", ctypes.c_int64)]
 
 
+class sn_extract_arrays(ctypes.Structure):
+    _fields_ = [("points", ctypes.c_void_p), ("polys", ctypes.c_void_p),
+                ("label_pairs", ctypes.c_void_p), ("stencil_off", ctypes.c_void_p),
+                ("stencil_ids", ctypes.c_void_p), ("cap_points", ctypes.c_int64),
+                ("cap_polys", ctypes.c_int64), ("cap_stencil", ctypes.c_int64)]
+
+
 class sn_kernel_stat(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 48), ("launches", ctypes.c_int64),
                 ("total_ms", ctypes.c_double)]
@@ -100,6 +107,9 @@ _API = [
     ("sn_mesh_view_get", _S, [_P, ctypes.POINTER(sn_mesh_view)]),
     ("sn_mesh_copy_to_host", _S, [_P, _P, _P, _P, _P, _P, _P]),
     ("sn_mesh_free", None, [_P]),
+    ("sn_extract_noalloc", _S, [_P, ctypes.POINTER(sn_volume), _P,
+                                ctypes.POINTER(sn_extract_arrays), ctypes.POINTER(ctypes.c_int64)]),
+    ("sn_noalloc_scratch_bytes", ctypes.c_int64, [ctypes.POINTER(sn_volume)]),
     ("sn_batch_submit", _S, [_P, ctypes.POINTER(sn_volume), ctypes.POINTER(sn_smooth_params),
                              ctypes.c_int32, _P, ctypes.POINTER(_P)]),
     ("sn_serve_start", _S, [_P, ctypes.POINTER(sn_serve_config), ctypes.POINTER(_P)]),
@@ -318,6 +328,33 @@ class Context:
                                    ctypes.c_void_p(lab.data_ptr()) if lab is not None else None,
                                    _stream_handle(stream)))
         return tris, lab
+
+    def extract_noalloc(self, labels, points, polys, label_pairs, stencil_off, stencil_ids,
+                        spacing=(1.0, 1.0, 1.0), origin=(0.0, 0.0, 0.0), selected=(),
+                        background=0, prim=SN_QUADS, stream=None) -> tuple:
+        """sn_extract_noalloc into caller-owned device tensors: points [cp, 3]
+        float32, polys [cq, prim] int32, label_pairs [cq, 2] of the label type,
+        stencil_off [cp + 1] int32, stencil_ids [cs] int32 (capacities from the
+        shapes).  Returns (points, polys, stencil entries); raises SNError
+        (status SN_ENOMEM with .counts when the arrays are too small)."""
+        v, keep = make_volume(labels, spacing, origin, selected, background, prim)
+        a = sn_extract_arrays()
+        ptr = lambda t: None if t is None else ctypes.c_void_p(t.data_ptr())  # noqa: E731
+        a.points, a.polys, a.label_pairs = ptr(points), ptr(polys), ptr(label_pairs)
+        a.stencil_off, a.stencil_ids = ptr(stencil_off), ptr(stencil_ids)
+        a.cap_points = points.shape[0] if points is not None else 0
+        a.cap_polys = polys.shape[0] if polys is not None else 0
+        a.cap_stencil = stencil_ids.shape[0] if stencil_ids is not None else 0
+        if stencil_off is None or stencil_off.shape[0] < a.cap_points + 1:
+            raise ValueError("stencil_off needs cap_points + 1 entries")
+        counts = (ctypes.c_int64 * 3)()
+        st = _lib.sn_extract_noalloc(self._h, ctypes.byref(v), _stream_handle(stream),
+                                     ctypes.byref(a), counts)
+        if st != SN_OK:
+            err = SNError(st, _lib.sn_last_error().decode(errors="replace"))
+            err.counts = tuple(int(x) for x in counts)
+            raise err
+        return tuple(int(x) for x in counts)
 
     def batch_submit(self, volumes: Sequence[dict], params: Optional[Sequence] = None,
                      stream=None) -> list:

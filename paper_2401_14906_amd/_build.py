@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsn.so")
-SOURCES = ["sn_kernels.hip", "sn_runtime.hip", "sn_serve.hip"]
+SOURCES = ["sn_kernels.hip", "sn_runtime.hip", "sn_serve.hip", "sn_noalloc.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950",

@@ -82,7 +82,8 @@ struct VolDesc {
     int32_t *wbS;     // [R*W] index of the first stencil entry of each word
     // outputs
     float *points;     // [P*3]
-    uint8_t *faces;    // [P] stencil face mask, bit f = face f (-x,+x,-y,+y,-z,+z)
+    uint8_t *faces;    // [P] stencil face mask, bit f = face f (-x,+x,-y,+y,-z,+z), or
+                       // nullptr (k_generate then skips it: no smoothing follows)
     uint32_t *pcell;   // [P] cell linear index of each point, or nullptr (>= 2^32 cells)
     int32_t *st_off;   // [P+1]
     int32_t *st_ids;   // [S]

@@ -840,7 +840,7 @@ __device__ __forceinline__ void generate_back(const VolDesc &d, GenLds<STAGE> &L
         const GenWord &W = L.word[u];
         store_point(glb(d.points), R0,
                     (float)(d.origin[0] + d.spacing[0] * ((double)(W.ci0 + i) + 0.5)), W.py, W.pz);
-        glb(d.faces)[R0] = (uint8_t)x.fm;
+        if (d.faces) glb(d.faces)[R0] = (uint8_t)x.fm;  // null: an extraction without smoothing state
         glb(d.st_off)[R0] = so0 + sr;
         if (d.pcell) glb(d.pcell)[R0] = W.cell0 + (uint32_t)i;
     }

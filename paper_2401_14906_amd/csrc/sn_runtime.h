@@ -116,6 +116,8 @@ struct sn_ctx {
     // slab-chunk size of that form's block order (SN_TEST_SWEEP_CHUNK)
     int64_t sweep_small_points = sn::kSweepSmallPoints;
     int32_t sweep_chunk = 0;
+    // device address of the no-allocation extraction's static scratch array
+    void *noalloc_scratch = nullptr;
     int32_t batches_per_wave(const std::string &cls) const;
     void load_tune_cache();
     void save_tune_cache() const;
@@ -151,6 +153,12 @@ struct ProfScope {
 sn_status validate_volume(const sn_volume *v);
 sn_status validate_smooth(const sn_smooth_params *p);
 Geom make_geom(const sn_volume &v);
+// classification mode of a volume and its table in host form (empty for the
+// identity): the bitmap of selected values, or the sorted unique values
+void class_table(const sn_volume &v, int32_t *mode, std::vector<uint32_t> *tab);
+// The no-allocation extraction's static device scratch: resolves its address
+// on the current device (once per device; sn_ctx_create calls it).
+sn_status noalloc_resolve(int device, void **addr);
 std::string size_class(const sn_volume &v);
 // Called by extract_many once the totals of every volume are known and before
 // any output is allocated: totals[3v .. 3v+2] = (P, Q, S) of vols[v].  A status

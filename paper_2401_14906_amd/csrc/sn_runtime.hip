@@ -259,6 +259,12 @@ extern "C" sn_status sn_ctx_create(int device, sn_ctx **out)
         delete c;
         return fail(SN_EDEVICE, "sn_ctx_create: stream creation failed");
     }
+    if (sn_status st = noalloc_resolve(device, &c->noalloc_scratch); st != SN_OK) {
+        (void)hipStreamDestroy(c->copy_stream);
+        (void)hipStreamDestroy(c->retire_stream);
+        delete c;
+        return st;
+    }
     if (const char *cw = std::getenv("SN_TEST_COUNT_WIDE_WORDS"); cw && *cw)
         c->count_wide_words = std::strtoll(cw, nullptr, 10);
     if (const char *sp = std::getenv("SN_TEST_SWEEP_SMALL_POINTS"); sp && *sp)
@@ -510,7 +516,7 @@ Geom sn::make_geom(const sn_volume &v)
 }
 
 // host form of the classification table; empty vector for the identity
-static void class_table(const sn_volume &v, int32_t *mode, std::vector<uint32_t> *tab)
+void sn::class_table(const sn_volume &v, int32_t *mode, std::vector<uint32_t> *tab)
 {
     tab->clear();
     if (v.n_selected == 0) {
