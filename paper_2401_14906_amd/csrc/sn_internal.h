@@ -140,6 +140,15 @@ struct SmoothDesc {
     // streams and offset stores take non-temporal hints, and a single mesh
     // takes the slab-chunked block order
     int32_t big;
+    // neighbour-table form.  0: [P][4] int32 ids of the -y, +y, -z, +z
+    // neighbours (-1 absent), read with the face byte.  Otherwise one 64-bit
+    // word per point: bits 0-1 the -x / +x face bits, then the id distances
+    // |p - q| of the -y and +y neighbours in pack_yb bits each and of the -z
+    // and +z neighbours in pack_zb bits each (0 = absent; a neighbour is
+    // never the point itself), 8 bytes per point instead of 17.  Used when
+    // the largest distances fit: cells per row for y, cells per slice for z
+    // (pack_yb + pack_zb <= 31, both >= 1).
+    int32_t pack_yb, pack_zb;
     double origin[3], spacing[3];
 };
 

@@ -1344,6 +1344,42 @@ __device__ __forceinline__ v4i stencil_yz(const SmoothDesc &s, uint32_t f, int64
     return q;
 }
 
+// The packed neighbour word of point p (SmoothDesc::pack_yb > 0): face bits
+// -x, +x and the id distances of the y/z neighbours q (ids of -y, +y, -z,
+// +z, -1 where absent).
+__device__ __forceinline__ uint64_t pack_nbr(const SmoothDesc &s, uint32_t f, int64_t p, v4i q)
+{
+    const uint32_t yb = (uint32_t)s.pack_yb, zb = (uint32_t)s.pack_zb;
+    uint64_t w = f & 3u;
+    w |= (uint64_t)(q.x >= 0 ? p - q.x : 0) << 2;
+    w |= (uint64_t)(q.y >= 0 ? q.y - p : 0) << (2 + yb);
+    w |= (uint64_t)(q.z >= 0 ? p - q.z : 0) << (2 + 2 * yb);
+    w |= (uint64_t)(q.w >= 0 ? q.w - p : 0) << (2 + 2 * yb + zb);
+    return w;
+}
+
+// Face mask and y/z neighbour ids of point p from its packed word.
+__device__ __forceinline__ void unpack_nbr(const SmoothDesc &s, uint64_t w, int64_t p, uint32_t &f,
+                                           v4i &q)
+{
+    const uint32_t yb = (uint32_t)s.pack_yb, zb = (uint32_t)s.pack_zb;
+    const uint64_t ym = (1ull << yb) - 1, zm = (1ull << zb) - 1;
+    const int32_t a = (int32_t)((w >> 2) & ym), b = (int32_t)((w >> (2 + yb)) & ym);
+    const int32_t c = (int32_t)((w >> (2 + 2 * yb)) & zm), d = (int32_t)((w >> (2 + 2 * yb + zb)) & zm);
+    const int32_t pi = (int32_t)p;
+    f = ((uint32_t)w & 3u) | (a ? 4u : 0u) | (b ? 8u : 0u) | (c ? 16u : 0u) | (d ? 32u : 0u);
+    q = v4i{a ? pi - a : -1, b ? pi + b : -1, c ? pi - c : -1, d ? pi + d : -1};
+}
+
+// Write point p's entry of the neighbour table in the mesh's form.
+__device__ __forceinline__ void store_nbr(const SmoothDesc &s, uint32_t f, int64_t p, v4i q)
+{
+    if (s.pack_yb)
+        glb(reinterpret_cast<uint64_t *>(s.nbr))[p] = pack_nbr(s, f, p, q);
+    else
+        glb(reinterpret_cast<v4i *>(s.nbr))[p] = q;
+}
+
 // Sweep 0: every input offset is zero, so p_q - p_p is the face step alone.
 // Reads the CSR stencil once and writes the y/z neighbour table.
 // Blocks of a sweep launch that carry points: a launch over many meshes has
@@ -1405,7 +1441,7 @@ __device__ __forceinline__ void jacobi_first_body(const Src &a, int64_t block0)
         const int64_t p = (b - first) * (kSweepBlock * K) + c * kSweepBlock + threadIdx.x;
         if (p >= s.P) break;
         const uint32_t f = glb(s.faces)[p];
-        glb(reinterpret_cast<v4i *>(s.nbr))[p] = stencil_yz(s, f, p);
+        store_nbr(s, f, p, stencil_yz(s, f, p));
         const float zero[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
         double x = 0.0, y = 0.0, z = 0.0;
         sweep_update(s, f, zero, zero, zero, x, y, z);
@@ -1459,7 +1495,12 @@ __device__ __forceinline__ float readlane_f(float x, int l)
 // the table through their face bytes instead of from an offset buffer; it
 // also builds the neighbour table from the CSR stencil.  The result equals
 // the two separate sweeps bit for bit.
-template <int K, bool FUSED, class Src>
+// BIG: 1 for a single mesh whose sweep data is far beyond the caches (its
+// read-once streams are loaded and its offsets stored with non-temporal
+// hints), 0 for one that is not, -1 to decide per mesh at run time (a launch
+// over many meshes).  A compile-time choice keeps the non-temporal loads from
+// being merged with the ordinary ones of the other branch.
+template <int K, bool FUSED, int BIG, class Src>
 __device__ __forceinline__ void jacobi_body(const Src &a, int32_t it)
 {
     const uint32_t nbl = sweep_blocks<K>(a);
@@ -1487,6 +1528,7 @@ __device__ __forceinline__ void jacobi_body(const Src &a, int32_t it)
 
     // the mesh's last sweep also writes world points from the cell indices
     const bool last = it == s.iters - 1 && s.pcell;
+    const bool big = BIG < 0 ? s.big != 0 : BIG == 1;
     uint32_t f[K], cell[K];
     v4i nb[K];
     float ox[K], oy[K], oz[K];
@@ -1498,17 +1540,29 @@ __device__ __forceinline__ void jacobi_body(const Src &a, int32_t it)
             if constexpr (FUSED) {
                 f[c] = glb(s.faces)[p];
                 nb[c] = stencil_yz(s, f[c], p);
-                glb(reinterpret_cast<v4i *>(s.nbr))[p] = nb[c];
+                store_nbr(s, f[c], p, nb[c]);
                 ox[c] = s_first[3 * f[c]], oy[c] = s_first[3 * f[c] + 1], oz[c] = s_first[3 * f[c] + 2];
             } else {
-                if (s.big) {  // large meshes: read-once streams
+                // own offset first: it is in flight while the table word is
+                // awaited for the neighbour ids
+                ox[c] = din[3 * p], oy[c] = din[3 * p + 1], oz[c] = din[3 * p + 2];
+                if (s.pack_yb) {  // one 8-byte word: face bits and id distances
+                    const SN_GLOBAL uint64_t *nw = glb(reinterpret_cast<const uint64_t *>(s.nbr));
+                    uint64_t w;
+                    if constexpr (BIG == 1)
+                        w = __builtin_nontemporal_load(nw + p);
+                    else if constexpr (BIG == 0)
+                        w = nw[p];
+                    else
+                        w = big ? __builtin_nontemporal_load(nw + p) : nw[p];
+                    unpack_nbr(s, w, p, f[c], nb[c]);
+                } else if (big) {  // large meshes: read-once streams
                     f[c] = __builtin_nontemporal_load(glb(s.faces) + p);
                     nb[c] = __builtin_nontemporal_load(nbr + p);
                 } else {
                     f[c] = glb(s.faces)[p];
                     nb[c] = nbr[p];
                 }
-                ox[c] = din[3 * p], oy[c] = din[3 * p + 1], oz[c] = din[3 * p + 2];
             }
             if (last) cell[c] = glb(s.pcell)[p];
         }
@@ -1592,7 +1646,7 @@ __device__ __forceinline__ void jacobi_body(const Src &a, int32_t it)
             y = y + s.lam * (sy * inv);
             z = z + s.lam * (sz * inv);
         }
-        if (s.big)  // large meshes: streaming stores
+        if (big)  // large meshes: streaming stores
             store_offset<true>(s, dout, p, x, y, z, last, cell[c]);
         else
             store_offset<false>(s, dout, p, x, y, z, last, cell[c]);
@@ -1604,13 +1658,13 @@ __global__ __launch_bounds__(kSweepBlock) void k_jacobi(const SmoothDesc *__rest
                                                 const int64_t *__restrict__ prefix, int32_t nvol,
                                                 int32_t it)
 {
-    jacobi_body<K, false>(ManySmooth{sds, prefix, nvol}, it);
+    jacobi_body<K, false, -1>(ManySmooth{sds, prefix, nvol}, it);
 }
 
-template <int K>
+template <int K, int BIG>
 __global__ __launch_bounds__(kSweepBlock) void k_jacobi_one(OneSmooth a, int32_t it)
 {
-    jacobi_body<K, false>(a, it);
+    jacobi_body<K, false, BIG>(a, it);
 }
 
 // Sweeps 0 and 1 in one launch (meshes of at least two sweeps; in a launch
@@ -1619,7 +1673,7 @@ __global__ __launch_bounds__(kSweepBlock) void k_jacobi_one(OneSmooth a, int32_t
 template <int K>
 __global__ __launch_bounds__(kSweepBlock) void k_jacobi_first2_one(OneSmooth a)
 {
-    jacobi_body<K, true>(a, 1);
+    jacobi_body<K, true, -1>(a, 1);
 }
 
 template <int K>
@@ -1627,7 +1681,7 @@ __global__ __launch_bounds__(kSweepBlock) void k_jacobi_first2(const SmoothDesc 
                                                        const int64_t *__restrict__ prefix,
                                                        int32_t nvol)
 {
-    jacobi_body<K, true>(ManySmooth{sds, prefix, nvol}, 1);
+    jacobi_body<K, true, -1>(ManySmooth{sds, prefix, nvol}, 1);
 }
 
 // ---------------------------------------------------------------------------
@@ -1937,9 +1991,12 @@ static void jacobi_one_k(const SmoothDesc &sd, int64_t nblocks, int32_t it, hipS
     if (it == 0)
         hipLaunchKernelGGL(k_jacobi_first_one<K>, dim3((uint32_t)nblocks), dim3(kSweepBlock), 0, s,
                            OneSmooth{sd});
+    else if (sd.big)
+        hipLaunchKernelGGL((k_jacobi_one<K, 1>), dim3((uint32_t)nblocks), dim3(kSweepBlock), 0, s,
+                           OneSmooth{sd}, it);
     else
-        hipLaunchKernelGGL(k_jacobi_one<K>, dim3((uint32_t)nblocks), dim3(kSweepBlock), 0, s, OneSmooth{sd},
-                           it);
+        hipLaunchKernelGGL((k_jacobi_one<K, 0>), dim3((uint32_t)nblocks), dim3(kSweepBlock), 0, s,
+                           OneSmooth{sd}, it);
 }
 
 hipError_t launch_jacobi(const SmoothDesc *d_sd, const int64_t *d_block_prefix, int32_t nvol,

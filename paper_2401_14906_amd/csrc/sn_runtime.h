@@ -116,6 +116,9 @@ struct sn_ctx {
     // slab-chunk size of that form's block order (SN_TEST_SWEEP_CHUNK)
     int64_t sweep_small_points = sn::kSweepSmallPoints;
     int32_t sweep_chunk = 0;
+    // SN_TEST_SWEEP_UNPACKED: every mesh keeps the 16-byte neighbour table
+    // (the form of meshes whose id distances do not fit the packed word)
+    bool sweep_unpacked = false;
     // device address of the no-allocation extraction's static scratch array
     void *noalloc_scratch = nullptr;
     int32_t batches_per_wave(const std::string &cls) const;

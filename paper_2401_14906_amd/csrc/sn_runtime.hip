@@ -269,6 +269,8 @@ extern "C" sn_status sn_ctx_create(int device, sn_ctx **out)
         c->count_wide_words = std::strtoll(cw, nullptr, 10);
     if (const char *sp = std::getenv("SN_TEST_SWEEP_SMALL_POINTS"); sp && *sp)
         c->sweep_small_points = std::max<int64_t>(0, std::strtoll(sp, nullptr, 10));
+    if (const char *su = std::getenv("SN_TEST_SWEEP_UNPACKED"); su && *su)
+        c->sweep_unpacked = std::strtoll(su, nullptr, 10) != 0;
     if (const char *sc = std::getenv("SN_TEST_SWEEP_CHUNK"); sc && *sc)
         c->sweep_chunk = (int32_t)std::min<int64_t>(std::max<int64_t>(0, std::strtoll(sc, nullptr, 10)),
                                                     int64_t(1) << 20);
@@ -1160,6 +1162,16 @@ static void fill_smooth_desc(const sn_mesh *m, const sn_smooth_params &p, Smooth
     sd->chunk = (int32_t)std::max<int64_t>(1, (per_slab + 8) / 16);
     if (m->ctx->sweep_chunk > 0) sd->chunk = m->ctx->sweep_chunk;
     sd->big = m->P > m->ctx->sweep_small_points ? 1 : 0;
+    // packed neighbour table when the id distances fit: at most a row of
+    // cells for y neighbours, a slice for z (an image has no z neighbours)
+    auto bits = [](int64_t v) {
+        int32_t b = 0;
+        while (b < 63 && (int64_t(1) << b) <= v) ++b;
+        return std::max<int32_t>(b, 1);
+    };
+    const bool image = m->d.prim == SN_LINES;
+    const int32_t yb = bits(m->d.g.CM), zb = image ? 1 : bits(m->d.g.CM * m->d.g.CN);
+    if (yb + zb <= 31 && !m->ctx->sweep_unpacked) sd->pack_yb = yb, sd->pack_zb = zb;
 }
 
 // Sweeps over `nvol` meshes (descriptor array), replayed from a HIP graph of

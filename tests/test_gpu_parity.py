@@ -397,3 +397,50 @@ def test_extreme_aspect_ratios(ctx, sn, torch):
         if o.n_points:
             ref = o.smooth(6, 0.7, 0.8, shape="sphere") - o.centres()
             assert np.max(np.abs(g.offsets.astype(np.float64) - ref)) <= TOL
+
+
+@pytest.mark.parametrize("form", ["knob", "wide"])
+def test_unpacked_neighbour_table(sn, torch, monkeypatch, form):
+    """The sweeps keep the 16-byte neighbour table (ids plus the face byte)
+    when a mesh's id distances do not fit the packed 8-byte word: forced by
+    the context knob SN_TEST_SWEEP_UNPACKED on tiny volumes, the spheres
+    configuration and a batch, and reached naturally by a volume whose rows
+    (4095 cells) and slices (4095 x 129 cells) need 12 + 20 distance bits.
+    Everything against the oracle; the batch equals the plain results."""
+    import oracle
+
+    rng = np.random.default_rng(81)
+    if form == "knob":
+        monkeypatch.setenv("SN_TEST_SWEEP_UNPACKED", "1")
+        cases = [(synth.blocky_tiny(rng, (37, 29, 23), 5, np.uint16), (21, 0.5, 1.0)),
+                 (synth.random_tiny(rng, (65, 9, 14), 4, np.uint8), (7, 1.0, 0.6)),
+                 (synth.spheres_small().labels, (16, 0.5, 1.0))]
+    else:
+        cases = [(synth.blocky_tiny(rng, (4096, 130, 3), 6, np.uint16), (12, 0.5, 0.8))]
+    c = sn.Context(0)
+    monkeypatch.delenv("SN_TEST_SWEEP_UNPACKED", raising=False)
+    try:
+        plain = []
+        for k, (lab, (it, lam, d)) in enumerate(cases):
+            announce(f"unpacked table ({form}) case {k}: dims={lab.shape[::-1]} {(it, lam, d)}")
+            t = sn.to_device(lab)
+            m = c.extract(t)
+            c.smooth(m, iterations=it, relaxation=lam, constraint=d)
+            g = m.to_host()
+            m.free()
+            o = oracle.extract(lab)
+            check_mesh(g, o, lab.dtype)
+            check_smooth(g, o, it, lam, d)
+            plain.append(g)
+        if len(cases) > 1:
+            announce(f"unpacked table ({form}): the cases as one batch")
+            ts = [sn.to_device(lab) for lab, _ in cases]
+            ms = c.batch_submit([dict(labels=t) for t in ts], [p for _, p in cases])
+            for k, m in enumerate(ms):
+                g = m.to_host()
+                m.free()
+                for f in ("points", "offsets", "polys", "label_pairs", "stencil_off",
+                          "stencil_ids"):
+                    assert np.array_equal(getattr(g, f), getattr(plain[k], f)), (k, f)
+    finally:
+        c.close()
