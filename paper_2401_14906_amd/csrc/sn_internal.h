@@ -64,7 +64,16 @@ struct Geom {
     int32_t NB;    // batches per cell row
     int64_t WS;    // words per sample row
     int64_t NSEG;  // 256-sample segments per sample row
+    int32_t RSH;   // log2 of the sample rows sharing one segment: 2 for rows of
+                   // at most 64 samples, 1 for at most 128, else 0
 };
+
+// k_edges segments of a volume: NSEG per sample row, or one per 2^RSH rows
+__host__ __device__ inline int64_t edge_segments(const Geom &g)
+{
+    const int64_t rows = g.N * g.O;
+    return g.RSH ? (rows + (int64_t(1) << g.RSH) - 1) >> g.RSH : rows * g.NSEG;
+}
 
 // Everything the word kernels need for one volume.
 struct VolDesc {

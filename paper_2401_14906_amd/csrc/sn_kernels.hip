@@ -346,8 +346,13 @@ constexpr int kSegPerWave = 4;  // 256-sample segments per wave
 typedef uint32_t v4u __attribute__((ext_vector_type(4)));
 typedef uint32_t v2u __attribute__((ext_vector_type(2)));
 
+// dword vectors at 4-byte alignment (the narrow rows' windows)
+typedef uint32_t v2u_a4 __attribute__((ext_vector_type(2), aligned(4)));
+typedef uint32_t v3u_a4 __attribute__((ext_vector_type(3), aligned(4)));
+typedef uint32_t v4u_a4 __attribute__((ext_vector_type(4), aligned(4)));
+
 template <typename T, bool WIDE>
-__device__ __forceinline__ void load_quad(const T *row_, int32_t i0, int32_t M1, T (&v)[4])
+__device__ __forceinline__ void load_quad(const T *row_, int32_t i0, int32_t M1, const T *vol_end, T (&v)[4])
 {
     const SN_GLOBAL T *row = glb(row_);
     if constexpr (WIDE) {
@@ -366,8 +371,41 @@ __device__ __forceinline__ void load_quad(const T *row_, int32_t i0, int32_t M1,
             v[3] = (T)(q >> 24);
         }
     } else {
+        // rows of any alignment: the dword-aligned window holding samples
+        // i0 .. i0+3, in one load (2, 3 or 4 dwords for 1-, 2- or 4-byte
+        // labels), then the samples cut out of it; values of samples past
+        // the row end are never used (they read the next row).  Only where
+        // the window would pass the end of the volume are the samples read
+        // one by one, clamped to the row.
+        if (i0 > M1) {
 #pragma unroll
-        for (int e = 0; e < 4; ++e) v[e] = row[(uint32_t)(i0 + e <= M1 ? i0 + e : M1)];
+            for (int e = 0; e < 4; ++e) v[e] = 0;
+            return;
+        }
+        constexpr int ND = sizeof(T) == 1 ? 2 : (sizeof(T) == 2 ? 3 : 4);
+        const uintptr_t a = reinterpret_cast<uintptr_t>(row_ + i0);
+        const uintptr_t ab = a & ~uintptr_t(3);
+        if (ab + 4 * ND <= reinterpret_cast<uintptr_t>(vol_end)) {
+            const SN_GLOBAL uint32_t *wp = reinterpret_cast<const SN_GLOBAL uint32_t *>(ab);
+            const uint32_t sh = (uint32_t)(a & 3u);
+            if constexpr (sizeof(T) == 1) {
+                const v2u_a4 q = *reinterpret_cast<const SN_GLOBAL v2u_a4 *>(wp);
+                const uint32_t x = __builtin_amdgcn_alignbyte(q.y, q.x, sh);
+                v[0] = (T)(x & 0xffu), v[1] = (T)((x >> 8) & 0xffu), v[2] = (T)((x >> 16) & 0xffu),
+                v[3] = (T)(x >> 24);
+            } else if constexpr (sizeof(T) == 2) {
+                const v3u_a4 q = *reinterpret_cast<const SN_GLOBAL v3u_a4 *>(wp);
+                const uint32_t x0 = __builtin_amdgcn_alignbyte(q.y, q.x, sh);
+                const uint32_t x1 = __builtin_amdgcn_alignbyte(q.z, q.y, sh);
+                v[0] = (T)(x0 & 0xffffu), v[1] = (T)(x0 >> 16), v[2] = (T)(x1 & 0xffffu), v[3] = (T)(x1 >> 16);
+            } else {
+                const v4u_a4 q = *reinterpret_cast<const SN_GLOBAL v4u_a4 *>(wp);
+                v[0] = (T)q.x, v[1] = (T)q.y, v[2] = (T)q.z, v[3] = (T)q.w;
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) v[e] = row[(uint32_t)(i0 + e <= M1 ? i0 + e : M1)];
+        }
     }
 }
 
@@ -388,19 +426,37 @@ __device__ __forceinline__ void edges_segment(const VolDesc &d, int64_t seg, int
 {
     const Geom &g = d.g;
     const uint32_t NSEG = (uint32_t)g.NSEG, N = (uint32_t)g.N;
-    const uint32_t srow = (uint32_t)seg / NSEG;
-    const int32_t m = (int32_t)((uint32_t)seg - srow * NSEG);
+    // rows of at most 64 or 128 samples share a segment (4 or 2 rows, 16 or
+    // 32 lanes each), so that short rows do not leave most lanes idle; every
+    // group of 16 lanes still covers one 64-sample word of one row
+    const uint32_t rsh = (uint32_t)g.RSH;
+    uint32_t srow;
+    int32_t m, i0;
+    bool rowok = true;
+    if (rsh == 0) {
+        srow = (uint32_t)seg / NSEG;
+        m = (int32_t)((uint32_t)seg - srow * NSEG);
+        i0 = 256 * m + 4 * lane;
+    } else {
+        const uint32_t lpr = 64u >> rsh;  // lanes per row
+        srow = ((uint32_t)seg << rsh) + ((uint32_t)lane >> (6u - rsh));
+        m = 0;
+        i0 = 4 * (int32_t)((uint32_t)lane & (lpr - 1u));
+        rowok = srow < N * (uint32_t)g.O;
+    }
     const int32_t j = (int32_t)(srow % N), k = (int32_t)(srow / N);
     const int32_t M1 = (int32_t)(g.M - 1);
-    const int32_t i0 = 256 * m + 4 * lane;
     const T *ra = static_cast<const T *>(d.labels) + (int64_t)srow * g.M;
-    const bool hasy = j + 1 < (int32_t)g.N, hasz = k + 1 < (int32_t)g.O;
-    T a[4], b[4] = {0, 0, 0, 0}, c[4] = {0, 0, 0, 0};
-    load_quad<T, WIDE>(ra, i0, M1, a);
-    if (hasy) load_quad<T, WIDE>(ra + g.M, i0, M1, b);
-    if (hasz) load_quad<T, WIDE>(ra + g.M * g.N, i0, M1, c);
+    const bool hasy = rowok && j + 1 < (int32_t)g.N, hasz = rowok && k + 1 < (int32_t)g.O;
+    T a[4] = {0, 0, 0, 0}, b[4] = {0, 0, 0, 0}, c[4] = {0, 0, 0, 0};
+    const T *vend = static_cast<const T *>(d.labels) + g.M * g.N * g.O;
+    if (rowok) load_quad<T, WIDE>(ra, i0, M1, vend, a);
+    if (hasy) load_quad<T, WIDE>(ra + g.M, i0, M1, vend, b);
+    if (hasz) load_quad<T, WIDE>(ra + g.M * g.N, i0, M1, vend, c);
+    // the sample after the segment (read by lane 63 for the last x edge; a
+    // shared segment's rows end inside it)
     T an = 0;
-    if (lane == 63) an = glb(ra)[(uint32_t)(256 * (m + 1) <= M1 ? 256 * (m + 1) : M1)];
+    if (lane == 63 && rsh == 0) an = glb(ra)[(uint32_t)(256 * (m + 1) <= M1 ? 256 * (m + 1) : M1)];
     uint32_t ca[5], cb[4], cc[4];
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
@@ -408,6 +464,8 @@ __device__ __forceinline__ void edges_segment(const VolDesc &d, int64_t seg, int
         cb[e] = classify<MODE>((uint32_t)b[e], d.cs);
         cc[e] = classify<MODE>((uint32_t)c[e], d.cs);
     }
+    // from the next lane; across a row boundary of a shared segment it is
+    // never used (the row ends before the lane's last sample)
     ca[4] = __shfl_down(ca[0], 1u);
     if (lane == 63) ca[4] = classify<MODE>((uint32_t)an, d.cs);
     uint32_t xn = 0, yn = 0, zn = 0;
@@ -419,8 +477,8 @@ __device__ __forceinline__ void edges_segment(const VolDesc &d, int64_t seg, int
         zn |= (hasz && (ca[e] != cc[e]) && i <= M1 ? 1u : 0u) << e;
     }
     const uint64_t X = merge_nibbles(xn, lane), Y = merge_nibbles(yn, lane), Z = merge_nibbles(zn, lane);
-    const int64_t wi = 4 * (int64_t)m + (lane >> 4);
-    if ((lane & 15) == 0 && wi < g.WS) {
+    const int64_t wi = rsh == 0 ? 4 * (int64_t)m + (lane >> 4) : (int64_t)(i0 >> 6);
+    if ((lane & 15) == 0 && wi < g.WS && rowok) {
         SN_GLOBAL uint64_t *P = glb(d.planes);
         const int64_t ps = (int64_t)g.N * g.O * g.WS;
         const int64_t o = (int64_t)srow * g.WS + wi;
@@ -443,7 +501,7 @@ __device__ __forceinline__ void edges_tile(const Src &a, int64_t tile_base, uint
     int64_t first;
     const VolDesc &d = vol_of(a, t, v, first);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
-    const int64_t nseg = d.g.N * d.g.O * d.g.NSEG;
+    const int64_t nseg = edge_segments(d.g);
     int64_t seg = (t - first) * (kWavesPerBlock * kSegPerWave) + (int64_t)wave * kSegPerWave;
     for (int q = 0; q < kSegPerWave; ++q, ++seg) {
         if (seg >= nseg) break;

@@ -151,7 +151,7 @@ extern "C" sn_status sn_extract_noalloc(sn_ctx *c, const sn_volume *vol, void *s
 
     int64_t tot[4] = {0, 0, 0, 0};
     const bool wide = vol->dims[0] % 4 == 0 && (reinterpret_cast<uintptr_t>(vol->labels) & 15) == 0;
-    const int64_t nseg = d.g.N * d.g.O * d.g.NSEG;
+    const int64_t nseg = edge_segments(d.g);
     const int64_t etiles = (nseg + kSegmentsPerTile - 1) / kSegmentsPerTile;
     if (nctiles > 0) {
         {

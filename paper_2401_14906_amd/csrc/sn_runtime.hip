@@ -514,6 +514,7 @@ Geom sn::make_geom(const sn_volume &v)
     g.NB = (g.W + kU - 1) / kU;
     g.WS = empty ? 0 : (g.M + 63) / 64;
     g.NSEG = empty ? 0 : (g.M + 255) / 256;
+    g.RSH = empty ? 0 : (g.M <= 64 ? 2 : (g.M <= 128 ? 1 : 0));
     return g;
 }
 
@@ -929,7 +930,7 @@ sn_status sn::extract_many(sn_ctx *c, const sn_volume *vols, int32_t n, hipStrea
         m->ntiles = std::max<int64_t>(1, (nbatch + TB - 1) / TB);  // k_emit
         const int64_t ngroups = (words + kGenWords - 1) / kGenWords;
         tile_prefix[k + 1] = tile_prefix[k] + std::max<int64_t>(1, (ngroups + TB - 1) / TB);
-        const int64_t nseg = d.g.N * d.g.O * d.g.NSEG;
+        const int64_t nseg = edge_segments(d.g);
         etile_prefix[k + 1] = etile_prefix[k] + (nseg + kSegmentsPerTile - 1) / kSegmentsPerTile;
         ctile_prefix[k + 1] = words;  // words for now; tiles below
         m->voxels = vol.dims[0] * vol.dims[1] * vol.dims[2];
