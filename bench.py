@@ -107,10 +107,11 @@ def measure_workload(ctx, sn, torch, vol, steps, warmup):
     t = sn.to_device(vol.labels)
     b = vol.labels.dtype.itemsize
     V = int(vol.labels.size)
-    # the schedule of the extraction kernels is picked by the library's
-    # autotuner for this size class (untimed, like the warm-up steps)
+    # the kernels' schedule is picked by the library's autotuner for this
+    # size class (untimed, like the warm-up steps)
     bpw = ctx.autotune(t, spacing=vol.spacing)
-    log(f"[bench] {vol.name}: autotuned batches per wave {bpw}; warmup {warmup}")
+    sched = ctx.schedule_get(t)
+    log(f"[bench] {vol.name}: autotuned schedule {sched}; warmup {warmup}")
     run_plain_steps(ctx, sn, torch, t, vol, warmup)
     # timed steps: HIP events bracket the sweeps (the dominant kernel, whose
     # launch time the roofline uses) and nothing else
@@ -152,6 +153,7 @@ def measure_workload(ctx, sn, torch, vol, steps, warmup):
     res = {
         "voxels": V, "points": P, "quads": Q, "stencil": S, "iterations": n,
         "batches_per_wave": bpw,
+        "schedule": sched,
         "ms_per_step": 1e3 * wall / steps,
         "gvox_per_s": V * steps / wall / 1e9,
         "extract_kernel_ms": ext_ms,
@@ -629,7 +631,7 @@ def workload_summary(vol, r, roof):
             "extract_frac_hbm": round(r["extract_frac_hbm"], 4),
             "smooth_gptit_per_s": round(r["smooth_gptit_per_s"], 3),
             "points": r["points"], ("segments" if img else "quads"): r["quads"],
-            "iterations": r["iterations"], "roofline": roof,
+            "iterations": r["iterations"], "schedule": r["schedule"], "roofline": roof,
             "kernels": {k: {kk: (round(vv, 3) if isinstance(vv, float) else vv)
                             for kk, vv in d.items()} for k, d in r["kernels"].items()}}
 
@@ -745,7 +747,7 @@ def main():
                    "labels": "all", "prim": "lines" if vol.labels.ndim == 2 else "quads",
                    "iterations": vol.iterations,
                    "relaxation": vol.relaxation, "constraint": vol.constraint,
-                   "batches_per_wave": res["batches_per_wave"]},
+                   "schedule": res["schedule"]},
         "extract_gvox_per_s": round(res["extract_gvox_per_s"], 3),
         "smooth_gptit_per_s": round(res["smooth_gptit_per_s"], 3),
         "mesh": {"points": res["points"], "quads": res["quads"], "stencil": res["stencil"]},

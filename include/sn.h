@@ -347,12 +347,35 @@ sn_status sn_serve_stop(sn_server *srv);
 
 /* ---- schedule tuning and profiling ----------------------------------------- */
 
-/* Time the candidate schedules (work items per wavefront in the generation
- * kernels: groups of 32 cell words in k_generate, batches of 4 words in k_emit)
- * for the volume's size class on this device and remember the fastest for it
- * (also written to SN_AUTOTUNE_CACHE if set).  Untuned classes use 1.  Returns
- * the chosen count (called batches-per-wave in this interface). */
+/* Pick the schedule (sn_schedule below) for the volume's size class on this
+ * device by timing: one knob at a time, with the others at their best so far,
+ * over the k_edges segments per wave (1, 2, 4, 8), the k_count form (1 or 4
+ * words per thread), the k_generate groups per wave (1, 2, 3, 4, 8), and, when
+ * the volume's mesh takes the large-mesh sweep form, the block-order chunk
+ * (half, once and twice the default; four sweeps timed each).  The choice is
+ * remembered for the class (and written to SN_AUTOTUNE_CACHE if set).
+ * `chosen`, if not NULL, receives the k_generate groups per wave (called
+ * batches-per-wave in this interface). */
 sn_status sn_autotune(sn_ctx *ctx, const sn_volume *vol, void *stream, int32_t *chosen);
+/* A schedule of the kernels for one size class of volumes (the label type,
+ * and the powers of two of the row length and of the number of cell rows).
+ * Results never depend on it. */
+typedef struct sn_schedule {
+    int32_t gen_groups;    /* k_generate: groups of 32 cell words per wave, and k_emit:
+                              batches of 4 words per wave (1..16; 1 untuned)            */
+    int32_t count_words;   /* k_count: cell words per thread, 1 or 4 (0, untuned: 4 from
+                              2^18 words in a launch, else 1)                          */
+    int32_t edge_segments; /* k_edges: 256-sample segments per wave (1..16; 4 untuned) */
+    int32_t sweep_chunk;   /* the sweeps of a mesh of more than 2^24 points: blocks each
+                              XCD takes in turn in the slab-chunked order (0, untuned:
+                              about a sixteenth of a slab's blocks)                    */
+} sn_schedule;
+/* The schedule the context uses for volumes of vol's size class (tuned, set,
+ * loaded from SN_AUTOTUNE_CACHE, or the untuned one). */
+sn_status sn_schedule_get(sn_ctx *ctx, const sn_volume *vol, sn_schedule *out);
+/* Use `in` for vol's size class from now on; SN_EINVAL for a value out of
+ * range.  sn_autotune overwrites it. */
+sn_status sn_schedule_set(sn_ctx *ctx, const sn_volume *vol, const sn_schedule *in);
 /* Force the batches-per-wave schedule of the generation kernels (1..16) for
  * every later launch on this context; 0 returns to the tuned/default choice.
  * Results do not depend on the schedule. */

@@ -86,6 +86,11 @@ class sn_extract_arrays(ctypes.Structure):
                 ("cap_polys", ctypes.c_int64), ("cap_stencil", ctypes.c_int64)]
 
 
+class sn_schedule(ctypes.Structure):
+    _fields_ = [("gen_groups", ctypes.c_int32), ("count_words", ctypes.c_int32),
+                ("edge_segments", ctypes.c_int32), ("sweep_chunk", ctypes.c_int32)]
+
+
 class sn_kernel_stat(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 48), ("launches", ctypes.c_int64),
                 ("total_ms", ctypes.c_double)]
@@ -121,6 +126,8 @@ _API = [
     ("sn_serve_stop", _S, [_P]),
     ("sn_autotune", _S, [_P, ctypes.POINTER(sn_volume), _P, ctypes.POINTER(ctypes.c_int32)]),
     ("sn_set_batches_per_wave", _S, [_P, ctypes.c_int32]),
+    ("sn_schedule_get", _S, [_P, ctypes.POINTER(sn_volume), ctypes.POINTER(sn_schedule)]),
+    ("sn_schedule_set", _S, [_P, ctypes.POINTER(sn_volume), ctypes.POINTER(sn_schedule)]),
     ("sn_profile_enable", _S, [_P, ctypes.c_int]),
     ("sn_profile_reset", _S, [_P]),
     ("sn_profile_read", _S, [_P, ctypes.POINTER(sn_kernel_stat), ctypes.c_int32,
@@ -391,6 +398,22 @@ class Context:
 
     def set_batches_per_wave(self, bpw: int):
         _check(_lib.sn_set_batches_per_wave(self._h, int(bpw)))
+
+    def schedule_get(self, labels, prim=SN_QUADS) -> dict:
+        """The kernel schedule used for volumes of this one's size class."""
+        v, keep = make_volume(labels, prim=prim)
+        sc = sn_schedule()
+        _check(_lib.sn_schedule_get(self._h, ctypes.byref(v), ctypes.byref(sc)))
+        return {f: int(getattr(sc, f)) for f, _ in sn_schedule._fields_}
+
+    def schedule_set(self, labels, prim=SN_QUADS, **fields):
+        """Set the kernel schedule of this volume's size class (the fields of
+        sn_schedule; those not given keep their current values)."""
+        cur = self.schedule_get(labels, prim)
+        cur.update({k: int(x) for k, x in fields.items()})
+        v, keep = make_volume(labels, prim=prim)
+        sc = sn_schedule(**cur)
+        _check(_lib.sn_schedule_set(self._h, ctypes.byref(v), ctypes.byref(sc)))
 
     def profile(self, on=True):
         """on: False/0 off, True/1 events per launch (a smoothing call's sweeps as a

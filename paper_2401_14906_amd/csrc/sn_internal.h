@@ -38,7 +38,23 @@ constexpr int32_t kPrimLines = 2;
 constexpr int kWavesPerBlock = 4;
 constexpr int kBlock = 64 * kWavesPerBlock;
 constexpr int kMaxBatchesPerWave = 16;
-constexpr int kSegmentsPerTile = 16;  // k_edges: 4 waves x 4 segments of 256 samples
+// k_edges: a wave takes 1..kMaxSegmentsPerWave segments of 256 samples (the
+// schedule's edge_segments), a tile kWavesPerBlock times that
+constexpr int kMaxSegmentsPerWave = 16;
+// A schedule of the kernels for one size class of volumes.  Results never
+// depend on it; sn_autotune picks it by timing.
+struct Schedule {
+    int32_t gen_groups = 1;   // k_generate: groups of 32 words per wave; k_emit: batches per wave
+    int32_t count_words = 0;  // k_count: words per thread, 1 or kCountWideV (0: by size)
+    int32_t edge_segs = 4;    // k_edges: 256-sample segments per wave
+    int32_t sweep_chunk = 0;  // a large single mesh's slab-chunked block order: blocks an
+                              // XCD takes in turn (0: about a sixteenth of a slab)
+};
+inline int64_t edge_tiles(int64_t segments, int32_t spw)
+{
+    const int64_t t = (int64_t)kWavesPerBlock * spw;
+    return (segments + t - 1) / t;
+}
 // k_generate: a wave takes groups of kGenWords consecutive words (any rows),
 // bpw groups per wave
 constexpr int kGenWords = 32;
@@ -200,7 +216,7 @@ constexpr uint64_t kValMask = (1ull << 62) - 1;
 //               as for k_edges.
 hipError_t launch_edges(int32_t dtype, int32_t mode, bool wide, const VolDesc *d_descs,
                         const int64_t *d_tile_prefix, int32_t nvol, int64_t tile_base,
-                        int64_t ntiles, uint64_t *d_zero, int64_t nzero, hipStream_t s);
+                        int64_t ntiles, uint64_t *d_zero, int64_t nzero, int32_t spw, hipStream_t s);
 // Where k_count leaves each volume's totals (P, Q, S) for the host: the last
 // tile of volume v writes totals[3v..3v+2] and then, after a system-scope
 // fence, stamps[v] = seq (host-visible memory; seq differs between calls).
@@ -237,7 +253,7 @@ hipError_t add_jacobi_nodes(hipGraph_t graph, const SmoothDesc *d_sd,
 // Single-volume forms: the descriptor travels by value in the kernel
 // arguments (no upload, no prefix array; tiles and blocks start at 0).
 hipError_t launch_edges_one(const VolDesc &d, bool wide, int64_t ntiles, uint64_t *d_zero,
-                            int64_t nzero, hipStream_t s);
+                            int64_t nzero, int32_t spw, hipStream_t s);
 hipError_t launch_count_one(const VolDesc &d, int64_t ntiles, int32_t words_per_thread,
                             uint64_t *d_status, uint32_t *d_ticket, const CountOut &out, hipStream_t s);
 hipError_t launch_generate_one(const VolDesc &d, bool staged, int64_t ntiles, int32_t bpw, hipStream_t s);

@@ -341,7 +341,6 @@ __device__ __forceinline__ int32_t wave_incl_scan_dpp(int32_t v, int lane)
 // into 64-bit words across 16 lanes.
 // ---------------------------------------------------------------------------
 
-constexpr int kSegPerWave = 4;  // 256-sample segments per wave
 
 typedef uint32_t v4u __attribute__((ext_vector_type(4)));
 typedef uint32_t v2u __attribute__((ext_vector_type(2)));
@@ -488,9 +487,11 @@ __device__ __forceinline__ void edges_segment(const VolDesc &d, int64_t seg, int
     }
 }
 
+// spw: 256-sample segments per wave (the schedule's edge_segments); a tile is
+// kWavesPerBlock * spw segments
 template <typename T, int MODE, bool WIDE, class Src>
 __device__ __forceinline__ void edges_tile(const Src &a, int64_t tile_base, uint64_t *zero,
-                                           int64_t nzero)
+                                           int64_t nzero, int32_t spw)
 {
     // clear the scan status words of the counting pass that follows
     for (int64_t z = (int64_t)blockIdx.x * kBlock + threadIdx.x; z < nzero;
@@ -502,8 +503,8 @@ __device__ __forceinline__ void edges_tile(const Src &a, int64_t tile_base, uint
     const VolDesc &d = vol_of(a, t, v, first);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int64_t nseg = edge_segments(d.g);
-    int64_t seg = (t - first) * (kWavesPerBlock * kSegPerWave) + (int64_t)wave * kSegPerWave;
-    for (int q = 0; q < kSegPerWave; ++q, ++seg) {
+    int64_t seg = (t - first) * (kWavesPerBlock * spw) + (int64_t)wave * spw;
+    for (int q = 0; q < spw; ++q, ++seg) {
         if (seg >= nseg) break;
         edges_segment<T, MODE, WIDE>(d, seg, lane);
     }
@@ -513,30 +514,32 @@ template <typename T, int MODE>
 __global__ __launch_bounds__(kBlock) void k_edges_wide(const VolDesc *__restrict__ descs,
                                                        const int64_t *__restrict__ prefix,
                                                        int32_t nvol, int64_t tile_base,
-                                                       uint64_t *zero, int64_t nzero)
+                                                       uint64_t *zero, int64_t nzero, int32_t spw)
 {
-    edges_tile<T, MODE, true>(ManyVols{descs, prefix, nvol}, tile_base, zero, nzero);
+    edges_tile<T, MODE, true>(ManyVols{descs, prefix, nvol}, tile_base, zero, nzero, spw);
 }
 
 template <typename T, int MODE>
 __global__ __launch_bounds__(kBlock) void k_edges_narrow(const VolDesc *__restrict__ descs,
                                                          const int64_t *__restrict__ prefix,
                                                          int32_t nvol, int64_t tile_base,
-                                                         uint64_t *zero, int64_t nzero)
+                                                         uint64_t *zero, int64_t nzero, int32_t spw)
 {
-    edges_tile<T, MODE, false>(ManyVols{descs, prefix, nvol}, tile_base, zero, nzero);
+    edges_tile<T, MODE, false>(ManyVols{descs, prefix, nvol}, tile_base, zero, nzero, spw);
 }
 
 template <typename T, int MODE>
-__global__ __launch_bounds__(kBlock) void k_edges_wide_one(OneVol a, uint64_t *zero, int64_t nzero)
+__global__ __launch_bounds__(kBlock) void k_edges_wide_one(OneVol a, uint64_t *zero, int64_t nzero,
+                                                           int32_t spw)
 {
-    edges_tile<T, MODE, true>(a, 0, zero, nzero);
+    edges_tile<T, MODE, true>(a, 0, zero, nzero, spw);
 }
 
 template <typename T, int MODE>
-__global__ __launch_bounds__(kBlock) void k_edges_narrow_one(OneVol a, uint64_t *zero, int64_t nzero)
+__global__ __launch_bounds__(kBlock) void k_edges_narrow_one(OneVol a, uint64_t *zero, int64_t nzero,
+                                                             int32_t spw)
 {
-    edges_tile<T, MODE, false>(a, 0, zero, nzero);
+    edges_tile<T, MODE, false>(a, 0, zero, nzero, spw);
 }
 
 // ---------------------------------------------------------------------------
@@ -1922,30 +1925,30 @@ hipError_t launch_tri_rule(int32_t rule, int32_t dtype, const int32_t *quads, co
 
 hipError_t launch_edges(int32_t dtype, int32_t mode, bool wide, const VolDesc *d_descs,
                         const int64_t *d_tile_prefix, int32_t nvol, int64_t tile_base,
-                        int64_t ntiles, uint64_t *d_zero, int64_t nzero, hipStream_t s)
+                        int64_t ntiles, uint64_t *d_zero, int64_t nzero, int32_t spw, hipStream_t s)
 {
     if (ntiles <= 0) return hipSuccess;
     if (wide) {
         SN_KEY_SWITCH(k_edges_wide, dim3((uint32_t)ntiles), dim3(kBlock), 0, s, d_descs,
-                      d_tile_prefix, nvol, tile_base, d_zero, nzero)
+                      d_tile_prefix, nvol, tile_base, d_zero, nzero, spw)
     } else {
         SN_KEY_SWITCH(k_edges_narrow, dim3((uint32_t)ntiles), dim3(kBlock), 0, s, d_descs,
-                      d_tile_prefix, nvol, tile_base, d_zero, nzero)
+                      d_tile_prefix, nvol, tile_base, d_zero, nzero, spw)
     }
     return hipGetLastError();
 }
 
 hipError_t launch_edges_one(const VolDesc &d, bool wide, int64_t ntiles, uint64_t *d_zero,
-                            int64_t nzero, hipStream_t s)
+                            int64_t nzero, int32_t spw, hipStream_t s)
 {
     if (ntiles <= 0) return hipSuccess;
     const int32_t dtype = d.dtype, mode = d.cs.mode;
     if (wide) {
         SN_KEY_SWITCH(k_edges_wide_one, dim3((uint32_t)ntiles), dim3(kBlock), 0, s, OneVol{d},
-                      d_zero, nzero)
+                      d_zero, nzero, spw)
     } else {
         SN_KEY_SWITCH(k_edges_narrow_one, dim3((uint32_t)ntiles), dim3(kBlock), 0, s, OneVol{d},
-                      d_zero, nzero)
+                      d_zero, nzero, spw)
     }
     return hipGetLastError();
 }

@@ -127,7 +127,8 @@ extern "C" sn_status sn_extract_noalloc(sn_ctx *c, const sn_volume *vol, void *s
     d.cs.n = (int32_t)tab.size();
 
     const int64_t words = d.g.R * d.g.W;
-    const int32_t cv = words >= c->count_wide_words ? kCountWideV : 1;
+    const Schedule sc = c->schedule(size_class(*vol));
+    const int32_t cv = sc.count_words > 0 ? sc.count_words : (words >= c->count_wide_words ? kCountWideV : 1);
     const int64_t nctiles = (words + cv * kCountBlock - 1) / (cv * kCountBlock);
     const NoAllocLayout l = layout(d.g, nctiles, tab.size());
     if (l.bytes > kScratchBytes)
@@ -152,11 +153,11 @@ extern "C" sn_status sn_extract_noalloc(sn_ctx *c, const sn_volume *vol, void *s
     int64_t tot[4] = {0, 0, 0, 0};
     const bool wide = vol->dims[0] % 4 == 0 && (reinterpret_cast<uintptr_t>(vol->labels) & 15) == 0;
     const int64_t nseg = edge_segments(d.g);
-    const int64_t etiles = (nseg + kSegmentsPerTile - 1) / kSegmentsPerTile;
+    const int64_t etiles = edge_tiles(nseg, sc.edge_segs);
     if (nctiles > 0) {
         {
             ProfScope ps(c, "k_edges", s);
-            HIP_TRY(launch_edges_one(d, wide, etiles, status, (int64_t)(l.nzero_bytes / 8), s));
+            HIP_TRY(launch_edges_one(d, wide, etiles, status, (int64_t)(l.nzero_bytes / 8), sc.edge_segs, s));
         }
         static std::atomic<int64_t> g_seq{0};
         const int64_t seq = g_seq.fetch_add(1, std::memory_order_relaxed) + 1;
@@ -188,7 +189,7 @@ extern "C" sn_status sn_extract_noalloc(sn_ctx *c, const sn_volume *vol, void *s
     // no smoothing state: no face bytes, no cell index per point
     d.faces = nullptr;
     d.pcell = nullptr;
-    const int32_t bpw = c->batches_per_wave(size_class(*vol));
+    const int32_t bpw = sc.gen_groups;
     const int64_t TB = kWavesPerBlock * bpw;
     const int64_t ngroups = (words + kGenWords - 1) / kGenWords;
     // at least one tile: the first writes stencil_off[P] = S

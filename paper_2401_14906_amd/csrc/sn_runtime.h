@@ -105,9 +105,10 @@ struct sn_ctx {
     std::mutex prof_mu;
     std::vector<ProfEv> prof_pending;
     std::map<std::string, std::pair<int64_t, double>> prof_stats;
-    // schedule table: size class -> batches per wave
+    // schedule table: size class -> schedule (sn_autotune, SN_AUTOTUNE_CACHE,
+    // sn_schedule_set); forced_bpw overrides every class's gen_groups
     mutable std::mutex tune_mu;
-    std::map<std::string, int32_t> tune;
+    std::map<std::string, sn::Schedule> tune;
     std::string tune_path;
     int32_t forced_bpw = 0;
     int64_t count_wide_words = sn::kCountWideWords;  // SN_TEST_COUNT_WIDE_WORDS overrides
@@ -121,7 +122,7 @@ struct sn_ctx {
     bool sweep_unpacked = false;
     // device address of the no-allocation extraction's static scratch array
     void *noalloc_scratch = nullptr;
-    int32_t batches_per_wave(const std::string &cls) const;
+    sn::Schedule schedule(const std::string &cls) const;
     void load_tune_cache();
     void save_tune_cache() const;
 };
@@ -132,6 +133,7 @@ struct sn_mesh {
     sn::VolDesc d{};            // host copy (device pointers inside)
     int64_t P = 0, Q = 0, S = 0, voxels = 0, ntiles = 0;
     int32_t bpw = 2;
+    sn::Schedule sched;  // the schedule of its extraction (and of its sweeps)
     std::vector<void *> blocks;  // every device block owned by the mesh
     float *da = nullptr, *db = nullptr;
     int32_t *nbr = nullptr;  // [P][4] y/z stencil neighbours, written by sweep 0
@@ -167,8 +169,10 @@ std::string size_class(const sn_volume &v);
 // any output is allocated: totals[3v .. 3v+2] = (P, Q, S) of vols[v].  A status
 // other than SN_OK ends the extraction with that status (no mesh).
 using AdmitFn = std::function<sn_status(const int64_t *totals)>;
+// sched: the schedule to use, or nullptr for the context's choice for the
+// largest volume's size class
 sn_status extract_many(sn_ctx *c, const sn_volume *vols, int32_t n, hipStream_t s,
-                       int32_t bpw_override, sn_mesh **out, const AdmitFn *admit = nullptr);
+                       const Schedule *sched, sn_mesh **out, const AdmitFn *admit = nullptr);
 // Device bytes, as the pool counts them (round_size per block), that an
 // extraction of v holds for the call only (cut-edge planes, quad and stencil
 // word bases, scan status, its share of the descriptor uploads), and that its
@@ -181,6 +185,8 @@ sn_status smooth_many(sn_ctx *c, sn_mesh **ms, const sn_smooth_params *pv, int32
 // the plain path of one mesh (sweeps launched one by one, descriptor by value)
 sn_status smooth_one(sn_ctx *c, sn_mesh *m, const sn_smooth_params *p, hipStream_t s);
 sn_status ensure_smooth_buffers(sn_mesh *m);
+// smoothing descriptor of a mesh for the given parameters
+void fill_smooth_desc(const sn_mesh *m, const sn_smooth_params &p, SmoothDesc *sd);
 // sweep `it` of grid.size() sweeps launches grid[it] blocks
 sn_status run_sweeps(sn_ctx *c, const SmoothDesc *d_sd, const int64_t *d_bp, int32_t nvol,
                      const std::vector<int64_t> &grid, int K, hipStream_t s);

@@ -411,34 +411,68 @@ std::string sn::size_class(const sn_volume &v)
     return os.str();
 }
 
-int32_t sn_ctx::batches_per_wave(const std::string &cls) const
+Schedule sn_ctx::schedule(const std::string &cls) const
 {
     std::lock_guard<std::mutex> g(tune_mu);
-    if (forced_bpw > 0) return forced_bpw;
+    // untuned: one k_generate group per wave, the fastest at every size
+    // measured (torso 31 us against 43-80 us, connectome 3.23 ms against
+    // 3.46-3.60 ms for 2 to 8 groups per wave), four k_edges segments per
+    // wave, the k_count form by size, the default block order
+    Schedule sc;
     auto it = tune.find(cls);
-    if (it != tune.end()) return it->second;
-    // untuned: one work item per wave, the fastest k_generate schedule at
-    // every size measured (torso 31 us against 43-80 us, connectome 3.23 ms
-    // against 3.46-3.60 ms for 2 to 8 groups per wave)
-    return 1;
+    if (it != tune.end()) sc = it->second;
+    if (forced_bpw > 0) sc.gen_groups = forced_bpw;
+    return sc;
+}
+
+static bool valid_schedule(const Schedule &s)
+{
+    return s.gen_groups >= 1 && s.gen_groups <= kMaxBatchesPerWave &&
+           (s.count_words == 0 || s.count_words == 1 || s.count_words == kCountWideV) &&
+           s.edge_segs >= 1 && s.edge_segs <= kMaxSegmentsPerWave && s.sweep_chunk >= 0 &&
+           s.sweep_chunk <= (1 << 20);
 }
 
 void sn_ctx::load_tune_cache()
 {
     std::ifstream f(tune_path);
     if (!f) return;
-    // flat JSON object {"class": batches_per_wave, ...}
+    // JSON object {"class": {"gen_groups": g, "count_words": c, "edge_segments": e,
+    // "sweep_chunk": k}, ...}; an older flat {"class": g} gives gen_groups alone
     std::string s((std::istreambuf_iterator<char>(f)), std::istreambuf_iterator<char>());
-    size_t p = 0;
+    auto field = [](const std::string &obj, const char *name, int32_t dflt) {
+        const std::string key = std::string("\"") + name + "\"";
+        const size_t p = obj.find(key);
+        if (p == std::string::npos) return dflt;
+        const size_t colon = obj.find(':', p + key.size());
+        return colon == std::string::npos ? dflt : (int32_t)std::atoi(obj.c_str() + colon + 1);
+    };
+    size_t p = s.find('{');
+    if (p == std::string::npos) return;
+    ++p;
     while ((p = s.find('"', p)) != std::string::npos) {
-        size_t q = s.find('"', p + 1);
+        const size_t q = s.find('"', p + 1);
         if (q == std::string::npos) break;
-        std::string key = s.substr(p + 1, q - p - 1);
+        const std::string key = s.substr(p + 1, q - p - 1);
         size_t colon = s.find(':', q);
         if (colon == std::string::npos) break;
-        int v = std::atoi(s.c_str() + colon + 1);
-        if (v >= 1 && v <= kMaxBatchesPerWave) tune[key] = v;
-        p = colon + 1;
+        size_t v = s.find_first_not_of(" \t\r\n", colon + 1);
+        if (v == std::string::npos) break;
+        Schedule sc;
+        if (s[v] == '{') {
+            const size_t e = s.find('}', v);
+            if (e == std::string::npos) break;
+            const std::string obj = s.substr(v, e - v + 1);
+            sc.gen_groups = field(obj, "gen_groups", 1);
+            sc.count_words = field(obj, "count_words", 0);
+            sc.edge_segs = field(obj, "edge_segments", 4);
+            sc.sweep_chunk = field(obj, "sweep_chunk", 0);
+            p = e + 1;
+        } else {
+            sc.gen_groups = (int32_t)std::atoi(s.c_str() + v);
+            p = v + 1;
+        }
+        if (valid_schedule(sc)) tune[key] = sc;
     }
 }
 
@@ -449,10 +483,13 @@ void sn_ctx::save_tune_cache() const
     f << "{";
     bool first = true;
     for (auto &kv : tune) {
-        f << (first ? "" : ", ") << "\"" << kv.first << "\": " << kv.second;
+        const Schedule &sc = kv.second;
+        f << (first ? "" : ",") << "\n \"" << kv.first << "\": {\"gen_groups\": " << sc.gen_groups
+          << ", \"count_words\": " << sc.count_words << ", \"edge_segments\": " << sc.edge_segs
+          << ", \"sweep_chunk\": " << sc.sweep_chunk << "}";
         first = false;
     }
-    f << "}\n";
+    f << "\n}\n";
 }
 
 // ---------------------------------------------------------------------------
@@ -812,7 +849,7 @@ static sn_status wait_totals(const int64_t *stamps, const std::vector<char> &cou
     } while (0)
 
 sn_status sn::extract_many(sn_ctx *c, const sn_volume *vols, int32_t n, hipStream_t s,
-                           int32_t bpw_override, sn_mesh **out, const AdmitFn *admit)
+                           const Schedule *sched, sn_mesh **out, const AdmitFn *admit)
 {
     if (!c || !vols || !out || n < 1) return fail(SN_EINVAL, "extract: bad arguments");
     for (int32_t v = 0; v < n; ++v) {
@@ -840,8 +877,8 @@ sn_status sn::extract_many(sn_ctx *c, const sn_volume *vols, int32_t n, hipStrea
         const int64_t vox = vols[v].dims[0] * vols[v].dims[1] * vols[v].dims[2];
         if (vox > big) big = vox, vb = v;
     }
-    const int32_t bpw =
-        bpw_override > 0 ? bpw_override : c->batches_per_wave(size_class(vols[vb]));
+    const Schedule sc = sched ? *sched : c->schedule(size_class(vols[vb]));
+    const int32_t bpw = sc.gen_groups;
     const int TB = kWavesPerBlock * bpw;
 
     // Volumes are processed grouped by (label type, classification mode): one
@@ -892,6 +929,7 @@ sn_status sn::extract_many(sn_ctx *c, const sn_volume *vols, int32_t n, hipStrea
         m->ctx = c;
         ctx_retain(c);
         m->bpw = bpw;
+        m->sched = sc;
         VolDesc &d = m->d;
         std::memset(&d, 0, sizeof d);
         d.labels = vol.labels;
@@ -931,7 +969,7 @@ sn_status sn::extract_many(sn_ctx *c, const sn_volume *vols, int32_t n, hipStrea
         const int64_t ngroups = (words + kGenWords - 1) / kGenWords;
         tile_prefix[k + 1] = tile_prefix[k] + std::max<int64_t>(1, (ngroups + TB - 1) / TB);
         const int64_t nseg = edge_segments(d.g);
-        etile_prefix[k + 1] = etile_prefix[k] + (nseg + kSegmentsPerTile - 1) / kSegmentsPerTile;
+        etile_prefix[k + 1] = etile_prefix[k] + edge_tiles(nseg, sc.edge_segs);
         ctile_prefix[k + 1] = words;  // words for now; tiles below
         m->voxels = vol.dims[0] * vol.dims[1] * vol.dims[2];
         hd[k] = d;
@@ -939,7 +977,8 @@ sn_status sn::extract_many(sn_ctx *c, const sn_volume *vols, int32_t n, hipStrea
     // count tiles: the wide form for launches of many words
     int64_t total_words = 0;
     for (int32_t k = 0; k < n; ++k) total_words += ctile_prefix[k + 1];
-    const int32_t cv = total_words >= c->count_wide_words ? kCountWideV : 1;
+    const int32_t cv = sc.count_words > 0 ? sc.count_words
+                                          : (total_words >= c->count_wide_words ? kCountWideV : 1);
     for (int32_t k = 0; k < n; ++k)
         ctile_prefix[k + 1] = ctile_prefix[k] + (ctile_prefix[k + 1] + cv * kCountBlock - 1) / (cv * kCountBlock);
     // groups: [gbeg[i], gbeg[i+1]) of the launch order share a key
@@ -977,7 +1016,8 @@ sn_status sn::extract_many(sn_ctx *c, const sn_volume *vols, int32_t n, hipStrea
     {
         ProfScope ps(c, "k_edges", s);
         if (one) {
-            HIP_TRY_CLEANUP(launch_edges_one(hd[0], wide(order[0]), etile_prefix[1], status, nzero, s));
+            HIP_TRY_CLEANUP(launch_edges_one(hd[0], wide(order[0]), etile_prefix[1], status, nzero,
+                                             sc.edge_segs, s));
         } else {
             bool zeroed = false;
             for (int32_t gi = 0; gi < ngroups; ++gi) {
@@ -985,7 +1025,7 @@ sn_status sn::extract_many(sn_ctx *c, const sn_volume *vols, int32_t n, hipStrea
                 const int64_t nt = etile_prefix[k1] - etile_prefix[k0];
                 HIP_TRY_CLEANUP(launch_edges(hd[k0].dtype, hd[k0].cs.mode, wide(order[k0]), d_desc + k0,
                                      d_tp + (n + 1) + k0, k1 - k0, etile_prefix[k0], nt, status,
-                                     (nt > 0 && !zeroed) ? nzero : 0, s));
+                                     (nt > 0 && !zeroed) ? nzero : 0, sc.edge_segs, s));
                 zeroed = zeroed || nt > 0;
             }
         }
@@ -1112,7 +1152,7 @@ sn_status sn::extract_many(sn_ctx *c, const sn_volume *vols, int32_t n, hipStrea
 extern "C" sn_status sn_extract(sn_ctx *c, const sn_volume *vol, void *stream, sn_mesh **out)
 {
     if (!out) return fail(SN_EINVAL, "sn_extract: out is NULL");
-    return extract_many(c, vol, 1, static_cast<hipStream_t>(stream), 0, out);
+    return extract_many(c, vol, 1, static_cast<hipStream_t>(stream), nullptr, out);
 }
 
 // ---------------------------------------------------------------------------
@@ -1145,7 +1185,7 @@ sn_status sn::ensure_smooth_buffers(sn_mesh *m)
 }
 
 // Smoothing descriptor of a mesh for the given parameters.
-static void fill_smooth_desc(const sn_mesh *m, const sn_smooth_params &p, SmoothDesc *sd)
+void sn::fill_smooth_desc(const sn_mesh *m, const sn_smooth_params &p, SmoothDesc *sd)
 {
     std::memset(sd, 0, sizeof *sd);
     sd->P = m->P, sd->faces = m->d.faces, sd->off = m->d.st_off, sd->ids = m->d.st_ids;
@@ -1161,6 +1201,7 @@ static void fill_smooth_desc(const sn_mesh *m, const sn_smooth_params &p, Smooth
     const int K = sweep_chunks(m->P);
     const int64_t per_slab = sweep_blocks_for(m->P, K) / std::max<int64_t>(1, m->d.g.CO);
     sd->chunk = (int32_t)std::max<int64_t>(1, (per_slab + 8) / 16);
+    if (m->sched.sweep_chunk > 0) sd->chunk = m->sched.sweep_chunk;
     if (m->ctx->sweep_chunk > 0) sd->chunk = m->ctx->sweep_chunk;
     sd->big = m->P > m->ctx->sweep_small_points ? 1 : 0;
     // packed neighbour table when the id distances fit: at most a row of
@@ -1408,7 +1449,7 @@ extern "C" sn_status sn_batch_submit(sn_ctx *c, const sn_volume *vols,
         }
     hipStream_t s = static_cast<hipStream_t>(stream);
     std::vector<sn_mesh *> ms(n, nullptr);
-    sn_status st = extract_many(c, vols, n, s, 0, ms.data());
+    sn_status st = extract_many(c, vols, n, s, nullptr, ms.data());
     if (st != SN_OK) return st;
     if (per_vol) {
         st = smooth_many(c, ms.data(), per_vol, n, s);
@@ -1425,6 +1466,33 @@ extern "C" sn_status sn_batch_submit(sn_ctx *c, const sn_volume *vols,
 // schedule tuner: time k_count + k_generate for each batches-per-wave candidate
 // ---------------------------------------------------------------------------
 
+// Time one extraction of `vol` under schedule `sc`: the best of three after a
+// warm-up, wall clock around the call and its completion.
+static sn_status time_extract(sn_ctx *c, const sn_volume *vol, hipStream_t s, const Schedule &sc,
+                              double *out)
+{
+    double best = 1e30;
+    for (int rep = 0; rep < 4; ++rep) {
+        HIP_TRY(hipStreamSynchronize(s));
+        const auto t0 = std::chrono::steady_clock::now();
+        sn_mesh *m = nullptr;
+        const sn_status st = extract_many(c, vol, 1, s, &sc, &m);
+        if (st != SN_OK) return st;
+        const hipError_t e = hipStreamSynchronize(s);
+        const auto t1 = std::chrono::steady_clock::now();
+        mesh_release(m);
+        if (e != hipSuccess) return fail(SN_EDEVICE, std::string("sn_autotune: ") + hipGetErrorString(e));
+        if (rep > 0) best = std::min(best, std::chrono::duration<double>(t1 - t0).count());
+    }
+    *out = best;
+    return SN_OK;
+}
+
+// Coordinate descent over the schedule, one knob at a time in the order of
+// the passes, each knob's candidates timed with the others at their best so
+// far: k_edges segments per wave, the k_count form, k_generate groups per
+// wave, and, for a mesh that takes the large-mesh sweep form, the chunk of its
+// block order (four sweeps timed per candidate).
 extern "C" sn_status sn_autotune(sn_ctx *c, const sn_volume *vol, void *stream, int32_t *chosen)
 {
     if (!c || !vol) return fail(SN_EINVAL, "sn_autotune: NULL argument");
@@ -1432,9 +1500,6 @@ extern "C" sn_status sn_autotune(sn_ctx *c, const sn_volume *vol, void *stream, 
     if (st != SN_OK) return st;
     hipStream_t s = static_cast<hipStream_t>(stream);
     HIP_TRY(hipSetDevice(c->device));
-    const int32_t cands[] = {1, 2, 3, 4, 8};
-    double best = 1e30;
-    int32_t arg = 2;
     // the timed runs record no profiling events; the setting is restored on every return
     struct ProfilingOff {
         sn_ctx *c;
@@ -1442,28 +1507,100 @@ extern "C" sn_status sn_autotune(sn_ctx *c, const sn_volume *vol, void *stream, 
         ~ProfilingOff() { c->profiling = was; }
     } off{c, c->profiling};
     c->profiling = false;
-    for (int32_t bpw : cands) {
-        double tbest = 1e30;
-        for (int rep = 0; rep < 4; ++rep) {
-            HIP_TRY(hipStreamSynchronize(s));
-            auto t0 = std::chrono::steady_clock::now();
-            sn_mesh *m = nullptr;
-            st = extract_many(c, vol, 1, s, bpw, &m);
-            if (st != SN_OK) return st;
-            const hipError_t e = hipStreamSynchronize(s);
-            auto t1 = std::chrono::steady_clock::now();
-            mesh_release(m);
-            if (e != hipSuccess) return fail(SN_EDEVICE, std::string("sn_autotune: ") + hipGetErrorString(e));
-            if (rep > 0) tbest = std::min(tbest, std::chrono::duration<double>(t1 - t0).count());
+    const std::string cls = size_class(*vol);
+    Schedule best;
+    {
+        std::lock_guard<std::mutex> g(c->tune_mu);
+        auto it = c->tune.find(cls);
+        if (it != c->tune.end()) best = it->second;
+    }
+    double tbest = 1e30;
+    st = time_extract(c, vol, s, best, &tbest);
+    if (st != SN_OK) return st;
+    auto knob = [&](int32_t Schedule::*field, std::initializer_list<int32_t> cands) -> sn_status {
+        for (int32_t v : cands) {
+            if (best.*field == v) continue;
+            Schedule sc = best;
+            sc.*field = v;
+            double t = 0;
+            const sn_status e = time_extract(c, vol, s, sc, &t);
+            if (e != SN_OK) return e;
+            if (t < tbest) tbest = t, best = sc;
         }
-        if (tbest < best) best = tbest, arg = bpw;
+        return SN_OK;
+    };
+    if ((st = knob(&Schedule::edge_segs, {1, 2, 4, 8})) != SN_OK) return st;
+    if ((st = knob(&Schedule::count_words, {1, kCountWideV})) != SN_OK) return st;
+    if ((st = knob(&Schedule::gen_groups, {1, 2, 3, 4, 8})) != SN_OK) return st;
+    // the sweeps' block order, for a mesh in the large-mesh form
+    {
+        sn_mesh *m = nullptr;
+        st = extract_many(c, vol, 1, s, &best, &m);
+        if (st != SN_OK) return st;
+        if (m->P > c->sweep_small_points && c->sweep_chunk == 0 && m->d.prim != SN_LINES) {
+            const sn_smooth_params p{4, 0.5f, 1.0f, SN_BOX};
+            SmoothDesc sd;
+            fill_smooth_desc(m, p, &sd);
+            const int32_t d0 = sd.chunk;  // the default (or the tuned) chunk
+            double cbest = 1e30;
+            int32_t carg = best.sweep_chunk;
+            for (int32_t ch : {d0 / 2, d0, 2 * d0}) {
+                if (ch < 1) continue;
+                m->sched.sweep_chunk = ch;
+                double t = 1e30;
+                for (int rep = 0; rep < 3 && st == SN_OK; ++rep) {
+                    HIP_TRY(hipStreamSynchronize(s));
+                    const auto t0 = std::chrono::steady_clock::now();
+                    st = smooth_one(c, m, &p, s);
+                    const hipError_t e = hipStreamSynchronize(s);
+                    const auto t1 = std::chrono::steady_clock::now();
+                    if (st == SN_OK && e != hipSuccess)
+                        st = fail(SN_EDEVICE, std::string("sn_autotune: ") + hipGetErrorString(e));
+                    if (rep > 0) t = std::min(t, std::chrono::duration<double>(t1 - t0).count());
+                }
+                if (st != SN_OK) break;
+                if (t < cbest) cbest = t, carg = ch == d0 && best.sweep_chunk == 0 ? 0 : ch;
+            }
+            best.sweep_chunk = carg;
+        }
+        mesh_release(m);
+        if (st != SN_OK) return st;
     }
     {
         std::lock_guard<std::mutex> g(c->tune_mu);
-        c->tune[size_class(*vol)] = arg;
+        c->tune[cls] = best;
         c->save_tune_cache();
     }
-    if (chosen) *chosen = arg;
+    if (chosen) *chosen = best.gen_groups;
+    return SN_OK;
+}
+
+extern "C" sn_status sn_schedule_get(sn_ctx *c, const sn_volume *vol, sn_schedule *out)
+{
+    if (!c || !vol || !out) return fail(SN_EINVAL, "sn_schedule_get: NULL argument");
+    sn_status st = validate_volume(vol);
+    if (st != SN_OK) return st;
+    const Schedule sc = c->schedule(size_class(*vol));
+    out->gen_groups = sc.gen_groups;
+    out->count_words = sc.count_words;
+    out->edge_segments = sc.edge_segs;
+    out->sweep_chunk = sc.sweep_chunk;
+    return SN_OK;
+}
+
+extern "C" sn_status sn_schedule_set(sn_ctx *c, const sn_volume *vol, const sn_schedule *in)
+{
+    if (!c || !vol || !in) return fail(SN_EINVAL, "sn_schedule_set: NULL argument");
+    sn_status st = validate_volume(vol);
+    if (st != SN_OK) return st;
+    Schedule sc;
+    sc.gen_groups = in->gen_groups;
+    sc.count_words = in->count_words;
+    sc.edge_segs = in->edge_segments;
+    sc.sweep_chunk = in->sweep_chunk;
+    if (!valid_schedule(sc)) return fail(SN_EINVAL, "sn_schedule_set: value out of range");
+    std::lock_guard<std::mutex> g(c->tune_mu);
+    c->tune[size_class(*vol)] = sc;
     return SN_OK;
 }
 

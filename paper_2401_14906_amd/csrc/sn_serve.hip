@@ -170,7 +170,7 @@ sn_status sn_server::run_fused(Request *const *b, const sn_volume *vols, const s
 {
     std::fill(ms, ms + n, nullptr);
     const AdmitFn admit = [&](const int64_t *totals) { return phase2(b, n, totals); };
-    sn_status st = extract_many(ctx, vols, n, s, 0, ms, &admit);
+    sn_status st = extract_many(ctx, vols, n, s, nullptr, ms, &admit);
     if (st == SN_OK) {
         // a batch of one takes the plain path (no descriptor upload, no graph build)
         st = n == 1 ? smooth_one(ctx, ms[0], ps, s) : smooth_many(ctx, ms, ps, n, s);

@@ -135,6 +135,116 @@ def test_schedule_invariance(ctx, sn, bpw):
         ctx.set_batches_per_wave(0)
 
 
+SCHEDULES = [dict(edge_segments=1, count_words=1, gen_groups=1),
+             dict(edge_segments=2, count_words=4, gen_groups=3),
+             dict(edge_segments=8, count_words=1, gen_groups=8),
+             dict(edge_segments=16, count_words=4, gen_groups=16)]
+
+
+@pytest.mark.parametrize("k", range(len(SCHEDULES)))
+def test_schedule_knobs(sn, torch, k):
+    """Every value of every schedule knob (k_edges segments per wave, the
+    k_count form, k_generate groups per wave) gives the oracle's results:
+    rows of ragged lengths (short rows sharing segments, rows of several
+    segments), all label types, an image, and a batch of them; the sweep
+    chunk of the large-mesh form on the torso and the 2D section."""
+    sc = SCHEDULES[k]
+    rng = np.random.default_rng(90 + k)
+    c = sn.Context(0)
+    try:
+        vols = [synth.blocky_tiny(rng, (M, 23, 11), 6, dt)
+                for M, dt in ((40, np.uint8), (100, np.uint16), (300, np.uint32), (530, np.uint16))]
+        for vol in vols:
+            announce(f"schedule {sc}: dims={vol.shape[::-1]} {vol.dtype}")
+            c.schedule_set(sn.to_device(vol), **sc)
+            assert {f: c.schedule_get(sn.to_device(vol))[f] for f in sc} == sc
+            run_case(c, sn, vol, iters=5)
+        img = synth.blocky_tiny(rng, (333, 97, 1), 5, np.uint16).reshape(97, 333)
+        ti = sn.to_device(img)
+        c.schedule_set(ti, prim=sn.SN_LINES, **sc)
+        m = c.extract(ti)
+        g = m.to_host()
+        m.free()
+        import oracle
+
+        o = oracle.extract2d(img)
+        np.testing.assert_array_equal(g.polys, o.quads)
+        np.testing.assert_array_equal(g.stencil_ids, o.st_ids)
+        # a batch takes the schedule of its largest volume
+        ts = [sn.to_device(v) for v in vols]
+        plain = []
+        for t in ts:
+            m = c.extract(t)
+            c.smooth(m, iterations=5)
+            plain.append(m.to_host())
+            m.free()
+        ms = c.batch_submit([dict(labels=t) for t in ts], [(5, 0.5, 1.0)] * len(ts))
+        for kk, m in enumerate(ms):
+            g = m.to_host()
+            m.free()
+            for f in ("points", "offsets", "polys", "label_pairs", "stencil_off", "stencil_ids"):
+                assert np.array_equal(getattr(g, f), getattr(plain[kk], f)), (kk, f)
+    finally:
+        c.close()
+
+
+def test_sweep_chunk_knob(sn, torch, monkeypatch):
+    """The sweep chunk of a schedule sets the slab-chunked block order of the
+    large-mesh form (here forced on the torso): offsets equal the oracle's for
+    chunks of 1, 7 and 64 blocks."""
+    import oracle
+
+    monkeypatch.setenv("SN_TEST_SWEEP_SMALL_POINTS", "0")
+    c = sn.Context(0)
+    monkeypatch.delenv("SN_TEST_SWEEP_SMALL_POINTS")
+    try:
+        v = synth.torso_like()
+        t = sn.to_device(v.labels)
+        o = oracle.extract(v.labels)
+        ref = o.smooth(v.iterations, v.relaxation, v.constraint) - o.centres()
+        for ch in (1, 7, 64):
+            announce(f"sweep chunk {ch} on the torso (large-mesh form)")
+            c.schedule_set(t, sweep_chunk=ch)
+            m = c.extract(t, spacing=v.spacing)
+            c.smooth(m, iterations=v.iterations, relaxation=v.relaxation, constraint=v.constraint)
+            g = m.to_host()
+            m.free()
+            assert np.max(np.abs(g.offsets.astype(np.float64) - ref)) <= TOL
+    finally:
+        c.close()
+
+
+def test_autotune_records_a_valid_schedule(sn, torch, tmp_path, monkeypatch):
+    """sn_autotune picks a schedule within the knobs' ranges, reports it, keeps
+    it in SN_AUTOTUNE_CACHE (read back by a new context), and extraction under
+    it gives the oracle's results."""
+    import json
+
+    cache = tmp_path / "tune.json"
+    monkeypatch.setenv("SN_AUTOTUNE_CACHE", str(cache))
+    c = sn.Context(0)
+    try:
+        rng = np.random.default_rng(95)
+        vol = synth.blocky_tiny(rng, (200, 60, 40), 7, np.uint16)
+        t = sn.to_device(vol)
+        announce("autotune on a 200x60x40 u16 volume")
+        g = c.autotune(t)
+        sc = c.schedule_get(t)
+        assert g == sc["gen_groups"]
+        assert sc["edge_segments"] in (1, 2, 4, 8) and sc["count_words"] in (1, 4)
+        assert sc["gen_groups"] in (1, 2, 3, 4, 8)
+        run_case(c, sn, vol, iters=4)
+        saved = json.loads(cache.read_text())
+        assert any(e["edge_segments"] == sc["edge_segments"] for e in saved.values())
+    finally:
+        c.close()
+    c2 = sn.Context(0)
+    try:
+        assert c2.schedule_get(t) == sc
+    finally:
+        c2.close()
+
+
 def test_dtype_edge_values(ctx, sn):
     rng = np.random.default_rng(5)
     for dt, top in ((np.uint8, 255), (np.uint16, 65535), (np.uint32, 2**32 - 1)):
