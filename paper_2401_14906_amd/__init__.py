@@ -265,11 +265,15 @@ def make_volume(labels, spacing=(1.0, 1.0, 1.0), origin=(0.0, 0.0, 0.0), selecte
     v.labels = labels.data_ptr()
     v.dtype = b
     v.dims[:] = (M, N, O)
-    v.spacing[:] = tuple(float(x) for x in spacing)
-    v.origin[:] = tuple(float(x) for x in origin)
-    sel = np.ascontiguousarray(np.asarray(list(selected), dtype=np.uint32))
-    v.selected = sel.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)) if sel.size else None
-    v.n_selected = int(sel.size)
+    sx, sy, sz = spacing
+    v.spacing[0], v.spacing[1], v.spacing[2] = float(sx), float(sy), float(sz)
+    ox, oy, oz = origin
+    v.origin[0], v.origin[1], v.origin[2] = float(ox), float(oy), float(oz)
+    sel = None
+    if len(selected):
+        sel = np.ascontiguousarray(np.asarray(list(selected), dtype=np.uint32))
+        v.selected = sel.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32))
+        v.n_selected = int(sel.size)
     v.background = int(background)
     v.prim = int(prim)
     return v, (labels, sel)

@@ -250,6 +250,10 @@ hipError_t launch_jacobi_first2(const SmoothDesc *d_sd, const int64_t *d_block_p
 hipError_t add_jacobi_nodes(hipGraph_t graph, const SmoothDesc *d_sd,
                             const int64_t *d_block_prefix, int32_t nvol, const int64_t *grid,
                             int32_t iters, int K);
+// Copy `bytes` (rounded up to 8) from pinned host memory, given by its
+// device-side mapping, to device memory `dst` with a kernel on `s`; both
+// buffers 8-byte aligned and at least the rounded size.
+hipError_t launch_stage(void *dst, const void *src_mapped, size_t bytes, hipStream_t s);
 // Single-volume forms: the descriptor travels by value in the kernel
 // arguments (no upload, no prefix array; tiles and blocks start at 0).
 hipError_t launch_edges_one(const VolDesc &d, bool wide, int64_t ntiles, uint64_t *d_zero,

@@ -2169,6 +2169,26 @@ hipError_t add_jacobi_nodes(hipGraph_t graph, const SmoothDesc *d_sd,
 }
 
 
+// Descriptor staging: a copy of `n` 8-byte words from host-mapped pinned
+// memory into device memory by the queue that runs the kernels, so that the
+// kernel after it waits on no other engine.
+__global__ __launch_bounds__(256) void k_stage(const uint64_t *__restrict__ src,
+                                               uint64_t *__restrict__ dst, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        glb(dst)[i] = src[i];
+}
+
+hipError_t launch_stage(void *dst, const void *src_mapped, size_t bytes, hipStream_t s)
+{
+    const int64_t n = (int64_t)((bytes + 7) / 8);
+    if (n <= 0) return hipSuccess;
+    const uint32_t blocks = (uint32_t)((n + 255) / 256 < 64 ? (n + 255) / 256 : 64);
+    hipLaunchKernelGGL(k_stage, dim3(blocks), dim3(256), 0, s, static_cast<const uint64_t *>(src_mapped),
+                       static_cast<uint64_t *>(dst), n);
+    return hipGetLastError();
+}
+
 hipError_t launch_triangulate(const VolDesc *d_descs, const int64_t *d_block_prefix, int32_t nvol,
                               int64_t nblocks, hipStream_t s)
 {

@@ -7,6 +7,7 @@
 #include <deque>
 #include <functional>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <tuple>
@@ -43,6 +44,21 @@ class EventCache {
     std::vector<hipEvent_t> free_;
 };
 
+class Pool;
+
+// A completion event of the pool's cache that the meshes of one batch share
+// (one marker on the stream instead of one per mesh); it goes back to the
+// pool's cache when its last holder lets go.
+struct SharedEvent {
+    SharedEvent(hipEvent_t e, Pool *p) : ev(e), home(p) {}
+    ~SharedEvent();
+    SharedEvent(const SharedEvent &) = delete;
+    SharedEvent &operator=(const SharedEvent &) = delete;
+    hipEvent_t ev;
+    Pool *home;
+};
+using EventRef = std::shared_ptr<SharedEvent>;
+
 class Pool {
   public:
     static inline const hipStream_t kNoWait = reinterpret_cast<hipStream_t>(~uintptr_t(0));
@@ -57,6 +73,12 @@ class Pool {
     // current work has completed.
     void release(void *p, hipStream_t after);
     void release_all(const std::vector<void *> &ps, hipStream_t after);
+    // As release_all, reused once `ev` has completed (the pending release
+    // holds a reference to it until then).
+    void release_all_after(const std::vector<void *> &ps, EventRef ev);
+    // An event (timing disabled) of the pool's cache; nullptr on failure.
+    EventRef shared_event();
+    void put_event(hipEvent_t e) { events_.put(e); }
     int64_t in_use() const;
     int64_t peak() const;
 
@@ -64,6 +86,7 @@ class Pool {
     struct Pending {
         hipEvent_t ev;
         std::vector<void *> blocks;
+        EventRef ref;  // set: ev is ref's (returned by dropping ref)
     };
     void reclaim_locked(bool wait);
     void raw_free(void *p);
@@ -88,9 +111,6 @@ struct sn_ctx {
     sn::Pool pool;    // device blocks
     sn::Pool pinned;  // pinned host staging
     hipStream_t copy_stream = nullptr;  // non-blocking, for copies to the host
-    // Freed meshes: the retire stream waits for each mesh's completion event
-    // and their pool blocks are released behind an event recorded on it.
-    hipStream_t retire_stream = nullptr;
     sn::EventCache timing_events{hipEventDefault};
     sn::EventCache sync_events{hipEventDisableTiming};  // ordering only (served requests)
     // profiling
@@ -122,6 +142,15 @@ struct sn_ctx {
     bool sweep_unpacked = false;
     // device address of the no-allocation extraction's static scratch array
     void *noalloc_scratch = nullptr;
+    // the sweeps of a batch: one HIP graph per call (default), or the kernels
+    // launched one by one (SN_BATCH_SWEEPS=eager)
+    bool batch_eager = false;
+    // sweep graphs launched and not yet known to be complete: destroyed once
+    // their event has completed (destroying a graph in flight would hold the
+    // host thread until it finishes)
+    std::mutex graph_mu;
+    std::vector<std::pair<hipGraphExec_t, hipEvent_t>> graph_retire;
+    void reap_graphs(bool wait);
     sn::Schedule schedule(const std::string &cls) const;
     void load_tune_cache();
     void save_tune_cache() const;
@@ -140,7 +169,9 @@ struct sn_mesh {
     const float *final_delta = nullptr;
 
 
-    hipEvent_t done_ev = nullptr;  // recorded after the last library work on the mesh
+    // recorded after the last library work on the mesh (shared by the meshes
+    // of one batch call)
+    sn::EventRef done;
 };
 
 namespace sn {
@@ -192,6 +223,8 @@ sn_status run_sweeps(sn_ctx *c, const SmoothDesc *d_sd, const int64_t *d_bp, int
                      const std::vector<int64_t> &grid, int K, hipStream_t s);
 sn_status run_sweeps_one(sn_ctx *c, const SmoothDesc &sd, int64_t nblocks, int K, hipStream_t s);
 sn_status mesh_mark(sn_mesh *m, hipStream_t s);
+// mesh_mark for meshes[0..n) (null entries skipped) with one event recorded once
+sn_status mesh_mark_all(sn_mesh *const *meshes, int32_t n, hipStream_t s);
 void mesh_release(sn_mesh *m);
 void ctx_retain(sn_ctx *c);
 void ctx_release(sn_ctx *c);  // frees the context with its last reference

@@ -134,7 +134,9 @@ void Pool::reclaim_locked(bool wait)
         const hipError_t q = wait ? hipEventSynchronize(pd.ev) : hipEventQuery(pd.ev);
         if (q == hipErrorNotReady) break;
         for (void *p : pd.blocks) free_.emplace(sizes_[p], p);
-        if (q == hipSuccess)
+        if (pd.ref)
+            pd.ref.reset();  // the event returns to the cache with its last holder
+        else if (q == hipSuccess)
             events_.put(pd.ev);
         else
             (void)hipEventDestroy(pd.ev);
@@ -227,6 +229,35 @@ void Pool::release_all(const std::vector<void *> &ps, hipStream_t after)
     pending_.push_back(Pending{ev, std::move(live)});
 }
 
+SharedEvent::~SharedEvent()
+{
+    if (home) home->put_event(ev);
+}
+
+EventRef Pool::shared_event()
+{
+    hipEvent_t e = events_.get();
+    if (!e) return nullptr;
+    return std::make_shared<SharedEvent>(e, this);
+}
+
+void Pool::release_all_after(const std::vector<void *> &ps, EventRef ev)
+{
+    std::lock_guard<std::mutex> g(mu_);
+    std::vector<void *> live;
+    for (void *p : ps) {
+        if (!p) continue;
+        auto it = sizes_.find(p);
+        if (it == sizes_.end()) continue;
+        in_use_ -= (int64_t)charged_[p];
+        charged_.erase(p);
+        live.push_back(p);
+    }
+    if (live.empty()) return;
+    hipEvent_t e = ev->ev;
+    pending_.push_back(Pending{e, std::move(live), std::move(ev)});
+}
+
 int64_t Pool::in_use() const
 {
     std::lock_guard<std::mutex> g(mu_);
@@ -253,15 +284,12 @@ extern "C" sn_status sn_ctx_create(int device, sn_ctx **out)
     }
     HIP_TRY(hipSetDevice(device));
     sn_ctx *c = new sn_ctx(device);
-    if (hipStreamCreateWithFlags(&c->copy_stream, hipStreamNonBlocking) != hipSuccess ||
-        hipStreamCreateWithFlags(&c->retire_stream, hipStreamNonBlocking) != hipSuccess) {
-        if (c->copy_stream) (void)hipStreamDestroy(c->copy_stream);
+    if (hipStreamCreateWithFlags(&c->copy_stream, hipStreamNonBlocking) != hipSuccess) {
         delete c;
         return fail(SN_EDEVICE, "sn_ctx_create: stream creation failed");
     }
     if (sn_status st = noalloc_resolve(device, &c->noalloc_scratch); st != SN_OK) {
         (void)hipStreamDestroy(c->copy_stream);
-        (void)hipStreamDestroy(c->retire_stream);
         delete c;
         return st;
     }
@@ -269,6 +297,8 @@ extern "C" sn_status sn_ctx_create(int device, sn_ctx **out)
         c->count_wide_words = std::strtoll(cw, nullptr, 10);
     if (const char *sp = std::getenv("SN_TEST_SWEEP_SMALL_POINTS"); sp && *sp)
         c->sweep_small_points = std::max<int64_t>(0, std::strtoll(sp, nullptr, 10));
+    if (const char *be = std::getenv("SN_BATCH_SWEEPS"); be && *be)
+        c->batch_eager = std::string(be) == "eager";
     if (const char *su = std::getenv("SN_TEST_SWEEP_UNPACKED"); su && *su)
         c->sweep_unpacked = std::strtoll(su, nullptr, 10) != 0;
     if (const char *sc = std::getenv("SN_TEST_SWEEP_CHUNK"); sc && *sc)
@@ -298,9 +328,7 @@ void sn::ctx_release(sn_ctx *c)
     if (c->refs.fetch_sub(1, std::memory_order_acq_rel) != 1) return;
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->copy_stream);
-    (void)hipStreamSynchronize(c->retire_stream);
     (void)hipStreamDestroy(c->copy_stream);
-    (void)hipStreamDestroy(c->retire_stream);
     delete c;
 }
 
@@ -313,10 +341,29 @@ sn_ctx::sn_ctx(int dev) : device(dev), pool(dev, false), pinned(dev, true) {}
 
 sn_ctx::~sn_ctx()
 {
+    reap_graphs(true);
     for (auto &p : prof_pending) {
         (void)hipEventDestroy(p.a);
         (void)hipEventDestroy(p.b);
     }
+}
+
+void sn_ctx::reap_graphs(bool wait)
+{
+    std::lock_guard<std::mutex> g(graph_mu);
+    size_t keep = 0;
+    for (size_t k = 0; k < graph_retire.size(); ++k) {
+        auto &gr = graph_retire[k];
+        const hipError_t q = wait ? hipEventSynchronize(gr.second) : hipEventQuery(gr.second);
+        if (q == hipErrorNotReady) {
+            graph_retire[keep++] = gr;
+            continue;
+        }
+        (void)hipGetLastError();
+        (void)hipGraphExecDestroy(gr.first);
+        sync_events.put(gr.second);
+    }
+    graph_retire.resize(keep);
 }
 
 // ---- profiling -------------------------------------------------------------
@@ -324,7 +371,7 @@ sn_ctx::~sn_ctx()
 ProfScope::ProfScope(sn_ctx *c, const char *name, hipStream_t s, int64_t launches)
     : c_(c), name_(name), s_(s), launches_(launches)
 {
-    if (!c_ || !c_->profiling) return;
+    if (!c_ || !c_->profiling || name_.empty()) return;  // an empty name: no events
     if (c_->profile_sweeps_only && name_ != "k_jacobi") return;
     a_ = c_->timing_events.get();
     b_ = c_->timing_events.get();
@@ -592,18 +639,13 @@ void sn::mesh_release(sn_mesh *m)
     if (!m) return;
     sn_ctx *c = m->ctx;
     (void)hipSetDevice(c->device);
-    // everything the library enqueued for this mesh precedes done_ev; the
-    // retire stream waits for it, and the blocks are released behind an event
-    // on the retire stream, without blocking the host
-    hipStream_t rs = c->retire_stream;
-    bool ordered = true;
-    if (m->done_ev && hipStreamWaitEvent(rs, m->done_ev, 0) != hipSuccess) {
-        (void)hipGetLastError();
-        (void)hipEventSynchronize(m->done_ev);
-        ordered = false;
-    }
-    if (m->done_ev) (void)hipEventDestroy(m->done_ev);
-    c->pool.release_all(m->blocks, ordered ? rs : Pool::kNoWait);
+    // everything the library enqueued for this mesh precedes done_ev: the
+    // blocks are reused once it has completed (the pool takes the event),
+    // without blocking the host
+    if (m->done)
+        c->pool.release_all_after(m->blocks, std::move(m->done));
+    else
+        c->pool.release_all(m->blocks, Pool::kNoWait);
     delete m;
     ctx_release(c);
 }
@@ -612,8 +654,25 @@ extern "C" void sn_mesh_free(sn_mesh *m) { mesh_release(m); }
 
 sn_status sn::mesh_mark(sn_mesh *m, hipStream_t s)
 {
-    if (!m->done_ev) HIP_TRY(hipEventCreateWithFlags(&m->done_ev, hipEventDisableTiming));
-    HIP_TRY(hipEventRecord(m->done_ev, s));
+    // an event shared with other meshes is not moved: this mesh takes its own
+    if (!m->done || m->done.use_count() > 1) {
+        m->done = m->ctx->pool.shared_event();
+        if (!m->done) return fail(SN_EDEVICE, "mesh: no event");
+    }
+    HIP_TRY(hipEventRecord(m->done->ev, s));
+    return SN_OK;
+}
+
+sn_status sn::mesh_mark_all(sn_mesh *const *meshes, int32_t n, hipStream_t s)
+{
+    sn_mesh *first = nullptr;
+    for (int32_t k = 0; k < n && !first; ++k) first = meshes[k];
+    if (!first) return SN_OK;
+    EventRef e = first->ctx->pool.shared_event();
+    if (!e) return fail(SN_EDEVICE, "mesh: no event");
+    HIP_TRY(hipEventRecord(e->ev, s));
+    for (int32_t k = 0; k < n; ++k)
+        if (meshes[k]) meshes[k]->done = e;
     return SN_OK;
 }
 
@@ -653,7 +712,7 @@ extern "C" sn_status sn_mesh_copy_to_host(const sn_mesh *m, float *points, int32
 {
     if (!m) return fail(SN_EINVAL, "sn_mesh_copy_to_host: mesh is NULL");
     HIP_TRY(hipSetDevice(m->ctx->device));
-    if (m->done_ev) HIP_TRY(hipEventSynchronize(m->done_ev));
+    if (m->done) HIP_TRY(hipEventSynchronize(m->done->ev));
     sn_mesh_view v;
     sn_mesh_view_get(m, &v);
     // a non-blocking stream of the context: no implicit ordering with the
@@ -685,6 +744,16 @@ extern "C" sn_status sn_mesh_copy_to_host(const sn_mesh *m, float *points, int32
 // ---------------------------------------------------------------------------
 
 namespace {
+
+// Upload of a staging block from the pinned pool to a device block (both
+// from the pools, so rounded to at least 512 bytes) by a kernel on `s`.
+hipError_t stage_upload(void *d, void *h, size_t bytes, hipStream_t s)
+{
+    void *hm = nullptr;
+    hipError_t e = hipHostGetDevicePointer(&hm, h, 0);
+    if (e != hipSuccess) return e;
+    return launch_stage(d, hm, bytes, s);
+}
 
 struct Scratch {
     sn_ctx *c;
@@ -1010,7 +1079,7 @@ sn_status sn::extract_many(sn_ctx *c, const sn_volume *vols, int32_t n, hipStrea
         std::memcpy(h_tp + (n + 1), etile_prefix.data(), sizeof(int64_t) * (n + 1));
         std::memcpy(h_tp + 2 * (n + 1), ctile_prefix.data(), sizeof(int64_t) * (n + 1));
     }
-    if (up_a > 0) HIP_TRY_CLEANUP(hipMemcpyAsync(d_up, h_up, up_a, hipMemcpyHostToDevice, s));
+    if (up_a > 0) HIP_TRY_CLEANUP(stage_upload(d_up, h_up, up_a, s));
     // the first edges launch clears the count pass's status words and ticket
     const int64_t nzero = (int64_t)((status_bytes + 256) / 8);
     {
@@ -1118,7 +1187,7 @@ sn_status sn::extract_many(sn_ctx *c, const sn_volume *vols, int32_t n, hipStrea
             if (hd[k].prim == SN_TRIS) acc += (hd[k].Q + 255) / 256;
         }
         h_qp[n] = acc;
-        HIP_TRY_CLEANUP(hipMemcpyAsync(d_b, h_b, up_b, hipMemcpyHostToDevice, s));
+        HIP_TRY_CLEANUP(stage_upload(d_b, h_b, up_b, s));
         VolDesc *d_desc2 = reinterpret_cast<VolDesc *>(d_b);
         {
             ProfScope ps(c, "k_generate", s);
@@ -1138,10 +1207,7 @@ sn_status sn::extract_many(sn_ctx *c, const sn_volume *vols, int32_t n, hipStrea
                                        n, acc, s));
         }
     }
-    for (int32_t k = 0; k < n; ++k) {
-        sn_status st = mesh_mark(meshes[order[k]], s);
-        if (st != SN_OK) return cleanup(st);
-    }
+    if (sn_status st = mesh_mark_all(meshes.data(), n, s); st != SN_OK) return cleanup(st);
     scr.retire(s);
     for (int32_t v = 0; v < n; ++v) out[v] = meshes[v];
     return SN_OK;
@@ -1223,17 +1289,19 @@ sn_status sn::run_sweeps(sn_ctx *c, const SmoothDesc *d_sd, const int64_t *d_bp,
 {
     const int32_t iters = (int32_t)grid.size();
     if (iters <= 0 || grid[0] <= 0) return SN_OK;
-    if (c->profile_eager) {
-        // eager launches, each sweep bracketed by its own events (sweeps 0
-        // and 1 together, as in the graph)
+    if (c->profile_eager || c->batch_eager) {
+        // eager launches (with profiling, each sweep bracketed by its own
+        // events; sweeps 0 and 1 together, as in the graph)
+        const bool each = c->profile_eager;
+        ProfScope all(c, each ? "" : "k_jacobi", s, each ? 0 : iters);
         int32_t it0 = 0;
         if (iters >= 2 && grid[1] > 0) {
-            ProfScope ps(c, "k_jacobi", s, 2);
+            ProfScope ps(c, each ? "k_jacobi" : "", s, each ? 2 : 0);
             HIP_TRY(launch_jacobi_first2(d_sd, d_bp, nvol, grid[0], grid[1], K, s));
             it0 = 2;
         }
         for (int32_t it = it0; it < iters && grid[it] > 0; ++it) {
-            ProfScope ps(c, "k_jacobi", s);
+            ProfScope ps(c, each ? "k_jacobi" : "", s, each ? 1 : 0);
             HIP_TRY(launch_jacobi(d_sd, d_bp, nvol, grid[it], it, K, s));
         }
         return SN_OK;
@@ -1250,8 +1318,22 @@ sn_status sn::run_sweeps(sn_ctx *c, const SmoothDesc *d_sd, const int64_t *d_bp,
     if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     if (e == hipSuccess) e = hipGraphLaunch(exec, s);
-    if (exec) (void)hipGraphExecDestroy(exec);
-    if (e != hipSuccess) return fail(SN_EDEVICE, std::string("smooth: sweep graph: ") + hipGetErrorString(e));
+    if (e != hipSuccess) {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        return fail(SN_EDEVICE, std::string("smooth: sweep graph: ") + hipGetErrorString(e));
+    }
+    // destroyed once the replay has completed (destroying it now would hold
+    // this thread until then, and the next call's work would start late)
+    hipEvent_t done = c->sync_events.get();
+    if (!done || hipEventRecord(done, s) != hipSuccess) {
+        (void)hipGetLastError();
+        if (done) c->sync_events.put(done);
+        (void)hipGraphExecDestroy(exec);
+        return SN_OK;
+    }
+    c->reap_graphs(false);
+    std::lock_guard<std::mutex> g(c->graph_mu);
+    c->graph_retire.emplace_back(exec, done);
     return SN_OK;
 }
 
@@ -1407,7 +1489,7 @@ sn_status sn::smooth_many(sn_ctx *c, sn_mesh **ms, const sn_smooth_params *pv, i
         scr.retire(s);
         return fail(SN_EDEVICE, std::string("batch smooth: ") + what + ": " + hipGetErrorString(e));
     };
-    if (hipError_t e = hipMemcpyAsync(d_up, h_up, up, hipMemcpyHostToDevice, s); e != hipSuccess)
+    if (hipError_t e = stage_upload(d_up, h_up, up, s); e != hipSuccess)
         return device_fail(e, "descriptor upload");
     sn_status st = run_sweeps(c, d_sd, d_p, n, grid, K, s);
     if (st != SN_OK) {
@@ -1430,11 +1512,7 @@ sn_status sn::smooth_many(sn_ctx *c, sn_mesh **ms, const sn_smooth_params *pv, i
         }
     }
     scr.retire(s);
-    for (int32_t v = 0; v < n; ++v) {
-        st = mesh_mark(ms[v], s);
-        if (st != SN_OK) return st;
-    }
-    return SN_OK;
+    return mesh_mark_all(ms, n, s);
 }
 
 extern "C" sn_status sn_batch_submit(sn_ctx *c, const sn_volume *vols,
