@@ -365,7 +365,8 @@ typedef struct sn_schedule {
                               batches of 4 words per wave (1..16; 1 untuned)            */
     int32_t count_words;   /* k_count: cell words per thread, 1 or 4 (0, untuned: 4 from
                               2^18 words in a launch, else 1)                          */
-    int32_t edge_segments; /* k_edges: 256-sample segments per wave (1..16; 4 untuned) */
+    int32_t edge_segments; /* k_edges: segments of four 64-sample words per wave
+                              (1..16; 4 untuned)                                     */
     int32_t sweep_chunk;   /* the sweeps of a mesh of more than 2^24 points: blocks each
                               XCD takes in turn in the slab-chunked order (0, untuned:
                               about a sixteenth of a slab's blocks)                    */

@@ -38,15 +38,15 @@ constexpr int32_t kPrimLines = 2;
 constexpr int kWavesPerBlock = 4;
 constexpr int kBlock = 64 * kWavesPerBlock;
 constexpr int kMaxBatchesPerWave = 16;
-// k_edges: a wave takes 1..kMaxSegmentsPerWave segments of 256 samples (the
-// schedule's edge_segments), a tile kWavesPerBlock times that
+// k_edges: a wave takes 1..kMaxSegmentsPerWave segments of four 64-sample
+// words (the schedule's edge_segments), a tile kWavesPerBlock times that
 constexpr int kMaxSegmentsPerWave = 16;
 // A schedule of the kernels for one size class of volumes.  Results never
 // depend on it; sn_autotune picks it by timing.
 struct Schedule {
     int32_t gen_groups = 1;   // k_generate: groups of 32 words per wave; k_emit: batches per wave
     int32_t count_words = 0;  // k_count: words per thread, 1 or kCountWideV (0: by size)
-    int32_t edge_segs = 4;    // k_edges: 256-sample segments per wave
+    int32_t edge_segs = 4;    // k_edges: segments of four sample-row words per wave
     int32_t sweep_chunk = 0;  // a large single mesh's slab-chunked block order: blocks an
                               // XCD takes in turn (0: about a sixteenth of a slab)
 };
@@ -69,9 +69,33 @@ constexpr int kCountWideV = 4;
 // words in 15.5 us narrow against 21 us wide)
 constexpr int64_t kCountWideWords = int64_t(1) << 18;
 
+// Division by a run-time constant d >= 1: n / d = (t + ((n - t) >> s1)) >> s2
+// with t = mulhi(n, m) (the round-up multiplier method for 32-bit operands).
+struct UDiv {
+    uint32_t d, m, s1, s2;
+};
+
+inline UDiv make_udiv(uint32_t d)
+{
+    uint32_t l = 0;
+    while (l < 32 && (uint64_t(1) << l) < d) ++l;  // l = ceil(log2 d)
+    UDiv u;
+    u.d = d;
+    u.m = (uint32_t)(((uint64_t(1) << 32) * ((uint64_t(1) << l) - d)) / d + 1);
+    u.s1 = l < 1 ? l : 1;
+    u.s2 = l > 1 ? l - 1 : 0;
+    return u;
+}
+
+__device__ __forceinline__ uint32_t udiv(uint32_t n, const UDiv &u)
+{
+    const uint32_t t = __umulhi(n, u.m);
+    return (t + ((n - t) >> u.s1)) >> u.s2;
+}
+
 // Sample lattice M x N x O; cell grid CM x CN x CO = (M-1)(N-1)(O-1).
-// Cut-edge planes (k_edges) hold one bit per sample, WS words per sample row,
-// computed in segments of 256 samples (NSEG per sample row).
+// Cut-edge planes (k_edges) hold one bit per sample, WS words per sample row;
+// k_edges takes them four words at a time in (sample row, word) order.
 struct Geom {
     int64_t M, N, O;
     int64_t CM, CN, CO;
@@ -79,16 +103,14 @@ struct Geom {
     int32_t W;     // words per cell row
     int32_t NB;    // batches per cell row
     int64_t WS;    // words per sample row
-    int64_t NSEG;  // 256-sample segments per sample row
-    int32_t RSH;   // log2 of the sample rows sharing one segment: 2 for rows of
-                   // at most 64 samples, 1 for at most 128, else 0
+    UDiv ws_div;   // division by WS (at least 1)
+    UDiv n_div;    // division by N (at least 1)
 };
 
-// k_edges segments of a volume: NSEG per sample row, or one per 2^RSH rows
+// k_edges segments of a volume: four consecutive sample-row words each
 __host__ __device__ inline int64_t edge_segments(const Geom &g)
 {
-    const int64_t rows = g.N * g.O;
-    return g.RSH ? (rows + (int64_t(1) << g.RSH) - 1) >> g.RSH : rows * g.NSEG;
+    return (g.N * g.O * g.WS + 3) / 4;
 }
 
 // Everything the word kernels need for one volume.
@@ -122,22 +144,6 @@ struct VolDesc {
 
 // Division of 32-bit values by an invariant divisor d >= 1 (Granlund and
 // Montgomery's method): with t = umulhi(n, m), n / d = (t + ((n - t) >> s1)) >> s2.
-struct UDiv {
-    uint32_t d, m, s1, s2;
-};
-
-inline UDiv make_udiv(uint32_t d)
-{
-    uint32_t l = 0;
-    while (l < 32 && (uint64_t(1) << l) < d) ++l;  // l = ceil(log2 d)
-    UDiv u;
-    u.d = d;
-    u.m = (uint32_t)(((uint64_t(1) << 32) * ((uint64_t(1) << l) - d)) / d + 1);
-    u.s1 = l < 1 ? l : 1;
-    u.s2 = l > 1 ? l - 1 : 0;
-    return u;
-}
-
 // One mesh's smoothing job.  Sweep 0 reads the CSR stencil (off, ids) and
 // writes nbr: per point the ids of its -y, +y, -z, +z stencil neighbours
 // (-1 where absent); later sweeps read nbr and take the -x / +x neighbours,
@@ -206,7 +212,7 @@ constexpr uint64_t kValMask = (1ull << 62) - 1;
 // Each launch covers tiles tile_base .. tile_base + ntiles - 1 of a global
 // tile numbering over the volumes of one extraction; tile_prefix[v] is the
 // first tile of volume v and tile_prefix[nvol] the end.
-//   k_edges   : a tile is 4*4 segments of 256 samples; every volume of a launch has
+//   k_edges   : a tile is 4*spw segments of four sample-row words; every volume of a launch has
 //               the given label type (bytes), classification mode and `wide`
 //               (rows 16-byte aligned and M % 4 == 0: one wide load per lane).
 //               The launch also zeroes d_zero[0 .. nzero) (the count pass's scan

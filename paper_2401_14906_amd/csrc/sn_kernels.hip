@@ -336,9 +336,10 @@ __device__ __forceinline__ int32_t wave_incl_scan_dpp(int32_t v, int lane)
 // ---------------------------------------------------------------------------
 // k_edges: cut-edge planes X, Y, Z (Sec. 2.2): bit i of word m of sample row
 // (j,k) of plane X is set iff C(i,j,k) != C(i+1,j,k) (Y: C(i,j+1,k), Z:
-// C(i,j,k+1)).  A wave takes 256 samples of a row, four per lane, with one
-// wide load per sample row (rows (j,k), (j+1,k), (j,k+1)); nibbles are merged
-// into 64-bit words across 16 lanes.
+// C(i,j,k+1)).  A wave takes four 64-sample words (of one row or of two
+// consecutive rows), four samples per lane, with one wide load per sample row
+// (rows (j,k), (j+1,k), (j,k+1)); nibbles are merged into 64-bit words across
+// 16 lanes.
 // ---------------------------------------------------------------------------
 
 
@@ -424,38 +425,31 @@ template <typename T, int MODE, bool WIDE>
 __device__ __forceinline__ void edges_segment(const VolDesc &d, int64_t seg, int lane)
 {
     const Geom &g = d.g;
-    const uint32_t NSEG = (uint32_t)g.NSEG, N = (uint32_t)g.N;
-    // rows of at most 64 or 128 samples share a segment (4 or 2 rows, 16 or
-    // 32 lanes each), so that short rows do not leave most lanes idle; every
-    // group of 16 lanes still covers one 64-sample word of one row
-    const uint32_t rsh = (uint32_t)g.RSH;
-    uint32_t srow;
-    int32_t m, i0;
-    bool rowok = true;
-    if (rsh == 0) {
-        srow = (uint32_t)seg / NSEG;
-        m = (int32_t)((uint32_t)seg - srow * NSEG);
-        i0 = 256 * m + 4 * lane;
-    } else {
-        const uint32_t lpr = 64u >> rsh;  // lanes per row
-        srow = ((uint32_t)seg << rsh) + ((uint32_t)lane >> (6u - rsh));
-        m = 0;
-        i0 = 4 * (int32_t)((uint32_t)lane & (lpr - 1u));
-        rowok = srow < N * (uint32_t)g.O;
-    }
-    const int32_t j = (int32_t)(srow % N), k = (int32_t)(srow / N);
+    // A segment is four consecutive words of the planes in (sample row, word)
+    // order, one per 16 lanes: the words of one row, or the last words of a
+    // row and the first of the next, so that rows of any length leave few
+    // lanes idle.  Group lane l covers samples 64*wi + 4l .. 64*wi + 4l + 3.
+    const uint32_t WS = (uint32_t)g.WS, N = (uint32_t)g.N;
+    const uint32_t tw = N * (uint32_t)g.O * WS;  // < 2^31 (validated)
+    const uint32_t fw = 4u * (uint32_t)seg + ((uint32_t)lane >> 4);
+    const bool wok = fw < tw;
+    const uint32_t srow = udiv(fw, g.ws_div);
+    const uint32_t wi = fw - srow * WS;
+    const uint32_t k = udiv(srow, g.n_div), j = srow - k * N;
     const int32_t M1 = (int32_t)(g.M - 1);
+    const int32_t i0 = 64 * (int32_t)wi + 4 * (lane & 15);
     const T *ra = static_cast<const T *>(d.labels) + (int64_t)srow * g.M;
-    const bool hasy = rowok && j + 1 < (int32_t)g.N, hasz = rowok && k + 1 < (int32_t)g.O;
+    const bool hasy = wok && j + 1 < N, hasz = wok && (int64_t)k + 1 < g.O;
     T a[4] = {0, 0, 0, 0}, b[4] = {0, 0, 0, 0}, c[4] = {0, 0, 0, 0};
     const T *vend = static_cast<const T *>(d.labels) + g.M * g.N * g.O;
-    if (rowok) load_quad<T, WIDE>(ra, i0, M1, vend, a);
+    if (wok) load_quad<T, WIDE>(ra, i0, M1, vend, a);
     if (hasy) load_quad<T, WIDE>(ra + g.M, i0, M1, vend, b);
     if (hasz) load_quad<T, WIDE>(ra + g.M * g.N, i0, M1, vend, c);
-    // the sample after the segment (read by lane 63 for the last x edge; a
-    // shared segment's rows end inside it)
+    // the sample after the word (its last x edge), read by the group's last lane
+    const bool last = (lane & 15) == 15;
+    const int32_t inext = 64 * (int32_t)wi + 64;
     T an = 0;
-    if (lane == 63 && rsh == 0) an = glb(ra)[(uint32_t)(256 * (m + 1) <= M1 ? 256 * (m + 1) : M1)];
+    if (last && wok && inext <= M1) an = glb(ra)[(uint32_t)inext];
     uint32_t ca[5], cb[4], cc[4];
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
@@ -463,10 +457,8 @@ __device__ __forceinline__ void edges_segment(const VolDesc &d, int64_t seg, int
         cb[e] = classify<MODE>((uint32_t)b[e], d.cs);
         cc[e] = classify<MODE>((uint32_t)c[e], d.cs);
     }
-    // from the next lane; across a row boundary of a shared segment it is
-    // never used (the row ends before the lane's last sample)
     ca[4] = __shfl_down(ca[0], 1u);
-    if (lane == 63) ca[4] = classify<MODE>((uint32_t)an, d.cs);
+    if (last) ca[4] = classify<MODE>((uint32_t)an, d.cs);
     uint32_t xn = 0, yn = 0, zn = 0;
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
@@ -476,18 +468,16 @@ __device__ __forceinline__ void edges_segment(const VolDesc &d, int64_t seg, int
         zn |= (hasz && (ca[e] != cc[e]) && i <= M1 ? 1u : 0u) << e;
     }
     const uint64_t X = merge_nibbles(xn, lane), Y = merge_nibbles(yn, lane), Z = merge_nibbles(zn, lane);
-    const int64_t wi = rsh == 0 ? 4 * (int64_t)m + (lane >> 4) : (int64_t)(i0 >> 6);
-    if ((lane & 15) == 0 && wi < g.WS && rowok) {
+    if ((lane & 15) == 0 && wok) {
         SN_GLOBAL uint64_t *P = glb(d.planes);
-        const int64_t ps = (int64_t)g.N * g.O * g.WS;
-        const int64_t o = (int64_t)srow * g.WS + wi;
-        P[o] = X;
-        P[ps + o] = Y;
-        P[2 * ps + o] = Z;
+        const int64_t ps = (int64_t)tw;
+        P[fw] = X;  // word wi of sample row srow
+        P[ps + fw] = Y;
+        P[2 * ps + fw] = Z;
     }
 }
 
-// spw: 256-sample segments per wave (the schedule's edge_segments); a tile is
+// spw: segments of four words per wave (the schedule's edge_segments); a tile is
 // kWavesPerBlock * spw segments
 template <typename T, int MODE, bool WIDE, class Src>
 __device__ __forceinline__ void edges_tile(const Src &a, int64_t tile_base, uint64_t *zero,
@@ -1321,11 +1311,6 @@ __device__ __forceinline__ void sweep_update(const SmoothDesc &s, uint32_t fc, c
 }
 
 
-__device__ __forceinline__ uint32_t udiv(uint32_t n, const UDiv &u)
-{
-    const uint32_t t = __umulhi(n, u.m);
-    return (t + ((n - t) >> u.s1)) >> u.s2;
-}
 
 // Hold the offset in the constraint region (a box of half-width d per axis, or
 // a sphere of radius d), store it, and in the mesh's last sweep also the

@@ -577,8 +577,8 @@ sn_status sn::validate_volume(const sn_volume *v)
         // the factors are bounded first, so that no product overflows int64
         const Geom g = make_geom(*v);
         if (g.R >= INT32_MAX || g.N * g.O >= INT32_MAX || g.R * g.W >= INT32_MAX ||
-            g.R * g.NB >= INT32_MAX || g.N * g.O * g.NSEG >= INT32_MAX)
-            return fail(SN_ETOOBIG, "volume has more than 2^31 cell words or sample segments");
+            g.R * g.NB >= INT32_MAX || g.N * g.O * g.WS >= INT32_MAX)
+            return fail(SN_ETOOBIG, "volume has more than 2^31 cell words or sample-row words");
     }
     return SN_OK;
 }
@@ -597,8 +597,9 @@ Geom sn::make_geom(const sn_volume &v)
     g.W = (int32_t)((g.CM + 63) / 64);
     g.NB = (g.W + kU - 1) / kU;
     g.WS = empty ? 0 : (g.M + 63) / 64;
-    g.NSEG = empty ? 0 : (g.M + 255) / 256;
-    g.RSH = empty ? 0 : (g.M <= 64 ? 2 : (g.M <= 128 ? 1 : 0));
+    // (clamped: make_geom also serves the validation of oversized volumes)
+    g.ws_div = make_udiv((uint32_t)std::max<int64_t>(std::min<int64_t>(g.WS, INT32_MAX), 1));
+    g.n_div = make_udiv((uint32_t)std::max<int64_t>(std::min<int64_t>(g.N, INT32_MAX), 1));
     return g;
 }
 
