@@ -69,8 +69,8 @@ constexpr int kCountWideV = 4;
 // words in 15.5 us narrow against 21 us wide)
 constexpr int64_t kCountWideWords = int64_t(1) << 18;
 
-// Division by a run-time constant d >= 1: n / d = (t + ((n - t) >> s1)) >> s2
-// with t = mulhi(n, m) (the round-up multiplier method for 32-bit operands).
+// Division of 32-bit values by an invariant divisor d >= 1 (Granlund and
+// Montgomery's method): with t = umulhi(n, m), n / d = (t + ((n - t) >> s1)) >> s2.
 struct UDiv {
     uint32_t d, m, s1, s2;
 };
@@ -142,8 +142,6 @@ struct VolDesc {
     int64_t P, Q, S;
 };
 
-// Division of 32-bit values by an invariant divisor d >= 1 (Granlund and
-// Montgomery's method): with t = umulhi(n, m), n / d = (t + ((n - t) >> s1)) >> s2.
 // One mesh's smoothing job.  Sweep 0 reads the CSR stencil (off, ids) and
 // writes nbr: per point the ids of its -y, +y, -z, +z stencil neighbours
 // (-1 where absent); later sweeps read nbr and take the -x / +x neighbours,
@@ -166,10 +164,11 @@ struct SmoothDesc {
     float *points;
     UDiv CM, CN;  // cells per row, rows per slice
     int32_t chunk;  // single large mesh: blocks an XCD takes in turn (about 1/16 of a slab)
-    // 1: the mesh's sweep data is far beyond the last-level cache (more than
-    // kSweepSmallPoints points, or the context's test threshold): read-once
-    // streams and offset stores take non-temporal hints, and a single mesh
-    // takes the slab-chunked block order
+    // 1: the sweep data is far beyond the last-level cache (more than
+    // kSweepSmallPoints points in the mesh, or in all meshes of a launch over
+    // many; or the context's test threshold): read-once streams and offset
+    // stores take non-temporal hints, and a single mesh takes the
+    // slab-chunked block order
     int32_t big;
     // neighbour-table form.  0: [P][4] int32 ids of the -y, +y, -z, +z
     // neighbours (-1 absent), read with the face byte.  Otherwise one 64-bit
@@ -245,8 +244,10 @@ hipError_t launch_emit(const VolDesc *d_descs, const SmoothDesc *d_sds, const in
 // block_prefix[v] = first block of volume v (kSweepBlock * K points per block, K
 // from sweep_chunks of the launch's points); it = 0 runs the first sweep
 // (zero input offsets, builds nbr)
+// (big: every mesh's descriptor says big, and the launch takes the
+// non-temporal form)
 hipError_t launch_jacobi(const SmoothDesc *d_sd, const int64_t *d_block_prefix, int32_t nvol,
-                         int64_t nblocks, int32_t it, int K, hipStream_t s);
+                         int64_t nblocks, int32_t it, int K, bool big, hipStream_t s);
 // sweeps 0 and 1 over many meshes: fused over the leading grid1 blocks (the
 // meshes of at least two sweeps), sweep 0 alone over blocks grid1 .. grid0
 hipError_t launch_jacobi_first2(const SmoothDesc *d_sd, const int64_t *d_block_prefix, int32_t nvol,
@@ -255,7 +256,7 @@ hipError_t launch_jacobi_first2(const SmoothDesc *d_sd, const int64_t *d_block_p
 // (sweep `it` launches grid[it] blocks; sweeps 0 and 1 as launch_jacobi_first2)
 hipError_t add_jacobi_nodes(hipGraph_t graph, const SmoothDesc *d_sd,
                             const int64_t *d_block_prefix, int32_t nvol, const int64_t *grid,
-                            int32_t iters, int K);
+                            int32_t iters, int K, bool big);
 // Copy `bytes` (rounded up to 8) from pinned host memory, given by its
 // device-side mapping, to device memory `dst` with a kernel on `s`; both
 // buffers 8-byte aligned and at least the rounded size.

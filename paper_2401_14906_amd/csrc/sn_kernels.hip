@@ -1699,12 +1699,14 @@ __device__ __forceinline__ void jacobi_body(const Src &a, int32_t it)
     }
 }
 
-template <int K>
+// BIG: 1 for a launch whose meshes' sweep data together is far beyond the
+// caches (every mesh's descriptor then says big), else 0
+template <int K, int BIG>
 __global__ __launch_bounds__(kSweepBlock) void k_jacobi(const SmoothDesc *__restrict__ sds,
                                                 const int64_t *__restrict__ prefix, int32_t nvol,
                                                 int32_t it)
 {
-    jacobi_body<K, false, -1>(ManySmooth{sds, prefix, nvol}, it);
+    jacobi_body<K, false, BIG>(ManySmooth{sds, prefix, nvol}, it);
 }
 
 template <int K, int BIG>
@@ -2021,13 +2023,16 @@ hipError_t launch_emit_one(const VolDesc &d, const SmoothDesc &sd, int64_t ntile
 
 template <int K>
 static void jacobi_k(const SmoothDesc *d_sd, const int64_t *d_block_prefix, int32_t nvol,
-                     int64_t nblocks, int32_t it, hipStream_t s)
+                     int64_t nblocks, int32_t it, bool big, hipStream_t s)
 {
     if (it == 0)
         hipLaunchKernelGGL(k_jacobi_first<K>, dim3((uint32_t)nblocks), dim3(kSweepBlock), 0, s, d_sd,
                            d_block_prefix, nvol, int64_t(0));
+    else if (big)
+        hipLaunchKernelGGL((k_jacobi<K, 1>), dim3((uint32_t)nblocks), dim3(kSweepBlock), 0, s, d_sd,
+                           d_block_prefix, nvol, it);
     else
-        hipLaunchKernelGGL(k_jacobi<K>, dim3((uint32_t)nblocks), dim3(kSweepBlock), 0, s, d_sd,
+        hipLaunchKernelGGL((k_jacobi<K, 0>), dim3((uint32_t)nblocks), dim3(kSweepBlock), 0, s, d_sd,
                            d_block_prefix, nvol, it);
 }
 
@@ -2046,13 +2051,13 @@ static void jacobi_one_k(const SmoothDesc &sd, int64_t nblocks, int32_t it, hipS
 }
 
 hipError_t launch_jacobi(const SmoothDesc *d_sd, const int64_t *d_block_prefix, int32_t nvol,
-                         int64_t nblocks, int32_t it, int K, hipStream_t s)
+                         int64_t nblocks, int32_t it, int K, bool big, hipStream_t s)
 {
     if (nblocks <= 0) return hipSuccess;
     if (K == 1)
-        jacobi_k<1>(d_sd, d_block_prefix, nvol, nblocks, it, s);
+        jacobi_k<1>(d_sd, d_block_prefix, nvol, nblocks, it, big, s);
     else
-        jacobi_k<2>(d_sd, d_block_prefix, nvol, nblocks, it, s);
+        jacobi_k<2>(d_sd, d_block_prefix, nvol, nblocks, it, big, s);
     return hipGetLastError();
 }
 
@@ -2105,7 +2110,7 @@ hipError_t launch_jacobi_first2(const SmoothDesc *d_sd, const int64_t *d_block_p
 // grid[1] blocks) and sweep 0 alone over the rest, then sweeps 2 ...
 hipError_t add_jacobi_nodes(hipGraph_t graph, const SmoothDesc *d_sd,
                             const int64_t *d_block_prefix, int32_t nvol, const int64_t *grid,
-                            int32_t iters, int K)
+                            int32_t iters, int K, bool big)
 {
     hipGraphNode_t prev = nullptr;
     auto add = [&](void *func, int64_t nblocks, void **args) -> hipError_t {
@@ -2144,10 +2149,11 @@ hipError_t add_jacobi_nodes(hipGraph_t graph, const SmoothDesc *d_sd,
         int64_t block0 = 0;
         void *args_first[] = {&d_sd, &d_block_prefix, &nvol, &block0};
         void *args[] = {&d_sd, &d_block_prefix, &nvol, &it};
-        const hipError_t e = it == 0 ? add(first(), grid[it], args_first)
-                                     : add(K == 1 ? reinterpret_cast<void *>(&k_jacobi<1>)
-                                                  : reinterpret_cast<void *>(&k_jacobi<2>),
-                                           grid[it], args);
+        void *sweep = K == 1 ? (big ? reinterpret_cast<void *>(&k_jacobi<1, 1>)
+                                    : reinterpret_cast<void *>(&k_jacobi<1, 0>))
+                             : (big ? reinterpret_cast<void *>(&k_jacobi<2, 1>)
+                                    : reinterpret_cast<void *>(&k_jacobi<2, 0>));
+        const hipError_t e = it == 0 ? add(first(), grid[it], args_first) : add(sweep, grid[it], args);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;

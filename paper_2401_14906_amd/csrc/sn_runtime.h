@@ -218,9 +218,10 @@ sn_status smooth_one(sn_ctx *c, sn_mesh *m, const sn_smooth_params *p, hipStream
 sn_status ensure_smooth_buffers(sn_mesh *m);
 // smoothing descriptor of a mesh for the given parameters
 void fill_smooth_desc(const sn_mesh *m, const sn_smooth_params &p, SmoothDesc *sd);
-// sweep `it` of grid.size() sweeps launches grid[it] blocks
+// sweep `it` of grid.size() sweeps launches grid[it] blocks; big: the
+// non-temporal form (every descriptor's big set)
 sn_status run_sweeps(sn_ctx *c, const SmoothDesc *d_sd, const int64_t *d_bp, int32_t nvol,
-                     const std::vector<int64_t> &grid, int K, hipStream_t s);
+                     const std::vector<int64_t> &grid, int K, bool big, hipStream_t s);
 sn_status run_sweeps_one(sn_ctx *c, const SmoothDesc &sd, int64_t nblocks, int K, hipStream_t s);
 sn_status mesh_mark(sn_mesh *m, hipStream_t s);
 // mesh_mark for meshes[0..n) (null entries skipped) with one event recorded once

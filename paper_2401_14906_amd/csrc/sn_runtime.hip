@@ -1051,12 +1051,17 @@ sn_status sn::extract_many(sn_ctx *c, const sn_volume *vols, int32_t n, hipStrea
                                           : (total_words >= c->count_wide_words ? kCountWideV : 1);
     for (int32_t k = 0; k < n; ++k)
         ctile_prefix[k + 1] = ctile_prefix[k] + (ctile_prefix[k + 1] + cv * kCountBlock - 1) / (cv * kCountBlock);
-    // groups: [gbeg[i], gbeg[i+1]) of the launch order share a key
-    std::vector<int32_t> gbeg;
-    for (int32_t k = 0; k < n; ++k)
+    // groups: [gbeg[i], gbeg[i+1]) of the launch order share a key (k_edges);
+    // k_generate does not depend on the row form, so its groups [ggbeg[i],
+    // ggbeg[i+1]) join the wide and narrow volumes of a key (adjacent in the order)
+    std::vector<int32_t> gbeg, ggbeg;
+    for (int32_t k = 0; k < n; ++k) {
         if (k == 0 || key(order[k]) != key(order[k - 1])) gbeg.push_back(k);
+        if (k == 0 || (key(order[k]) >> 1) != (key(order[k - 1]) >> 1)) ggbeg.push_back(k);
+    }
     gbeg.push_back(n);
-    const int32_t ngroups = (int32_t)gbeg.size() - 1;
+    ggbeg.push_back(n);
+    const int32_t ngroups = (int32_t)gbeg.size() - 1, nggroups = (int32_t)ggbeg.size() - 1;
 
     const int64_t nctiles = ctile_prefix[n];
     // k_count writes the per-volume totals, then a stamp, straight into
@@ -1192,8 +1197,8 @@ sn_status sn::extract_many(sn_ctx *c, const sn_volume *vols, int32_t n, hipStrea
         VolDesc *d_desc2 = reinterpret_cast<VolDesc *>(d_b);
         {
             ProfScope ps(c, "k_generate", s);
-            for (int32_t gi = 0; gi < ngroups; ++gi) {
-                const int32_t k0 = gbeg[gi], k1 = gbeg[gi + 1];
+            for (int32_t gi = 0; gi < nggroups; ++gi) {
+                const int32_t k0 = ggbeg[gi], k1 = ggbeg[gi + 1];
                 int64_t gp = 0, gw = 0;
                 for (int32_t k = k0; k < k1; ++k) gp += hd[k].P, gw += hd[k].g.R * hd[k].g.W;
                 const bool staged = gp >= kGenStagedPointsPerWord * gw;
@@ -1286,7 +1291,7 @@ void sn::fill_smooth_desc(const sn_mesh *m, const sn_smooth_params &p, SmoothDes
 // Sweeps over `nvol` meshes (descriptor array), replayed from a HIP graph of
 // kernel nodes built for this call; sweep `it` launches grid[it] blocks
 sn_status sn::run_sweeps(sn_ctx *c, const SmoothDesc *d_sd, const int64_t *d_bp, int32_t nvol,
-                         const std::vector<int64_t> &grid, int K, hipStream_t s)
+                         const std::vector<int64_t> &grid, int K, bool big, hipStream_t s)
 {
     const int32_t iters = (int32_t)grid.size();
     if (iters <= 0 || grid[0] <= 0) return SN_OK;
@@ -1303,7 +1308,7 @@ sn_status sn::run_sweeps(sn_ctx *c, const SmoothDesc *d_sd, const int64_t *d_bp,
         }
         for (int32_t it = it0; it < iters && grid[it] > 0; ++it) {
             ProfScope ps(c, each ? "k_jacobi" : "", s, each ? 1 : 0);
-            HIP_TRY(launch_jacobi(d_sd, d_bp, nvol, grid[it], it, K, s));
+            HIP_TRY(launch_jacobi(d_sd, d_bp, nvol, grid[it], it, K, big, s));
         }
         return SN_OK;
     }
@@ -1315,7 +1320,7 @@ sn_status sn::run_sweeps(sn_ctx *c, const SmoothDesc *d_sd, const int64_t *d_bp,
     hipGraph_t graph;
     hipGraphExec_t exec = nullptr;
     HIP_TRY(hipGraphCreate(&graph, 0));
-    hipError_t e = add_jacobi_nodes(graph, d_sd, d_bp, nvol, grid.data(), iters, K);
+    hipError_t e = add_jacobi_nodes(graph, d_sd, d_bp, nvol, grid.data(), iters, K, big);
     if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     if (e == hipSuccess) e = hipGraphLaunch(exec, s);
@@ -1470,10 +1475,13 @@ sn_status sn::smooth_many(sn_ctx *c, sn_mesh **ms, const sn_smooth_params *pv, i
     VolDesc *d_vd = reinterpret_cast<VolDesc *>(d_up + sizeof(SmoothDesc) * n);
     int64_t *d_p = reinterpret_cast<int64_t *>(d_up + (sizeof(SmoothDesc) + sizeof(VolDesc)) * n);
     bool need_emit = false;
+    // the launch's sweep data together decides the non-temporal form
+    const bool big = all_points > c->sweep_small_points;
     for (int32_t k = 0; k < n; ++k) {
         sn_mesh *m = ms[ord[k]];
         SmoothDesc &h = h_sd[k];
         fill_smooth_desc(m, pv[ord[k]], &h);
+        h.big = big ? 1 : 0;
         h.iters = iters_of(ord[k]);
         need_emit = need_emit || h.iters == 0 || !h.pcell;
         m->final_delta =
@@ -1492,7 +1500,7 @@ sn_status sn::smooth_many(sn_ctx *c, sn_mesh **ms, const sn_smooth_params *pv, i
     };
     if (hipError_t e = stage_upload(d_up, h_up, up, s); e != hipSuccess)
         return device_fail(e, "descriptor upload");
-    sn_status st = run_sweeps(c, d_sd, d_p, n, grid, K, s);
+    sn_status st = run_sweeps(c, d_sd, d_p, n, grid, K, big, s);
     if (st != SN_OK) {
         scr.retire(s);
         return st;
