@@ -100,7 +100,8 @@ typedef struct sn_server sn_server;
 
 /* One label volume and its extraction parameters (Sec. 2.1, 2.2, 2.5). */
 typedef struct sn_volume {
-    const void *labels;        /* device, dims[0]*dims[1]*dims[2] values, x fastest       */
+    const void *labels;        /* device, dims[0]*dims[1]*dims[2] values, x fastest,
+                                  aligned to the dtype                                    */
     int32_t dtype;             /* sn_dtype: bytes per label                               */
     int64_t dims[3];           /* M, N, O >= 1; a dim below 2 gives an empty mesh (O = 1
                                   for SN_LINES)                                            */

@@ -370,42 +370,91 @@ __device__ __forceinline__ void load_quad(const T *row_, int32_t i0, int32_t M1,
             v[0] = (T)(q & 0xffu), v[1] = (T)((q >> 8) & 0xffu), v[2] = (T)((q >> 16) & 0xffu),
             v[3] = (T)(q >> 24);
         }
-    } else {
-        // rows of any alignment: the dword-aligned window holding samples
-        // i0 .. i0+3, in one load (2, 3 or 4 dwords for 1-, 2- or 4-byte
-        // labels), then the samples cut out of it; values of samples past
-        // the row end are never used (they read the next row).  Only where
-        // the window would pass the end of the volume are the samples read
-        // one by one, clamped to the row.
+    } else if constexpr (sizeof(T) == 4) {
+        // rows of any alignment: the four samples as one 4-dword load (labels
+        // are 4-byte aligned); only where it would pass the end of the volume
+        // are they read one by one, clamped to the row
         if (i0 > M1) {
 #pragma unroll
             for (int e = 0; e < 4; ++e) v[e] = 0;
             return;
         }
-        constexpr int ND = sizeof(T) == 1 ? 2 : (sizeof(T) == 2 ? 3 : 4);
         const uintptr_t a = reinterpret_cast<uintptr_t>(row_ + i0);
-        const uintptr_t ab = a & ~uintptr_t(3);
-        if (ab + 4 * ND <= reinterpret_cast<uintptr_t>(vol_end)) {
-            const SN_GLOBAL uint32_t *wp = reinterpret_cast<const SN_GLOBAL uint32_t *>(ab);
-            const uint32_t sh = (uint32_t)(a & 3u);
-            if constexpr (sizeof(T) == 1) {
-                const v2u_a4 q = *reinterpret_cast<const SN_GLOBAL v2u_a4 *>(wp);
-                const uint32_t x = __builtin_amdgcn_alignbyte(q.y, q.x, sh);
-                v[0] = (T)(x & 0xffu), v[1] = (T)((x >> 8) & 0xffu), v[2] = (T)((x >> 16) & 0xffu),
-                v[3] = (T)(x >> 24);
-            } else if constexpr (sizeof(T) == 2) {
-                const v3u_a4 q = *reinterpret_cast<const SN_GLOBAL v3u_a4 *>(wp);
-                const uint32_t x0 = __builtin_amdgcn_alignbyte(q.y, q.x, sh);
-                const uint32_t x1 = __builtin_amdgcn_alignbyte(q.z, q.y, sh);
-                v[0] = (T)(x0 & 0xffffu), v[1] = (T)(x0 >> 16), v[2] = (T)(x1 & 0xffffu), v[3] = (T)(x1 >> 16);
-            } else {
-                const v4u_a4 q = *reinterpret_cast<const SN_GLOBAL v4u_a4 *>(wp);
-                v[0] = (T)q.x, v[1] = (T)q.y, v[2] = (T)q.z, v[3] = (T)q.w;
-            }
+        if (a + 16 <= reinterpret_cast<uintptr_t>(vol_end)) {
+            const v4u_a4 q = *reinterpret_cast<const SN_GLOBAL v4u_a4 *>(a);
+            v[0] = (T)q.x, v[1] = (T)q.y, v[2] = (T)q.z, v[3] = (T)q.w;
         } else {
 #pragma unroll
             for (int e = 0; e < 4; ++e) v[e] = row[(uint32_t)(i0 + e <= M1 ? i0 + e : M1)];
         }
+    } else {
+        // 1- and 2-byte labels in rows of any alignment: win_issue/win_finish
+        static_assert(sizeof(T) == 4, "narrow 1- and 2-byte rows take the window loads");
+    }
+}
+
+// Narrow rows of 1- and 2-byte labels: samples i0 .. i0+3 lie in the
+// dword-aligned window of ND = 2 or 3 dwords at or below their address, and
+// its last dword is the first of the next lane's window (the next four
+// samples of the row: the lanes of one 16-lane group share a row and its
+// activity).  A lane loads ND - 1 dwords and takes the last from the next
+// lane; the group's last lane, and a lane whose next lane's window would pass
+// the end of the volume, load it themselves.  Samples past the row end are
+// loaded (the next row's) but never used.  Where a lane's own window would
+// pass the end of the volume, its samples are read one by one, clamped to the
+// row.  Two steps, so that the loads of all three rows are in flight before
+// the exchange between lanes waits for them.
+struct Win {
+    uint32_t w0, w1, wl, sh;
+    bool inb, own;
+};
+
+template <typename T>
+__device__ __forceinline__ Win win_issue(const T *row_, int32_t i0, const T *vol_end, int lane, bool active)
+{
+    constexpr int ND = sizeof(T) == 1 ? 2 : 3;
+    Win w{0u, 0u, 0u, 0u, false, false};
+    const uintptr_t a = reinterpret_cast<uintptr_t>(row_ + i0);
+    const uintptr_t ab = a & ~uintptr_t(3);
+    const uintptr_t end = reinterpret_cast<uintptr_t>(vol_end);
+    w.sh = (uint32_t)(a & 3u);
+    w.inb = active && ab + 4 * ND <= end;
+    w.own = (lane & 15) == 15 || ab + 4 * (ND - 1) + 4 * ND > end;
+    if (w.inb) {
+        const SN_GLOBAL uint32_t *wp = reinterpret_cast<const SN_GLOBAL uint32_t *>(ab);
+        if constexpr (ND == 2) {
+            w.w0 = wp[0];
+        } else {
+            const v2u_a4 q = *reinterpret_cast<const SN_GLOBAL v2u_a4 *>(wp);
+            w.w0 = q.x, w.w1 = q.y;
+        }
+        if (w.own) w.wl = wp[ND - 1];
+    }
+    return w;
+}
+
+// every lane of the wave runs this (the exchange reads the next lane)
+template <typename T>
+__device__ __forceinline__ void win_finish(const Win &w, const T *row_, int32_t i0, int32_t M1, bool active,
+                                           T (&v)[4])
+{
+    // the next lane's first dword (wave_shl:1; lane 63 is a group's last)
+    const uint32_t nx = (uint32_t)__builtin_amdgcn_mov_dpp((int)w.w0, 0x130, 0xf, 0xf, false);
+    if (w.inb) {
+        const uint32_t wl = w.own ? w.wl : nx;
+        if constexpr (sizeof(T) == 1) {
+            const uint32_t x = __builtin_amdgcn_alignbyte(wl, w.w0, w.sh);
+            v[0] = (T)(x & 0xffu), v[1] = (T)((x >> 8) & 0xffu), v[2] = (T)((x >> 16) & 0xffu),
+            v[3] = (T)(x >> 24);
+        } else {
+            const uint32_t x0 = __builtin_amdgcn_alignbyte(w.w1, w.w0, w.sh);
+            const uint32_t x1 = __builtin_amdgcn_alignbyte(wl, w.w1, w.sh);
+            v[0] = (T)(x0 & 0xffffu), v[1] = (T)(x0 >> 16), v[2] = (T)(x1 & 0xffffu), v[3] = (T)(x1 >> 16);
+        }
+    } else if (active) {
+        const SN_GLOBAL T *row = glb(row_);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) v[e] = row[(uint32_t)(i0 + e <= M1 ? i0 + e : M1)];
     }
 }
 
@@ -442,9 +491,18 @@ __device__ __forceinline__ void edges_segment(const VolDesc &d, int64_t seg, int
     const bool hasy = wok && j + 1 < N, hasz = wok && (int64_t)k + 1 < g.O;
     T a[4] = {0, 0, 0, 0}, b[4] = {0, 0, 0, 0}, c[4] = {0, 0, 0, 0};
     const T *vend = static_cast<const T *>(d.labels) + g.M * g.N * g.O;
-    if (wok) load_quad<T, WIDE>(ra, i0, M1, vend, a);
-    if (hasy) load_quad<T, WIDE>(ra + g.M, i0, M1, vend, b);
-    if (hasz) load_quad<T, WIDE>(ra + g.M * g.N, i0, M1, vend, c);
+    if constexpr (!WIDE && sizeof(T) <= 2) {
+        const Win wa = win_issue<T>(ra, i0, vend, lane, wok);
+        const Win wb = win_issue<T>(ra + g.M, i0, vend, lane, hasy);
+        const Win wc = win_issue<T>(ra + g.M * g.N, i0, vend, lane, hasz);
+        win_finish<T>(wa, ra, i0, M1, wok, a);
+        win_finish<T>(wb, ra + g.M, i0, M1, hasy, b);
+        win_finish<T>(wc, ra + g.M * g.N, i0, M1, hasz, c);
+    } else {
+        if (wok) load_quad<T, WIDE>(ra, i0, M1, vend, a);
+        if (hasy) load_quad<T, WIDE>(ra + g.M, i0, M1, vend, b);
+        if (hasz) load_quad<T, WIDE>(ra + g.M * g.N, i0, M1, vend, c);
+    }
     // the sample after the word (its last x edge), read by the group's last lane
     const bool last = (lane & 15) == 15;
     const int32_t inext = 64 * (int32_t)wi + 64;

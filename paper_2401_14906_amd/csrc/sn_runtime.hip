@@ -572,6 +572,8 @@ sn_status sn::validate_volume(const sn_volume *v)
     }
     const bool empty = v->dims[0] < 2 || v->dims[1] < 2 || (v->prim != SN_LINES && v->dims[2] < 2);
     if (!v->labels && !empty) return fail(SN_EINVAL, "labels is NULL");
+    if ((reinterpret_cast<uintptr_t>(v->labels) & (uintptr_t)(v->dtype - 1)) != 0)
+        return fail(SN_EINVAL, "labels is not aligned to its dtype");
     {
         // the kernels index rows, words and batches of one volume with int32;
         // the factors are bounded first, so that no product overflows int64

@@ -93,3 +93,26 @@ def test_struct_layouts_match_header(tmp_path):
         assert int(got[name]) == ctypes.sizeof(st), name
         for f, _ in st._fields_:
             assert int(got[f"{name}.{f}"]) == getattr(st, f).offset, f"{name}.{f}"
+
+
+def test_volume_checks_without_gpu(lib):
+    """Volume validation (run by sn_noalloc_scratch_bytes, which needs no
+    device): labels must be aligned to their dtype; sizes follow the dims."""
+    import paper_2401_14906_amd as sn
+
+    def vol(ptr, dtype, dims=(37, 20, 9)):
+        v = sn.sn_volume()
+        v.labels = ptr
+        v.dtype = dtype
+        v.dims[0], v.dims[1], v.dims[2] = dims
+        v.spacing[0] = v.spacing[1] = v.spacing[2] = 1.0
+        v.prim = sn.SN_QUADS
+        return v
+
+    base = 1 << 20  # never dereferenced: no compute call is made
+    for dtype in (1, 2, 4):
+        assert lib.sn_noalloc_scratch_bytes(ctypes.byref(vol(base + dtype, dtype))) > 0
+        if dtype > 1:
+            assert lib.sn_noalloc_scratch_bytes(ctypes.byref(vol(base + 1, dtype))) == -1
+    assert lib.sn_noalloc_scratch_bytes(ctypes.byref(vol(base + 2, 4))) == -1
+    assert b"aligned" in lib.sn_last_error()

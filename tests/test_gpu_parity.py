@@ -555,3 +555,30 @@ def test_unpacked_neighbour_table(sn, torch, monkeypatch, form):
                     assert np.array_equal(getattr(g, f), getattr(plain[k], f)), (k, f)
     finally:
         c.close()
+
+
+@pytest.mark.gpu
+def test_labels_at_unaligned_offsets(ctx, sn, torch):
+    """Label volumes that start at every element offset of a larger buffer
+    (base addresses not 4- or 16-byte aligned: the narrow row loads), with
+    rows of odd and of 4-multiple lengths, equal the oracle."""
+    import oracle
+
+    rng = np.random.default_rng(77)
+    for dt, offs in ((np.uint8, (1, 2, 3, 5)), (np.uint16, (1, 2, 3)), (np.uint32, (1, 2, 3))):
+        for dims in ((37, 11, 7), (64, 9, 6), (200, 5, 4)):
+            vol = synth.blocky_tiny(rng, dims, 6, dt)
+            n = vol.size
+            for off in offs:
+                announce(f"unaligned: {np.dtype(dt).name} dims={dims} offset={off}")
+                buf = np.zeros(n + 8, dt)
+                buf[off:off + n] = vol.ravel()
+                tb = sn.to_device(buf)
+                t = tb[off:off + n].view(vol.shape)
+                m = ctx.extract(t)
+                ctx.smooth(m, iterations=3, relaxation=0.5, constraint=1.0)
+                g = m.to_host()
+                o = oracle.extract(vol)
+                check_mesh(g, o, vol.dtype)
+                check_smooth(g, o, 3, 0.5, 1.0)
+                m.free()
