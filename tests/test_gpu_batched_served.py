@@ -145,6 +145,40 @@ def test_batched_schedules_and_repeat(ctx, sn):
         ctx.set_batches_per_wave(0)
 
 
+def test_meshes_freed_while_their_batch_runs(ctx, sn):
+    """The meshes of one batch call share a completion event, and a freed
+    mesh's blocks go back to the pool to be reused once that event has
+    completed.  Meshes freed while their batch still runs, a batch mesh
+    smoothed again on its own (it then takes an event of its own) whose batch
+    mates are freed before it, and later calls that reuse the freed blocks:
+    every mesh keeps the plain path's bytes."""
+    vols = mixed_volumes(24, 16)
+    ts = [sn.to_device(v["labels"]) for v in vols]
+    alone = [plain_result(ctx, sn, t, v) for t, v in zip(ts, vols)]
+    specs = [dict(labels=t, spacing=v["spacing"], selected=v["selected"],
+                  background=v["background"]) for t, v in zip(ts, vols)]
+    params = [v["params"] for v in vols]
+    for rep in range(3):
+        announce(f"free while running, round {rep}")
+        ms = ctx.batch_submit(specs, params)
+        for m in ms[::2]:
+            m.free()  # its batch is most likely still running
+        again = ctx.batch_submit(specs, params)
+        keep = ms[1]
+        it, lam, d = vols[1]["params"]
+        ctx.smooth(keep, iterations=it, relaxation=lam, constraint=d)
+        for m in ms[3::2]:
+            m.free()
+        plain = [plain_result(ctx, sn, ts[k], vols[k]) for k in (0, 2, 4)]
+        same_mesh(keep.to_host(), alone[1], f"round {rep}: re-smoothed batch mesh")
+        keep.free()
+        for k, m in enumerate(again):
+            same_mesh(m.to_host(), alone[k], f"round {rep}: second batch volume {k}")
+            m.free()
+        for g, k in zip(plain, (0, 2, 4)):
+            same_mesh(g, alone[k], f"round {rep}: plain volume {k}")
+
+
 def test_served_equals_alone(ctx, sn, torch):
     """Requests submitted in a burst are fused into batches on two streams; every
     result equals the plain result for the same request run alone."""
