@@ -286,7 +286,10 @@ int64_t sn_noalloc_scratch_bytes(const sn_volume *vol);
  * HIP-graph replay of the smoothing sweeps for the whole batch, with per-volume
  * sweep counts.  per_vol may be NULL (no smoothing).  Each out_meshes[v] equals
  * what sn_extract + sn_smooth give for volume v alone.  On failure no mesh is
- * returned. */
+ * returned.  The meshes of one call share one completion event; each can be
+ * freed on its own at any time.  With SN_BATCH_SWEEPS=eager in the
+ * environment when the context is created, the sweeps are launched one by one
+ * instead of from a graph (same results). */
 sn_status sn_batch_submit(sn_ctx *ctx, const sn_volume *vols, const sn_smooth_params *per_vol,
                           int32_t n, void *stream, sn_mesh **out_meshes);
 
