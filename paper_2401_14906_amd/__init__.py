@@ -279,6 +279,82 @@ def make_volume(labels, spacing=(1.0, 1.0, 1.0), origin=(0.0, 0.0, 0.0), selecte
     return v, (labels, sel)
 
 
+def _np_layout(cls, formats):
+    """A numpy record type laid out as the ctypes structure `cls`."""
+    names = [n for n, _ in cls._fields_]
+    return np.dtype({"names": names, "formats": formats,
+                     "offsets": [getattr(cls, n).offset for n in names],
+                     "itemsize": ctypes.sizeof(cls)})
+
+
+_VOL_NP = _np_layout(sn_volume, [np.uint64, np.int32, (np.int64, 3), (np.float64, 3),
+                                 (np.float64, 3), np.uint64, np.int32, np.uint32, np.int32])
+_PAR_NP = _np_layout(sn_smooth_params, [np.int32, np.float32, np.float32, np.int32])
+_VOLUME_KEYS = frozenset(("labels", "spacing", "origin", "selected", "background", "prim"))
+
+
+def volume_array(volumes):
+    """sn_volume[n] for dicts of make_volume's keyword arguments, as one numpy
+    record array (the same checks and values as make_volume, without a ctypes
+    structure per volume); returns (array, keepalive)."""
+    import torch
+
+    n = len(volumes)
+    a = np.zeros(n, _VOL_NP)
+    ptr, size, dims, prim = [0] * n, [0] * n, [None] * n, [SN_QUADS] * n
+    keep = []
+    a["spacing"] = 1.0
+    for k, d in enumerate(volumes):
+        if not _VOLUME_KEYS.issuperset(d):
+            raise TypeError(f"unknown volume fields {sorted(set(d) - _VOLUME_KEYS)}")
+        labels = d["labels"]
+        if not isinstance(labels, torch.Tensor) or not labels.is_cuda:
+            raise TypeError("labels must be a CUDA (HIP) torch tensor")
+        nd = labels.dim()
+        if nd not in (2, 3) or not labels.is_contiguous():
+            raise ValueError("labels must be a contiguous 3-D tensor (O, N, M) or image (N, M)")
+        pk = int(d.get("prim", SN_QUADS))
+        if nd == 2:
+            if pk not in (SN_QUADS, SN_LINES):
+                raise ValueError("an image is contoured with segments (SN_LINES)")
+            pk = SN_LINES
+        b = labels.element_size()
+        if b not in (1, 2, 4) or labels.is_floating_point():
+            raise TypeError("labels must hold 8-, 16- or 32-bit integers")
+        O, N, M = (1, *labels.shape) if nd == 2 else labels.shape
+        ptr[k], size[k], dims[k], prim[k] = labels.data_ptr(), b, (M, N, O), pk
+        sel = None
+        if "spacing" in d:
+            a["spacing"][k] = [float(x) for x in d["spacing"]]
+        if "origin" in d:
+            a["origin"][k] = [float(x) for x in d["origin"]]
+        if len(d.get("selected", ())):
+            sel = np.ascontiguousarray(np.asarray(list(d["selected"]), dtype=np.uint32))
+            a["selected"][k] = sel.ctypes.data
+            a["n_selected"][k] = sel.size
+        if "background" in d:
+            a["background"][k] = int(d["background"])
+        keep.append((labels, sel))
+    if n:
+        a["labels"], a["dtype"], a["dims"], a["prim"] = ptr, size, dims, prim
+    return a, keep
+
+
+def params_array(params):
+    """sn_smooth_params[n] for (iterations, relaxation, constraint[, shape])
+    tuples, as one numpy record array."""
+    n = len(params)
+    a = np.zeros(n, _PAR_NP)
+    it, lam, d, sh = [0] * n, [0.0] * n, [0.0] * n, [0] * n
+    for k, p in enumerate(params):
+        it[k], lam[k], d[k] = int(p[0]), float(p[1]), float(p[2])
+        if len(p) > 3:
+            sh[k] = SHAPES[p[3]] if isinstance(p[3], str) else int(p[3])
+    if n:
+        a["iterations"], a["relaxation"], a["constraint"], a["shape"] = it, lam, d, sh
+    return a
+
+
 # constraint regions of the smoothing (sn_constraint_shape)
 SHAPES = {"box": 0, "sphere": 1}
 
@@ -372,19 +448,16 @@ class Context:
         """volumes: dicts of make_volume keyword arguments; params: (iters, relax, constr[,
         shape])."""
         n = len(volumes)
-        arr = (sn_volume * n)()
-        keep = []
-        for k, d in enumerate(volumes):
-            v, kp = make_volume(**d)
-            arr[k] = v
-            keep.append(kp)
+        arr, keep = volume_array(volumes)
         parr = None
         if params is not None:
-            parr = (sn_smooth_params * n)()
-            for k, p in enumerate(params):
-                parr[k] = smooth_params(*p)
+            if len(params) != n:
+                raise ValueError("one smoothing parameter tuple per volume")
+            pa = params_array(params)
+            parr = pa.ctypes.data_as(ctypes.POINTER(sn_smooth_params))
         outs = (ctypes.c_void_p * n)()
-        _check(_lib.sn_batch_submit(self._h, arr, parr, n, _stream_handle(stream), outs))
+        _check(_lib.sn_batch_submit(self._h, arr.ctypes.data_as(ctypes.POINTER(sn_volume)), parr, n,
+                                    _stream_handle(stream), outs))
         return [Mesh(outs[k], keep[k]) for k in range(n)]
 
     def autotune(self, labels, spacing=(1.0, 1.0, 1.0), selected=(), background=0,

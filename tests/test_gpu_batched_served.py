@@ -103,6 +103,37 @@ def plain_result(ctx, sn, t, v):
     return g
 
 
+def test_batch_marshalling_matches_single(sn, torch):
+    """The batch call's record arrays hold, field for field, what the
+    single-volume structures hold (the selected labels by content)."""
+    import ctypes
+
+    rng = np.random.default_rng(5)
+    specs = [dict(labels=sn.to_device(rng.integers(0, 9, (4, 5, 7)).astype(np.uint8))),
+             dict(labels=sn.to_device(rng.integers(0, 9, (3, 6)).astype(np.uint16)),
+                  spacing=(0.5, 2, 3), origin=(1, -2, 7.5)),
+             dict(labels=sn.to_device(rng.integers(0, 9, (6, 5, 4)).astype(np.uint32)),
+                  selected=(3, 1, 3), background=2, prim=sn.SN_TRIS)]
+    arr, keep = sn.volume_array(specs)
+    for k, d in enumerate(specs):
+        v, kp = sn.make_volume(**d)
+        for f in ("labels", "dtype", "n_selected", "background", "prim"):
+            assert int(arr[f][k]) == int(getattr(v, f) or 0), (k, f)
+        for f in ("dims", "spacing", "origin"):
+            assert list(arr[f][k]) == list(getattr(v, f)), (k, f)
+        if v.n_selected:
+            got = np.ctypeslib.as_array(ctypes.cast(int(arr["selected"][k]),
+                                                    ctypes.POINTER(ctypes.c_uint32)), (v.n_selected,))
+            assert list(got) == list(v.selected[:v.n_selected])
+    pa = sn.params_array([(5, 0.25, 0.8), (0, 1.0, 0.0, "sphere"), (7, 0.5, 1.0, 1)])
+    for k, p in enumerate([(5, 0.25, 0.8), (0, 1.0, 0.0, "sphere"), (7, 0.5, 1.0, 1)]):
+        q = sn.smooth_params(*p)
+        assert (int(pa["iterations"][k]), float(pa["relaxation"][k]), float(pa["constraint"][k]),
+                int(pa["shape"][k])) == (q.iterations, q.relaxation, q.constraint, q.shape)
+    with pytest.raises(TypeError):
+        sn.volume_array([dict(labels=specs[0]["labels"], spacng=(1, 1, 1))])
+
+
 def test_batched_equals_plain(ctx, sn):
     vols = mixed_volumes(21, 40)
     ts = [sn.to_device(v["labels"]) for v in vols]
