@@ -1513,16 +1513,24 @@ __device__ __forceinline__ uint32_t slab_chunk_block(uint32_t b, uint32_t nb, ui
 
 // Logical block of a sweep.  Small meshes, whose sweep data fits the
 // last-level cache, gain from XCD-contiguous blocks (stencil neighbours in
-// the same L2), and so does a launch over many meshes (with one chunk per
-// wave; the hardware's order with two was 10.0 ms against 8.3 ms for a batch
-// of 64 volumes).  A single large mesh streams from HBM and takes the
-// slab-chunked order.
-template <int K>
-__device__ __forceinline__ int64_t sweep_block(const ManySmooth &, uint32_t b, uint32_t nb)
+// the same L2), and so does a launch over many meshes whose sweep data
+// together fits (with one chunk per wave; the hardware's order with two was
+// 10.0 ms against 8.3 ms for a batch of 64 volumes).  A single large mesh
+// streams from HBM and takes the slab-chunked order, and so does a launch
+// over many meshes whose data together is beyond the caches, with runs of
+// kManySweepChunk blocks (64-volume batch of 20.5 M points: 4.19-4.29 ms of
+// sweeps for runs of 64 to 1024 blocks, 4.38 ms XCD-contiguous, 4.47 ms in
+// hardware order).  BIG as for jacobi_body; a launch over many meshes gives
+// all of them the same big.
+constexpr uint32_t kManySweepChunk = 128;
+template <int K, int BIG>
+__device__ __forceinline__ int64_t sweep_block(const ManySmooth &a, uint32_t b, uint32_t nb)
 {
-    return K == 1 ? xcd_block(b, nb) : (int64_t)b;
+    if (K != 1) return (int64_t)b;
+    const bool big = BIG < 0 ? a.sds[0].big != 0 : BIG == 1;
+    return big ? (int64_t)slab_chunk_block(b, nb, kManySweepChunk) : xcd_block(b, nb);
 }
-template <int K>
+template <int K, int BIG>
 __device__ __forceinline__ int64_t sweep_block(const OneSmooth &a, uint32_t b, uint32_t nb)
 {
     return !a.s.big ? xcd_block(b, nb) : (int64_t)slab_chunk_block(b, nb, (uint32_t)a.s.chunk);
@@ -1535,7 +1543,7 @@ __device__ __forceinline__ void jacobi_first_body(const Src &a, int64_t block0)
 {
     const uint32_t nb = sweep_blocks<K>(a);
     if (blockIdx.x >= nb) return;
-    const int64_t b = block0 + sweep_block<K>(a, blockIdx.x, nb);
+    const int64_t b = block0 + sweep_block<K, -1>(a, blockIdx.x, nb);
     int64_t first;
     const SmoothDesc &s = smooth_of(a, b, first);
     if (s.iters < 1) return;
@@ -1609,7 +1617,7 @@ __device__ __forceinline__ void jacobi_body(const Src &a, int32_t it)
 {
     const uint32_t nbl = sweep_blocks<K>(a);
     if (blockIdx.x >= nbl) return;
-    const int64_t b = sweep_block<K>(a, blockIdx.x, nbl);
+    const int64_t b = sweep_block<K, BIG>(a, blockIdx.x, nbl);
     int64_t first;
     const SmoothDesc &s = smooth_of(a, b, first);
     if (it >= s.iters) return;  // this mesh has finished its sweeps
