@@ -140,6 +140,10 @@ struct sn_ctx {
     // SN_TEST_SWEEP_UNPACKED: every mesh keeps the 16-byte neighbour table
     // (the form of meshes whose id distances do not fit the packed word)
     bool sweep_unpacked = false;
+    // test knob (SN_TEST_NO_PCELL): meshes keep no cell index per point, as
+    // for volumes of 2^32 cells or more, so world points come from k_emit
+    // after the sweeps
+    bool no_pcell = false;
     // device address of the no-allocation extraction's static scratch array
     void *noalloc_scratch = nullptr;
     // the sweeps of a batch: one HIP graph per call (default), or the kernels

@@ -301,6 +301,8 @@ extern "C" sn_status sn_ctx_create(int device, sn_ctx **out)
         c->batch_eager = std::string(be) == "eager";
     if (const char *su = std::getenv("SN_TEST_SWEEP_UNPACKED"); su && *su)
         c->sweep_unpacked = std::strtoll(su, nullptr, 10) != 0;
+    if (const char *np = std::getenv("SN_TEST_NO_PCELL"); np && *np)
+        c->no_pcell = std::strtoll(np, nullptr, 10) != 0;
     if (const char *sc = std::getenv("SN_TEST_SWEEP_CHUNK"); sc && *sc)
         c->sweep_chunk = (int32_t)std::min<int64_t>(std::max<int64_t>(0, std::strtoll(sc, nullptr, 10)),
                                                     int64_t(1) << 20);
@@ -1167,7 +1169,7 @@ sn_status sn::extract_many(sn_ctx *c, const sn_volume *vols, int32_t n, hipStrea
             d.tri_pairs = blk + ol.o_tp;
             qblocks += (m->Q + 255) / 256;
         }
-        d.pcell = ol.cells32 ? reinterpret_cast<uint32_t *>(blk + ol.o_pc) : nullptr;
+        d.pcell = ol.cells32 && !c->no_pcell ? reinterpret_cast<uint32_t *>(blk + ol.o_pc) : nullptr;
         hd[k] = d;
     }
     if (one) {

@@ -213,3 +213,63 @@ def test_paper_scale_synthetic(sn, torch, monkeypatch, big):
                          slab=32, workers=WORKERS)
     finally:
         c.close()
+
+
+def test_world_points_from_emit(sn, torch, monkeypatch):
+    """Volumes of 2^32 cells or more keep no cell index per point, so their
+    world points come from k_emit after the sweeps instead of from the last
+    sweep.  The knob SN_TEST_NO_PCELL sends small volumes there: plain calls
+    (both sweep forms) and a batch give the bytes of the ordinary path, and
+    the oracle's offsets and world points."""
+    import oracle
+
+    rng = np.random.default_rng(61)
+    vols = [synth.blocky_tiny(rng, (45, 23, 17), 6, np.uint16),
+            synth.random_tiny(rng, (19, 31, 12), 4, np.uint8),
+            synth.blocky_tiny(rng, (130, 9, 7), 5, np.uint32)]
+    params = [(9, 0.5, 0.8), (0, 0.5, 1.0), (4, 1.0, 0.3)]
+    spacing, origin = (0.7, 1.3, 2.1), (3.0, -4.0, 1.5)
+    monkeypatch.delenv("SN_TEST_NO_PCELL", raising=False)
+    ref_ctx = sn.Context(0)
+    try:
+        ref = []
+        for v, (it, lam, d) in zip(vols, params):
+            m = ref_ctx.extract(sn.to_device(v), spacing=spacing, origin=origin)
+            ref_ctx.smooth(m, iterations=it, relaxation=lam, constraint=d)
+            ref.append(m.to_host())
+            m.free()
+    finally:
+        ref_ctx.close()
+    for small in ("", "0"):
+        monkeypatch.setenv("SN_TEST_NO_PCELL", "1")
+        if small:
+            monkeypatch.setenv("SN_TEST_SWEEP_SMALL_POINTS", small)
+        else:
+            monkeypatch.delenv("SN_TEST_SWEEP_SMALL_POINTS", raising=False)
+        c = sn.Context(0)
+        try:
+            ts = [sn.to_device(v) for v in vols]
+            for k, (t, (it, lam, d)) in enumerate(zip(ts, params)):
+                announce(f"no cell index: volume {k}, large-mesh form {bool(small)}")
+                m = c.extract(t, spacing=spacing, origin=origin)
+                c.smooth(m, iterations=it, relaxation=lam, constraint=d)
+                g = m.to_host()
+                m.free()
+                for f in ("points", "offsets", "polys", "label_pairs", "stencil_off", "stencil_ids"):
+                    assert np.array_equal(getattr(g, f), getattr(ref[k], f)), (k, f)
+                o = oracle.extract(vols[k])
+                pos = o.smooth(it, lam, d)
+                if o.n_points:
+                    assert np.max(np.abs(g.offsets.astype(np.float64) - (pos - o.centres()))) <= TOL
+                    w = oracle.world(pos, origin, spacing)
+                    ulp = np.spacing(np.abs(w).astype(np.float32)).astype(np.float64)
+                    assert np.all(np.abs(g.points.astype(np.float64) - w) <= TOL * np.asarray(spacing) + ulp)
+            announce(f"no cell index: a batch, large-mesh form {bool(small)}")
+            ms = c.batch_submit([dict(labels=t, spacing=spacing, origin=origin) for t in ts], params)
+            for k, m in enumerate(ms):
+                g = m.to_host()
+                m.free()
+                for f in ("points", "offsets", "polys", "label_pairs", "stencil_off", "stencil_ids"):
+                    assert np.array_equal(getattr(g, f), getattr(ref[k], f)), (k, f)
+        finally:
+            c.close()
